@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""ST-HOSVD benchmark on one MI355X.
+
+Workload: the 512 x 512 x 512 float32 smooth field (32 Gaussian blobs + 8 plane
+waves + 1e-4 white noise, seed 0), relative error target 1e-3, ST-HOSVD with
+split-precision (bf16x3) Gram matrices and mode products, FP64 eigensolver.
+The plain FP32 path is timed on the same input beside it.
+
+One step = one full ST-HOSVD (every mode: Gram, eigensolver, rank choice,
+projection) of the resident input.  `value` is input GB/s of the bf16x3 path:
+input bytes / mean step time over the timed steps.
+
+Extra fields:
+  roofline      dominant MFMA kernel (Gram matrix of the first processed mode),
+                its mean duration from HIP events recorded on the library's
+                stream inside the timed region;
+  mfma_frac     FP32-equivalent MFMA fractions (Gram only, Gram + mode product,
+                end to end) against 2516.6/3 TFLOP/s;
+  cpu_baseline  the FP64 CPU oracle on the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+PEAK_BF16_TFLOPS = 2516.6    # MI355X dense bf16 MFMA
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 MFMA
+PEAK_HBM_GBS = 8000.0
+METRIC = "ST-HOSVD input GB/s + % MFMA peak at rel err 1e-3, split-prec vs plain FP32"
+
+
+def algorithmic_flops(dims, ranks, order):
+    """Per-mode algorithmic flops: Gram n_k (n_k + 1) M_k, mode product 2 n_k r_k M_k,
+    M_k = product of the other current mode sizes."""
+    cur = list(dims)
+    gram, ttm = {}, {}
+    for k in order:
+        m = 1
+        for j, c in enumerate(cur):
+            if j != k:
+                m *= c
+        n = cur[k]
+        gram[k] = n * (n + 1) * m
+        ttm[k] = 2 * n * ranks[k] * m
+        cur[k] = ranks[k]
+    return gram, ttm
+
+
+def time_path(atc, torch, x, eps, precision, steps, warmup, ws, out):
+    for _ in range(warmup):
+        atc.sthosvd(x, eps, precision, workspace=ws, out=out, profile=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(steps):
+        results.append(atc.sthosvd(x, eps, precision, workspace=ws, out=out, profile=True))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / steps, results
+
+
+def mean_phase(results, name, k):
+    return sum(r.phase_ms[name][k] for r in results) / len(results)
+
+
+def rel_error_gpu(atc, torch, x, t):
+    """|X - X~| / |X| with X~ rebuilt by the library; differences summed in FP64."""
+    xh = atc.reconstruct(t.core.contiguous(), [f.contiguous() for f in t.factors])
+    d = (x.double() - xh.double()).pow(2).sum()
+    return float(torch.sqrt(d / x.double().pow(2).sum()))
+
+
+def cpu_baseline(x_np, eps):
+    import numpy as np
+
+    import oracle
+
+    x64 = np.ascontiguousarray(x_np, dtype=np.float64)
+    t0 = time.perf_counter()
+    t = oracle.sthosvd(x64, eps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    return {
+        "value": round(x_np.nbytes / dt / 1e9, 4),
+        "unit": "GB/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": "full workload: one FP64 ST-HOSVD of the 512^3 field at eps 1e-3 (%.1f s, ranks %s)"
+                  % (dt, t.ranks),
+        "ranks": t.ranks,
+        "seconds": round(dt, 3),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512, help="edge of the cubic field")
+    ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison path")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the ST-HOSVD here runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2107_01384_amd as atc
+    import synth
+
+    dims = (args.n,) * 3
+    x_np = synth.field(dims, 0)
+    x = torch.from_numpy(x_np).cuda()
+    nbytes = x_np.nbytes
+    ws = torch.empty(atc.sthosvd_workspace_size(dims, torch.float32, precision="bf16x3"), dtype=torch.uint8,
+                     device="cuda")
+    out = (torch.empty(x.numel(), dtype=torch.float32, device="cuda"),
+           [torch.empty(n * n, dtype=torch.float32, device="cuda") for n in dims])
+    print("bench: field %s generated, %d steps + %d warmup" % (dims, args.steps, args.warmup), file=sys.stderr,
+          flush=True)
+
+    ms_bf, res_bf = time_path(atc, torch, x, args.eps, "bf16x3", args.steps, args.warmup, ws, out)
+    t_bf = res_bf[-1]
+    err_bf = rel_error_gpu(atc, torch, x, t_bf)
+    print("bench: bf16x3 %.3f ms/step ranks %s err %.4e" % (ms_bf, t_bf.ranks, err_bf), file=sys.stderr, flush=True)
+
+    gram, ttm = algorithmic_flops(dims, t_bf.ranks, t_bf.order)
+    k0 = t_bf.order[0]
+    gram_ms = {k: mean_phase(res_bf, "gram", k) for k in t_bf.order}
+    ttm_ms = {k: mean_phase(res_bf, "ttm", k) for k in t_bf.order}
+    eig_ms = {k: mean_phase(res_bf, "eig", k) for k in t_bf.order}
+    red_ms = {k: mean_phase(res_bf, "reduce", k) for k in t_bf.order}
+    peak_eq = PEAK_BF16_TFLOPS / 3.0
+    g_fl = sum(gram.values())
+    t_fl = sum(ttm.values())
+    frac_gram = g_fl / (sum(gram_ms.values()) * 1e-3) / 1e12 / peak_eq
+    frac_gt = (g_fl + t_fl) / ((sum(gram_ms.values()) + sum(ttm_ms.values())) * 1e-3) / 1e12 / peak_eq
+    frac_e2e = (g_fl + t_fl) / (ms_bf * 1e-3) / 1e12 / peak_eq
+    # dominant MFMA kernel: the first mode's Gram matrix; bf16 operations = 3 per FP32-equivalent product
+    achieved = 3.0 * gram[k0] / (gram_ms[k0] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                "kernel": "k_gram<bf16x3, contiguous-R> mode %d" % k0, "kernel_ms": round(gram_ms[k0], 4)}
+
+    fp32 = None
+    if not args.no_fp32:
+        ms_32, res_32 = time_path(atc, torch, x, args.eps, "native", args.steps, args.warmup, ws, out)
+        t_32 = res_32[-1]
+        err_32 = rel_error_gpu(atc, torch, x, t_32)
+        g32 = {k: mean_phase(res_32, "gram", k) for k in t_32.order}
+        fp32 = {"value": round(nbytes / (ms_32 * 1e-3) / 1e9, 3), "ms_per_step": round(ms_32, 4),
+                "ranks": t_32.ranks, "rel_error": err_32,
+                "gram_mode0_tflops": round(gram[k0] / (g32[k0] * 1e-3) / 1e12, 2),
+                "gram_mode0_frac_fp32_peak": round(gram[k0] / (g32[k0] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+                "speedup_bf16x3_vs_fp32": round(ms_32 / ms_bf, 3)}
+        print("bench: fp32 %.3f ms/step ranks %s err %.4e" % (ms_32, t_32.ranks, err_32), file=sys.stderr,
+              flush=True)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(x_np, args.eps)
+
+    line = {
+        "metric": METRIC,
+        "value": round(nbytes / (ms_bf * 1e-3) / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_bf, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": "ST-HOSVD of a %dx%dx%d float32 smooth field (blobs + plane waves + 1e-4 noise, "
+                               "seed 0), rel err %g, bf16x3 Gram/TTM, FP64 eigensolver" % (dims + (args.eps,)),
+                   "shape": list(dims), "rel_error": args.eps, "parallelism": "single GPU"},
+        "ranks": t_bf.ranks,
+        "rel_error_achieved": err_bf,
+        "mfma_frac": {"gram": round(frac_gram, 4), "gram_ttm": round(frac_gt, 4), "e2e": round(frac_e2e, 4),
+                      "peak_tflops_fp32_equiv": round(peak_eq, 1)},
+        "phase_ms": {"gram": {str(k): round(v, 4) for k, v in gram_ms.items()},
+                     "reduce": {str(k): round(v, 4) for k, v in red_ms.items()},
+                     "eig": {str(k): round(v, 4) for k, v in eig_ms.items()},
+                     "ttm": {str(k): round(v, 4) for k, v in ttm_ms.items()}},
+        "roofline": roofline,
+        "fp32_path": fp32,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

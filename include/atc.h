@@ -1,0 +1,250 @@
+/*
+ * atc.h -- C ABI of the MI355X (gfx950) ST-HOSVD library.
+ *
+ * The library computes the sequentially truncated higher-order SVD (ST-HOSVD)
+ * of a dense tensor, the first phase of the ATC Tucker compressor
+ * (arXiv 2107.01384, Section 3.2, Algorithm 1; Section 4.1), and the Tucker
+ * reconstruction (U_1, ..., U_d) . B (Section 3.2) with its adjoint.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Tensors are dense, row-major (C order, last index fastest), as the
+ *    paper's flattened binary format (Section 5, "Supported types and I/O").
+ *  * Every data pointer is a DEVICE pointer on the current HIP device unless
+ *    the comment says "host".  `stream` is a hipStream_t passed as void*;
+ *    NULL means the default stream.  All work is enqueued on that stream.
+ *  * The caller allocates every buffer (inputs, outputs and the workspace
+ *    whose size the matching *_workspace_size call returns).  The library
+ *    never frees caller memory and keeps no pointer past the call, except
+ *    the explicit plan / graph objects below, which own their own memory
+ *    until destroyed.
+ *  * Errors: every entry point returns an atc_status.  Arguments are checked
+ *    before anything is enqueued; on error nothing is enqueued (except for
+ *    ATC_ERR_DEVICE / ATC_ERR_NOT_CONVERGED / ATC_ERR_NONFINITE_INPUT /
+ *    ATC_ERR_UNSUPPORTED raised mid-computation, after which output buffers
+ *    hold unspecified values).  atc_last_error() returns a thread-local
+ *    message describing the last failure of the calling thread.  No C++
+ *    exception and no abort crosses this boundary.
+ *  * Calls are re-entrant on different streams with different workspaces.
+ */
+#ifndef ATC_H_
+#define ATC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ATC_MAX_DIMS 8
+
+typedef enum {
+    ATC_OK = 0,
+    ATC_ERR_INVALID_ARGUMENT = -1,   /* NULL pointer, bad size, bad option value */
+    ATC_ERR_UNSUPPORTED = -2,        /* valid request outside what is built (e.g. mode too long) */
+    ATC_ERR_WORKSPACE_TOO_SMALL = -3,
+    ATC_ERR_DEVICE = -4,             /* a HIP runtime call failed */
+    ATC_ERR_NOT_CONVERGED = -5,      /* eigensolver hit its sweep cap */
+    ATC_ERR_NONFINITE_INPUT = -6,    /* |A|^2 of the input is NaN or Inf */
+    ATC_ERR_INTERNAL = -7
+} atc_status;
+
+typedef enum { ATC_F32 = 0, ATC_F64 = 1 } atc_dtype;
+
+/* Arithmetic of the Gram matrix and the projection (mode product).
+ *  NATIVE : FP64 MFMA for float64 input, FP32 MFMA for float32 input
+ *           (FP32 products accumulated in FP32 over chunks of 128 terms,
+ *           chunks summed in FP64).
+ *  BF16X3 : float32 input only.  Each operand a is split into
+ *           a_hi = bf16(a), a_lo = bf16(a - a_hi); a*b is formed on the bf16
+ *           matrix cores as hi*hi + hi*lo + lo*hi with FP32 accumulation
+ *           (chunks summed in FP64 as above).  Gram tiles on the diagonal add
+ *           lo*lo as well, so the diagonal (where the dropped lo*lo term would
+ *           always be positive) carries no bias.
+ * The eigensolver, rank choice and every tail sum are FP64 in both cases. */
+typedef enum { ATC_PREC_NATIVE = 0, ATC_PREC_BF16X3 = 1 } atc_precision;
+
+/* Per-mode share of the SSE budget S = rtmss * (rel_error * |A|)^2
+ * (Section 4.1.3; the paper defers the rule to the ST-HOSVD literature).
+ *  ADAPTIVE : mode i (0-based in processing order) gets (S - used) / (d - i)
+ *  EQUAL    : every mode gets S / d
+ * r_k is the smallest r >= 1 whose discarded eigenvalue sum fits the share. */
+typedef enum { ATC_RANK_ADAPTIVE = 0, ATC_RANK_EQUAL = 1 } atc_rank_rule;
+
+typedef struct {
+    int32_t ndim;                /* order d, 1 <= d <= ATC_MAX_DIMS */
+    int32_t dtype;               /* atc_dtype */
+    int64_t dims[ATC_MAX_DIMS];  /* n_0 .. n_{d-1}, each >= 1 */
+} atc_shape;
+
+typedef struct {
+    double rel_error;            /* target |A - A~| / |A| (Section 2.1, "relative error"); >= 0 */
+    double rtmss;                /* rank_truncation_max_sse_share (Section 4.1.3), in [0, 1]; default 1 */
+    int32_t precision;           /* atc_precision; default NATIVE */
+    int32_t rank_rule;           /* atc_rank_rule; default ADAPTIVE */
+    int32_t has_order;           /* nonzero: use mode_order (Section 4.1.1, user order) */
+    int32_t mode_order[ATC_MAX_DIMS]; /* permutation of 0..d-1 */
+    int32_t has_fixed_ranks;     /* nonzero: use fixed_ranks instead of the budget rule */
+    int32_t fixed_ranks[ATC_MAX_DIMS]; /* 1 <= r_k <= n_k */
+    int32_t max_sweeps;          /* eigensolver sweep cap; 0 = default (60) */
+    int32_t eig_path;            /* 0 = automatic, 1 = force dense Jacobi, 2 = force subspace (n > 64) */
+    int32_t profile;             /* nonzero: time each phase with stream events (atc_result.*_ms) */
+    int32_t reserved[5];
+} atc_sthosvd_opts;
+
+/* Host-side record of one ST-HOSVD call. */
+typedef struct {
+    int64_t ranks[ATC_MAX_DIMS];   /* chosen r_k (natural mode index) */
+    int32_t order[ATC_MAX_DIMS];   /* processing order used */
+    double norm2;                  /* |A|^2 (trace of the first Gram matrix) */
+    double sse_pred;               /* sum over modes of the discarded eigenvalues (Section 4.1.3) */
+    double tail[ATC_MAX_DIMS];     /* discarded energy per mode */
+    double budget[ATC_MAX_DIMS];   /* budget share per mode */
+    int32_t eig_path[ATC_MAX_DIMS];/* 1 = dense Jacobi, 2 = subspace iteration */
+    int32_t eig_sweeps[ATC_MAX_DIMS];
+    double elapsed_ms;             /* device time of the call, stream events */
+    /* with opts.profile, per processed mode (natural index): Gram kernel,
+     * split-K reduction, eigensolver + rank choice, mode-product kernel */
+    double gram_ms[ATC_MAX_DIMS];
+    double reduce_ms[ATC_MAX_DIMS];
+    double eig_ms[ATC_MAX_DIMS];
+    double ttm_ms[ATC_MAX_DIMS];
+} atc_result;
+
+/* Fills *o with the defaults documented above (rel_error = 1e-3). */
+void atc_default_opts(atc_sthosvd_opts* o);
+
+/* Bytes of device workspace atc_sthosvd needs for this shape and options
+ * (0 on invalid arguments). */
+size_t atc_sthosvd_workspace_size(const atc_shape* shape, const atc_sthosvd_opts* opts);
+
+/*
+ * ST-HOSVD (Section 3.2, Algorithm 1; mode order and error control of
+ * Section 4.1): for each mode k in processing order, form the Gram matrix of
+ * the mode-k unfolding of the current tensor, eigendecompose it in FP64,
+ * keep the r_k leading eigenvectors (largest-magnitude entry of each made
+ * positive) and project mode k onto them.
+ *
+ *  x        input tensor, dtype shape->dtype, prod(dims) elements.
+ *  core     output core, same dtype, row-major r_0 x ... x r_{d-1} in natural
+ *           mode order; capacity prod(dims) elements (worst case r = n).
+ *  factors  host array of d device pointers; factors[k] receives U_k as a
+ *           row-major n_k x r_k matrix of the input dtype; capacity n_k^2.
+ *  result   host pointer, filled on success.
+ * The call returns after the work has completed (it reads each r_k back to
+ * size the next step).
+ */
+atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_opts* opts,
+                       void* core, void* const* factors, atc_result* result,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---------------------------------------------------------------- batched */
+
+/* Device-side record of one block of a batched call. */
+typedef struct {
+    int32_t ranks[3];
+    int32_t status;       /* 0 ok, else an atc_status value */
+    double norm2;
+    double sse_pred;
+    double tail[3];
+} atc_block_result;
+
+typedef struct atc_batch_plan atc_batch_plan;
+
+/*
+ * Plans the ST-HOSVD of many independent 3-way float32 blocks in one
+ * persistent launch (each block treated exactly as atc_sthosvd would with
+ * precision BF16X3 or NATIVE, mode order by increasing length).
+ *  dims     host array, nblocks x 3 mode sizes, each in [1, 64].
+ *  The plan fixes: input offsets (blocks packed back to back in block order),
+ *  core slots (prod(dims) floats per block) and factor slots (n_k^2 floats per
+ *  mode), the longest-first processing order and the launch configuration.
+ * The plan owns device memory until atc_batch_plan_destroy.
+ */
+atc_status atc_batch_plan_create(const int32_t* dims, int64_t nblocks, const atc_sthosvd_opts* opts,
+                                 atc_batch_plan** plan);
+void atc_batch_plan_destroy(atc_batch_plan* plan);
+
+/* Sizes in elements (float32) of the input arena, core arena and factor
+ * arena, and the workspace bytes; any pointer may be NULL. */
+atc_status atc_batch_plan_info(const atc_batch_plan* plan, int64_t* input_elems, int64_t* core_elems,
+                               int64_t* factor_elems, size_t* workspace_bytes);
+
+/* Host arrays of nblocks entries each (any may be NULL): element offsets of
+ * block b in the input, core and factor arenas (factor k of block b starts at
+ * factor_off[b] + sum_{j<k} n_j^2). */
+atc_status atc_batch_plan_offsets(const atc_batch_plan* plan, int64_t* input_off, int64_t* core_off,
+                                  int64_t* factor_off);
+
+/* Runs the plan: no host synchronisation, no allocation, capturable in a
+ * HIP graph.  results: device array of nblocks atc_block_result. */
+atc_status atc_sthosvd_batched(atc_batch_plan* plan, const float* arena, float* core_arena,
+                               float* factor_arena, atc_block_result* results,
+                               void* workspace, size_t workspace_bytes, void* stream);
+
+/* Times every candidate launch configuration of the persistent kernel on
+ * these buffers (median of `reps` runs each) and stores the fastest in the
+ * plan.  If cache_path is non-NULL the choice is read from / appended to that
+ * JSON-lines file, keyed by architecture, precision and block-size histogram.
+ * out_choice (host, may be NULL) receives the chosen candidate index. */
+atc_status atc_batch_autotune(atc_batch_plan* plan, const float* arena, float* core_arena,
+                              float* factor_arena, atc_block_result* results,
+                              void* workspace, size_t workspace_bytes, void* stream,
+                              int32_t reps, const char* cache_path, int32_t* out_choice);
+
+typedef struct atc_graph atc_graph;
+
+/* Captures one atc_sthosvd_batched call (all its launches) into a HIP graph
+ * on `stream` and instantiates it; replays run the same buffers. */
+atc_status atc_batch_graph_create(atc_batch_plan* plan, const float* arena, float* core_arena,
+                                  float* factor_arena, atc_block_result* results,
+                                  void* workspace, size_t workspace_bytes, void* stream,
+                                  atc_graph** graph);
+atc_status atc_graph_launch(atc_graph* graph, void* stream);
+void atc_graph_destroy(atc_graph* graph);
+
+/* ---------------------------------------------------------- reconstruction */
+
+/* Workspace for atc_reconstruct (shape: the full n_k; ranks: r_k). */
+size_t atc_reconstruct_workspace_size(const atc_shape* shape, const int64_t* ranks);
+
+/*
+ * Tucker reconstruction X~ = (U_0, ..., U_{d-1}) . G (Section 3.2): every mode
+ * of the core G (r_0 x ... x r_{d-1}) is expanded by its factor U_k (n_k x r_k,
+ * row-major).  The mode order minimises sum_i n_{p1}..n_{pi} r_{pi}..r_{pd}
+ * (Section 4.1.1, exhaustive search, first lexicographic order on ties).
+ *  ranks    host array of d ranks, 1 <= r_k <= n_k.
+ *  factors  host array of d device pointers.
+ *  xhat     output, prod(n) elements, dtype shape->dtype.
+ * Arithmetic: FP32 MFMA for float32, FP64 MFMA for float64.
+ */
+atc_status atc_reconstruct(const atc_shape* shape, const int64_t* ranks, const void* core,
+                           const void* const* factors, void* xhat,
+                           void* workspace, size_t workspace_bytes, void* stream);
+
+size_t atc_reconstruct_backward_workspace_size(const atc_shape* shape, const int64_t* ranks);
+
+/*
+ * Adjoint of atc_reconstruct: given R = dL/dX~ (same shape as X~), writes
+ *   dcore      = R x_0 U_0^T x_1 U_1^T ... x_{d-1} U_{d-1}^T     (r_0 x ... x r_{d-1})
+ *   dfactors[n] = R_(n) W_(n)^T, W = G x_{m != n} U_m              (n_n x r_n)
+ * (the mode-product rules of Section 3.1).  Partial products are recomputed
+ * from G and the U_k, not read from the forward pass.  dfactors: host array of
+ * d device pointers; any of dcore / dfactors[n] may be NULL to skip it.
+ */
+atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks, const void* core,
+                                    const void* const* factors, const void* dxhat, void* dcore,
+                                    void* const* dfactors, void* workspace, size_t workspace_bytes,
+                                    void* stream);
+
+/* ------------------------------------------------------------------ misc */
+const char* atc_status_string(atc_status s);
+const char* atc_last_error(void);
+/* Library version string, e.g. "atc-mi355x 0.1 gfx950". */
+const char* atc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ATC_H_ */

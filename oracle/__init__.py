@@ -7,8 +7,8 @@ Jacobi) live in ``oracle.c``; the algorithm itself is written out here step by
 step in the order of the paper.
 
 Paper passages followed (arXiv 2107.01384):
-  * Section 2.1 (tensor concepts): norm, mode-k unfolding, mode-k product;
-  * Section 3.1 / Algorithm 1 (ST-HOSVD): per mode, factor from the SVD of the
+  * Section 3.1 (tensor concepts): norm, mode-k unfolding, mode-k product;
+  * Section 3.2 / Algorithm 1 (ST-HOSVD): per mode, factor from the SVD of the
     current unfolding (here: eigenvectors of its Gram matrix, whose eigenvalues
     are the squared singular values), truncation rank, projection;
   * Section 4.1.1 (mode processing order): increasing mode length by default,
@@ -101,7 +101,7 @@ def lnr(dims: Sequence[int], k: int):
 
 # ---------------------------------------------------------------- primitives
 def norm2(x) -> float:
-    """Squared Euclidean norm <X, X> (Section 2.1)."""
+    """Squared Euclidean norm <X, X> (Section 3.1)."""
     x = _f64(x)
     return float(_load().oracle_norm2(_ptr(x), x.size))
 
@@ -128,7 +128,7 @@ def cross_gram(x, w, k: int) -> np.ndarray:
 
 
 def mode_product(y, k: int, m) -> np.ndarray:
-    """Z = M x_k Y, i.e. Z_(k) = M Y_(k) (Section 2.1); M has shape (m, n_k)."""
+    """Z = M x_k Y, i.e. Z_(k) = M Y_(k) (Section 3.1); M has shape (m, n_k)."""
     y, m = _f64(y), _f64(m)
     L, n, R = lnr(y.shape, k)
     if m.shape[1] != n:
@@ -217,7 +217,7 @@ def sthosvd(x, eps: float, order=None, rtmss: float = 1.0, rule: str = "adaptive
     """ST-HOSVD (Algorithm 1) with Gram + eigendecomposition per mode, in FP64.
 
     x: array of any real dtype (converted to float64, exact for float32).
-    eps: target relative error |A - A~| / |A| (Section 2, RE).
+    eps: target relative error |A - A~| / |A| (Section 2.1, relative error).
     Returns a Tucker record: core (natural mode order), factors U_k (n_k x r_k).
     """
     if rule not in ("adaptive", "equal"):
@@ -291,7 +291,7 @@ def reconstruct_order(dims: Sequence[int], ranks: Sequence[int]):
 
 
 def reconstruct(core, factors, order=None) -> np.ndarray:
-    """(U_1, ..., U_d) . B (Section 2.2): expand every mode of the core by its factor."""
+    """(U_1, ..., U_d) . B (Section 3.2): expand every mode of the core by its factor."""
     y = _f64(core)
     dims = [f.shape[0] for f in factors]
     ranks = list(y.shape)

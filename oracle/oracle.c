@@ -10,7 +10,7 @@
  * (L, n, R): L = product of the sizes before mode k, n = size of mode k,
  * R = product of the sizes after mode k.  Element (l, i, r) sits at
  * (l * n + i) * R + r.  This view is exact for a row-major tensor and needs no
- * data movement (Section 2.1: the matricization may order the fibers in any
+ * data movement (Section 3.1: the matricization may order the fibers in any
  * consistent manner, and neither the Gram matrix nor the mode product depends
  * on that order).
  *
@@ -41,7 +41,7 @@ static double orc_dot(const double* x, int64_t sx, const double* y, int64_t sy, 
     return orc_combine(s);
 }
 
-/* Squared Euclidean norm (Section 2.1: inner product of a tensor with itself),
+/* Squared Euclidean norm (Section 3.1: inner product of a tensor with itself),
  * by pairwise (recursive halving) summation of the squares. */
 static double orc_sumsq(const double* x, int64_t n) {
     if (n <= 64) {
@@ -98,7 +98,7 @@ void oracle_gram(const double* Y, int64_t L, int64_t n, int64_t R, double* G) {
 }
 
 /*
- * Mode product (Section 2.1): Z = M x_k Y, i.e. Z_(k) = M Y_(k).
+ * Mode product (Section 3.1): Z = M x_k Y, i.e. Z_(k) = M Y_(k).
  *   Z[l, j, r] = sum_i M[j, i] * Y[l, i, r],  M: (m, n) row-major, Y: (L, n, R), Z: (L, m, R).
  * The truncating projection of Algorithm 1 is M = U^T (m = r_k < n); the
  * expansion used by reconstruction is M = U (the core's r_k grows to n_k).

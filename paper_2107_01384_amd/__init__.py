@@ -1,0 +1,327 @@
+"""Python binding of libatc, the MI355X (gfx950) ST-HOSVD library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libatc.so`` behind the C ABI declared in ``include/atc.h``.
+PyTorch provides device memory and the current HIP stream.  There is no CPU
+fallback: if the library is missing or no GPU is present the calls raise.
+
+Entry points (same names as the C ABI, minus the ``atc_`` prefix):
+  * ``sthosvd(x, rel_error, ...)``            -- ST-HOSVD (Algorithm 1, Section 3.2)
+  * ``BatchPlan`` / ``sthosvd_batched(...)``  -- many small blocks, one persistent launch
+  * ``reconstruct(core, factors)``            -- Tucker reconstruction (Section 3.2)
+  * ``reconstruct_backward(core, factors, dxhat)`` and ``TuckerReconstruct``
+    (a ``torch.autograd.Function`` whose backward is the hand-written adjoint).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libatc.so")
+MAX_DIMS = 8
+
+ATC_F32, ATC_F64 = 0, 1
+PRECISIONS = {"native": 0, "bf16x3": 1}
+RULES = {"adaptive": 0, "equal": 1}
+STATUS = {
+    0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small", -4: "device error",
+    -5: "eigensolver did not converge", -6: "non-finite input", -7: "internal error",
+}
+
+
+class AtcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("atc status %d (%s): %s" % (status, STATUS.get(status, "?"), message))
+        self.status = status
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("dims", ctypes.c_int64 * MAX_DIMS)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("rel_error", ctypes.c_double), ("rtmss", ctypes.c_double), ("precision", ctypes.c_int32),
+        ("rank_rule", ctypes.c_int32), ("has_order", ctypes.c_int32), ("mode_order", ctypes.c_int32 * MAX_DIMS),
+        ("has_fixed_ranks", ctypes.c_int32), ("fixed_ranks", ctypes.c_int32 * MAX_DIMS),
+        ("max_sweeps", ctypes.c_int32), ("eig_path", ctypes.c_int32), ("profile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("ranks", ctypes.c_int64 * MAX_DIMS), ("order", ctypes.c_int32 * MAX_DIMS), ("norm2", ctypes.c_double),
+        ("sse_pred", ctypes.c_double), ("tail", ctypes.c_double * MAX_DIMS), ("budget", ctypes.c_double * MAX_DIMS),
+        ("eig_path", ctypes.c_int32 * MAX_DIMS), ("eig_sweeps", ctypes.c_int32 * MAX_DIMS),
+        ("elapsed_ms", ctypes.c_double), ("gram_ms", ctypes.c_double * MAX_DIMS),
+        ("reduce_ms", ctypes.c_double * MAX_DIMS), ("eig_ms", ctypes.c_double * MAX_DIMS),
+        ("ttm_ms", ctypes.c_double * MAX_DIMS),
+    ]
+
+
+class BlockResult(ctypes.Structure):
+    _fields_ = [
+        ("ranks", ctypes.c_int32 * 3), ("status", ctypes.c_int32), ("norm2", ctypes.c_double),
+        ("sse_pred", ctypes.c_double), ("tail", ctypes.c_double * 3),
+    ]
+
+
+# (name, restype, argtypes) of every symbol include/atc.h declares
+_VP, _SZ, _I64, _I32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int32
+_P = ctypes.POINTER
+SIGNATURES = [
+    ("atc_default_opts", None, [_P(Opts)]),
+    ("atc_sthosvd_workspace_size", _SZ, [_P(Shape), _P(Opts)]),
+    ("atc_sthosvd", _I32, [_VP, _P(Shape), _P(Opts), _VP, _P(_VP), _P(Result), _VP, _SZ, _VP]),
+    ("atc_batch_plan_create", _I32, [_P(_I32), _I64, _P(Opts), _P(_VP)]),
+    ("atc_batch_plan_destroy", None, [_VP]),
+    ("atc_batch_plan_info", _I32, [_VP, _P(_I64), _P(_I64), _P(_I64), _P(_SZ)]),
+    ("atc_batch_plan_offsets", _I32, [_VP, _P(_I64), _P(_I64), _P(_I64)]),
+    ("atc_sthosvd_batched", _I32, [_VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    ("atc_batch_autotune", _I32, [_VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP, _I32, ctypes.c_char_p, _P(_I32)]),
+    ("atc_batch_graph_create", _I32, [_VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP, _P(_VP)]),
+    ("atc_graph_launch", _I32, [_VP, _VP]),
+    ("atc_graph_destroy", None, [_VP]),
+    ("atc_reconstruct_workspace_size", _SZ, [_P(Shape), _P(_I64)]),
+    ("atc_reconstruct", _I32, [_P(Shape), _P(_I64), _VP, _P(_VP), _VP, _VP, _SZ, _VP]),
+    ("atc_reconstruct_backward_workspace_size", _SZ, [_P(Shape), _P(_I64)]),
+    ("atc_reconstruct_backward", _I32, [_P(Shape), _P(_I64), _VP, _P(_VP), _VP, _VP, _P(_VP), _VP, _SZ, _VP]),
+    ("atc_status_string", ctypes.c_char_p, [_I32]),
+    ("atc_last_error", ctypes.c_char_p, []),
+    ("atc_version", ctypes.c_char_p, []),
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libatc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libatc.so is not built (%s); run paper_2107_01384_amd.build.build()" % path)
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise AtcError(status, load().atc_last_error().decode(errors="replace"))
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _require_gpu(t: torch.Tensor, what: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor" % what)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % what)
+    if t.dtype not in (torch.float32, torch.float64):
+        raise ValueError("%s must be float32 or float64" % what)
+
+
+def _shape(dims: Sequence[int], dtype: torch.dtype) -> Shape:
+    s = Shape()
+    s.ndim = len(dims)
+    s.dtype = ATC_F64 if dtype == torch.float64 else ATC_F32
+    for i, n in enumerate(dims):
+        s.dims[i] = int(n)
+    return s
+
+
+def make_opts(rel_error: float = 1e-3, precision: str = "native", order=None, rtmss: float = 1.0,
+              rule: str = "adaptive", fixed_ranks=None, max_sweeps: int = 0, eig_path: int = 0,
+              profile: bool = False) -> Opts:
+    o = Opts()
+    load().atc_default_opts(ctypes.byref(o))
+    o.rel_error = float(rel_error)
+    o.rtmss = float(rtmss)
+    o.precision = PRECISIONS[precision]
+    o.rank_rule = RULES[rule]
+    if order is not None:
+        o.has_order = 1
+        for i, k in enumerate(order):
+            o.mode_order[i] = int(k)
+    if fixed_ranks is not None:
+        o.has_fixed_ranks = 1
+        for i, r in enumerate(fixed_ranks):
+            o.fixed_ranks[i] = int(r)
+    o.max_sweeps = int(max_sweeps)
+    o.eig_path = int(eig_path)
+    o.profile = 1 if profile else 0
+    return o
+
+
+@dataclass
+class Tucker:
+    core: torch.Tensor
+    factors: List[torch.Tensor]
+    ranks: List[int]
+    order: List[int]
+    norm2: float
+    sse_pred: float
+    tails: List[float]
+    budgets: List[float]
+    eig_path: List[int]
+    eig_sweeps: List[int]
+    elapsed_ms: float
+    phase_ms: dict
+
+
+def sthosvd_workspace_size(dims, dtype=torch.float32, **opt_kw) -> int:
+    s = _shape(dims, dtype)
+    o = make_opts(**opt_kw)
+    n = load().atc_sthosvd_workspace_size(ctypes.byref(s), ctypes.byref(o))
+    if n == 0:
+        _check(-1)
+    return int(n)
+
+
+def sthosvd(x: torch.Tensor, rel_error: float = 1e-3, precision: str = "native", order=None, rtmss: float = 1.0,
+            rule: str = "adaptive", fixed_ranks=None, max_sweeps: int = 0, eig_path: int = 0,
+            workspace: Optional[torch.Tensor] = None, stream=None, profile: bool = False,
+            out: Optional[tuple] = None) -> Tucker:
+    """ST-HOSVD of x (GPU tensor) to relative error rel_error; see atc_sthosvd in include/atc.h."""
+    lib = load()
+    _require_gpu(x, "x")
+    dims = list(x.shape)
+    s = _shape(dims, x.dtype)
+    o = make_opts(rel_error, precision, order, rtmss, rule, fixed_ranks, max_sweeps, eig_path, profile)
+    need = lib.atc_sthosvd_workspace_size(ctypes.byref(s), ctypes.byref(o))
+    if need == 0:
+        _check(-1)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    if out is not None:  # preallocated (core, [factors]) buffers of full capacity
+        core, facs = out
+    else:
+        core = torch.empty(x.numel(), dtype=x.dtype, device=x.device)
+        facs = [torch.empty(n * n, dtype=x.dtype, device=x.device) for n in dims]
+    fptr = (ctypes.c_void_p * len(dims))(*[f.data_ptr() for f in facs])
+    res = Result()
+    st = lib.atc_sthosvd(ctypes.c_void_p(x.data_ptr()), ctypes.byref(s), ctypes.byref(o),
+                         ctypes.c_void_p(core.data_ptr()), fptr, ctypes.byref(res),
+                         ctypes.c_void_p(workspace.data_ptr()), need, ctypes.c_void_p(_stream(stream)))
+    _check(st)
+    d = len(dims)
+    ranks = [int(res.ranks[k]) for k in range(d)]
+    ncore = 1
+    for r in ranks:
+        ncore *= r
+    return Tucker(
+        core=core[:ncore].view(*ranks),
+        factors=[facs[k][: dims[k] * ranks[k]].view(dims[k], ranks[k]) for k in range(d)],
+        ranks=ranks, order=[int(res.order[k]) for k in range(d)], norm2=float(res.norm2),
+        sse_pred=float(res.sse_pred), tails=[float(res.tail[k]) for k in range(d)],
+        budgets=[float(res.budget[k]) for k in range(d)], eig_path=[int(res.eig_path[k]) for k in range(d)],
+        eig_sweeps=[int(res.eig_sweeps[k]) for k in range(d)], elapsed_ms=float(res.elapsed_ms),
+        phase_ms={name: [float(getattr(res, name + "_ms")[k]) for k in range(d)]
+                  for name in ("gram", "reduce", "eig", "ttm")})
+
+
+# ----------------------------------------------------------------- reconstruction
+def _ranks_arr(ranks):
+    a = (ctypes.c_int64 * MAX_DIMS)()
+    for i, r in enumerate(ranks):
+        a[i] = int(r)
+    return a
+
+
+def reconstruct(core: torch.Tensor, factors: Sequence[torch.Tensor], stream=None) -> torch.Tensor:
+    """X~ = (U_0, ..., U_{d-1}) . G; see atc_reconstruct."""
+    lib = load()
+    _require_gpu(core, "core")
+    for f in factors:
+        _require_gpu(f, "factor")
+        if f.dtype != core.dtype:
+            raise ValueError("factors must have the core's dtype")
+    dims = [int(f.shape[0]) for f in factors]
+    ranks = [int(f.shape[1]) for f in factors]
+    if list(core.shape) != ranks:
+        raise ValueError("core shape %s does not match factor ranks %s" % (list(core.shape), ranks))
+    s = _shape(dims, core.dtype)
+    ra = _ranks_arr(ranks)
+    need = lib.atc_reconstruct_workspace_size(ctypes.byref(s), ra)
+    if need == 0:
+        _check(-1)
+    ws = torch.empty(need, dtype=torch.uint8, device=core.device)
+    out = torch.empty(dims, dtype=core.dtype, device=core.device)
+    fptr = (ctypes.c_void_p * len(dims))(*[f.data_ptr() for f in factors])
+    _check(lib.atc_reconstruct(ctypes.byref(s), ra, ctypes.c_void_p(core.data_ptr()), fptr,
+                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), need,
+                               ctypes.c_void_p(_stream(stream))))
+    return out
+
+
+def reconstruct_backward(core: torch.Tensor, factors: Sequence[torch.Tensor], dxhat: torch.Tensor,
+                         need_core: bool = True, need_factors=None, stream=None):
+    """(dL/dG, [dL/dU_n]) for R = dL/dX~ = dxhat; see atc_reconstruct_backward."""
+    lib = load()
+    _require_gpu(core, "core")
+    _require_gpu(dxhat, "dxhat")
+    dims = [int(f.shape[0]) for f in factors]
+    ranks = [int(f.shape[1]) for f in factors]
+    if list(dxhat.shape) != dims:
+        raise ValueError("dxhat shape must equal the full tensor shape")
+    d = len(dims)
+    if need_factors is None:
+        need_factors = [True] * d
+    s = _shape(dims, core.dtype)
+    ra = _ranks_arr(ranks)
+    need = lib.atc_reconstruct_backward_workspace_size(ctypes.byref(s), ra)
+    if need == 0:
+        _check(-1)
+    ws = torch.empty(need, dtype=torch.uint8, device=core.device)
+    dcore = torch.empty_like(core) if need_core else None
+    dfs = [torch.empty(dims[k], ranks[k], dtype=core.dtype, device=core.device) if need_factors[k] else None
+           for k in range(d)]
+    fptr = (ctypes.c_void_p * d)(*[f.data_ptr() for f in factors])
+    dptr = (ctypes.c_void_p * d)(*[(t.data_ptr() if t is not None else None) for t in dfs])
+    _check(lib.atc_reconstruct_backward(ctypes.byref(s), ra, ctypes.c_void_p(core.data_ptr()), fptr,
+                                        ctypes.c_void_p(dxhat.data_ptr()),
+                                        ctypes.c_void_p(dcore.data_ptr() if dcore is not None else None), dptr,
+                                        ctypes.c_void_p(ws.data_ptr()), need, ctypes.c_void_p(_stream(stream))))
+    return dcore, dfs
+
+
+class TuckerReconstruct(torch.autograd.Function):
+    """X~ = (U_0, ..., U_{d-1}) . G with the hand-written adjoint.
+
+    Saves only G and the U_n; the backward recomputes every partial product."""
+
+    @staticmethod
+    def forward(ctx, core, *factors):
+        core = core.contiguous()
+        factors = [f.contiguous() for f in factors]
+        ctx.save_for_backward(core, *factors)
+        return reconstruct(core, factors)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        core, *factors = ctx.saved_tensors
+        need_core = ctx.needs_input_grad[0]
+        need_f = list(ctx.needs_input_grad[1:])
+        dcore, dfs = reconstruct_backward(core, factors, grad_out.contiguous(), need_core, need_f)
+        return (dcore, *dfs)
+
+
+def tucker_reconstruct(core, *factors):
+    return TuckerReconstruct.apply(core, *factors)
+
+
+from .batched import BatchPlan, sthosvd_batched  # noqa: E402  (after the ctypes definitions)

@@ -1,0 +1,744 @@
+// C ABI of libatc: argument checks, workspace carving and the host-side
+// sequencing of the per-mode kernels.  No exception leaves this file.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "atc_internal.hpp"
+
+using namespace atc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+atc_status fail(atc_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(ATC_ERR_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                     \
+    } while (0)
+
+constexpr int MAX_MODE = 4096;       // longest mode the eigensolvers accept
+constexpr int SUBSPACE_M = 64;       // subspace size of the leading-eigenpair path
+constexpr int SUBSPACE_ITERS = 2;    // power steps before the Rayleigh-Ritz projection
+constexpr int SUBSPACE_GUARD = 8;    // Ritz pairs the chosen rank must leave unused
+constexpr int DEFAULT_SWEEPS = 60;
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Carver {
+    size_t off = 0;
+    char* base = nullptr;
+    void* take(size_t bytes) {
+        void* p = base ? base + off : nullptr;
+        off = align_up(off + bytes);
+        return p;
+    }
+};
+
+int64_t prod(const int64_t* d, int a, int b) {
+    int64_t p = 1;
+    for (int i = a; i < b; ++i) p *= d[i];
+    return p;
+}
+
+atc_status check_shape(const atc_shape* s) {
+    if (!s) return fail(ATC_ERR_INVALID_ARGUMENT, "shape is NULL");
+    if (s->ndim < 1 || s->ndim > ATC_MAX_DIMS)
+        return fail(ATC_ERR_INVALID_ARGUMENT, "ndim %d outside [1, %d]", s->ndim, ATC_MAX_DIMS);
+    if (s->dtype != ATC_F32 && s->dtype != ATC_F64) return fail(ATC_ERR_INVALID_ARGUMENT, "unknown dtype %d", s->dtype);
+    double total = 1.0;
+    for (int k = 0; k < s->ndim; ++k) {
+        if (s->dims[k] < 1) return fail(ATC_ERR_INVALID_ARGUMENT, "dims[%d] = %lld < 1", k, (long long)s->dims[k]);
+        total *= (double)s->dims[k];
+    }
+    if (total > 9.0e15) return fail(ATC_ERR_UNSUPPORTED, "tensor too large");
+    return ATC_OK;
+}
+
+atc_status check_opts(const atc_shape* s, const atc_sthosvd_opts* o) {
+    if (!o) return fail(ATC_ERR_INVALID_ARGUMENT, "opts is NULL");
+    if (!(o->rel_error >= 0.0) || !std::isfinite(o->rel_error))
+        return fail(ATC_ERR_INVALID_ARGUMENT, "rel_error must be finite and >= 0");
+    if (!(o->rtmss >= 0.0 && o->rtmss <= 1.0)) return fail(ATC_ERR_INVALID_ARGUMENT, "rtmss must lie in [0, 1]");
+    if (o->precision != ATC_PREC_NATIVE && o->precision != ATC_PREC_BF16X3)
+        return fail(ATC_ERR_INVALID_ARGUMENT, "unknown precision %d", o->precision);
+    if (o->precision == ATC_PREC_BF16X3 && s->dtype != ATC_F32)
+        return fail(ATC_ERR_UNSUPPORTED, "BF16X3 precision needs float32 input");
+    if (o->rank_rule != ATC_RANK_ADAPTIVE && o->rank_rule != ATC_RANK_EQUAL)
+        return fail(ATC_ERR_INVALID_ARGUMENT, "unknown rank rule %d", o->rank_rule);
+    if (o->max_sweeps < 0) return fail(ATC_ERR_INVALID_ARGUMENT, "max_sweeps < 0");
+    if (o->eig_path < 0 || o->eig_path > 2) return fail(ATC_ERR_INVALID_ARGUMENT, "eig_path must be 0, 1 or 2");
+    if (o->has_order) {
+        int seen[ATC_MAX_DIMS] = {0};
+        for (int i = 0; i < s->ndim; ++i) {
+            const int k = o->mode_order[i];
+            if (k < 0 || k >= s->ndim || seen[k]) return fail(ATC_ERR_INVALID_ARGUMENT, "mode_order is not a permutation");
+            seen[k] = 1;
+        }
+    }
+    if (o->has_fixed_ranks) {
+        for (int k = 0; k < s->ndim; ++k)
+            if (o->fixed_ranks[k] < 1 || o->fixed_ranks[k] > s->dims[k])
+                return fail(ATC_ERR_INVALID_ARGUMENT, "fixed_ranks[%d] outside [1, n_k]", k);
+    }
+    for (int k = 0; k < s->ndim; ++k)
+        if (s->dims[k] > MAX_MODE) return fail(ATC_ERR_UNSUPPORTED, "mode %d longer than %d", k, MAX_MODE);
+    return ATC_OK;
+}
+
+void processing_order(const atc_shape* s, const atc_sthosvd_opts* o, int* order) {
+    const int d = s->ndim;
+    for (int i = 0; i < d; ++i) order[i] = o->has_order ? o->mode_order[i] : i;
+    if (!o->has_order)  // Section 4.1.1: increasing mode length, stable
+        std::stable_sort(order, order + d, [&](int a, int b) { return s->dims[a] < s->dims[b]; });
+}
+
+int prec_of(const atc_shape* s, const atc_sthosvd_opts* o) {
+    if (s->dtype == ATC_F64) return PREC_F64;
+    return o->precision == ATC_PREC_BF16X3 ? PREC_BF16X3 : PREC_F32;
+}
+
+size_t part_capacity(int nmax) {
+    const size_t t = (size_t)ceil_div(nmax, TILE);
+    const size_t one_split = t * t * TILE * TILE * sizeof(double);  // cross Gram: all tile pairs
+    return std::max<size_t>((size_t)64 << 20, one_split);
+}
+
+struct SthosvdWs {
+    void* buf[2];
+    double* part;
+    size_t part_cap;
+    double* G;
+    double* lam;
+    double* V;
+    double* jac;     // global Jacobi scratch
+    double* sub;     // subspace scratch
+    double* Mt64;
+    float* Mt32;
+    __bf16* Mth;
+    __bf16* Mtl;
+    DevBook* book;
+};
+
+size_t carve_sthosvd(const atc_shape* s, char* base, SthosvdWs* w) {
+    const int d = s->ndim;
+    int64_t N = prod(s->dims, 0, d);
+    int nmax = 1;
+    for (int k = 0; k < d; ++k) nmax = std::max<int>(nmax, (int)s->dims[k]);
+    const size_t esz = s->dtype == ATC_F64 ? 8 : 4;
+    const size_t n2 = (size_t)nmax * nmax;
+    const int mpad = nmax + (nmax & 1);
+    Carver c;
+    c.base = base;
+    SthosvdWs t{};
+    t.buf[0] = c.take(d > 1 ? (size_t)N * esz : 0);
+    t.buf[1] = c.take(d > 2 ? (size_t)N * esz : 0);
+    t.part_cap = part_capacity(nmax);
+    t.part = (double*)c.take(t.part_cap);
+    t.G = (double*)c.take(n2 * 8);
+    t.lam = (double*)c.take((size_t)nmax * 8);
+    t.V = (double*)c.take(n2 * 8);
+    t.jac = (double*)c.take(nmax > 64 ? (size_t)2 * mpad * mpad * 8 : 0);
+    t.sub = (double*)c.take(nmax > 64 ? subspace_ws_doubles(nmax, SUBSPACE_M) * 8 : 0);
+    t.Mt64 = (double*)c.take(s->dtype == ATC_F64 ? n2 * 8 : 0);
+    t.Mt32 = (float*)c.take(s->dtype == ATC_F32 ? n2 * 4 : 0);
+    t.Mth = (__bf16*)c.take(s->dtype == ATC_F32 ? n2 * 2 : 0);
+    t.Mtl = (__bf16*)c.take(s->dtype == ATC_F32 ? n2 * 2 : 0);
+    t.book = (DevBook*)c.take(sizeof(DevBook));
+    if (w) *w = t;
+    return c.off;
+}
+
+struct StreamTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool ok = false;
+    explicit StreamTimer(hipStream_t st) {
+        ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
+             hipEventRecord(a, st) == hipSuccess;
+    }
+    double stop(hipStream_t st) {
+        float ms = 0.f;
+        if (ok && hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess)
+            hipEventElapsedTime(&ms, a, b);
+        return ms;
+    }
+    ~StreamTimer() {
+        if (a) hipEventDestroy(a);
+        if (b) hipEventDestroy(b);
+    }
+};
+
+// Per-mode phase events (Gram, reduction, eigensolver + rank choice, mode
+// product), created once per thread and reused.
+struct PhaseEvents {
+    static constexpr int PER_MODE = 5;
+    hipEvent_t ev[ATC_MAX_DIMS][PER_MODE];
+    bool ready = false;
+    bool init() {
+        if (ready) return true;
+        for (int i = 0; i < ATC_MAX_DIMS; ++i)
+            for (int j = 0; j < PER_MODE; ++j)
+                if (hipEventCreate(&ev[i][j]) != hipSuccess) return false;
+        ready = true;
+        return true;
+    }
+};
+thread_local PhaseEvents g_phase;
+
+double event_ms(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.0;
+    return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+void atc_default_opts(atc_sthosvd_opts* o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->rel_error = 1e-3;
+    o->rtmss = 1.0;
+    o->precision = ATC_PREC_NATIVE;
+    o->rank_rule = ATC_RANK_ADAPTIVE;
+}
+
+size_t atc_sthosvd_workspace_size(const atc_shape* shape, const atc_sthosvd_opts* opts) {
+    if (check_shape(shape) != ATC_OK || check_opts(shape, opts) != ATC_OK) return 0;
+    return carve_sthosvd(shape, nullptr, nullptr);
+}
+
+atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_opts* opts, void* core,
+                       void* const* factors, atc_result* result, void* workspace, size_t workspace_bytes,
+                       void* stream) {
+    atc_status s;
+    if ((s = check_shape(shape)) != ATC_OK) return s;
+    if ((s = check_opts(shape, opts)) != ATC_OK) return s;
+    if (!x || !core || !factors) return fail(ATC_ERR_INVALID_ARGUMENT, "x, core and factors must be non-NULL");
+    const int d = shape->ndim;
+    for (int k = 0; k < d; ++k)
+        if (!factors[k]) return fail(ATC_ERR_INVALID_ARGUMENT, "factors[%d] is NULL", k);
+    const size_t need = carve_sthosvd(shape, nullptr, nullptr);
+    if (!workspace || workspace_bytes < need)
+        return fail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    SthosvdWs w;
+    carve_sthosvd(shape, (char*)workspace, &w);
+    hipStream_t st = (hipStream_t)stream;
+    const int prec = prec_of(shape, opts);
+    const bool f64 = shape->dtype == ATC_F64;
+    const int max_sweeps = opts->max_sweeps > 0 ? opts->max_sweeps : DEFAULT_SWEEPS;
+    int order[ATC_MAX_DIMS];
+    processing_order(shape, opts, order);
+
+    const bool prof = opts->profile != 0;
+    if (prof && !g_phase.init()) return fail(ATC_ERR_DEVICE, "hipEventCreate failed");
+    auto mark = [&](int i, int j) -> hipError_t { return prof ? hipEventRecord(g_phase.ev[i][j], st) : hipSuccess; };
+
+    StreamTimer timer(st);
+    HIP_TRY(hipMemsetAsync(w.book, 0, sizeof(DevBook), st));
+    int64_t cur[ATC_MAX_DIMS];
+    for (int k = 0; k < d; ++k) cur[k] = shape->dims[k];
+    const void* src = x;
+    DevBook hb;
+    int paths[ATC_MAX_DIMS] = {0};
+    for (int i = 0; i < d; ++i) {
+        const int k = order[i];
+        const int64_t L = prod(cur, 0, k), R = prod(cur, k + 1, d);
+        const int n = (int)cur[k];
+        const GramPlan gp = gram_plan(prec, L, n, n, R, true, w.part_cap);
+        HIP_TRY(mark(i, 0));
+        HIP_TRY(launch_gram(prec, gp, src, src, w.part, st));
+        HIP_TRY(mark(i, 1));
+        HIP_TRY(launch_gram_reduce(gp, w.part, w.G, st));
+        HIP_TRY(mark(i, 2));
+
+        SelectArgs sa{};
+        sa.G = w.G;
+        sa.n = n;
+        sa.lam = w.lam;
+        sa.V = w.V;
+        sa.pos = i;
+        sa.d = d;
+        sa.k = k;
+        sa.rule = opts->rank_rule;
+        sa.fixed_rank = opts->has_fixed_ranks ? opts->fixed_ranks[k] : -1;
+        sa.rtmss = opts->rtmss;
+        sa.eps2 = opts->rel_error * opts->rel_error;
+        sa.book = w.book;
+        sa.ufac = factors[k];
+        sa.ufac_f64 = f64 ? 1 : 0;
+        sa.Mt64 = f64 ? w.Mt64 : nullptr;
+        sa.Mt32 = f64 ? nullptr : w.Mt32;
+        sa.Mth = prec == PREC_BF16X3 ? w.Mth : nullptr;
+        sa.Mtl = prec == PREC_BF16X3 ? w.Mtl : nullptr;
+        sa.guard = SUBSPACE_GUARD;
+        int32_t* sweeps_dev = &w.book->sweeps[k];
+        int32_t* ok_dev = &w.book->eig_ok;
+
+        const bool use_sub = n > 64 && opts->eig_path != 1;
+        bool dense_done = false;
+        if (n <= 64) {
+            HIP_TRY(launch_eig_jacobi_lds(w.G, n, n, max_sweeps, w.lam, w.V, n, sweeps_dev, ok_dev, st));
+            sa.ldv = n;
+            sa.ncand = n;
+            sa.subspace = 0;
+            dense_done = true;
+            paths[k] = 1;
+        } else if (use_sub) {
+            const int m = std::min(SUBSPACE_M, n);
+            HIP_TRY(run_subspace_eig(w.G, n, m, SUBSPACE_ITERS, max_sweeps, w.sub, w.lam, w.V, sweeps_dev, ok_dev, st));
+            sa.ldv = m;
+            sa.ncand = m;
+            sa.subspace = 1;
+            paths[k] = 2;
+        } else {
+            HIP_TRY(launch_eig_jacobi_global(w.G, n, max_sweeps, w.jac, w.lam, w.V, sweeps_dev, ok_dev, st));
+            sa.ldv = n;
+            sa.ncand = n;
+            sa.subspace = 0;
+            dense_done = true;
+            paths[k] = 1;
+        }
+        HIP_TRY(launch_select_factor(sa, st));
+        HIP_TRY(hipMemcpyAsync(&hb, w.book, sizeof(DevBook), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (hb.status != 0) return fail((atc_status)hb.status, "input |A|^2 is not finite");
+        if (hb.need_dense && !dense_done) {
+            if (opts->eig_path == 2)
+                return fail(ATC_ERR_UNSUPPORTED, "mode %d: rank needs more than %d Ritz pairs", k,
+                            SUBSPACE_M - SUBSPACE_GUARD);
+            const int32_t zero = 0;
+            HIP_TRY(hipMemcpyAsync(&w.book->need_dense, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
+            HIP_TRY(launch_eig_jacobi_global(w.G, n, max_sweeps, w.jac, w.lam, w.V, sweeps_dev, ok_dev, st));
+            sa.ldv = n;
+            sa.ncand = n;
+            sa.subspace = 0;
+            paths[k] = 1;
+            HIP_TRY(launch_select_factor(sa, st));
+            HIP_TRY(hipMemcpyAsync(&hb, w.book, sizeof(DevBook), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        if (!hb.eig_ok) return fail(ATC_ERR_NOT_CONVERGED, "mode %d: eigensolver hit %d sweeps", k, max_sweeps);
+        const int r = hb.rank[k];
+        if (r < 1 || r > n) return fail(ATC_ERR_INTERNAL, "mode %d: rank %d outside [1, %d]", k, r, n);
+        void* dst = (i == d - 1) ? core : w.buf[i % 2];
+        const TtmPlan tp = ttm_plan(prec, L, n, R, r);
+        const void* M = f64 ? (const void*)w.Mt64 : (const void*)w.Mt32;
+        HIP_TRY(mark(i, 3));
+        HIP_TRY(launch_ttm(prec, tp, src, M, w.Mth, w.Mtl, dst, st));
+        HIP_TRY(mark(i, 4));
+        cur[k] = r;
+        src = dst;
+    }
+    HIP_TRY(hipMemcpyAsync(&hb, w.book, sizeof(DevBook), hipMemcpyDeviceToHost, st));
+    const double ms = timer.stop(st);
+    HIP_TRY(hipStreamSynchronize(st));
+    if (result) {
+        memset(result, 0, sizeof(*result));
+        for (int i = 0; i < d; ++i) {
+            const int k = order[i];
+            result->ranks[k] = hb.rank[k];
+            result->order[i] = order[i];
+            result->tail[k] = hb.tail[k];
+            result->budget[k] = hb.budget[k];
+            result->eig_path[k] = paths[k];
+            result->eig_sweeps[k] = hb.sweeps[k];
+            if (prof) {
+                hipEvent_t* e = g_phase.ev[i];
+                result->gram_ms[k] = event_ms(e[0], e[1]);
+                result->reduce_ms[k] = event_ms(e[1], e[2]);
+                result->eig_ms[k] = event_ms(e[2], e[3]);
+                result->ttm_ms[k] = event_ms(e[3], e[4]);
+            }
+        }
+        result->norm2 = hb.norm2;
+        result->sse_pred = hb.used;
+        result->elapsed_ms = ms;
+    }
+    return ATC_OK;
+}
+
+// ------------------------------------------------------------ reconstruction
+
+namespace {
+
+int64_t recon_cost(const int64_t* n, const int64_t* r, const int* p, int d) {
+    int64_t total = 0;
+    for (int i = 0; i < d; ++i) {
+        int64_t t = 1;
+        for (int j = 0; j <= i; ++j) t *= n[p[j]];
+        for (int j = i; j < d; ++j) t *= r[p[j]];
+        total += t;
+    }
+    return total;
+}
+
+// Section 4.1.1: exhaustive search, first permutation in lexicographic order on ties.
+void best_order(const int64_t* n, const int64_t* r, int d, int* out) {
+    int p[ATC_MAX_DIMS];
+    for (int i = 0; i < d; ++i) p[i] = i;
+    int64_t best = -1;
+    do {
+        const int64_t c = recon_cost(n, r, p, d);
+        if (best < 0 || c < best) {
+            best = c;
+            for (int i = 0; i < d; ++i) out[i] = p[i];
+        }
+    } while (std::next_permutation(p, p + d));
+}
+
+atc_status check_ranks(const atc_shape* s, const int64_t* ranks) {
+    if (!ranks) return fail(ATC_ERR_INVALID_ARGUMENT, "ranks is NULL");
+    for (int k = 0; k < s->ndim; ++k)
+        if (ranks[k] < 1 || ranks[k] > s->dims[k])
+            return fail(ATC_ERR_INVALID_ARGUMENT, "ranks[%d] outside [1, n_k]", k);
+    for (int k = 0; k < s->ndim; ++k)
+        if (s->dims[k] > MAX_MODE) return fail(ATC_ERR_UNSUPPORTED, "mode %d longer than %d", k, MAX_MODE);
+    return ATC_OK;
+}
+
+struct MatBufs {
+    double* m64;
+    float* m32;
+};
+
+size_t carve_recon(const atc_shape* s, const int64_t* ranks, char* base, void** buf, MatBufs* mb) {
+    const int d = s->ndim;
+    const size_t esz = s->dtype == ATC_F64 ? 8 : 4;
+    int order[ATC_MAX_DIMS];
+    best_order(s->dims, ranks, d, order);
+    int64_t cur[ATC_MAX_DIMS];
+    for (int k = 0; k < d; ++k) cur[k] = ranks[k];
+    int64_t big = 1;
+    for (int i = 0; i + 1 < d; ++i) {
+        cur[order[i]] = s->dims[order[i]];
+        big = std::max<int64_t>(big, prod(cur, 0, d));
+    }
+    size_t nr = 1;
+    for (int k = 0; k < d; ++k) nr = std::max<size_t>(nr, (size_t)s->dims[k] * ranks[k]);
+    Carver c;
+    c.base = base;
+    void* b0 = c.take((size_t)big * esz);
+    void* b1 = c.take((size_t)big * esz);
+    double* m64 = (double*)c.take(s->dtype == ATC_F64 ? nr * 8 : 0);
+    float* m32 = (float*)c.take(s->dtype == ATC_F32 ? nr * 4 : 0);
+    if (buf) {
+        buf[0] = b0;
+        buf[1] = b1;
+    }
+    if (mb) {
+        mb->m64 = m64;
+        mb->m32 = m32;
+    }
+    return c.off;
+}
+
+}  // namespace
+
+size_t atc_reconstruct_workspace_size(const atc_shape* shape, const int64_t* ranks) {
+    if (check_shape(shape) != ATC_OK || check_ranks(shape, ranks) != ATC_OK) return 0;
+    return carve_recon(shape, ranks, nullptr, nullptr, nullptr);
+}
+
+atc_status atc_reconstruct(const atc_shape* shape, const int64_t* ranks, const void* core, const void* const* factors,
+                           void* xhat, void* workspace, size_t workspace_bytes, void* stream) {
+    atc_status s;
+    if ((s = check_shape(shape)) != ATC_OK) return s;
+    if ((s = check_ranks(shape, ranks)) != ATC_OK) return s;
+    if (!core || !factors || !xhat) return fail(ATC_ERR_INVALID_ARGUMENT, "core, factors and xhat must be non-NULL");
+    const int d = shape->ndim;
+    for (int k = 0; k < d; ++k)
+        if (!factors[k]) return fail(ATC_ERR_INVALID_ARGUMENT, "factors[%d] is NULL", k);
+    const size_t need = carve_recon(shape, ranks, nullptr, nullptr, nullptr);
+    if (!workspace || workspace_bytes < need)
+        return fail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    void* buf[2];
+    MatBufs mb;
+    carve_recon(shape, ranks, (char*)workspace, buf, &mb);
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = shape->dtype == ATC_F64;
+    const int prec = f64 ? PREC_F64 : PREC_F32;
+    int order[ATC_MAX_DIMS];
+    best_order(shape->dims, ranks, d, order);
+    int64_t cur[ATC_MAX_DIMS];
+    for (int k = 0; k < d; ++k) cur[k] = ranks[k];
+    const void* src = core;
+    for (int i = 0; i < d; ++i) {
+        const int k = order[i];
+        const int64_t L = prod(cur, 0, k), R = prod(cur, k + 1, d);
+        const int rk = (int)ranks[k], nk = (int)shape->dims[k];
+        // M = U_k (n_k x r_k): expands mode k from r_k to n_k
+        HIP_TRY(launch_prepare_matrix(prec, factors[k], f64, nk, rk, 0, f64 ? mb.m64 : nullptr, f64 ? nullptr : mb.m32,
+                                      nullptr, nullptr, st));
+        void* dst = (i == d - 1) ? xhat : buf[i % 2];
+        const TtmPlan tp = ttm_plan(prec, L, rk, R, nk);
+        HIP_TRY(launch_ttm(prec, tp, src, f64 ? (const void*)mb.m64 : (const void*)mb.m32, nullptr, nullptr, dst, st));
+        cur[k] = nk;
+        src = dst;
+    }
+    return ATC_OK;
+}
+
+// ---------------------------------------------------- reconstruction adjoint
+//
+// dG = R x_0 U_0^T ... x_{d-1} U_{d-1}^T and dU_n = T_n(n) G_(n)^T with
+// T_n = R x_{m != n} U_m^T: dL/dU_n = R_(n) (G x_{m != n} U_m)_(n)^T by the
+// mode-product rules, and moving the U_m (m != n) to the other side of the
+// contraction gives the T_n form, which only ever shrinks tensors.
+// The T_n share work through a two-level tree: P = R x_a U_a^T is formed once
+// (mode a shrinks first), every T_n with n != a is then shrunk from P, and
+// T_a needs one more pass over R.
+
+namespace {
+
+struct BwdPlan {
+    int a;                 // mode shrunk first
+    int64_t big;           // largest intermediate (elements)
+};
+
+// elements of the tensor after shrinking the modes in `mask`
+int64_t shrunk_size(const atc_shape* s, const int64_t* ranks, unsigned mask) {
+    int64_t t = 1;
+    for (int k = 0; k < s->ndim; ++k) t *= (mask >> k & 1) ? ranks[k] : s->dims[k];
+    return t;
+}
+
+BwdPlan bwd_plan(const atc_shape* s, const int64_t* ranks) {
+    const int d = s->ndim;
+    BwdPlan p{};
+    // shrink first the mode with the largest reduction of the tensor
+    p.a = 0;
+    double best = 0;
+    for (int k = 0; k < d; ++k) {
+        const double red = (double)s->dims[k] / (double)ranks[k];
+        if (red > best) {
+            best = red;
+            p.a = k;
+        }
+    }
+    p.big = 1;
+    for (int k = 0; k < d; ++k) p.big = std::max<int64_t>(p.big, shrunk_size(s, ranks, 1u << k));
+    return p;
+}
+
+size_t carve_bwd(const atc_shape* s, const int64_t* ranks, char* base, void** bufs, double** part, size_t* part_cap,
+                 double** cg, MatBufs* mb) {
+    const int d = s->ndim;
+    const size_t esz = s->dtype == ATC_F64 ? 8 : 4;
+    const BwdPlan p = bwd_plan(s, ranks);
+    int nmax = 1;
+    size_t nr = 1;
+    for (int k = 0; k < d; ++k) {
+        nmax = std::max<int>(nmax, (int)s->dims[k]);
+        nr = std::max<size_t>(nr, (size_t)s->dims[k] * ranks[k]);
+    }
+    Carver c;
+    c.base = base;
+    void* P = c.take((size_t)p.big * esz);     // R shrunk in one mode
+    void* b0 = c.take((size_t)p.big * esz);    // chain scratch
+    void* b1 = c.take((size_t)p.big * esz);
+    const size_t pc = part_capacity(nmax);
+    double* pt = (double*)c.take(pc);
+    double* cgb = (double*)c.take(nr * 8);
+    double* m64 = (double*)c.take((size_t)d * nr * 8);
+    float* m32 = (float*)c.take(s->dtype == ATC_F32 ? (size_t)d * nr * 4 : 0);
+    if (bufs) {
+        bufs[0] = P;
+        bufs[1] = b0;
+        bufs[2] = b1;
+    }
+    if (part) *part = pt;
+    if (part_cap) *part_cap = pc;
+    if (cg) *cg = cgb;
+    if (mb) {
+        mb->m64 = m64;
+        mb->m32 = m32;
+    }
+    return c.off;
+}
+
+__global__ void k_cast_out(const double* src, void* dst, int64_t count, int to_f64) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    if (to_f64) ((double*)dst)[i] = src[i];
+    else ((float*)dst)[i] = (float)src[i];
+}
+
+}  // namespace
+
+size_t atc_reconstruct_backward_workspace_size(const atc_shape* shape, const int64_t* ranks) {
+    if (check_shape(shape) != ATC_OK || check_ranks(shape, ranks) != ATC_OK) return 0;
+    return carve_bwd(shape, ranks, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks, const void* core,
+                                    const void* const* factors, const void* dxhat, void* dcore, void* const* dfactors,
+                                    void* workspace, size_t workspace_bytes, void* stream) {
+    atc_status s;
+    if ((s = check_shape(shape)) != ATC_OK) return s;
+    if ((s = check_ranks(shape, ranks)) != ATC_OK) return s;
+    if (!core || !factors || !dxhat) return fail(ATC_ERR_INVALID_ARGUMENT, "core, factors and dxhat must be non-NULL");
+    const int d = shape->ndim;
+    for (int k = 0; k < d; ++k)
+        if (!factors[k]) return fail(ATC_ERR_INVALID_ARGUMENT, "factors[%d] is NULL", k);
+    const size_t need = carve_bwd(shape, ranks, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (!workspace || workspace_bytes < need)
+        return fail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    void* bufs[3];
+    double* part;
+    size_t part_cap;
+    double* cg;
+    MatBufs mb;
+    carve_bwd(shape, ranks, (char*)workspace, bufs, &part, &part_cap, &cg, &mb);
+    hipStream_t st = (hipStream_t)stream;
+    const bool f64 = shape->dtype == ATC_F64;
+    const int prec = f64 ? PREC_F64 : PREC_F32;
+    const size_t esz = f64 ? 8 : 4;
+    size_t nr = 1;
+    for (int k = 0; k < d; ++k) nr = std::max<size_t>(nr, (size_t)shape->dims[k] * ranks[k]);
+    // U_k^T (r_k x n_k) for every mode
+    std::vector<const void*> Mt(d);
+    for (int k = 0; k < d; ++k) {
+        double* m64 = mb.m64 + (size_t)k * nr;
+        float* m32 = f64 ? nullptr : mb.m32 + (size_t)k * nr;
+        HIP_TRY(launch_prepare_matrix(prec, factors[k], f64, (int)shape->dims[k], (int)ranks[k], 1, f64 ? m64 : nullptr,
+                                      m32, nullptr, nullptr, st));
+        Mt[k] = f64 ? (const void*)m64 : (const void*)m32;
+    }
+    const BwdPlan bp = bwd_plan(shape, ranks);
+
+    // Shrinks `src` (current sizes cur) in every mode of `modes` (in order) and
+    // leaves the result in *out (one of the scratch buffers or `final_dst`).
+    auto shrink_chain = [&](const void* src, int64_t* cur, const std::vector<int>& modes, void* final_dst,
+                            const void** out) -> atc_status {
+        const void* s_ = src;
+        int flip = 0;
+        for (size_t i = 0; i < modes.size(); ++i) {
+            const int k = modes[i];
+            const int64_t L = prod(cur, 0, k), R = prod(cur, k + 1, d);
+            void* dst = (i + 1 == modes.size() && final_dst) ? final_dst : bufs[1 + flip];
+            flip ^= 1;
+            const TtmPlan tp = ttm_plan(prec, L, (int)cur[k], R, (int)ranks[k]);
+            HIP_TRY(launch_ttm(prec, tp, s_, Mt[k], nullptr, nullptr, dst, st));
+            cur[k] = ranks[k];
+            s_ = dst;
+        }
+        *out = s_;
+        return ATC_OK;
+    };
+    // dU_n = T_n(n) G_(n)^T: cross Gram over the (L, ., R) view of mode n
+    auto factor_grad = [&](const void* Tn, int n) -> atc_status {
+        if (!dfactors || !dfactors[n]) return ATC_OK;
+        int64_t rr[ATC_MAX_DIMS];
+        for (int k = 0; k < d; ++k) rr[k] = ranks[k];
+        const int64_t L = prod(rr, 0, n), R = prod(rr, n + 1, d);
+        const GramPlan gp = gram_plan(prec, L, (int)shape->dims[n], (int)ranks[n], R, false, part_cap);
+        HIP_TRY(launch_gram(prec, gp, Tn, core, part, st));
+        HIP_TRY(launch_gram_reduce(gp, part, cg, st));
+        const int64_t cnt = shape->dims[n] * ranks[n];
+        hipLaunchKernelGGL(k_cast_out, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, cg, dfactors[n], cnt,
+                           f64 ? 1 : 0);
+        HIP_TRY(hipGetLastError());
+        return ATC_OK;
+    };
+
+    // P = R x_a U_a^T
+    const int a = bp.a;
+    int64_t curP[ATC_MAX_DIMS];
+    for (int k = 0; k < d; ++k) curP[k] = shape->dims[k];
+    {
+        const int64_t L = prod(curP, 0, a), R = prod(curP, a + 1, d);
+        const TtmPlan tp = ttm_plan(prec, L, (int)curP[a], R, (int)ranks[a]);
+        HIP_TRY(launch_ttm(prec, tp, dxhat, Mt[a], nullptr, nullptr, bufs[0], st));
+        curP[a] = ranks[a];
+    }
+    // T_n for n != a from P (P itself stays intact in bufs[0])
+    for (int n = 0; n < d; ++n) {
+        if (n == a) continue;
+        std::vector<int> modes;
+        for (int k = 0; k < d; ++k)
+            if (k != a && k != n) modes.push_back(k);
+        int64_t cur[ATC_MAX_DIMS];
+        for (int k = 0; k < d; ++k) cur[k] = curP[k];
+        const void* Tn = bufs[0];
+        if (!modes.empty()) {
+            atc_status e = shrink_chain(bufs[0], cur, modes, nullptr, &Tn);
+            if (e != ATC_OK) return e;
+        }
+        atc_status e = factor_grad(Tn, n);
+        if (e != ATC_OK) return e;
+        // dG = T_n x_n U_n^T, once
+        if (dcore && n == (a == 0 ? 1 : 0)) {
+            std::vector<int> last{n};
+            const void* outp;
+            // shrink T_n in mode n straight into dcore
+            const void* srcT = Tn;
+            if (srcT == bufs[1] || srcT == bufs[2] || srcT == bufs[0]) {
+                // copy-free: the chain reads srcT and writes dcore
+            }
+            e = shrink_chain(srcT, cur, last, dcore, &outp);
+            if (e != ATC_OK) return e;
+        }
+    }
+    // T_a: one more pass over R, shrinking every other mode
+    if (dfactors && dfactors[a]) {
+        std::vector<int> modes;
+        for (int k = 0; k < d; ++k)
+            if (k != a) modes.push_back(k);
+        int64_t cur[ATC_MAX_DIMS];
+        for (int k = 0; k < d; ++k) cur[k] = shape->dims[k];
+        const void* Ta = dxhat;
+        if (!modes.empty()) {
+            atc_status e = shrink_chain(dxhat, cur, modes, nullptr, &Ta);
+            if (e != ATC_OK) return e;
+        }
+        atc_status e = factor_grad(Ta, a);
+        if (e != ATC_OK) return e;
+    }
+    if (dcore && d == 1) {
+        // d == 1: dG = R x_0 U_0^T is P itself
+        HIP_TRY(hipMemcpyAsync(dcore, bufs[0], (size_t)ranks[0] * esz, hipMemcpyDeviceToDevice, st));
+    }
+    return ATC_OK;
+}
+
+// ------------------------------------------------------------------- misc
+
+const char* atc_status_string(atc_status s) {
+    switch (s) {
+        case ATC_OK: return "ok";
+        case ATC_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case ATC_ERR_UNSUPPORTED: return "unsupported";
+        case ATC_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case ATC_ERR_DEVICE: return "device error";
+        case ATC_ERR_NOT_CONVERGED: return "eigensolver did not converge";
+        case ATC_ERR_NONFINITE_INPUT: return "non-finite input";
+        case ATC_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char* atc_last_error(void) { return g_last_error.c_str(); }
+
+const char* atc_version(void) { return "atc-mi355x 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,384 @@
+// Gram matrix (SYRK) and cross-Gram kernels on MFMA.
+//
+// For the mode-k step of Algorithm 1 (Section 3.2) the left singular vectors of
+// the unfolding B_(k) are the eigenvectors of G = B_(k) B_(k)^T.  The current
+// tensor is read in place through its (L, n, R) view (Section 3.1: fiber order
+// inside the unfolding does not change G), so no transpose is ever made:
+//   G[a, b] = sum_{l, r} X[l, a, r] * Y[l, b, r]         (Y == X for G)
+//
+// One workgroup (4 waves) owns a 64 x 64 output tile and a contiguous range
+// of K steps (split-K).  Each step stages a 64 x BK slab of both operands in
+// LDS; each wave computes a 32 x 32 quarter with 16 x 16 MFMA blocks.
+//   PREC_F64   : v_mfma_f64_16x16x4f64, FP64 accumulation.
+//   PREC_F32   : v_mfma_f32_16x16x4f32, FP32 accumulation flushed into FP64
+//                registers every FLUSH_TERMS contracted terms.
+//   PREC_BF16X3: operands split on load into bf16 hi + lo; products
+//                hi*hi + hi*lo + lo*hi (and lo*lo on diagonal tiles, so the
+//                diagonal, whose dropped lo*lo would always be positive, is
+//                unbiased) with v_mfma_f32_16x16x32_bf16, flushed to FP64
+//                like PREC_F32.
+// Each workgroup writes its FP64 partial tile; a second kernel sums the splits
+// in a fixed order, so the result is bit-reproducible.
+#include "atc_internal.hpp"
+
+namespace atc {
+namespace {
+
+__device__ inline void decode_upper_pair(int pair, int tiles, int& ti, int& tj) {
+    int p = pair, i = 0;
+    while (p >= tiles - i) {
+        p -= tiles - i;
+        ++i;
+    }
+    ti = i;
+    tj = i + p;
+}
+
+__host__ __device__ inline int upper_pair_index(int ti, int tj, int tiles) {
+    return ti * tiles - ti * (ti - 1) / 2 + (tj - ti);
+}
+
+template <int P> struct GramSmem;
+template <> struct GramSmem<PREC_F64> {
+    double x[TILE][KDepth<PREC_F64>::value + 1];
+    double y[TILE][KDepth<PREC_F64>::value + 1];
+};
+template <> struct GramSmem<PREC_F32> {
+    float x[TILE][KDepth<PREC_F32>::value + 1];
+    float y[TILE][KDepth<PREC_F32>::value + 1];
+};
+template <> struct GramSmem<PREC_BF16X3> {
+    // row stride 40 bf16 = 80 bytes keeps every 8-element read 16-byte aligned
+    __bf16 xh[TILE][KDepth<PREC_BF16X3>::value + 8];
+    __bf16 xl[TILE][KDepth<PREC_BF16X3>::value + 8];
+    __bf16 yh[TILE][KDepth<PREC_BF16X3>::value + 8];
+    __bf16 yl[TILE][KDepth<PREC_BF16X3>::value + 8];
+};
+
+// Element slot of the per-step operand slab owned by this thread.
+struct Slot {
+    int row;   // row inside the 64-row tile
+    int kk;    // column inside the step (contracted index)
+    int p, r;  // SR: plane and r of the slot
+    bool ok;   // slot maps into the slab
+};
+
+template <int LAYOUT, int BK>
+__device__ inline Slot make_slot(int tid, int e, int64_t R, int planes) {
+    Slot s;
+    s.p = 0;
+    s.r = 0;
+    s.ok = true;
+    if (LAYOUT == LAYOUT_KC) {
+        s.row = tid / BK + (NTHREADS / BK) * e;
+        s.kk = tid % BK;
+    } else if (LAYOUT == LAYOUT_NC) {
+        s.row = tid % TILE;
+        s.kk = tid / TILE + (NTHREADS / TILE) * e;
+    } else {
+        const int Ri = (int)R;
+        const int q = tid + NTHREADS * e;
+        s.r = q % Ri;
+        s.row = (q / Ri) % TILE;
+        s.p = q / (TILE * Ri);
+        s.ok = s.p < planes;
+        s.kk = s.p * Ri + s.r;
+    }
+    return s;
+}
+
+// Global offset of slot `s` at step `step` for rows of an (L, nrows, R) view,
+// or -1 if the element lies outside the tensor.
+template <int LAYOUT, int BK>
+__device__ inline int64_t slot_offset(const Slot& s, int64_t step, int64_t spl, int rowg, int nrows,
+                                      int64_t L, int64_t R, int planes) {
+    if (!s.ok || rowg >= nrows) return -1;
+    if (LAYOUT == LAYOUT_KC) {
+        const int64_t l = step / spl;
+        const int64_t r0 = (step - l * spl) * BK;
+        if (r0 + s.kk >= R) return -1;
+        return (l * nrows + rowg) * R + r0 + s.kk;
+    } else if (LAYOUT == LAYOUT_NC) {
+        const int64_t k = step * BK + s.kk;
+        if (k >= L) return -1;
+        return k * nrows + rowg;
+    } else {
+        const int64_t l = step * planes + s.p;
+        if (l >= L) return -1;
+        return (l * nrows + rowg) * R + s.r;
+    }
+}
+
+template <int P, int LAYOUT, bool SYM>
+__global__ __launch_bounds__(NTHREADS) void k_gram(const typename ElemOf<P>::T* __restrict__ X,
+                                                   const typename ElemOf<P>::T* __restrict__ Y, int nx,
+                                                   int ny, int64_t L, int64_t R, int64_t steps, int nsplit,
+                                                   int tiles_x, int tiles_y, int npairs, int planes,
+                                                   double* __restrict__ part) {
+    using T = typename ElemOf<P>::T;
+    constexpr int BK = KDepth<P>::value;
+    constexpr int E = TILE * BK / NTHREADS;
+    __shared__ GramSmem<P> sm;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int pair = blockIdx.x;
+    const int split = blockIdx.y;
+    int ti, tj;
+    if (SYM) {
+        decode_upper_pair(pair, tiles_x, ti, tj);
+    } else {
+        ti = pair / tiles_y;
+        tj = pair % tiles_y;
+    }
+    const bool diag = SYM && ti == tj;
+    const int row0 = ti * TILE, col0 = tj * TILE;
+    const int64_t s0 = steps * split / nsplit;
+    const int64_t s1 = steps * (split + 1) / nsplit;
+    const int64_t spl = ceil_div(R, BK);
+
+    Slot sl[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) sl[e] = make_slot<LAYOUT, BK>(tid, e, R, planes);
+
+    if (LAYOUT == LAYOUT_SR) {
+        // columns no slot writes stay zero for the whole kernel
+        for (int idx = tid; idx < TILE * BK; idx += NTHREADS) {
+            const int rr = idx / BK, kk = idx % BK;
+            if constexpr (P == PREC_BF16X3) {
+                sm.xh[rr][kk] = (__bf16)0.0f; sm.xl[rr][kk] = (__bf16)0.0f;
+                sm.yh[rr][kk] = (__bf16)0.0f; sm.yl[rr][kk] = (__bf16)0.0f;
+            } else {
+                sm.x[rr][kk] = (T)0; sm.y[rr][kk] = (T)0;
+            }
+        }
+    }
+
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    f64x4 acc64[2][2];
+    f32x4 acc32[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            acc64[a][b] = f64x4{0, 0, 0, 0};
+            acc32[a][b] = f32x4{0, 0, 0, 0};
+        }
+    constexpr int FLUSH_STEPS = FLUSH_TERMS / BK;
+    int since_flush = 0;
+
+    for (int64_t s = s0; s < s1; ++s) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const Slot& q = sl[e];
+            const int64_t ox = slot_offset<LAYOUT, BK>(q, s, spl, row0 + q.row, nx, L, R, planes);
+            const T vx = ox >= 0 ? X[ox] : (T)0;
+            T vy = (T)0;
+            if (!diag) {
+                const int64_t oy = slot_offset<LAYOUT, BK>(q, s, spl, col0 + q.row, ny, L, R, planes);
+                vy = oy >= 0 ? Y[oy] : (T)0;
+            }
+            if (q.ok) {
+                if constexpr (P == PREC_BF16X3) {
+                    const __bf16 xh = (__bf16)vx;
+                    sm.xh[q.row][q.kk] = xh;
+                    sm.xl[q.row][q.kk] = (__bf16)(vx - (float)xh);
+                    if (!diag) {
+                        const __bf16 yh = (__bf16)vy;
+                        sm.yh[q.row][q.kk] = yh;
+                        sm.yl[q.row][q.kk] = (__bf16)(vy - (float)yh);
+                    }
+                } else {
+                    sm.x[q.row][q.kk] = vx;
+                    if (!diag) sm.y[q.row][q.kk] = vy;
+                }
+            }
+        }
+        __syncthreads();
+
+        if constexpr (P == PREC_BF16X3) {
+            const int kq = 8 * (lane >> 4);
+            bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int rr = wr + a * 16 + (lane & 15);
+                ah[a] = *reinterpret_cast<const bf16x8*>(&sm.xh[rr][kq]);
+                al[a] = *reinterpret_cast<const bf16x8*>(&sm.xl[rr][kq]);
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int cc = wc + b * 16 + (lane & 15);
+                if (diag) {
+                    bh[b] = *reinterpret_cast<const bf16x8*>(&sm.xh[cc][kq]);
+                    bl[b] = *reinterpret_cast<const bf16x8*>(&sm.xl[cc][kq]);
+                } else {
+                    bh[b] = *reinterpret_cast<const bf16x8*>(&sm.yh[cc][kq]);
+                    bl[b] = *reinterpret_cast<const bf16x8*>(&sm.yl[cc][kq]);
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc32[a][b], 0, 0, 0);
+                    acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc32[a][b], 0, 0, 0);
+                    acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc32[a][b], 0, 0, 0);
+                    if (diag)
+                        acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bl[b], acc32[a][b], 0, 0, 0);
+                }
+        } else {
+#pragma unroll
+            for (int k4 = 0; k4 < BK; k4 += 4) {
+                const int kk = k4 + (lane >> 4);
+                T av[2], bv[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) av[a] = sm.x[wr + a * 16 + (lane & 15)][kk];
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    bv[b] = diag ? sm.x[wc + b * 16 + (lane & 15)][kk] : sm.y[wc + b * 16 + (lane & 15)][kk];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        if constexpr (P == PREC_F64)
+                            acc64[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc64[a][b], 0, 0, 0);
+                        else
+                            acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc32[a][b], 0, 0, 0);
+                    }
+            }
+        }
+        if constexpr (P != PREC_F64) {
+            if (++since_flush == FLUSH_STEPS) {
+                since_flush = 0;
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc64[a][b][v] += (double)acc32[a][b][v];
+                        acc32[a][b] = f32x4{0, 0, 0, 0};
+                    }
+            }
+        }
+    }
+    if constexpr (P != PREC_F64) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc64[a][b][v] += (double)acc32[a][b][v];
+    }
+    // 16x16 MFMA result layout: column lane%16, row mfma16_row(lane, v)
+    double* out = part + ((int64_t)split * npairs + pair) * (TILE * TILE);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = wr + a * 16 + mfma16_row<P>(lane, v);
+                const int j = wc + b * 16 + (lane & 15);
+                out[i * TILE + j] = acc64[a][b][v];
+            }
+}
+
+__global__ void k_gram_reduce(const double* __restrict__ part, int nsplit, int npairs, int tiles_x,
+                              int tiles_y, int nx, int ny, int sym, double* __restrict__ C) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nx * ny) return;
+    const int a = (int)(idx / ny), b = (int)(idx % ny);
+    if (sym && a > b) return;
+    const int ti = a / TILE, tj = b / TILE;
+    const int pair = sym ? upper_pair_index(ti, tj, tiles_x) : ti * tiles_y + tj;
+    const int i = a % TILE, j = b % TILE;
+    double s = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) s += part[((int64_t)sp * npairs + pair) * (TILE * TILE) + i * TILE + j];
+    C[(int64_t)a * ny + b] = s;
+    if (sym) C[(int64_t)b * ny + a] = s;
+}
+
+template <int P, int LAYOUT, bool SYM>
+hipError_t launch_gram_t(const GramPlan& g, const void* X, const void* Y, double* part, hipStream_t st) {
+    using T = typename ElemOf<P>::T;
+    dim3 grid(g.npairs, g.nsplit);
+    hipLaunchKernelGGL((k_gram<P, LAYOUT, SYM>), grid, dim3(NTHREADS), 0, st, (const T*)X, (const T*)Y, g.nx,
+                       g.ny, g.L, g.R, g.steps, g.nsplit, g.tiles_x, g.tiles_y, g.npairs, g.planes, part);
+    return hipGetLastError();
+}
+
+template <int P, bool SYM>
+hipError_t launch_gram_l(const GramPlan& g, const void* X, const void* Y, double* part, hipStream_t st) {
+    switch (g.layout) {
+        case LAYOUT_KC: return launch_gram_t<P, LAYOUT_KC, SYM>(g, X, Y, part, st);
+        case LAYOUT_NC: return launch_gram_t<P, LAYOUT_NC, SYM>(g, X, Y, part, st);
+        default: return launch_gram_t<P, LAYOUT_SR, SYM>(g, X, Y, part, st);
+    }
+}
+
+template <int P>
+hipError_t launch_gram_p(const GramPlan& g, const void* X, const void* Y, double* part, hipStream_t st) {
+    return g.sym ? launch_gram_l<P, true>(g, X, Y, part, st) : launch_gram_l<P, false>(g, X, Y, part, st);
+}
+
+}  // namespace
+
+GramPlan gram_plan(int prec, int64_t L, int nx, int ny, int64_t R, bool sym, size_t part_capacity_bytes) {
+    GramPlan g{};
+    const int BK = prec == PREC_F64 ? KDepth<PREC_F64>::value : KDepth<PREC_F32>::value;
+    g.L = L;
+    g.R = R;
+    g.nx = nx;
+    g.ny = ny;
+    g.sym = sym ? 1 : 0;
+    g.planes = 1;
+    if (R >= BK) {
+        g.layout = LAYOUT_KC;
+        g.steps = L * ceil_div(R, BK);
+    } else if (R == 1) {
+        g.layout = LAYOUT_NC;
+        g.steps = ceil_div(L, BK);
+    } else {
+        g.layout = LAYOUT_SR;
+        g.planes = BK / (int)R;
+        g.steps = ceil_div(L, g.planes);
+    }
+    g.tiles_x = (int)ceil_div(nx, TILE);
+    g.tiles_y = (int)ceil_div(ny, TILE);
+    g.npairs = sym ? g.tiles_x * (g.tiles_x + 1) / 2 : g.tiles_x * g.tiles_y;
+    // enough workgroups to cover 256 CUs several times, at least 8 steps each
+    int64_t want = ceil_div(2048, g.npairs);
+    int64_t max_by_steps = g.steps / 8 > 0 ? g.steps / 8 : 1;
+    int64_t max_by_mem = (int64_t)(part_capacity_bytes / ((size_t)g.npairs * TILE * TILE * sizeof(double)));
+    int64_t ns = want;
+    if (ns > max_by_steps) ns = max_by_steps;
+    if (ns > max_by_mem) ns = max_by_mem;
+    if (ns > 65535) ns = 65535;
+    if (ns < 1) ns = 1;
+    g.nsplit = (int)ns;
+    g.part_capacity = part_capacity_bytes;
+    g.part_bytes = (size_t)g.nsplit * g.npairs * TILE * TILE * sizeof(double);
+    return g;
+}
+
+hipError_t launch_gram(int prec, const GramPlan& g, const void* X, const void* Y, double* part, hipStream_t st) {
+    if (g.part_bytes > g.part_capacity) return hipErrorInvalidValue;  // partials would not fit
+    switch (prec) {
+        case PREC_F64: return launch_gram_p<PREC_F64>(g, X, Y, part, st);
+        case PREC_F32: return launch_gram_p<PREC_F32>(g, X, Y, part, st);
+        default: return launch_gram_p<PREC_BF16X3>(g, X, Y, part, st);
+    }
+}
+
+hipError_t launch_gram_reduce(const GramPlan& g, const double* part, double* C, hipStream_t st) {
+    const int64_t total = (int64_t)g.nx * g.ny;
+    const int threads = 256;
+    const int64_t blocks = ceil_div(total, threads);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)blocks), dim3(threads), 0, st, part, g.nsplit, g.npairs,
+                       g.tiles_x, g.tiles_y, g.nx, g.ny, g.sym, C);
+    return hipGetLastError();
+}
+
+}  // namespace atc

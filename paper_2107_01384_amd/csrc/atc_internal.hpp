@@ -1,0 +1,155 @@
+// Internal declarations shared by the HIP translation units of libatc.
+// Everything here is gfx950 (CDNA4) code: 64-wide wavefronts, MFMA matrix
+// cores, 160 KB of LDS per compute unit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/atc.h"
+
+namespace atc {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Arithmetic of a contraction (Gram matrix or mode product).
+enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
+
+// How the contracted index of an (L, n, R) view is walked:
+//  KC: R large, the R index is contiguous -> tiles step along R inside one l.
+//  NC: R == 1, the n index is contiguous -> tiles step along l.
+//  SR: 1 < R < tile depth -> a tile covers whole (n x R) planes of several l.
+enum Layout : int { LAYOUT_KC = 0, LAYOUT_NC = 1, LAYOUT_SR = 2 };
+
+template <int P> struct ElemOf { typedef float T; };
+template <> struct ElemOf<PREC_F64> { typedef double T; };
+
+// Device-side bookkeeping of one ST-HOSVD call (Section 4.1.3 error control).
+struct DevBook {
+    double norm2;        // |A|^2, trace of the first Gram matrix
+    double S;            // SSE budget rtmss * eps^2 * |A|^2
+    double used;         // discarded energy so far
+    double tail[ATC_MAX_DIMS];
+    double budget[ATC_MAX_DIMS];
+    double trace[ATC_MAX_DIMS];
+    int32_t rank[ATC_MAX_DIMS];
+    int32_t sweeps[ATC_MAX_DIMS];
+    int32_t status;      // 0, or a negative atc_status
+    int32_t need_dense;  // subspace basis too small for the chosen rank
+    int32_t eig_ok;      // last eigensolve converged
+    int32_t pad;
+};
+
+// ------------------------------------------------------------ small helpers
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Tile geometry of the Gram and mode-product kernels.
+constexpr int TILE = 64;          // output tile edge
+constexpr int NTHREADS = 256;     // 4 waves
+constexpr int FLUSH_TERMS = 128;  // FP32 accumulation chunk before the FP64 add
+
+template <int P> struct KDepth { static constexpr int value = 32; };
+template <> struct KDepth<PREC_F64> { static constexpr int value = 16; };
+
+// Output row held in register v by `lane` for the 16 x 16 MFMA blocks (the
+// column is lane % 16): the FP32-accumulating f32 / bf16 forms hold rows
+// 4*(lane/16) + v, the f64 form holds rows lane/16 + 4*v (measured on gfx950).
+template <int P>
+__device__ inline int mfma16_row(int lane, int v) {
+    return P == PREC_F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+}
+
+// ------------------------------------------------------------ launchers
+// All launchers enqueue on `st` and return hipGetLastError().
+
+// Gram / cross-Gram partials: part[split][pair][64*64] in FP64.
+//   X: (L, nx, R) view, Y: (L, ny, R) view (Y == X and sym for a Gram matrix).
+struct GramPlan {
+    int layout;
+    int64_t L, R;
+    int nx, ny;
+    int sym;
+    int tiles_x, tiles_y, npairs;
+    int64_t steps;   // K steps of depth KDepth
+    int nsplit;
+    int planes;      // SR: planes of R per step
+    size_t part_bytes, part_capacity;
+};
+GramPlan gram_plan(int prec, int64_t L, int nx, int ny, int64_t R, bool sym, size_t part_capacity_bytes);
+hipError_t launch_gram(int prec, const GramPlan& g, const void* X, const void* Y, double* part,
+                       hipStream_t st);
+// Sums the split partials in fixed order into C (nx x ny, row-major, FP64);
+// symmetric plans write both triangles from the upper one.
+hipError_t launch_gram_reduce(const GramPlan& g, const double* part, double* C, hipStream_t st);
+
+// Mode product Z = M x_k Y on the (L, n, R) view: Z[l, j, r] = sum_i M[j, i] Y[l, i, r].
+// M is m_out x n row-major: FP64 for PREC_F64, FP32 for PREC_F32, and for
+// PREC_BF16X3 two bf16 arrays (Mh, Ml) holding hi/lo of the FP32 matrix.
+struct TtmPlan {
+    int layout;
+    int64_t L, R;
+    int n, m_out;
+    int64_t ctiles;  // column tiles
+    int jtiles;
+    int planes;
+    int64_t tiles_per_l;
+};
+TtmPlan ttm_plan(int prec, int64_t L, int n, int64_t R, int m_out);
+hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, const void* Mh,
+                      const void* Ml, void* Z, hipStream_t st);
+
+// Symmetric eigensolvers (FP64).  Outputs lam (descending; not clamped, so a
+// tail sum over rounding-level eigenvalues of an FP32-accurate Gram matrix
+// averages their errors instead of keeping only the positive ones) and
+// V (row-major n x ncols, column j is the eigenvector of lam[j]).
+// Dense one-workgroup Jacobi with the matrix in LDS, n <= 64.
+hipError_t launch_eig_jacobi_lds(const double* G, int n, int ldg, int max_sweeps, double* lam,
+                                 double* V, int ldv, int32_t* sweeps_out, int32_t* ok_out,
+                                 hipStream_t st);
+// Dense one-workgroup Jacobi in global memory, any n (slow; fallback).
+hipError_t launch_eig_jacobi_global(const double* G, int n, int max_sweeps, double* A_ws, double* lam,
+                                    double* V, int32_t* sweeps_out, int32_t* ok_out, hipStream_t st);
+
+// Subspace iteration with Rayleigh-Ritz for the leading m eigenpairs of an
+// n x n PSD matrix (n > 64, m <= 64).  ws must hold subspace_ws_doubles(n, m).
+size_t subspace_ws_doubles(int n, int m);
+hipError_t run_subspace_eig(const double* G, int n, int m, int iters, int max_sweeps, double* ws,
+                            double* lam, double* V, int32_t* sweeps_out, int32_t* ok_out,
+                            hipStream_t st);
+
+// Rank choice, sign rule and factor output for mode position i (of d) on mode k.
+struct SelectArgs {
+    const double* lam;    // descending eigenvalues (ncand of them)
+    const double* V;      // n x ncand, column j <-> lam[j]
+    int ldv;
+    const double* G;      // the Gram matrix (trace), ldg = n
+    int n;
+    int ncand;            // n (dense) or m (subspace)
+    int subspace;         // 1: tails are trace - prefix sums, rank must leave a guard
+    int guard;
+    int pos, d, k;
+    int rule;             // atc_rank_rule
+    int fixed_rank;       // -1: budget rule
+    double rtmss, eps2;
+    DevBook* book;
+    void* ufac;           // user factor n x r row-major (dtype)
+    int ufac_f64;
+    double* Mt64;         // U^T, r x n, FP64 (mode product of the FP64 path)
+    float* Mt32;          // U^T, r x n, FP32
+    __bf16* Mth;          // hi/lo split of Mt32
+    __bf16* Mtl;
+};
+hipError_t launch_select_factor(const SelectArgs& a, hipStream_t st);
+
+// Prepares the mode-product matrix for reconstruction: M = U (n x r, dtype)
+// converted to FP64 / FP32 / bf16 hi-lo.  transpose != 0 gives U^T (r x n).
+hipError_t launch_prepare_matrix(int prec, const void* U, int src_f64, int rows, int cols, int transpose,
+                                 double* M64, float* M32, __bf16* Mh, __bf16* Ml, hipStream_t st);
+
+// Zeroes n bytes with a kernel (capturable in a graph, unlike memset nodes).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+
+}  // namespace atc

@@ -4,7 +4,7 @@ This module only draws random numbers and evaluates the closed-form test fields;
 it contains none of the ST-HOSVD arithmetic (no Gram, eigensolver, rank choice or
 mode product of the method).  Every generator is deterministic in its seed.
 
-Stand-ins for the paper's datasets (Section 5.1, Table 4): the paper's volumes
+Stand-ins for the paper's datasets (Section 6.1, Table 4): the paper's volumes
 (Isotropic turbulence, Hurricane, ...) are not available here, so smooth
 multi-scale fields of the same shapes are built from Gaussian blobs, plane waves
 and white noise.

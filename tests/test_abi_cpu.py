@@ -1,0 +1,99 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol that
+include/atc.h declares, sizes its structs like the header, and rejects bad
+arguments before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2107_01384_amd as atc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "atc.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(atc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = atc.load()
+    names = declared_symbols()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    bound = {s[0] for s in atc.SIGNATURES}
+    assert set(names) == bound
+
+
+def test_struct_sizes_match_header(tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include "%s"\nint main(){printf("%%zu %%zu %%zu %%zu",'
+                   'sizeof(atc_sthosvd_opts),sizeof(atc_result),sizeof(atc_block_result),sizeof(atc_shape));}\n'
+                   % HEADER)
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert [int(v) for v in out] == [ctypes.sizeof(atc.Opts), ctypes.sizeof(atc.Result),
+                                     ctypes.sizeof(atc.BlockResult), ctypes.sizeof(atc.Shape)]
+
+
+def _shape(dims, dtype=0):
+    s = atc.Shape()
+    s.ndim = len(dims)
+    s.dtype = dtype
+    for i, n in enumerate(dims):
+        s.dims[i] = n
+    return s
+
+
+def test_argument_validation_without_device():
+    lib = atc.load()
+    o = atc.make_opts(1e-3)
+    s = _shape([4, 5, 6])
+    ws = lib.atc_sthosvd_workspace_size(ctypes.byref(s), ctypes.byref(o))
+    assert ws > 0
+    null = ctypes.c_void_p(None)
+    facs = (ctypes.c_void_p * 3)(1, 1, 1)
+    # NULL input
+    st = lib.atc_sthosvd(null, ctypes.byref(s), ctypes.byref(o), ctypes.c_void_p(1), facs, None,
+                         ctypes.c_void_p(1), ws, null)
+    assert st == -1 and b"non-NULL" in lib.atc_last_error()
+    # workspace too small
+    st = lib.atc_sthosvd(ctypes.c_void_p(1), ctypes.byref(s), ctypes.byref(o), ctypes.c_void_p(1), facs, None,
+                         ctypes.c_void_p(1), ws - 1, null)
+    assert st == -3
+    # bad shapes and options
+    for bad in (_shape([4, 0, 6]), _shape([]), _shape([2] * 9 if False else [5, 5], dtype=7)):
+        assert lib.atc_sthosvd(ctypes.c_void_p(1), ctypes.byref(bad), ctypes.byref(o), ctypes.c_void_p(1), facs,
+                               None, ctypes.c_void_p(1), ws, null) == -1
+    for kw in ({"rel_error": -1.0}, {"rtmss": 1.5}, {"order": [0, 0, 1]}, {"fixed_ranks": [5, 1, 1]},
+               {"max_sweeps": -3}, {"eig_path": 3}):
+        args = {"rel_error": 1e-3}
+        args.update(kw)
+        ob = atc.make_opts(**args)
+        assert lib.atc_sthosvd(ctypes.c_void_p(1), ctypes.byref(s), ctypes.byref(ob), ctypes.c_void_p(1), facs,
+                               None, ctypes.c_void_p(1), ws, null) == -1, kw
+    # bf16x3 needs float32 input; modes beyond 4096 are not built
+    o3 = atc.make_opts(1e-3, "bf16x3")
+    assert lib.atc_sthosvd(ctypes.c_void_p(1), ctypes.byref(_shape([4, 5], 1)), ctypes.byref(o3), ctypes.c_void_p(1),
+                           facs, None, ctypes.c_void_p(1), ws, null) == -2
+    assert lib.atc_sthosvd_workspace_size(ctypes.byref(_shape([5000, 2])), ctypes.byref(o)) == 0
+    # reconstruction: ranks outside [1, n]
+    ra = (ctypes.c_int64 * 8)(3, 6, 2)
+    assert lib.atc_reconstruct_workspace_size(ctypes.byref(s), ra) == 0
+    ra = (ctypes.c_int64 * 8)(3, 5, 2)
+    assert lib.atc_reconstruct_workspace_size(ctypes.byref(s), ra) > 0
+    assert lib.atc_status_string(-5) == b"eigensolver did not converge"
+
+
+def test_workspace_size_scales_with_tensor():
+    lib = atc.load()
+    o = atc.make_opts(1e-3, "bf16x3")
+    small = lib.atc_sthosvd_workspace_size(ctypes.byref(_shape([64, 64, 64])), ctypes.byref(o))
+    big = lib.atc_sthosvd_workspace_size(ctypes.byref(_shape([512, 512, 512])), ctypes.byref(o))
+    assert big > 2 * 512 ** 3 * 4 > small

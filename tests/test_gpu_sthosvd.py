@@ -1,0 +1,160 @@
+"""GPU parity of atc_sthosvd against the FP64 oracle (called through the C ABI).
+
+Bars:
+  * FP64 path: ranks identical, predicted SSE within 1e-9 relative, kept
+    subspaces (projectors) within 1e-9, reconstruction within 1e-11 of the
+    oracle's (relative to |X|).
+  * FP32 and BF16X3 paths: ranks identical or boundary-degenerate (the oracle's
+    discarded energy at the GPU rank within 10% of the mode budget), achieved
+    error <= 1.02 eps, and |X~_gpu - X~_oracle| / |X| reported and bounded.
+Shapes cover every loader layout of the Gram and mode-product kernels
+(contiguous-R, R == 1, 1 < R < tile depth), ragged tiles (n not a multiple
+of 64) and both eigensolver paths (dense Jacobi, subspace iteration).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2107_01384_amd as atc
+import synth
+from gpu_helpers import gpu_rel_error, log, np64, projector_gap, rank_parity, recon_rel_diff, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(x, eps, dtype, **kw):
+    log("sthosvd", x.shape, dtype, eps, kw)
+    xd = to_dev(x, dtype)
+    t = atc.sthosvd(xd, eps, **kw)
+    torch.cuda.synchronize()
+    return t
+
+
+F64_SHAPES = [(5, 6, 7), (13, 17, 3), (70, 9, 11), (3, 130, 20), (40, 33, 2, 5), (257,), (12, 40)]
+
+
+@pytest.mark.parametrize("shape", F64_SHAPES)
+def test_f64_parity_random(shape):
+    rng = np.random.default_rng(sum(shape))
+    # graded spectrum so that the budget cuts at a well separated point
+    x = rng.standard_normal(shape)
+    for k, n in enumerate(shape):
+        scale = np.logspace(0, -3, n).reshape([-1 if i == k else 1 for i in range(len(shape))])
+        x = x * scale
+    for eps in (1e-1, 1e-2):
+        t_o = oracle.sthosvd(x, eps)
+        t_g = _run(x, eps, torch.float64)
+        assert t_g.ranks == t_o.ranks, (t_g.ranks, t_o.ranks)
+        assert t_g.order == t_o.order
+        assert abs(t_g.norm2 - t_o.norm2) <= 1e-12 * t_o.norm2
+        assert abs(t_g.sse_pred - t_o.sse_pred) <= 1e-9 * t_o.norm2
+        for k in range(len(shape)):
+            assert projector_gap(np64(t_g.factors[k]), t_o.factors[k]) < 1e-9
+        assert recon_rel_diff(x, t_g, t_o) < 1e-11
+        assert gpu_rel_error(x, t_g) <= eps * (1 + 1e-9)
+
+
+def test_f64_config_64cube_known_rank():
+    """64^3 float64 Tucker (core 8^3) + 1e-3 relative noise at eps = 1e-2: ranks (8,8,8)."""
+    x = synth.tucker_c1("relative")
+    t_o = oracle.sthosvd(x, 1e-2, order=[0, 1, 2])
+    t_g = _run(x, 1e-2, torch.float64, order=[0, 1, 2])
+    assert t_g.ranks == [8, 8, 8] == t_o.ranks
+    err = gpu_rel_error(x, t_g)
+    assert err <= 1.02e-2
+    assert abs(err - oracle.rel_error(x, t_o.core, t_o.factors)) <= 1e-12
+    for k in range(3):
+        assert projector_gap(np64(t_g.factors[k]), t_o.factors[k]) < 1e-10
+    log("C1 ranks", t_g.ranks, "err", err)
+
+
+def test_f64_noiseless_exact_recovery():
+    x, core, facs = synth.known_rank_tucker((48, 40, 56), (4, 6, 5), seed=3)
+    t_g = _run(x, 1e-6, torch.float64)
+    assert t_g.ranks == [4, 6, 5]
+    assert gpu_rel_error(x, t_g) < 1e-13
+    for k in range(3):
+        assert projector_gap(np64(t_g.factors[k]), facs[k]) < 1e-12
+
+
+def test_f64_fixed_ranks_and_equal_rule():
+    x = synth.field((20, 24, 28), 4).astype(np.float64)
+    t_o = oracle.sthosvd(x, 1e-2, fixed_ranks=[3, 5, 7])
+    t_g = _run(x, 1e-2, torch.float64, fixed_ranks=[3, 5, 7])
+    assert t_g.ranks == [3, 5, 7]
+    assert abs(t_g.sse_pred - t_o.sse_pred) <= 1e-9 * t_o.norm2
+    t_o = oracle.sthosvd(x, 1e-3, rule="equal")
+    t_g = _run(x, 1e-3, torch.float64, rule="equal")
+    assert t_g.ranks == t_o.ranks
+    assert recon_rel_diff(x, t_g, t_o) < 1e-11
+
+
+# (shape, eps): layouts: mode-0 contiguous R, middle modes R == 13 (1 < R < 32),
+# last mode R == 1; n = 70, 100 > 64 use the subspace eigensolver
+F32_CASES = [((24, 36, 40), 1e-2), ((33, 64, 13), 1e-3), ((48, 20, 29, 13), 1e-3), ((100, 70, 45), 1e-3),
+             ((16, 16, 16), 1e-4)]
+
+
+@pytest.mark.parametrize("precision", ["native", "bf16x3"])
+@pytest.mark.parametrize("shape,eps", F32_CASES)
+def test_f32_parity_fields(shape, eps, precision):
+    if len(shape) == 3:
+        x = synth.field(shape, 7)
+    else:
+        x = np.stack([synth.field(shape[:3], 70 + f) for f in range(shape[3])], axis=-1)
+    t_o = oracle.sthosvd(x, eps)
+    t_g = _run(x, eps, torch.float32, precision=precision)
+    ok, how = rank_parity(t_g, t_o, 0.1)
+    err = gpu_rel_error(x, t_g)
+    diff = recon_rel_diff(x, t_g, t_o) if t_g.ranks == t_o.ranks else float("nan")
+    log("  ranks gpu", t_g.ranks, "oracle", t_o.ranks, how, "err %.4e" % err, "diff %.3e" % diff,
+        "paths", t_g.eig_path)
+    assert ok, how
+    assert err <= 1.02 * eps
+    assert abs(t_g.norm2 - t_o.norm2) <= 1e-5 * t_o.norm2
+    if t_g.ranks == t_o.ranks:
+        assert diff <= 0.2 * eps
+
+
+def test_dense_and_subspace_paths_agree():
+    x = synth.field((90, 80, 70), 11)
+    t_o = oracle.sthosvd(x, 1e-3)
+    t_s = _run(x, 1e-3, torch.float32, eig_path=2)
+    t_d = _run(x, 1e-3, torch.float32, eig_path=1)
+    assert t_s.eig_path[0] == 2 and t_d.eig_path[0] == 1
+    for name, t in (("subspace", t_s), ("dense", t_d)):
+        log(name, t.ranks, "tails/b", [t.tails[k] / t.budgets[k] for k in range(3)], "sweeps", t.eig_sweeps,
+            "norm2", t.norm2)
+    log("oracle", t_o.ranks, "tails/b", [t_o.tails[k] / t_o.budgets[k] for k in range(3)], "norm2", t_o.norm2)
+    # same Gram matrix, two eigensolvers: unbiased tails on both sides
+    assert t_s.ranks == t_d.ranks
+    for k in range(3):
+        assert abs(t_s.tails[k] - t_d.tails[k]) <= 0.02 * t_d.budgets[k]
+    ok, how = rank_parity(t_s, t_o, 0.1)
+    assert ok, how
+    # two power steps leave ~(lambda_noise / lambda_r)^2 of the subspace unresolved
+    for k in range(3):
+        assert projector_gap(np64(t_s.factors[k]), np64(t_d.factors[k])) < 2e-3
+    assert recon_rel_diff(x, t_s, t_o) <= 0.1 * 1e-3
+
+
+def test_zero_and_nonfinite_inputs():
+    z = np.zeros((8, 9, 10))
+    t = _run(z, 1e-3, torch.float64)
+    assert t.ranks == [1, 1, 1] and t.sse_pred == 0.0
+    bad = np.ones((8, 9, 10), dtype=np.float32)
+    bad[3, 4, 5] = np.inf
+    with pytest.raises(atc.AtcError) as e:
+        _run(bad, 1e-3, torch.float32)
+    assert e.value.status == -6
+
+
+def test_deterministic_bits():
+    x = synth.field((64, 48, 56), 2)
+    a = _run(x, 1e-3, torch.float32, precision="bf16x3")
+    b = _run(x, 1e-3, torch.float32, precision="bf16x3")
+    assert a.ranks == b.ranks
+    assert torch.equal(a.core, b.core)
+    for fa, fb in zip(a.factors, b.factors):
+        assert torch.equal(fa, fb)

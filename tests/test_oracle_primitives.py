@@ -17,7 +17,7 @@ SHAPES = [(5, 6, 7), (1, 9, 4), (7, 1, 3), (3, 4, 1), (2, 3, 4, 5), (13,), (4, 4
 
 
 def unfold(x, k):
-    """Mode-k matricization (Section 2.1): mode-k fibers as columns."""
+    """Mode-k matricization (Section 3.1): mode-k fibers as columns."""
     return np.moveaxis(x, k, 0).reshape(x.shape[k], -1)
 
 
@@ -63,7 +63,7 @@ def test_mode_product_matches_einsum(shape):
 
 
 def test_mode_product_properties():
-    """Section 2.1: products along different modes commute; along one mode they compose;
+    """Section 3.1: products along different modes commute; along one mode they compose;
     an orthogonal matrix preserves the norm."""
     rng = np.random.default_rng(14)
     x = rng.standard_normal((4, 5, 6))

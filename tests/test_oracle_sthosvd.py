@@ -3,7 +3,7 @@
 Closed forms (super-diagonal tensor), the matrix case (d = 2 is the truncated SVD,
 checked against numpy.linalg.svd, Eckart-Young), exact recovery of tensors of
 known multilinear rank, the identity |X - X~|^2 = sum of the discarded eigenvalues
-(Section 4.1.3), orthonormal factors (Section 2.2), all-orthogonality of the core
+(Section 4.1.3), orthonormal factors (Section 3.2), all-orthogonality of the core
 in the last processed mode, invariances, and the published-shape configurations.
 """
 import numpy as np
