@@ -294,48 +294,46 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         int32_t* sweeps_dev = &w.book->sweeps[k];
         int32_t* ok_dev = &w.book->eig_ok;
 
-        const bool use_sub = n > 64 && opts->eig_path != 1;
-        bool dense_done = false;
-        if (n <= 64) {
-            HIP_TRY(launch_eig_jacobi_lds(w.G, n, n, max_sweeps, w.lam, w.V, n, sweeps_dev, ok_dev, st));
-            sa.ldv = n;
-            sa.ncand = n;
-            sa.subspace = 0;
-            dense_done = true;
-            paths[k] = 1;
-        } else if (use_sub) {
-            const int m = std::min(SUBSPACE_M, n);
-            HIP_TRY(run_subspace_eig(w.G, n, m, SUBSPACE_ITERS, max_sweeps, w.sub, w.lam, w.V, sweeps_dev, ok_dev, st));
-            sa.ldv = m;
-            sa.ncand = m;
-            sa.subspace = 1;
-            paths[k] = 2;
-        } else {
-            HIP_TRY(launch_eig_jacobi_global(w.G, n, max_sweeps, w.jac, w.lam, w.V, sweeps_dev, ok_dev, st));
-            sa.ldv = n;
-            sa.ncand = n;
-            sa.subspace = 0;
-            dense_done = true;
-            paths[k] = 1;
-        }
-        HIP_TRY(launch_select_factor(sa, st));
-        HIP_TRY(hipMemcpyAsync(&hb, w.book, sizeof(DevBook), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        if (hb.status != 0) return fail((atc_status)hb.status, "input |A|^2 is not finite");
-        if (hb.need_dense && !dense_done) {
-            if (opts->eig_path == 2)
-                return fail(ATC_ERR_UNSUPPORTED, "mode %d: rank needs more than %d Ritz pairs", k,
-                            SUBSPACE_M - SUBSPACE_GUARD);
-            const int32_t zero = 0;
-            HIP_TRY(hipMemcpyAsync(&w.book->need_dense, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
-            HIP_TRY(launch_eig_jacobi_global(w.G, n, max_sweeps, w.jac, w.lam, w.V, sweeps_dev, ok_dev, st));
-            sa.ldv = n;
-            sa.ncand = n;
-            sa.subspace = 0;
-            paths[k] = 1;
+        // eigensolver ladder: n <= 64 dense in LDS; otherwise subspace m = 32,
+        // then m = 64, then dense in global memory, each step taken only when the
+        // chosen rank does not leave `guard` unused Ritz pairs.  FP64 input keeps
+        // the dense solver (the subspace iteration is accurate to what an
+        // FP32-grade Gram matrix carries, not to FP64) unless eig_path forces it.
+        const int32_t zero = 0;
+        const bool dense_first = n <= 64 || opts->eig_path == 1 || (f64 && opts->eig_path != 2);
+        int attempt = dense_first ? 2 : 0;
+        for (;; ++attempt) {
+            if (attempt < 2) {
+                const int m = attempt == 0 ? std::min(SUBSPACE_M / 2, n) : std::min(SUBSPACE_M, n);
+                HIP_TRY(run_subspace_eig(w.G, n, m, SUBSPACE_ITERS, max_sweeps, w.sub, w.lam, w.V, sweeps_dev, ok_dev,
+                                         st));
+                sa.ldv = m;
+                sa.ncand = m;
+                sa.subspace = 1;
+                paths[k] = 2;
+            } else if (n <= 64) {
+                HIP_TRY(launch_eig_jacobi_lds(w.G, n, n, max_sweeps, w.lam, w.V, n, sweeps_dev, ok_dev, st));
+                sa.ldv = n;
+                sa.ncand = n;
+                sa.subspace = 0;
+                paths[k] = 1;
+            } else {
+                HIP_TRY(launch_eig_jacobi_global(w.G, n, max_sweeps, w.jac, w.lam, w.V, sweeps_dev, ok_dev, st));
+                sa.ldv = n;
+                sa.ncand = n;
+                sa.subspace = 0;
+                paths[k] = 1;
+            }
             HIP_TRY(launch_select_factor(sa, st));
             HIP_TRY(hipMemcpyAsync(&hb, w.book, sizeof(DevBook), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
+            if (hb.status != 0) return fail((atc_status)hb.status, "input |A|^2 is not finite");
+            if (!hb.need_dense) break;
+            if (attempt >= 2) return fail(ATC_ERR_INTERNAL, "mode %d: dense eigensolver asked for more", k);
+            if (attempt == 1 && opts->eig_path == 2)
+                return fail(ATC_ERR_UNSUPPORTED, "mode %d: rank needs more than %d Ritz pairs", k,
+                            SUBSPACE_M - SUBSPACE_GUARD);
+            HIP_TRY(hipMemcpyAsync(&w.book->need_dense, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
         }
         if (!hb.eig_ok) return fail(ATC_ERR_NOT_CONVERGED, "mode %d: eigensolver hit %d sweeps", k, max_sweeps);
         const int r = hb.rank[k];

@@ -8,27 +8,28 @@
 // discarded squared singular values) need the extra precision.
 //
 // Dense path: cyclic two-sided Jacobi with the round-robin parallel ordering
-// (n/2 disjoint rotations per round, n-1 rounds per sweep), one workgroup,
-// matrix and eigenvectors in LDS for n <= 64, or in global memory (any n,
-// slow) as the fallback.  A rotation is skipped when
-// |a_pq| <= tol * sqrt(|a_pp a_qq|), tol = n * 2^-53; a sweep with no rotation
-// ends the iteration.
+// (m/2 disjoint rotations per round, m-1 rounds per sweep).  A rotation is
+// skipped when |a_pq| <= tol * sqrt(|a_pp a_qq|), tol = n * 2^-53; a rotated
+// pair is annihilated exactly and its diagonal set from the 2 x 2 formulas;
+// a sweep with no rotation ends the iteration.  For m <= 64 one workgroup
+// holds the matrix and the eigenvectors in LDS and thread (k, l) owns the
+// 2 x 2 block (pair k, pair l), so a round is one read-modify-write pass.
+// Larger n use the same iteration in global memory (slow; a fallback).
 //
 // Subspace path (n > 64): the ranks this method keeps are small next to n, so
-// only the leading m (<= 64) eigenpairs are needed: subspace iteration with a
-// Rayleigh-Ritz projection at every step, the small m x m problems solved by
-// the LDS Jacobi.  Ritz values never exceed the true eigenvalues, so the tail
-// trace(G) - sum(kept Ritz values) over-estimates the discarded energy and
-// the error bound still holds; a rank that reaches into the last `guard`
-// Ritz pairs sends the mode to the dense path instead.
+// only the leading m (32 or 64) eigenpairs are needed: power steps with CGS2
+// re-orthonormalisation, Q_0 = orth(G Omega), Q_t = orth(G Q_{t-1}), then a
+// Rayleigh-Ritz projection B = Q^T G Q = W diag(theta) W^T, U = Q W, the
+// m x m problem solved by the LDS Jacobi.  Ritz values never exceed the true
+// eigenvalues, so the tail trace(G) - sum(kept Ritz values) over-estimates the
+// discarded energy and the error bound still holds; a rank that reaches into
+// the last `guard` Ritz pairs sends the mode to a larger m or the dense path.
 #include <math.h>
 
 #include "atc_internal.hpp"
 
 namespace atc {
 namespace {
-
-constexpr int JMAX = 64;
 
 __device__ inline void round_robin_pair(int round, int k, int m, int& p, int& q) {
     // circle method: player 0 fixed, players 1..m-1 rotate
@@ -67,19 +68,48 @@ __device__ inline bool schur2(double app, double aqq, double apq, double tol, do
     return true;
 }
 
-// ------------------------------------------------------------------ LDS Jacobi
-__global__ __launch_bounds__(256) void k_eig_jacobi_lds(const double* __restrict__ G, int n, int ldg,
-                                                        int max_sweeps, double* __restrict__ lam,
-                                                        double* __restrict__ V, int ldv,
-                                                        int32_t* __restrict__ sweeps_out,
-                                                        int32_t* __restrict__ ok_out) {
-    __shared__ double A[JMAX][JMAX + 1];
-    __shared__ double Vs[JMAX][JMAX + 1];
-    __shared__ int pp[JMAX / 2], qq[JMAX / 2];
-    __shared__ double cs[JMAX / 2], sn[JMAX / 2], dpp[JMAX / 2], dqq[JMAX / 2];
+// deterministic pseudo-random value in [-1, 1) (splitmix64 of the key)
+__device__ inline double hash_unit(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return (double)(x >> 11) * 0x1p-52 - 1.0;
+}
+
+// Sum over the workgroup in a fixed order (wave shuffles, then waves in order).
+__device__ inline double block_sum(double s, double* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) red[wave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += red[w];
+        red[16] = t;
+    }
+    __syncthreads();
+    const double r = red[16];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------- LDS Jacobi (m <= 64)
+template <int MAXM>
+__global__ __launch_bounds__((MAXM / 2) * (MAXM / 2)) void k_eig_jacobi_lds(
+    const double* __restrict__ G, int n, int ldg, int max_sweeps, double* __restrict__ lam, double* __restrict__ V,
+    int ldv, int32_t* __restrict__ sweeps_out, int32_t* __restrict__ ok_out) {
+    constexpr int H = MAXM / 2;
+    __shared__ double A[MAXM][MAXM + 1];
+    __shared__ double Vs[MAXM][MAXM + 1];
+    __shared__ int pp[H], qq[H];
+    __shared__ double cs[H], sn[H], dpp[H], dqq[H];
     __shared__ int rotated;
+    __shared__ int rank_of[MAXM];
     const int tid = threadIdx.x;
     const int m = n + (n & 1);
+    const int h = m / 2;
+    const int kb = tid / H, lb = tid % H;  // row pair, column pair of this thread's block
     for (int idx = tid; idx < m * m; idx += blockDim.x) {
         const int i = idx / m, j = idx % m;
         A[i][j] = (i < n && j < n) ? G[(int64_t)i * ldg + j] : 0.0;
@@ -93,7 +123,7 @@ __global__ __launch_bounds__(256) void k_eig_jacobi_lds(const double* __restrict
         if (tid == 0) rotated = 0;
         __syncthreads();
         for (int round = 0; round < m - 1; ++round) {
-            if (tid < m / 2) {
+            if (tid < h) {
                 int p, q;
                 round_robin_pair(round, tid, m, p, q);
                 double c, s, dp, dq;
@@ -106,37 +136,46 @@ __global__ __launch_bounds__(256) void k_eig_jacobi_lds(const double* __restrict
                 dqq[tid] = dq;
             }
             __syncthreads();
-            for (int idx = tid; idx < (m / 2) * m; idx += blockDim.x) {
-                const int k = idx / m, j = idx % m;
-                const double c = cs[k], s = sn[k];
-                if (s == 0.0) continue;
-                const int p = pp[k], q = qq[k];
-                const double x = A[p][j], y = A[q][j];
-                A[p][j] = c * x - s * y;
-                A[q][j] = s * x + c * y;
-            }
-            __syncthreads();
-            for (int idx = tid; idx < m * (m / 2); idx += blockDim.x) {
-                const int i = idx / (m / 2), k = idx % (m / 2);
-                const double c = cs[k], s = sn[k];
-                if (s == 0.0) continue;
-                const int p = pp[k], q = qq[k];
-                const double x = A[i][p], y = A[i][q];
-                A[i][p] = c * x - s * y;
-                A[i][q] = s * x + c * y;
-                const double vx = Vs[i][p], vy = Vs[i][q];
-                Vs[i][p] = c * vx - s * vy;
-                Vs[i][q] = s * vx + c * vy;
-            }
-            __syncthreads();
-            // the rotated pair is annihilated exactly and its diagonal set from the
-            // 2x2 formulas (the row and column passes leave rounding residue there)
-            if (tid < m / 2 && sn[tid] != 0.0) {
-                const int p = pp[tid], q = qq[tid];
-                A[p][q] = 0.0;
-                A[q][p] = 0.0;
-                A[p][p] = dpp[tid];
-                A[q][q] = dqq[tid];
+            if (kb < h && lb < h) {
+                const int p = pp[kb], q = qq[kb];
+                const double c1 = cs[kb], s1 = sn[kb];
+                if (kb == lb) {
+                    if (s1 != 0.0) {
+                        A[p][p] = dpp[kb];
+                        A[q][q] = dqq[kb];
+                        A[p][q] = 0.0;
+                        A[q][p] = 0.0;
+                    }
+                } else if (kb < lb) {
+                    // block (rows p,q ; cols p2,q2) <- J_k^T block J_l, mirrored into (l, k)
+                    const int p2 = pp[lb], q2 = qq[lb];
+                    const double c2 = cs[lb], s2 = sn[lb];
+                    if (s1 != 0.0 || s2 != 0.0) {
+                        const double a = A[p][p2], b = A[p][q2], c = A[q][p2], d = A[q][q2];
+                        const double ra = c1 * a - s1 * c, rb = c1 * b - s1 * d;
+                        const double rc = s1 * a + c1 * c, rd = s1 * b + c1 * d;
+                        const double na = c2 * ra - s2 * rb, nb = s2 * ra + c2 * rb;
+                        const double nc = c2 * rc - s2 * rd, nd = s2 * rc + c2 * rd;
+                        A[p][p2] = na;
+                        A[p][q2] = nb;
+                        A[q][p2] = nc;
+                        A[q][q2] = nd;
+                        A[p2][p] = na;
+                        A[q2][p] = nb;
+                        A[p2][q] = nc;
+                        A[q2][q] = nd;
+                    }
+                }
+                // eigenvector rows 2 lb and 2 lb + 1, columns of pair k: V <- V J_k
+                if (s1 != 0.0) {
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const int i = 2 * lb + t;
+                        const double x = Vs[i][p], y = Vs[i][q];
+                        Vs[i][p] = c1 * x - s1 * y;
+                        Vs[i][q] = s1 * x + c1 * y;
+                    }
+                }
             }
             __syncthreads();
         }
@@ -145,7 +184,6 @@ __global__ __launch_bounds__(256) void k_eig_jacobi_lds(const double* __restrict
         __syncthreads();
     }
     // eigenvalues = diagonal; order descending, equal values by index
-    __shared__ int rank_of[JMAX];
     for (int i = tid; i < n; i += blockDim.x) {
         const double li = A[i][i];
         int r = 0;
@@ -156,10 +194,7 @@ __global__ __launch_bounds__(256) void k_eig_jacobi_lds(const double* __restrict
         rank_of[i] = r;
     }
     __syncthreads();
-    for (int i = tid; i < n; i += blockDim.x) {
-        const double li = A[i][i];
-        lam[rank_of[i]] = li;  // unclamped: tail sums keep the sign of rounding-level values
-    }
+    for (int i = tid; i < n; i += blockDim.x) lam[rank_of[i]] = A[i][i];  // unclamped (see select)
     for (int idx = tid; idx < n * n; idx += blockDim.x) {
         const int row = idx / n, i = idx % n;
         V[(int64_t)row * ldv + rank_of[i]] = Vs[row][i];
@@ -268,62 +303,78 @@ __global__ __launch_bounds__(1024) void k_eig_jacobi_global(const double* __rest
     }
 }
 
-// ------------------------------------------------------------ small FP64 GEMM
-// C[i, j] = alpha * sum_k A(i, k) B(k, j) (+ beta * C), with A(i, k) = A[i*sa0 + k*sa1],
-// B(k, j) = B[k*sb0 + j*sb1]; optional column scale of B: B(k, j) * bscale[j].
-__global__ __launch_bounds__(256) void k_gemm64(int M, int N, int K, const double* __restrict__ A, int64_t sa0,
-                                                int64_t sa1, const double* __restrict__ B, int64_t sb0, int64_t sb1,
-                                                const double* __restrict__ bscale, double* __restrict__ C,
-                                                int64_t ldc) {
-    __shared__ double As[32][33];
-    __shared__ double Bs[32][33];
+// ------------------------------------------------------- small FP64 products
+// C (n x m) = A (n x n, row-major) * B (n x m, row-major), m <= 64.
+// A workgroup stages 4 rows of A (in chunks of 512) and computes 4 x m outputs.
+constexpr int GR_ROWS = 4;
+constexpr int GR_KC = 512;
+__global__ __launch_bounds__(256) void k_gemm_rows(const double* __restrict__ A, const double* __restrict__ B,
+                                                   double* __restrict__ C, int n, int m) {
+    __shared__ double As[GR_ROWS][GR_KC];
     const int tid = threadIdx.x;
-    const int tx = tid % 16, ty = tid / 16;
-    const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
-    double acc[2][2] = {{0, 0}, {0, 0}};
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        for (int idx = tid; idx < 32 * 32; idx += 256) {
-            const int r = idx / 32, c = idx % 32;
-            const int gi = i0 + r, gk = k0 + c;
-            As[r][c] = (gi < M && gk < K) ? A[gi * sa0 + gk * sa1] : 0.0;
-            const int bk = k0 + r, bj = j0 + c;
-            double bv = (bk < K && bj < N) ? B[bk * sb0 + bj * sb1] : 0.0;
-            if (bscale && bj < N) bv *= bscale[bj];
-            Bs[r][c] = bv;
+    const int r = tid >> 6, j = tid & 63;
+    const int row = blockIdx.x * GR_ROWS + r;
+    double acc = 0.0;
+    for (int k0 = 0; k0 < n; k0 += GR_KC) {
+        const int kc = min(GR_KC, n - k0);
+        for (int idx = tid; idx < GR_ROWS * GR_KC; idx += blockDim.x) {
+            const int rr = idx / GR_KC, kk = idx % GR_KC;
+            const int grow = blockIdx.x * GR_ROWS + rr;
+            As[rr][kk] = (grow < n && kk < kc) ? A[(int64_t)grow * n + k0 + kk] : 0.0;
         }
         __syncthreads();
-#pragma unroll 8
-        for (int k = 0; k < 32; ++k) {
-            const double a0 = As[ty * 2][k], a1 = As[ty * 2 + 1][k];
-            const double b0 = Bs[k][tx * 2], b1 = Bs[k][tx * 2 + 1];
-            acc[0][0] += a0 * b0;
-            acc[0][1] += a0 * b1;
-            acc[1][0] += a1 * b0;
-            acc[1][1] += a1 * b1;
-        }
+        if (j < m)
+            for (int kk = 0; kk < kc; ++kk) acc += As[r][kk] * B[(int64_t)(k0 + kk) * m + j];
         __syncthreads();
     }
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-            const int gi = i0 + ty * 2 + a, gj = j0 + tx * 2 + b;
-            if (gi < M && gj < N) C[gi * ldc + gj] = acc[a][b];
-        }
+    if (row < n && j < m) C[(int64_t)row * m + j] = acc;
 }
 
-hipError_t gemm64(int M, int N, int K, const double* A, int64_t sa0, int64_t sa1, const double* B, int64_t sb0,
-                  int64_t sb1, const double* bscale, double* C, int64_t ldc, hipStream_t st) {
-    dim3 grid((unsigned)ceil_div(N, 32), (unsigned)ceil_div(M, 32));
-    hipLaunchKernelGGL(k_gemm64, grid, dim3(256), 0, st, M, N, K, A, sa0, sa1, B, sb0, sb1, bscale, C, ldc);
-    return hipGetLastError();
+// Partial C_c = A_c^T B_c over row chunk c of 64 rows (A: n x ma, B: n x mb).
+constexpr int TN_ROWS = 64;
+__global__ __launch_bounds__(256) void k_gemm_tn_partial(const double* __restrict__ A, const double* __restrict__ B,
+                                                         double* __restrict__ part, int n, int ma, int mb) {
+    __shared__ double As[TN_ROWS][65];
+    __shared__ double Bs[TN_ROWS][65];
+    const int tid = threadIdx.x;
+    const int r0 = blockIdx.x * TN_ROWS;
+    for (int idx = tid; idx < TN_ROWS * 64; idx += blockDim.x) {
+        const int rr = idx / 64, c = idx % 64;
+        const int row = r0 + rr;
+        As[rr][c] = (row < n && c < ma) ? A[(int64_t)row * ma + c] : 0.0;
+        Bs[rr][c] = (row < n && c < mb) ? B[(int64_t)row * mb + c] : 0.0;
+    }
+    __syncthreads();
+    double* out = part + (int64_t)blockIdx.x * ma * mb;
+    for (int o = tid; o < ma * mb; o += blockDim.x) {
+        const int i = o / mb, j = o % mb;
+        double s = 0.0;
+        for (int rr = 0; rr < TN_ROWS; ++rr) s += As[rr][i] * Bs[rr][j];
+        out[o] = s;
+    }
 }
 
-// deterministic pseudo-random fill in [-1, 1) (splitmix64 of the index)
-__device__ inline double hash_unit(uint64_t x) {
-    x += 0x9E3779B97F4A7C15ull;
-    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-    x ^= x >> 31;
-    return (double)(x >> 11) * 0x1p-52 - 1.0;
+__global__ void k_sum_partials(const double* __restrict__ part, int nparts, int count, double* __restrict__ C) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= count) return;
+    double s = 0.0;
+    for (int c = 0; c < nparts; ++c) s += part[(int64_t)c * count + o];
+    C[o] = s;
+}
+
+// C (n x mb) = A (n x ma) * W (ma x mb), everything row-major, ma, mb <= 64.
+__global__ __launch_bounds__(256) void k_gemm_small(const double* __restrict__ A, const double* __restrict__ W,
+                                                    double* __restrict__ C, int n, int ma, int mb) {
+    __shared__ double Ws[64][65];
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < ma * mb; idx += blockDim.x) Ws[idx / mb][idx % mb] = W[idx];
+    __syncthreads();
+    const int r = tid >> 6, j = tid & 63;
+    const int row = blockIdx.x * 4 + r;
+    if (row >= n || j >= mb) return;
+    double s = 0.0;
+    for (int c = 0; c < ma; ++c) s += A[(int64_t)row * ma + c] * Ws[c][j];
+    C[(int64_t)row * mb + j] = s;
 }
 
 __global__ void k_fill_random(double* Q, int n, int m, uint64_t salt) {
@@ -335,24 +386,61 @@ __global__ void k_fill_random(double* Q, int n, int m, uint64_t salt) {
 // Gram-Schmidt applied twice per column (CGS2); a column that loses all but
 // 1e-10 of its norm is numerically dependent and is replaced by a
 // pseudo-random vector (then orthogonalised again), or zeroed if that fails.
-// One workgroup; the current column is staged in LDS.
-__device__ inline double block_sum(double s, double* red, int lane, int wave, int nw) {
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) red[wave] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int w = 0; w < nw; ++w) t += red[w];
-        red[16] = t;
+// One workgroup; the whole basis sits column-major in LDS (n * m doubles).
+__global__ __launch_bounds__(1024) void k_cgs2_lds(double* __restrict__ X, int n, int m, uint64_t salt) {
+    extern __shared__ double Xs[];  // column c at Xs + c * n
+    __shared__ double h[64];
+    __shared__ double red[17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    for (int idx = tid; idx < n * m; idx += blockDim.x) {
+        const int i = idx / m, c = idx % m;
+        Xs[c * n + i] = X[idx];
     }
     __syncthreads();
-    const double r = red[16];
-    __syncthreads();
-    return r;
+    for (int j = 0; j < m; ++j) {
+        double* xj = Xs + j * n;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            double s = 0.0;
+            for (int i = tid; i < n; i += blockDim.x) s += xj[i] * xj[i];
+            const double norm0 = sqrt(block_sum(s, red));
+            for (int pass = 0; pass < 2 && j > 0; ++pass) {
+                for (int c = wave; c < j; c += nw) {
+                    const double* xc = Xs + c * n;
+                    double d = 0.0;
+                    for (int i = lane; i < n; i += 64) d += xc[i] * xj[i];
+                    for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+                    if (lane == 0) h[c] = d;
+                }
+                __syncthreads();
+                for (int i = tid; i < n; i += blockDim.x) {
+                    double v = xj[i];
+                    for (int c = 0; c < j; ++c) v -= Xs[c * n + i] * h[c];
+                    xj[i] = v;
+                }
+                __syncthreads();
+            }
+            s = 0.0;
+            for (int i = tid; i < n; i += blockDim.x) s += xj[i] * xj[i];
+            const double nrm = sqrt(block_sum(s, red));
+            if (nrm > 1e-10 * norm0 && nrm > 0.0 && isfinite(nrm)) {
+                for (int i = tid; i < n; i += blockDim.x) xj[i] /= nrm;
+                __syncthreads();
+                break;
+            }
+            for (int i = tid; i < n; i += blockDim.x)
+                xj[i] = attempt == 0 ? hash_unit(((uint64_t)i * 977 + j) * 0x2545F4914F6CDD1Dull + salt) : 0.0;
+            __syncthreads();
+        }
+    }
+    for (int idx = tid; idx < n * m; idx += blockDim.x) {
+        const int i = idx / m, c = idx % m;
+        X[idx] = Xs[c * n + i];
+    }
 }
 
-__global__ __launch_bounds__(1024) void k_cgs2(double* __restrict__ X, int n, int m, uint64_t salt) {
-    extern __shared__ double col[];     // n doubles
+// The same with the basis in global memory (n * m too large for LDS).
+__global__ __launch_bounds__(1024) void k_cgs2_global(double* __restrict__ X, int n, int m, uint64_t salt) {
+    extern __shared__ double col[];  // n doubles
     __shared__ double h[64];
     __shared__ double red[17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
@@ -362,7 +450,7 @@ __global__ __launch_bounds__(1024) void k_cgs2(double* __restrict__ X, int n, in
         for (int attempt = 0; attempt < 2; ++attempt) {
             double s = 0.0;
             for (int i = tid; i < n; i += blockDim.x) s += col[i] * col[i];
-            const double norm0 = sqrt(block_sum(s, red, lane, wave, nw));
+            const double norm0 = sqrt(block_sum(s, red));
             for (int pass = 0; pass < 2 && j > 0; ++pass) {
                 for (int c = wave; c < j; c += nw) {
                     double d = 0.0;
@@ -381,13 +469,12 @@ __global__ __launch_bounds__(1024) void k_cgs2(double* __restrict__ X, int n, in
             }
             s = 0.0;
             for (int i = tid; i < n; i += blockDim.x) s += col[i] * col[i];
-            const double nrm = sqrt(block_sum(s, red, lane, wave, nw));
+            const double nrm = sqrt(block_sum(s, red));
             if (nrm > 1e-10 * norm0 && nrm > 0.0 && isfinite(nrm)) {
                 for (int i = tid; i < n; i += blockDim.x) col[i] /= nrm;
                 __syncthreads();
                 break;
             }
-            // dependent column: retry once with a pseudo-random vector, else zero it
             for (int i = tid; i < n; i += blockDim.x)
                 col[i] = attempt == 0 ? hash_unit(((uint64_t)i * 977 + j) * 0x2545F4914F6CDD1Dull + salt) : 0.0;
             __syncthreads();
@@ -397,21 +484,48 @@ __global__ __launch_bounds__(1024) void k_cgs2(double* __restrict__ X, int n, in
     }
 }
 
+constexpr size_t CGS2_LDS_MAX = 128 * 1024;  // bytes of basis kept in LDS
+
+bool cgs2_lds_ready() {
+    static int state = 0;  // 0 unknown, 1 ok, -1 not available
+    if (state == 0) {
+        state = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_cgs2_lds),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)CGS2_LDS_MAX) == hipSuccess
+                    ? 1
+                    : -1;
+    }
+    return state == 1;
+}
+
+hipError_t orthonormalise(double* X, int n, int m, uint64_t salt, hipStream_t st) {
+    const size_t bytes = sizeof(double) * (size_t)n * m;
+    if (bytes <= CGS2_LDS_MAX && cgs2_lds_ready()) {
+        hipLaunchKernelGGL(k_cgs2_lds, dim3(1), dim3(1024), bytes, st, X, n, m, salt);
+    } else {
+        hipLaunchKernelGGL(k_cgs2_global, dim3(1), dim3(1024), sizeof(double) * (size_t)n, st, X, n, m, salt);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_eig_jacobi_lds(const double* G, int n, int ldg, int max_sweeps, double* lam, double* V, int ldv,
                                  int32_t* sweeps_out, int32_t* ok_out, hipStream_t st) {
-    if (n > JMAX || n < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_eig_jacobi_lds, dim3(1), dim3(256), 0, st, G, n, ldg, max_sweeps, lam, V, ldv,
-                       sweeps_out, ok_out);
+    if (n < 1 || n > 64) return hipErrorInvalidValue;
+    if (n <= 32)
+        hipLaunchKernelGGL((k_eig_jacobi_lds<32>), dim3(1), dim3(256), 0, st, G, n, ldg, max_sweeps, lam, V, ldv,
+                           sweeps_out, ok_out);
+    else
+        hipLaunchKernelGGL((k_eig_jacobi_lds<64>), dim3(1), dim3(1024), 0, st, G, n, ldg, max_sweeps, lam, V, ldv,
+                           sweeps_out, ok_out);
     return hipGetLastError();
 }
 
 hipError_t launch_eig_jacobi_global(const double* G, int n, int max_sweeps, double* A_ws, double* lam, double* V,
                                     int32_t* sweeps_out, int32_t* ok_out, hipStream_t st) {
     const int m = n + (n & 1);
+    // pair indices (2 x m/2 ints) then c, s and the two new diagonals (4 x m/2 doubles);
     // A_ws holds 2 * m * m doubles: the working matrix, then the eigenvector accumulator
-    // pair indices (2 x m/2 ints) then c, s and the two new diagonals (4 x m/2 doubles)
     const size_t shm = (size_t)m * sizeof(int) + (size_t)2 * m * sizeof(double) + 64;
     if (shm > 64 * 1024) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_eig_jacobi_global, dim3(1), dim3(1024), shm, st, G, n, max_sweeps, A_ws, lam, V,
@@ -420,39 +534,47 @@ hipError_t launch_eig_jacobi_global(const double* G, int n, int max_sweeps, doub
 }
 
 size_t subspace_ws_doubles(int n, int m) {
-    return (size_t)3 * n * m + (size_t)2 * m * m + (size_t)m + 64;
+    const size_t chunks = (size_t)ceil_div(n, TN_ROWS);
+    return (size_t)3 * n * m + (size_t)2 * m * m + chunks * (size_t)m * m + 64;
 }
 
-// Leading m eigenpairs of the PSD matrix G (n x n): power steps with
+// Leading m eigenpairs of the PSD matrix G (n x n): power steps with CGS2
 // re-orthonormalisation, Q_0 = orth(G Omega), Q_t = orth(G Q_{t-1}), then the
-// Rayleigh-Ritz projection B = Q^T G Q = W diag(theta) W^T, U = Q W.
+// Rayleigh-Ritz projection B = Q^T G Q = W diag(theta) W^T, V = Q W (n x m).
 hipError_t run_subspace_eig(const double* G, int n, int m, int iters, int max_sweeps, double* ws, double* lam,
                             double* V, int32_t* sweeps_out, int32_t* ok_out, hipStream_t st) {
-    if (m > JMAX || m < 2 || n < m || n > 4096) return hipErrorInvalidValue;
+    if (m > 64 || m < 2 || n < m || n > 4096) return hipErrorInvalidValue;
     double* Q = ws;                       // n x m
     double* Z = Q + (size_t)n * m;        // n x m
     double* Y = Z + (size_t)n * m;        // n x m
     double* B = Y + (size_t)n * m;        // m x m
     double* W = B + (size_t)m * m;        // m x m
+    double* part = W + (size_t)m * m;     // chunks x m x m
+    const int chunks = (int)ceil_div(n, TN_ROWS);
     hipError_t e;
-    const int nb = (int)ceil_div((int64_t)n * m, 256);
-    const size_t shm = sizeof(double) * (size_t)n;
-    hipLaunchKernelGGL(k_fill_random, dim3(nb), dim3(256), 0, st, Y, n, m, (uint64_t)0x5eed);
+    const unsigned gr = (unsigned)ceil_div(n, GR_ROWS);
+    hipLaunchKernelGGL(k_fill_random, dim3((unsigned)ceil_div((int64_t)n * m, 256)), dim3(256), 0, st, Y, n, m,
+                       (uint64_t)0x5eed);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int steps = iters < 1 ? 1 : iters;
     for (int it = 0; it < steps; ++it) {
-        if ((e = gemm64(n, m, n, G, n, 1, it == 0 ? Y : Z, m, 1, nullptr, Q, m, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_cgs2, dim3(1), dim3(1024), shm, st, Q, n, m, (uint64_t)(it + 1));
+        hipLaunchKernelGGL(k_gemm_rows, dim3(gr), dim3(256), 0, st, G, it == 0 ? Y : Z, Q, n, m);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = orthonormalise(Q, n, m, (uint64_t)(it + 1), st)) != hipSuccess) return e;
         if (it + 1 < steps) {
             if ((e = hipMemcpyAsync(Z, Q, sizeof(double) * n * m, hipMemcpyDeviceToDevice, st)) != hipSuccess)
                 return e;
         }
     }
-    if ((e = gemm64(n, m, n, G, n, 1, Q, m, 1, nullptr, Z, m, st)) != hipSuccess) return e;
-    if ((e = gemm64(m, m, n, Q, 1, m, Z, m, 1, nullptr, B, m, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gemm_rows, dim3(gr), dim3(256), 0, st, G, Q, Z, n, m);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gemm_tn_partial, dim3(chunks), dim3(256), 0, st, Q, Z, part, n, m, m);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)ceil_div(m * m, 256)), dim3(256), 0, st, part, chunks, m * m, B);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_eig_jacobi_lds(B, m, m, max_sweeps, lam, W, m, sweeps_out, ok_out, st)) != hipSuccess) return e;
-    return gemm64(n, m, m, Q, m, 1, W, m, 1, nullptr, V, m, st);
+    hipLaunchKernelGGL(k_gemm_small, dim3(gr), dim3(256), 0, st, Q, W, V, n, m, m);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------- rank select + factor
@@ -460,13 +582,16 @@ namespace {
 
 __global__ __launch_bounds__(256) void k_select_factor(SelectArgs a) {
     __shared__ int r_s;
+    __shared__ double red[17];
     __shared__ int sign_s[4096];
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     DevBook* bk = a.book;
+    // trace of G (fixed-order block sum)
+    double part = 0.0;
+    for (int i = tid; i < a.n; i += blockDim.x) part += a.G[(int64_t)i * a.n + i];
+    const double tr = block_sum(part, red);
     if (tid == 0) {
-        // trace of G in a fixed order
-        double tr = 0.0;
-        for (int i = 0; i < a.n; ++i) tr += a.G[(int64_t)i * a.n + i];
         if (a.pos == 0) {
             bk->norm2 = tr;
             bk->S = a.rtmss * a.eps2 * tr;
@@ -478,13 +603,14 @@ __global__ __launch_bounds__(256) void k_select_factor(SelectArgs a) {
         int r = a.n;
         double tail_r = 0.0;
         if (!a.subspace) {
-            // tail(r) = sum_{j >= r} lam_j, added from the smallest upward
+            // tail(r) = sum_{j >= r} lam_j, added from the smallest upward; the
+            // eigenvalues are not clamped, so rounding-level negative values of
+            // an FP32-accurate Gram matrix offset the positive ones
             double acc = 0.0;
             int best = a.n;
             double best_tail = 0.0;
             for (int j = a.n - 1; j >= 0; --j) {
-                // acc = tail at r = j + 1
-                if (j + 1 >= 1 && acc <= b) {
+                if (acc <= b) {  // acc = tail at r = j + 1
                     best = j + 1;
                     best_tail = acc;
                 }
@@ -532,18 +658,31 @@ __global__ __launch_bounds__(256) void k_select_factor(SelectArgs a) {
     __syncthreads();
     if (bk->need_dense) return;
     const int r = r_s;
-    // sign rule: largest-magnitude entry of each kept column positive (first row on ties)
-    for (int j = tid; j < r; j += blockDim.x) {
+    // sign rule: largest-magnitude entry of each kept column positive (first row on ties);
+    // one wave per column, lanes scan rows, then a fixed-order shuffle reduction
+    for (int j = wave; j < r; j += nw) {
         double best = -1.0;
+        int bi = 0x7fffffff;
         double val = 0.0;
-        for (int i = 0; i < a.n; ++i) {
+        for (int i = lane; i < a.n; i += 64) {
             const double v = a.V[(int64_t)i * a.ldv + j];
             if (fabs(v) > best) {
                 best = fabs(v);
+                bi = i;
                 val = v;
             }
         }
-        sign_s[j] = val < 0.0 ? -1 : 1;
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o);
+            const int oi = __shfl_xor(bi, o);
+            const double ov = __shfl_xor(val, o);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+                val = ov;
+            }
+        }
+        if (lane == 0) sign_s[j] = val < 0.0 ? -1 : 1;
     }
     __syncthreads();
     for (int64_t idx = tid; idx < (int64_t)a.n * r; idx += blockDim.x) {
@@ -557,9 +696,9 @@ __global__ __launch_bounds__(256) void k_select_factor(SelectArgs a) {
             const float f = (float)u;
             a.Mt32[t] = f;
             if (a.Mth) {
-                const __bf16 h = (__bf16)f;
-                a.Mth[t] = h;
-                a.Mtl[t] = (__bf16)(f - (float)h);
+                const __bf16 hh = (__bf16)f;
+                a.Mth[t] = hh;
+                a.Mtl[t] = (__bf16)(f - (float)hh);
             }
         }
     }
