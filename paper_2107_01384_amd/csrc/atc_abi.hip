@@ -126,6 +126,8 @@ struct SthosvdWs {
     void* buf[2];
     double* part;
     size_t part_cap;
+    double* dpart;   // exact-diagonal partials of the tiled Gram kernel
+    size_t dpart_cap;
     double* G;
     double* lam;
     double* V;
@@ -153,6 +155,8 @@ size_t carve_sthosvd(const atc_shape* s, char* base, SthosvdWs* w) {
     t.buf[1] = c.take(d > 2 ? (size_t)N * esz : 0);
     t.part_cap = part_capacity(nmax);
     t.part = (double*)c.take(t.part_cap);
+    t.dpart_cap = (size_t)512 * nmax * sizeof(double);
+    t.dpart = (double*)c.take(t.dpart_cap);
     t.G = (double*)c.take(n2 * 8);
     t.lam = (double*)c.take((size_t)nmax * 8);
     t.V = (double*)c.take(n2 * 8);
@@ -264,12 +268,22 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         const int k = order[i];
         const int64_t L = prod(cur, 0, k), R = prod(cur, k + 1, d);
         const int n = (int)cur[k];
-        const GramPlan gp = gram_plan(prec, L, n, n, R, true, w.part_cap);
-        HIP_TRY(mark(i, 0));
-        HIP_TRY(launch_gram(prec, gp, src, src, w.part, st));
-        HIP_TRY(mark(i, 1));
-        HIP_TRY(launch_gram_reduce(gp, w.part, w.G, st));
-        HIP_TRY(mark(i, 2));
+        GramKcPlan kp{};
+        if (gram_kc_applicable(prec, R)) kp = gram_kc_plan(prec, L, n, R, w.part_cap, w.dpart_cap);
+        if (kp.ok) {
+            HIP_TRY(mark(i, 0));
+            HIP_TRY(launch_gram_kc(prec, kp, (const float*)src, (float*)w.part, w.dpart, st));
+            HIP_TRY(mark(i, 1));
+            HIP_TRY(launch_gram_kc_reduce(kp, (const float*)w.part, w.dpart, w.G, st));
+            HIP_TRY(mark(i, 2));
+        } else {
+            const GramPlan gp = gram_plan(prec, L, n, n, R, true, w.part_cap);
+            HIP_TRY(mark(i, 0));
+            HIP_TRY(launch_gram(prec, gp, src, src, w.part, st));
+            HIP_TRY(mark(i, 1));
+            HIP_TRY(launch_gram_reduce(gp, w.part, w.G, st));
+            HIP_TRY(mark(i, 2));
+        }
 
         SelectArgs sa{};
         sa.G = w.G;

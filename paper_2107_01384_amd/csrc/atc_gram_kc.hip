@@ -1,0 +1,315 @@
+// Gram matrix (SYRK) of an (L, n, R) view whose R index is contiguous and a
+// multiple of 4 -- the layout of every mode but the last of a row-major
+// tensor, and where almost all of the Gram work of an ST-HOSVD is done (the
+// first mode sees the whole input).
+//
+//   G[a, b] = sum_{l, r} X[l, a, r] X[l, b, r]      (Section 3.2, Algorithm 1)
+//
+// Work decomposition: 128 x 128 output tiles of the upper triangle times
+// split-K ranges.  Block b runs on XCD b % 8; the tiles of one split are
+// given consecutive slots of the same XCD, so the rows of one K slab are
+// fetched from HBM once and served to the other tiles of that split from
+// that XCD's L2.  Each workgroup: 4 waves, each owning a 64 x 64 quarter made
+// of 2 x 2 blocks of 32 x 32 MFMAs; K advances in steps of 32 with the next
+// step's global loads (float4, coalesced along R) held in registers while the
+// current step is multiplied out of LDS.
+//   PREC_BF16X3: every loaded float is split into bf16 hi + lo on the way to
+//     LDS; three v_mfma_f32_32x32x16_bf16 per 32 x 32 x 16 (hi*hi, hi*lo,
+//     lo*hi); the diagonal is replaced by the exact sum of squares of the
+//     loaded floats accumulated in FP64 (the dropped lo*lo would bias it).
+//   PREC_F32: v_mfma_f32_32x32x2f32, same diagonal treatment.
+// A workgroup accumulates one split (a few thousand terms) in FP32 and
+// writes an FP32 partial tile; the reduction adds the splits in FP64 in a
+// fixed order.
+#include "atc_internal.hpp"
+
+namespace atc {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int KC_BM = 128;
+constexpr int KC_BK = 32;
+constexpr int KC_PAD_BF = 8;   // bf16 row stride 40 (80 bytes: 16-byte aligned fragment reads)
+constexpr int KC_PAD_F = 1;
+
+__device__ inline void kc_decode_pair(int pair, int tiles, int& ti, int& tj) {
+    int p = pair, i = 0;
+    while (p >= tiles - i) {
+        p -= tiles - i;
+        ++i;
+    }
+    ti = i;
+    tj = i + p;
+}
+
+__host__ __device__ inline int kc_pair_index(int ti, int tj, int tiles) {
+    return ti * tiles - ti * (ti - 1) / 2 + (tj - ti);
+}
+
+template <int P> struct KcSmem;
+template <> struct KcSmem<PREC_BF16X3> {
+    __bf16 ah[KC_BM][KC_BK + KC_PAD_BF];
+    __bf16 al[KC_BM][KC_BK + KC_PAD_BF];
+    __bf16 bh[KC_BM][KC_BK + KC_PAD_BF];
+    __bf16 bl[KC_BM][KC_BK + KC_PAD_BF];
+};
+template <> struct KcSmem<PREC_F32> {
+    float a[KC_BM][KC_BK + KC_PAD_F];
+    float b[KC_BM][KC_BK + KC_PAD_F];
+};
+
+// 32 x 32 MFMA result layout: register v of lane l holds column l % 32 of
+// row 8 * (v / 4) + 4 * (l / 32) + v % 4.
+__device__ inline int mfma32_row(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+
+template <int P>
+__device__ inline void kc_store(KcSmem<P>& sm, bool second, int row, int col, const float4& v) {
+    if constexpr (P == PREC_BF16X3) {
+        const float x[4] = {v.x, v.y, v.z, v.w};
+        union {
+            __bf16 h[4];
+            uint2 u;
+        } hi, lo;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            hi.h[e] = (__bf16)x[e];
+            lo.h[e] = (__bf16)(x[e] - (float)hi.h[e]);
+        }
+        *reinterpret_cast<uint2*>(second ? &sm.bh[row][col] : &sm.ah[row][col]) = hi.u;
+        *reinterpret_cast<uint2*>(second ? &sm.bl[row][col] : &sm.al[row][col]) = lo.u;
+    } else {
+        float* p = second ? &sm.b[row][col] : &sm.a[row][col];
+        p[0] = v.x;
+        p[1] = v.y;
+        p[2] = v.z;
+        p[3] = v.w;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_gram_kc(const float* __restrict__ X, int n, int64_t L, int64_t R,
+                                                 int64_t steps, int nsplit, int tiles, int npairs,
+                                                 float* __restrict__ part, double* __restrict__ dpart) {
+    __shared__ KcSmem<P> sm;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    // XCD-aware block -> (pair, split): the pairs of one split share an XCD
+    const int b = blockIdx.x;
+    const int xcd = b & 7, slot = b >> 3;
+    const int pair = slot % npairs;
+    const int split = (slot / npairs) * 8 + xcd;
+    if (split >= nsplit) return;
+    int ti, tj;
+    kc_decode_pair(pair, tiles, ti, tj);
+    const bool diag = ti == tj;
+    const int row0 = ti * KC_BM, col0 = tj * KC_BM;
+    const int64_t s0 = steps * split / nsplit, s1 = steps * (split + 1) / nsplit;
+    const int64_t spl = ceil_div(R, KC_BK);
+
+    // load slots: 8 threads per row (4 floats each), rows lr + 32 i
+    const int lr = tid >> 3, lc = (tid & 7) * 4;
+    float4 ra[4], rb[4];
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto load = [&](int64_t s) {
+        const int64_t l = s / spl;
+        const int64_t r = (s - l * spl) * KC_BK + lc;
+        const bool rok = r < R;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ra_row = row0 + lr + 32 * i;
+            ra[i] = (rok && ra_row < n) ? *reinterpret_cast<const float4*>(X + (l * n + ra_row) * R + r) : zero4;
+            if (!diag) {
+                const int rb_row = col0 + lr + 32 * i;
+                rb[i] = (rok && rb_row < n) ? *reinterpret_cast<const float4*>(X + (l * n + rb_row) * R + r) : zero4;
+            }
+        }
+    };
+
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    // two-level FP32 accumulation: the MFMA accumulators hold a chunk of
+    // FLUSH_TERMS terms, chunk sums are added into `tot` (fewer, larger
+    // roundings than one long MFMA accumulation; half the registers of FP64)
+    f32x16 acc[2][2], tot[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                acc[a][c][v] = 0.f;
+                tot[a][c][v] = 0.f;
+            }
+    double dsq[4] = {0.0, 0.0, 0.0, 0.0};
+    constexpr int FLUSH_STEPS = FLUSH_TERMS / KC_BK;
+    int since_flush = 0;
+    auto flush = [&]() {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                tot[a][c] += acc[a][c];
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[a][c][v] = 0.f;
+            }
+    };
+
+    if (s0 < s1) load(s0);
+    for (int64_t s = s0; s < s1; ++s) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            kc_store<P>(sm, false, lr + 32 * i, lc, ra[i]);
+            if (!diag) kc_store<P>(sm, true, lr + 32 * i, lc, rb[i]);
+            if (diag) {
+                const double x0 = ra[i].x, x1 = ra[i].y, x2 = ra[i].z, x3 = ra[i].w;
+                dsq[i] += x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3;
+            }
+        }
+        __syncthreads();
+        if (s + 1 < s1) load(s + 1);
+#pragma unroll
+        for (int sl = 0; sl < KC_BK / 16; ++sl) {
+            if constexpr (P == PREC_BF16X3) {
+                const int kq = sl * 16 + 8 * (lane >> 5);
+                bf16x8 ah[2], al[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int rr = wr + a * 32 + (lane & 31);
+                    ah[a] = *reinterpret_cast<const bf16x8*>(&sm.ah[rr][kq]);
+                    al[a] = *reinterpret_cast<const bf16x8*>(&sm.al[rr][kq]);
+                }
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int cc = wc + c * 32 + (lane & 31);
+                    const bf16x8 bh = diag ? *reinterpret_cast<const bf16x8*>(&sm.ah[cc][kq])
+                                           : *reinterpret_cast<const bf16x8*>(&sm.bh[cc][kq]);
+                    const bf16x8 bl = diag ? *reinterpret_cast<const bf16x8*>(&sm.al[cc][kq])
+                                           : *reinterpret_cast<const bf16x8*>(&sm.bl[cc][kq]);
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh, acc[a][c], 0, 0, 0);
+                        acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl, acc[a][c], 0, 0, 0);
+                        acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh, acc[a][c], 0, 0, 0);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < 16; kk += 2) {
+                    const int k = sl * 16 + kk + (lane >> 5);
+                    float av[2], bv[2];
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) av[a] = sm.a[wr + a * 32 + (lane & 31)][k];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+                        bv[c] = diag ? sm.a[wc + c * 32 + (lane & 31)][k] : sm.b[wc + c * 32 + (lane & 31)][k];
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c)
+                            acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a], bv[c], acc[a][c], 0, 0, 0);
+                }
+            }
+        }
+        if (++since_flush == FLUSH_STEPS) {
+            since_flush = 0;
+            flush();
+        }
+        __syncthreads();
+    }
+    flush();
+    float* out = part + ((int64_t)split * npairs + pair) * (KC_BM * KC_BM);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = wr + a * 32 + mfma32_row(lane, v);
+                const int j = wc + c * 32 + (lane & 31);
+                out[i * KC_BM + j] = tot[a][c][v];
+            }
+    if (diag) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double s = dsq[i];
+            s += __shfl_xor(s, 1);
+            s += __shfl_xor(s, 2);
+            s += __shfl_xor(s, 4);
+            const int row = row0 + lr + 32 * i;
+            if ((tid & 7) == 0 && row < n) dpart[(int64_t)split * n + row] = s;
+        }
+    }
+}
+
+__global__ void k_gram_kc_reduce(const float* __restrict__ part, const double* __restrict__ dpart, int nsplit,
+                                 int npairs, int tiles, int n, double* __restrict__ G) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * n) return;
+    const int a = (int)(idx / n), b = (int)(idx % n);
+    if (a > b) return;
+    double s = 0.0;
+    if (a == b) {
+        for (int sp = 0; sp < nsplit; ++sp) s += dpart[(int64_t)sp * n + a];
+    } else {
+        const int ti = a / KC_BM, tj = b / KC_BM;
+        const int pair = kc_pair_index(ti, tj, tiles);
+        const int i = a % KC_BM, j = b % KC_BM;
+        for (int sp = 0; sp < nsplit; ++sp)
+            s += (double)part[((int64_t)sp * npairs + pair) * (KC_BM * KC_BM) + i * KC_BM + j];
+    }
+    G[(int64_t)a * n + b] = s;
+    G[(int64_t)b * n + a] = s;
+}
+
+}  // namespace
+
+bool gram_kc_applicable(int prec, int64_t R) { return prec != PREC_F64 && R >= KC_BK && R % 4 == 0; }
+
+GramKcPlan gram_kc_plan(int prec, int64_t L, int n, int64_t R, size_t part_capacity_bytes,
+                        size_t dpart_capacity_bytes) {
+    (void)prec;
+    GramKcPlan g{};
+    g.L = L;
+    g.R = R;
+    g.n = n;
+    g.tiles = (int)ceil_div(n, KC_BM);
+    g.npairs = g.tiles * (g.tiles + 1) / 2;
+    g.steps = L * ceil_div(R, KC_BK);
+    // about two workgroups per CU in one wave of dispatch, a multiple of 8 splits
+    int64_t ns = (512 / g.npairs) / 8 * 8;
+    if (ns < 8) ns = 8;
+    const int64_t by_steps = (g.steps / 16) / 8 * 8;  // at least 16 steps per split
+    if (ns > by_steps) ns = by_steps < 8 ? 8 : by_steps;
+    const size_t tile_bytes = (size_t)KC_BM * KC_BM * sizeof(float);
+    while (ns > 8 && ((size_t)ns * g.npairs * tile_bytes > part_capacity_bytes ||
+                      (size_t)ns * n * sizeof(double) > dpart_capacity_bytes))
+        ns -= 8;
+    g.nsplit = (int)ns;
+    g.part_bytes = (size_t)ns * g.npairs * tile_bytes;
+    g.dpart_bytes = (size_t)ns * n * sizeof(double);
+    g.ok = g.part_bytes <= part_capacity_bytes && g.dpart_bytes <= dpart_capacity_bytes;
+    return g;
+}
+
+hipError_t launch_gram_kc(int prec, const GramKcPlan& g, const float* X, float* part, double* dpart,
+                          hipStream_t st) {
+    if (!g.ok) return hipErrorInvalidValue;
+    const int blocks = g.nsplit * g.npairs;  // nsplit is a multiple of 8
+    if (prec == PREC_BF16X3)
+        hipLaunchKernelGGL(k_gram_kc<PREC_BF16X3>, dim3(blocks), dim3(256), 0, st, X, g.n, g.L, g.R, g.steps,
+                           g.nsplit, g.tiles, g.npairs, part, dpart);
+    else
+        hipLaunchKernelGGL(k_gram_kc<PREC_F32>, dim3(blocks), dim3(256), 0, st, X, g.n, g.L, g.R, g.steps, g.nsplit,
+                           g.tiles, g.npairs, part, dpart);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram_kc_reduce(const GramKcPlan& g, const float* part, const double* dpart, double* G,
+                                 hipStream_t st) {
+    const int64_t total = (int64_t)g.n * g.n;
+    hipLaunchKernelGGL(k_gram_kc_reduce, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, part, dpart, g.nsplit,
+                       g.npairs, g.tiles, g.n, G);
+    return hipGetLastError();
+}
+
+}  // namespace atc

@@ -85,6 +85,25 @@ hipError_t launch_gram(int prec, const GramPlan& g, const void* X, const void* Y
 // symmetric plans write both triangles from the upper one.
 hipError_t launch_gram_reduce(const GramPlan& g, const double* part, double* C, hipStream_t st);
 
+// Gram matrix of a float32 (L, n, R) view with contiguous R (R >= 32, R % 4 == 0):
+// 128 x 128 MFMA tiles, split-K, FP32 partial tiles + FP64 exact diagonal.
+struct GramKcPlan {
+    int64_t L, R;
+    int n;
+    int tiles, npairs;
+    int64_t steps;
+    int nsplit;      // multiple of 8 (one group per XCD)
+    size_t part_bytes, dpart_bytes;
+    bool ok;
+};
+bool gram_kc_applicable(int prec, int64_t R);
+GramKcPlan gram_kc_plan(int prec, int64_t L, int n, int64_t R, size_t part_capacity_bytes,
+                        size_t dpart_capacity_bytes);
+hipError_t launch_gram_kc(int prec, const GramKcPlan& g, const float* X, float* part, double* dpart,
+                          hipStream_t st);
+hipError_t launch_gram_kc_reduce(const GramKcPlan& g, const float* part, const double* dpart, double* G,
+                                 hipStream_t st);
+
 // Mode product Z = M x_k Y on the (L, n, R) view: Z[l, j, r] = sum_i M[j, i] Y[l, i, r].
 // M is m_out x n row-major: FP64 for PREC_F64, FP32 for PREC_F32, and for
 // PREC_BF16X3 two bf16 arrays (Mh, Ml) holding hi/lo of the FP32 matrix.
