@@ -95,6 +95,111 @@ def cpu_baseline(x_np, eps):
     }
 
 
+def bench_batched(args):
+    """4096 blocks, sizes uniform in {16,24,32,48,64} per mode, eps 1e-3, one persistent
+    launch replayed from a HIP graph; value = input GB/s over the replays."""
+    import numpy as np
+    import torch
+
+    import paper_2107_01384_amd as atc
+    import synth
+
+    dims = synth.batch_dims(4096, seed=2024)
+    arena_np, _ = synth.batch_arena(dims, 10_000)
+    arena = torch.from_numpy(arena_np).cuda()
+    plan = atc.BatchPlan(dims, args.eps, "bf16x3")
+    core, fac, res, ws = plan.allocate()
+    choice = plan.autotune(arena, core, fac, res, ws, reps=3)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.capture(arena, core, fac, res, ws, stream=stream)
+        for _ in range(args.warmup):
+            plan.replay(stream=stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.replay(stream=stream)
+        stream.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    recs = plan.results(res)
+    line = {"metric": "batched ST-HOSVD input GB/s at rel err 1e-3 (4096 blocks, one persistent launch)",
+            "value": round(arena_np.nbytes / (ms * 1e-3) / 1e9, 3), "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
+            "config": {"workload": "4096 float32 blocks, modes uniform in {16,24,32,48,64}, blob+wave fields, "
+                                   "eps 1e-3, HIP graph replay", "input_mb": round(arena_np.nbytes / 1e6, 1)},
+            "autotune_choice": choice, "status_ok": bool(np.all(recs["status"] == 0)),
+            "mean_ranks": [float(v) for v in recs["ranks"].mean(axis=0)]}
+    print(json.dumps(line), flush=True)
+
+
+def bench_recon(args):
+    """Tucker reconstruction 128^3 x 64 from a 32^3 x 16 core (float32), forward and adjoint."""
+    import numpy as np
+    import torch
+
+    import paper_2107_01384_amd as atc
+    import synth
+
+    core_np, facs_np, y_np = synth.recon_model()
+    core = torch.from_numpy(core_np).float().cuda()
+    facs = [torch.from_numpy(f).float().cuda() for f in facs_np]
+    y = torch.from_numpy(y_np).cuda()
+
+    def fwd():
+        return atc.reconstruct(core, facs)
+
+    xh = fwd()
+    dx = xh - y
+    for _ in range(args.warmup):
+        fwd()
+        atc.reconstruct_backward(core, facs, dx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd()
+    torch.cuda.synchronize()
+    ms_f = (time.perf_counter() - t0) * 1e3 / args.steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        atc.reconstruct_backward(core, facs, dx)
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - t0) * 1e3 / args.steps
+    out_bytes = xh.numel() * 4
+    line = {"metric": "Tucker reconstruction output GB/s (forward) and adjoint ms", "value": round(out_bytes / (ms_f * 1e-3) / 1e9, 3),
+            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_f, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "X~ = G x U0..U3, G 32x32x32x16, X~ 128x128x128x64 float32"},
+            "backward_ms": round(ms_b, 4), "backward_input_gbs": round(out_bytes / (ms_b * 1e-3) / 1e9, 3)}
+    print(json.dumps(line), flush=True)
+
+
+def bench_fourway(args):
+    """200 x 500 x 500 x 13 float32 (13 independent fields stacked last), eps 1e-3, bf16x3."""
+    import torch
+
+    import paper_2107_01384_amd as atc
+    import synth
+
+    x_np = synth.field4()
+    x = torch.from_numpy(x_np).cuda()
+    res = {}
+    for prec in ("bf16x3", "native"):
+        ws = torch.empty(atc.sthosvd_workspace_size(list(x.shape), torch.float32, precision=prec), dtype=torch.uint8,
+                         device="cuda")
+        ms, rr = time_path(atc, torch, x, args.eps, prec, args.steps, args.warmup, ws, None)
+        res[prec] = (ms, rr[-1])
+    ms, t = res["bf16x3"]
+    line = {"metric": "ST-HOSVD input GB/s at rel err 1e-3 (4-way)", "value": round(x_np.nbytes / (ms * 1e-3) / 1e9, 3),
+            "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
+            "config": {"workload": "200x500x500x13 float32, 13 independent fields stacked on the last mode, eps 1e-3"},
+            "ranks": t.ranks, "eig_path": t.eig_path, "rel_error_achieved": rel_error_gpu(atc, torch, x, t),
+            "phase_ms": {k: [round(v, 4) for v in vals] for k, vals in t.phase_ms.items()},
+            "fp32_ms_per_step": round(res["native"][0], 4), "fp32_ranks": res["native"][1].ranks}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +207,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic field")
     ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--workload", default="field", choices=["field", "batched", "recon", "fourway"],
+                    help="field: the 512^3 headline (default); the others print their own line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison path")
     args = ap.parse_args()
@@ -109,6 +216,9 @@ def main():
         print("bench.py measures one GPU only: the ST-HOSVD here runs on a single MI355X "
               "(multi-GPU sharding is a design note, not built); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "field":
+        {"batched": bench_batched, "recon": bench_recon, "fourway": bench_fourway}[args.workload](args)
+        return
 
     import numpy as np
     import torch
