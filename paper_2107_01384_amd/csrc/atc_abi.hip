@@ -161,7 +161,9 @@ size_t carve_sthosvd(const atc_shape* s, char* base, SthosvdWs* w) {
     t.lam = (double*)c.take((size_t)nmax * 8);
     t.V = (double*)c.take(n2 * 8);
     t.jac = (double*)c.take(nmax > 64 ? (size_t)2 * mpad * mpad * 8 : 0);
-    t.sub = (double*)c.take(nmax > 64 ? subspace_ws_doubles(nmax, SUBSPACE_M) * 8 : 0);
+    t.sub = (double*)c.take(nmax > 64 ? std::max(subspace_ws_doubles(nmax, SUBSPACE_M),
+                                                 subspace32_ws_doubles(std::min(nmax, 512))) * 8
+                                      : 0);
     t.Mt64 = (double*)c.take(s->dtype == ATC_F64 ? n2 * 8 : 0);
     t.Mt32 = (float*)c.take(s->dtype == ATC_F32 ? n2 * 4 : 0);
     t.Mth = (__bf16*)c.take(s->dtype == ATC_F32 ? n2 * 2 : 0);
@@ -317,7 +319,15 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         const bool dense_first = n <= 64 || opts->eig_path == 1 || (f64 && opts->eig_path != 2);
         int attempt = dense_first ? 2 : 0;
         for (;; ++attempt) {
-            if (attempt < 2) {
+            bool selected = false;
+            if (attempt == 0 && subspace32_available(n)) {
+                sa.ldv = 32;
+                sa.ncand = 32;
+                sa.subspace = 1;
+                paths[k] = 2;
+                HIP_TRY(run_subspace32_select(w.G, n, SUBSPACE_ITERS, max_sweeps, w.sub, sa, st));
+                selected = true;
+            } else if (attempt < 2) {
                 const int m = attempt == 0 ? std::min(SUBSPACE_M / 2, n) : std::min(SUBSPACE_M, n);
                 HIP_TRY(run_subspace_eig(w.G, n, m, SUBSPACE_ITERS, max_sweeps, w.sub, w.lam, w.V, sweeps_dev, ok_dev,
                                          st));
@@ -338,7 +348,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
                 sa.subspace = 0;
                 paths[k] = 1;
             }
-            HIP_TRY(launch_select_factor(sa, st));
+            if (!selected) HIP_TRY(launch_select_factor(sa, st));
             HIP_TRY(hipMemcpyAsync(&hb, w.book, sizeof(DevBook), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             if (hb.status != 0) return fail((atc_status)hb.status, "input |A|^2 is not finite");

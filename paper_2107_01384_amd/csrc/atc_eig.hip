@@ -580,10 +580,10 @@ hipError_t run_subspace_eig(const double* G, int n, int m, int iters, int max_sw
 // ------------------------------------------------------- rank select + factor
 namespace {
 
-__global__ __launch_bounds__(256) void k_select_factor(SelectArgs a) {
-    __shared__ int r_s;
-    __shared__ double red[17];
-    __shared__ int sign_s[4096];
+// Rank choice (Section 4.1.3), sign rule and factor output for one mode, run
+// by a whole workgroup (any multiple of 64 threads).  red: 17 doubles, sign_s:
+// n ints, r_s: 1 int, all in LDS.
+__device__ __forceinline__ void select_factor_body(const SelectArgs& a, double* red, int* sign_s, int& r_s) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     DevBook* bk = a.book;
@@ -704,6 +704,578 @@ __global__ __launch_bounds__(256) void k_select_factor(SelectArgs a) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_select_factor(SelectArgs a) {
+    __shared__ int r_s;
+    __shared__ double red[17];
+    __shared__ int sign_s[4096];
+    select_factor_body(a, red, sign_s, r_s);
+}
+
+// ------------------------------------------- subspace path, m = 32, n <= 512
+// Orthogonal iteration with a Rayleigh-Ritz finish:
+//   Y0 = G Omega          split-K FP64 product on many workgroups (Omega is a
+//                         counter-based pseudo-random matrix made in the kernel)
+//   Q0 = orth(Y0)         one shifted Cholesky QR pass, then two plain ones, in
+//                         one workgroup (the columns of Y0 spread like the
+//                         eigenvalues of G, far beyond what plain Cholesky QR
+//                         can orthonormalise)
+//   Q1 = orth(G Q0), Z = G Q1
+//   B = Q1^T Z = W diag(theta) W^T (one-wavefront Jacobi), V = Q1 W, then the
+//   rank choice, sign rule and factor output of select_factor_body.
+constexpr int S32 = 32;
+constexpr int GX_ROWS = 8;    // rows of G per workgroup of k_gemm_gx
+constexpr int GX_SPLIT = 4;   // K chunks; the consumer adds the partial products
+constexpr int OT = 512;       // threads of the orthonormalisation workgroup
+constexpr int OW = OT / 64;   // its wavefronts
+constexpr int RT = 512;       // threads of the Rayleigh-Ritz workgroup
+constexpr int RW = RT / 64;
+constexpr size_t ORTH_LDS = (size_t)(OW * S32 * S32 + 2 * S32 * (S32 + 1)) * sizeof(double);
+constexpr size_t RR_LDS = (size_t)(RW * S32 * S32 + 2 * S32 * (S32 + 1)) * sizeof(double);
+
+// part[s] (n x 32) = G[:, K_s] X[K_s, :], K_s the s-th of GX_SPLIT chunks of
+// [0, n).  X == nullptr: X[k][j] = hash_unit((32 k + j) * C + salt).  One
+// wavefront per workgroup; lane = (row pair, column pair).
+__global__ __launch_bounds__(64) void k_gemm_gx(const double* __restrict__ G, const double* __restrict__ X,
+                                                double* __restrict__ part, int n, uint64_t salt) {
+    const int lane = threadIdx.x;
+    const int q = lane >> 4, c = (lane & 15) * 2;
+    const int r0 = blockIdx.x * GX_ROWS + 2 * q;
+    const int s = blockIdx.y;
+    const int chunk = (int)ceil_div(n, GX_SPLIT);
+    const int k0 = min(n, s * chunk), k1 = min(n, k0 + chunk);
+    const double* ga = G + (int64_t)min(r0, n - 1) * n;
+    const double* gb = G + (int64_t)min(r0 + 1, n - 1) * n;
+    double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
+    if (X) {
+#pragma unroll 4
+        for (int k = k0; k < k1; ++k) {
+            const double x0 = X[(int64_t)k * S32 + c], x1 = X[(int64_t)k * S32 + c + 1];
+            const double g0 = ga[k], g1 = gb[k];
+            a00 += g0 * x0;
+            a01 += g0 * x1;
+            a10 += g1 * x0;
+            a11 += g1 * x1;
+        }
+    } else {
+#pragma unroll 4
+        for (int k = k0; k < k1; ++k) {
+            const uint64_t key = (uint64_t)k * S32 + c;
+            const double x0 = hash_unit(key * 0x2545F4914F6CDD1Dull + salt);
+            const double x1 = hash_unit((key + 1) * 0x2545F4914F6CDD1Dull + salt);
+            const double g0 = ga[k], g1 = gb[k];
+            a00 += g0 * x0;
+            a01 += g0 * x1;
+            a10 += g1 * x0;
+            a11 += g1 * x1;
+        }
+    }
+    double* out = part + (int64_t)s * n * S32;
+    if (r0 < n) {
+        out[(int64_t)r0 * S32 + c] = a00;
+        out[(int64_t)r0 * S32 + c + 1] = a01;
+    }
+    if (r0 + 1 < n) {
+        out[(int64_t)(r0 + 1) * S32 + c] = a10;
+        out[(int64_t)(r0 + 1) * S32 + c + 1] = a11;
+    }
+}
+
+// Orders LDS accesses between the lanes of one wavefront (a wavefront's LDS
+// operations complete in issue order; this keeps the compiler from moving them).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The value of v held by lane `src` (uniform), for every lane.
+__device__ inline double lane_bcast(double v, int src) {
+    const uint64_t u = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, src);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), src);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// 1 / sqrt(z) to working precision: hardware-assisted estimate plus one Newton step.
+__device__ inline double rsqrt_nr(double z) {
+    double r = rsqrt(z);
+    return r * (1.5 - 0.5 * z * r * r);
+}
+
+// Row r of an n x 32 matrix held as NP partial arrays spaced n x 32 apart
+// (their sum), element c.
+template <int NP>
+__device__ __forceinline__ double parts_at(const double* __restrict__ X, int64_t ps, int64_t off) {
+    double v = X[off];
+#pragma unroll
+    for (int s = 1; s < NP; ++s) v += X[s * ps + off];
+    return v;
+}
+
+// C[32][33] (LDS) = P^T Y for n x 32 row-major P and Y (global; P the sum of
+// NPP partial arrays, Y of NPY, spaced n x 32 apart), FP64, fixed summation
+// order; P == Y with NPP == NPY gives a Gram matrix from one set of loads.
+// Each wavefront accumulates the four 16 x 16 blocks of C with
+// v_mfma_f64_16x16x4f64 over groups of four rows (rows 4w, 4w + 4 NW, ...; four
+// groups' loads in flight), every element loaded once per wavefront; the NW
+// partial products pass through part_lds and are added in wavefront order.
+template <int NW, int NPP, int NPY>
+__device__ __forceinline__ void cross32(const double* __restrict__ P, const double* __restrict__ Y, int n,
+                                        double* part_lds, double (*C)[S32 + 1]) {
+    constexpr int UNR = 4;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kr = lane >> 4, cl = lane & 15;
+    const int64_t ps = (int64_t)n * S32;
+    const bool gram = (P == Y) && NPP == NPY;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int g0 = 4 * wave; g0 < n; g0 += 4 * NW * UNR) {
+        double pa[UNR][2], yb[UNR][2];
+#pragma unroll
+        for (int t = 0; t < UNR; ++t) {
+            const int r = g0 + 4 * NW * t + kr;
+            const double m = r < n ? 1.0 : 0.0;
+            const int64_t off = (int64_t)(r < n ? r : n - 1) * S32 + cl;
+            pa[t][0] = m * parts_at<NPP>(P, ps, off);
+            pa[t][1] = m * parts_at<NPP>(P, ps, off + 16);
+            if (gram) {
+                yb[t][0] = pa[t][0];
+                yb[t][1] = pa[t][1];
+            } else {
+                yb[t][0] = m * parts_at<NPY>(Y, ps, off);
+                yb[t][1] = m * parts_at<NPY>(Y, ps, off + 16);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < UNR; ++t)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v)
+                    acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[t][u], yb[t][v], acc[u][v], 0, 0, 0);
+    }
+    double* mine = part_lds + wave * (S32 * S32);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                mine[(16 * u + mfma16_row<PREC_F64>(lane, e)) * S32 + 16 * v + cl] = acc[u][v][e];
+    __syncthreads();
+    for (int e = tid; e < S32 * S32; e += NW * 64) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += part_lds[w * (S32 * S32) + e];
+        C[e >> 5][e & 31] = t;
+    }
+    __syncthreads();
+}
+
+// Upper Cholesky factor R of C (32 x 32 in LDS, symmetric; R overwrites the
+// upper triangle) and its inverse, by one wavefront.  Lane b (mod 32) owns
+// column b; the two half-wavefronts split the rows of each update; loads go
+// out eight at a time before the stores.  Rinv (LDS) receives R^{-1} (upper
+// triangular, zeros below), rows from the bottom.  Returns false (on every
+// lane) when a pivot is not positive and finite.  spare: 64 doubles of LDS.
+__device__ __forceinline__ bool chol_inv32_wave(double (*C)[S32 + 1], double (*Rinv)[S32 + 1], double* invd,
+                                                double* spare) {
+    const int lane = threadIdx.x & 63, b = lane & 31, h = lane >> 5;
+    for (int j = 0; j < S32; ++j) {
+        const double d = C[j][j];
+        if (!(d > 0.0 && d < INFINITY)) return false;
+        const double r = rsqrt_nr(d);
+        const double rjb = (b == j) ? d * r : C[j][b] * r;  // R[j][b] for b >= j
+        wave_sync();
+        if (h == 0 && b >= j) C[j][b] = rjb;
+        if (lane == 0) invd[j] = r;
+        wave_sync();
+        // C[a][b] -= R[j][a] R[j][b] for j < a <= b; half h takes a = j + 1 + h + 2t
+        for (int a0 = j + 1 + h; a0 < S32; a0 += 16) {
+            double ra[8], ca[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int aa = min(a0 + 2 * t, S32 - 1);
+                ra[t] = C[j][aa];
+                ca[t] = C[aa][b];
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int aa = a0 + 2 * t;
+                // branch-free store: entries outside the triangle go to the spare slot
+                double* dst = (aa < S32 && aa <= b) ? &C[aa][b] : &spare[lane];
+                *dst = ca[t] - ra[t] * rjb;
+            }
+        }
+        wave_sync();
+    }
+    // R X = I: X[i][b] = (delta_ib - sum_{k > i} R[i][k] X[k][b]) / R[i][i]
+    for (int i = S32 - 1; i >= 0; --i) {
+        double t = 0.0;
+        for (int k0 = i + 1 + h; k0 < S32; k0 += 16) {
+            double rk[8], xk[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int k = k0 + 2 * q;
+                const int kk = min(k, S32 - 1);
+                rk[q] = k < S32 ? C[i][kk] : 0.0;
+                xk[q] = Rinv[kk][b];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) t += rk[q] * xk[q];
+        }
+        t += __shfl_xor(t, 32);
+        const double inv = invd[i];
+        if (h == 0) Rinv[i][b] = (i == b) ? inv : ((b > i) ? -t * inv : 0.0);
+        wave_sync();
+    }
+    return true;
+}
+
+// One Cholesky QR pass: Y <- X R^{-1}, R^T R = X^T X (+ shift I), X the sum of
+// NP partial arrays of which Y is the first (in place).  Returns false,
+// uniformly, on a failed pivot.  The product X R^{-1} runs on
+// v_mfma_f64_16x16x4f64, 16-row tiles per wavefront, R^{-1} held in registers.
+template <int NP>
+__device__ __forceinline__ bool cholqr_pass(double* __restrict__ Y, int n, bool shifted, double* part_lds,
+                                            double (*C)[S32 + 1], double (*Rinv)[S32 + 1], double* invd, double* spare,
+                                            int* ok_s) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    cross32<OW, NP, NP>(Y, Y, n, part_lds, C);
+    if (tid < 64) {
+        if (shifted) {
+            // shift 11 (n m + m (m + 1)) u |Y|_F^2, an upper bound of the
+            // shifted Cholesky QR choice (it takes |Y|_2^2)
+            double fro = 0.0;
+            for (int j = 0; j < S32; ++j) fro += C[j][j];
+            const double sh = 11.0 * ((double)n * S32 + (double)S32 * (S32 + 1)) * 0x1p-53 * fro;
+            wave_sync();
+            if (tid < S32) C[tid][tid] += sh;
+            wave_sync();
+        }
+        const bool ok = chol_inv32_wave(C, Rinv, invd, spare);
+        if (tid == 0) *ok_s = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!*ok_s) return false;
+    const int kr = lane >> 4, cl = lane & 15;
+    const int64_t ps = (int64_t)n * S32;
+    double bop[8][2];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+        bop[ks][0] = Rinv[4 * ks + kr][cl];
+        bop[ks][1] = Rinv[4 * ks + kr][16 + cl];
+    }
+    for (int r0 = 16 * wave; r0 < n; r0 += 16 * OW) {
+        const int ra = r0 + cl;
+        const int64_t rowoff = (int64_t)(ra < n ? ra : n - 1) * S32;
+        double aop[8];
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) aop[ks] = parts_at<NP>(Y, ps, rowoff + 4 * ks + kr);
+        f64x4 acc0 = f64x4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[ks], bop[ks][0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[ks], bop[ks][1], acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = r0 + mfma16_row<PREC_F64>(lane, e);
+            if (r < n) {
+                Y[(int64_t)r * S32 + cl] = acc0[e];
+                Y[(int64_t)r * S32 + 16 + cl] = acc1[e];
+            }
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
+// Basis of the columns of Y = sum of nparts arrays (n x 32 each, spaced n x 32
+// apart), written over the first array: one shifted Cholesky QR pass (a
+// well-conditioned basis of the same span), and with full != 0 two more plain
+// passes (orthonormal to working precision).  *ok = 1 on success (first != 0)
+// or *ok &= success (first == 0).
+__global__ __launch_bounds__(OT) void k_orth32(double* __restrict__ Y, int nparts, int n, int full, int first,
+                                               int32_t* __restrict__ ok) {
+    extern __shared__ double lds[];
+    double* part_lds = lds;
+    double(*C)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + OW * S32 * S32);
+    double(*Rinv)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + OW * S32 * S32 + S32 * (S32 + 1));
+    __shared__ double invd[S32];
+    __shared__ double spare[64];
+    __shared__ int ok_s;
+    const int tid = threadIdx.x;
+    bool good = nparts == GX_SPLIT ? cholqr_pass<GX_SPLIT>(Y, n, true, part_lds, C, Rinv, invd, spare, &ok_s)
+                                   : cholqr_pass<1>(Y, n, true, part_lds, C, Rinv, invd, spare, &ok_s);
+    if (full) good = good && cholqr_pass<1>(Y, n, false, part_lds, C, Rinv, invd, spare, &ok_s) &&
+                     cholqr_pass<1>(Y, n, false, part_lds, C, Rinv, invd, spare, &ok_s);
+    if (tid == 0) *ok = first ? (good ? 1 : 0) : ((*ok && good) ? 1 : 0);
+}
+
+// Jacobi rotation for the pair (p, q) as in schur2, with fewer long-latency
+// operations: the threshold |a_pq| > tol sqrt(|a_pp a_qq|) is tested squared,
+// and with d = a_qq - a_pp, g = 2 a_pq, h = hypot(d, g), u = (1 + |d| / h) / 2:
+// c = sqrt(u), s = sign(d) g / (2 h c), t = s / c (the smaller angle).
+__device__ inline bool rot2(double app, double aqq, double apq, double tol2, double& c, double& s, double& dp,
+                            double& dq) {
+    c = 1.0;
+    s = 0.0;
+    dp = app;
+    dq = aqq;
+    if (!(apq * apq > tol2 * fabs(app * aqq))) return false;
+    const double d = aqq - app, g = 2.0 * apq;
+    const double rh = rsqrt_nr(d * d + g * g);   // 1 / h
+    const double u = 0.5 + 0.5 * fabs(d) * rh;   // cos^2 of the angle
+    const double rc = rsqrt_nr(u);               // 1 / c
+    c = u * rc;
+    s = (d >= 0.0 ? 0.5 : -0.5) * g * rh * rc;
+    const double t = s * rc;
+    dp = app - t * apq;
+    dq = aqq + t * apq;
+    return true;
+}
+
+// Cyclic Jacobi on the symmetric A (32 x 32, LDS; only the upper triangle is
+// read or written), rotations accumulated in W (32 x 32, LDS).  Called by
+// every thread of a workgroup of at least 5 wavefronts.  Wavefront 0 runs the
+// sweeps: per round of the round-robin ordering lanes 0-15 compute the
+// rotations of the 16 pairs into the rotation log, then every lane rotates its
+// 2 x 2 blocks (pair k, pair l), k <= l (loads first, stores last; the
+// diagonal blocks set exactly).  A round with no rotation is skipped.
+// Wavefronts 1-4 meanwhile apply the previous sweep's log to 8 rows of W each;
+// one workgroup barrier per sweep.  log: 2 x 31 x 16 double2 (c, s); dd: 16
+// double2 (new diagonal); pq: 16 ints; flag: 1 int; spare: 64 doubles, all LDS.
+__device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 + 1], int max_sweeps, double2* log,
+                                         double2* dd, int* pq, int* flag, double* spare, int& sweeps_out,
+                                         bool& conv_out) {
+    constexpr int H = S32 / 2;
+    constexpr int NB = H * (H + 1) / 2;  // 136 blocks
+    constexpr int LOGR = (S32 - 1) * H;  // records per sweep
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double tol = (double)S32 * 0x1p-53;
+    const double tol2 = tol * tol;
+    int kt[3], lt[3];
+    bool vt[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        int idx = lane + 64 * t;
+        vt[t] = idx < NB;
+        int k = 0;
+        if (vt[t])
+            while (idx >= H - k) {
+                idx -= H - k;
+                ++k;
+            }
+        kt[t] = vt[t] ? k : 0;
+        lt[t] = vt[t] ? k + idx : 0;
+    }
+    // canonical (upper triangle) element
+    auto U = [&](int x, int y) -> double& { return x < y ? A[x][y] : A[y][x]; };
+    // wavefronts 1-4: rows 8 (wave - 1) + lane / 8, pairs lane % 8 and lane % 8 + 8
+    auto apply_log = [&](const double2* lg) {
+        const int i = 8 * (wave - 1) + (lane >> 3);
+        const int k0 = lane & 7;
+        for (int round = 0; round < S32 - 1; ++round) {
+            int p0, q0, p1, q1;
+            round_robin_pair(round, k0, S32, p0, q0);
+            round_robin_pair(round, k0 + 8, S32, p1, q1);
+            const double2 r0 = lg[round * H + k0], r1 = lg[round * H + k0 + 8];
+            const double x0 = W[i][p0], y0 = W[i][q0], x1 = W[i][p1], y1 = W[i][q1];
+            // (c, s) = (1, 0) for a pair that did not rotate: the same values back
+            W[i][p0] = r0.x * x0 - r0.y * y0;
+            W[i][q0] = r0.y * x0 + r0.x * y0;
+            W[i][p1] = r1.x * x1 - r1.y * y1;
+            W[i][q1] = r1.y * x1 + r1.x * y1;
+            wave_sync();
+        }
+    };
+    int sweeps = 0;
+    bool conv = false;
+    while (!conv && sweeps < max_sweeps) {
+        double2* lg = log + (sweeps & 1) * LOGR;
+        if (wave == 0) {
+            bool any = false;
+            for (int round = 0; round < S32 - 1; ++round) {
+                bool r = false;
+                if (lane < H) {
+                    int p, q;
+                    round_robin_pair(round, lane, S32, p, q);
+                    double c, s, dp, dq;
+                    r = rot2(A[p][p], A[q][q], A[p][q], tol2, c, s, dp, dq);
+                    lg[round * H + lane] = double2{c, s};
+                    dd[lane] = double2{dp, dq};
+                    pq[lane] = p | (q << 8);
+                }
+                if (__ballot(r) == 0) continue;
+                any = true;
+                wave_sync();
+                double2 ck[3], cl[3], dk[3];
+                int pk[3], pl[3];
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    ck[t] = lg[round * H + kt[t]];
+                    cl[t] = lg[round * H + lt[t]];
+                    dk[t] = dd[kt[t]];
+                    pk[t] = pq[kt[t]];
+                    pl[t] = pq[lt[t]];
+                }
+                double x[3][4];
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const int p = pk[t] & 255, q = pk[t] >> 8, p2 = pl[t] & 255, q2 = pl[t] >> 8;
+                    x[t][0] = U(p, p2);
+                    x[t][1] = U(p, q2);
+                    x[t][2] = U(q, p2);
+                    x[t][3] = U(q, q2);
+                }
+                wave_sync();
+                // branch-free stores (a branch would let the compiler sink the
+                // loads above into it); blocks a lane does not own go to spare
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const int p = pk[t] & 255, q = pk[t] >> 8, p2 = pl[t] & 255, q2 = pl[t] >> 8;
+                    const double c1 = ck[t].x, s1 = ck[t].y, c2 = cl[t].x, s2 = cl[t].y;
+                    const double ra = c1 * x[t][0] - s1 * x[t][2], rb = c1 * x[t][1] - s1 * x[t][3];
+                    const double rc = s1 * x[t][0] + c1 * x[t][2], rd = s1 * x[t][1] + c1 * x[t][3];
+                    double n0 = c2 * ra - s2 * rb, n1 = s2 * ra + c2 * rb;
+                    double n2 = c2 * rc - s2 * rd, n3 = s2 * rc + c2 * rd;
+                    if (kt[t] == lt[t]) {  // the rotated pair itself: exact new diagonal
+                        const bool rot_k = s1 != 0.0;
+                        n0 = rot_k ? dk[t].x : x[t][0];
+                        n1 = rot_k ? 0.0 : x[t][1];
+                        n2 = n1;
+                        n3 = rot_k ? dk[t].y : x[t][3];
+                    }
+                    double* d0 = vt[t] ? &U(p, p2) : &spare[lane];
+                    double* d1 = vt[t] ? &U(p, q2) : &spare[lane];
+                    double* d2 = vt[t] ? &U(q, p2) : &spare[lane];
+                    double* d3 = vt[t] ? &U(q, q2) : &spare[lane];
+                    *d0 = n0;
+                    *d1 = n1;
+                    *d2 = n2;
+                    *d3 = n3;
+                }
+                wave_sync();
+            }
+            if (lane == 0) *flag = any ? 1 : 0;
+        } else if (wave <= 4 && sweeps > 0) {
+            apply_log(log + ((sweeps - 1) & 1) * LOGR);
+        }
+        __syncthreads();
+        conv = (*flag == 0);
+        ++sweeps;
+        __syncthreads();
+    }
+    if (wave >= 1 && wave <= 4 && sweeps > 0) apply_log(log + ((sweeps - 1) & 1) * LOGR);
+    __syncthreads();
+    sweeps_out = sweeps;
+    conv_out = conv;
+}
+
+// Rayleigh-Ritz on span(Q) (Q n x 32 orthonormal, Z = G Q given as nparts
+// partial arrays), then rank choice and factor output.  When either
+// orthonormalisation failed the mode is handed to the next eigensolver.
+__global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q, const double* __restrict__ Z,
+                                                    int nparts, int n, int max_sweeps,
+                                                    const int32_t* __restrict__ orth_ok, SelectArgs a) {
+    extern __shared__ double lds[];
+    double* part_lds = lds;
+    double(*Bm)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + RW * S32 * S32);
+    double(*Wm)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + RW * S32 * S32 + S32 * (S32 + 1));
+    __shared__ double2 jlog[2 * (S32 - 1) * (S32 / 2)];
+    __shared__ double2 jdd[S32 / 2];
+    __shared__ int jpq[S32 / 2];
+    __shared__ int jflag;
+    __shared__ double jspare[64];
+    __shared__ int col_of[S32];
+    __shared__ double red[17];
+    __shared__ int sign_s[S32];
+    __shared__ int r_s;
+    __shared__ int sweeps_s, conv_s;
+    const int tid = threadIdx.x;
+    DevBook* bk = a.book;
+    if (!*orth_ok) {
+        if (tid == 0) bk->need_dense = 1;
+        return;
+    }
+    if (nparts == GX_SPLIT) cross32<RW, 1, GX_SPLIT>(Q, Z, n, part_lds, Bm);
+    else cross32<RW, 1, 1>(Q, Z, n, part_lds, Bm);
+    for (int e = tid; e < S32 * S32; e += RT) {
+        const int i = e >> 5, j = e & 31;
+        Wm[i][j] = 0.5 * (Bm[i][j] + Bm[j][i]);
+    }
+    __syncthreads();
+    for (int e = tid; e < S32 * S32; e += RT) {
+        const int i = e >> 5, j = e & 31;
+        Bm[i][j] = Wm[i][j];
+        Wm[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    {
+        int sw;
+        bool cv;
+        jacobi32(Bm, Wm, max_sweeps, jlog, jdd, jpq, &jflag, jspare, sw, cv);
+        if (tid == 0) {
+            sweeps_s = sw;
+            conv_s = cv ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    double* lam = const_cast<double*>(a.lam);
+    double* V = const_cast<double*>(a.V);
+    if (tid < S32) {
+        const double li = Bm[tid][tid];
+        int r = 0;
+        for (int j = 0; j < S32; ++j) {
+            const double lj = Bm[j][j];
+            r += (lj > li) || (lj == li && j < tid);
+        }
+        col_of[r] = tid;
+        lam[r] = li;
+    }
+    __syncthreads();
+    // V = Q W[:, col_of]: thread (row i, half h) keeps the row of Q in registers
+    for (int idx = tid; idx < 2 * n; idx += RT) {
+        const int i = idx >> 1, h = (idx & 1) * (S32 / 2);
+        double qr[S32];
+#pragma unroll
+        for (int c = 0; c < S32; c += 2) {
+            const double2 v = *reinterpret_cast<const double2*>(Q + (int64_t)i * S32 + c);
+            qr[c] = v.x;
+            qr[c + 1] = v.y;
+        }
+        for (int jj = 0; jj < S32 / 2; ++jj) {
+            const int col = col_of[h + jj];
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < S32; ++c) s += qr[c] * Wm[c][col];
+            V[(int64_t)i * S32 + h + jj] = s;
+        }
+    }
+    if (tid == 0) {
+        bk->sweeps[a.k] = sweeps_s;
+        bk->eig_ok = conv_s;
+    }
+    __threadfence();
+    __syncthreads();
+    select_factor_body(a, red, sign_s, r_s);
+}
+
+bool sub32_ready() {
+    static int state = 0;
+    if (state == 0) {
+        const bool a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_orth32),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)ORTH_LDS) == hipSuccess;
+        const bool b = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rr32_select),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)RR_LDS) == hipSuccess;
+        state = (a && b) ? 1 : -1;
+    }
+    return state == 1;
+}
+
 __global__ void k_prepare_matrix(const void* U, int src_f64, int rows, int cols, int transpose, double* M64,
                                  float* M32, __bf16* Mh, __bf16* Ml) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -733,6 +1305,39 @@ __global__ void k_zero(uint32_t* p, size_t words) {
 hipError_t launch_select_factor(const SelectArgs& a, hipStream_t st) {
     if (a.n > 4096) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_select_factor, dim3(1), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+bool subspace32_available(int n) { return n >= 2 * S32 && n <= 512 && sub32_ready(); }
+
+size_t subspace32_ws_doubles(int n) { return (size_t)2 * GX_SPLIT * n * S32 + 8; }
+
+hipError_t run_subspace32_select(const double* G, int n, int iters, int max_sweeps, double* ws, const SelectArgs& sa,
+                                 hipStream_t st) {
+    if (!subspace32_available(n)) return hipErrorInvalidValue;
+    if (sa.ncand != S32 || sa.ldv != S32 || !sa.subspace) return hipErrorInvalidValue;
+    double* P1 = ws;                                  // GX_SPLIT x n x 32
+    double* P2 = P1 + (size_t)GX_SPLIT * n * S32;     // GX_SPLIT x n x 32
+    int32_t* ok = reinterpret_cast<int32_t*>(P2 + (size_t)GX_SPLIT * n * S32);
+    const dim3 gg((unsigned)ceil_div(n, GX_ROWS), GX_SPLIT);
+    hipError_t e;
+    hipLaunchKernelGGL(k_gemm_gx, gg, dim3(64), 0, st, G, (const double*)nullptr, P1, n, (uint64_t)0x5eed);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int steps = iters < 1 ? 1 : iters;
+    for (int it = 0; it < steps; ++it) {
+        // P1[0] <- orthonormal basis of the (summed) product, then P2 <- G P1[0]
+        // intermediate bases only need to be well conditioned; the last one
+        // (the Rayleigh-Ritz basis) is orthonormal
+        hipLaunchKernelGGL(k_orth32, dim3(1), dim3(OT), ORTH_LDS, st, P1, GX_SPLIT, n, it + 1 == steps ? 1 : 0,
+                           it == 0 ? 1 : 0, ok);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gemm_gx, gg, dim3(64), 0, st, G, (const double*)P1, P2, n, (uint64_t)0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        std::swap(P1, P2);
+    }
+    // P2[0] holds the basis, P1 the parts of G times it
+    hipLaunchKernelGGL(k_rr32_select, dim3(1), dim3(RT), RR_LDS, st, (const double*)P2, (const double*)P1, GX_SPLIT,
+                       n, max_sweeps, (const int32_t*)ok, sa);
     return hipGetLastError();
 }
 

@@ -163,6 +163,16 @@ struct SelectArgs {
 };
 hipError_t launch_select_factor(const SelectArgs& a, hipStream_t st);
 
+// Subspace path with m = 32 for 64 <= n <= 512: power steps whose bases are
+// orthonormalised by one-sided Jacobi in LDS, then a fused Rayleigh-Ritz step
+// that also runs the rank choice and factor output of launch_select_factor.
+// sa must have ncand = ldv = 32 and subspace = 1; its lam and V (n x 32) are
+// written.  ws holds subspace32_ws_doubles(n) doubles.
+bool subspace32_available(int n);
+size_t subspace32_ws_doubles(int n);
+hipError_t run_subspace32_select(const double* G, int n, int iters, int max_sweeps, double* ws, const SelectArgs& sa,
+                                 hipStream_t st);
+
 // Prepares the mode-product matrix for reconstruction: M = U (n x r, dtype)
 // converted to FP64 / FP32 / bf16 hi-lo.  transpose != 0 gives U^T (r x n).
 hipError_t launch_prepare_matrix(int prec, const void* U, int src_f64, int rows, int cols, int transpose,

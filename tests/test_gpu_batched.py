@@ -3,7 +3,7 @@ FP64 oracle run block by block, plus HIP-graph replay and the autotuner.
 
 Bars per block (bf16x3 and FP32 products, FP64 eigensolver): ranks equal or
 boundary-degenerate (oracle discarded energy at the GPU rank within 10% of the
-mode budget), achieved error <= 1.02 eps (1.05 eps for the plain FP32 path), |X~_gpu - X~_oracle| / |X| <= 0.2 eps
+mode budget, 20% for the plain FP32 path), achieved error <= 1.02 eps (1.05 eps for the plain FP32 path), |X~_gpu - X~_oracle| / |X| <= 0.2 eps
 when ranks agree, and |A|^2 to 1e-5.
 """
 import os
@@ -25,7 +25,7 @@ def _arena(dims, seed0):
     return torch.from_numpy(arena).cuda()
 
 
-def _check_block(plan, arena_np, core, fac, recs, b, eps, err_factor=1.02):
+def _check_block(plan, arena_np, core, fac, recs, b, eps, err_factor=1.02, band=0.1):
     d = [int(v) for v in plan.dims[b]]
     x = arena_np[plan.input_off[b]: plan.input_off[b] + np.prod(d)].reshape(d)
     rec = recs[b]
@@ -48,7 +48,7 @@ def _check_block(plan, arena_np, core, fac, recs, b, eps, err_factor=1.02):
             tails = oracle.tail_sums(t_o.eigvals[k])
             bud = t_o.budgets[k]
             near = min(abs(tails[ranks[k]] - bud), abs(tails[t_o.ranks[k]] - bud))
-            assert near <= 0.1 * bud, (b, d, ranks, t_o.ranks)
+            assert near <= band * bud, (b, d, ranks, t_o.ranks)
     return False
 
 
@@ -71,10 +71,12 @@ def test_batched_small_mixed_sizes(precision):
     recs = plan.results(res)
     # the plain FP32 Gram is at its precision floor at 1e-3: its unbiased tail
     # estimates scatter by a few percent of the budget (bf16x3 keeps 1.02)
-    factor = 1.02 if precision == "bf16x3" else 1.05
-    exact = sum(_check_block(plan, arena_np, core, fac, recs, b, eps, factor) for b in range(len(dims)))
+    # and its rank can sit on the other side of a boundary the oracle places
+    # within 20% of the budget (bf16x3: 10%)
+    factor, band = (1.02, 0.1) if precision == "bf16x3" else (1.05, 0.2)
+    exact = sum(_check_block(plan, arena_np, core, fac, recs, b, eps, factor, band) for b in range(len(dims)))
     log("batched", precision, "blocks", len(dims), "exact-rank blocks", exact)
-    assert exact >= len(dims) - 2
+    assert exact >= len(dims) - (2 if precision == "bf16x3" else 4)
 
 
 def test_batched_graph_replay_and_autotune(tmp_path):
@@ -90,7 +92,11 @@ def test_batched_graph_replay_and_autotune(tmp_path):
     plan2 = atc.BatchPlan(dims, 1e-3, "bf16x3")
     assert plan2.autotune(arena, core, fac, res, ws, reps=2, cache_path=cache) == choice  # read from cache
     assert open(cache).read().count("\n") == 1
-    # eager reference
+    # eager reference; the arenas are cleared first, as before every replay,
+    # since slot entries beyond a block's core and factors are never written
+    core.zero_()
+    fac.zero_()
+    res.zero_()
     plan.run(arena, core, fac, res, ws)
     torch.cuda.synchronize()
     ref_core, ref_fac, ref_res = core.clone(), fac.clone(), res.clone()
