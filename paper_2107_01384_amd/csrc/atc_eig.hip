@@ -664,12 +664,21 @@ __device__ __forceinline__ void select_factor_body(const SelectArgs& a, double* 
         double best = -1.0;
         int bi = 0x7fffffff;
         double val = 0.0;
-        for (int i = lane; i < a.n; i += 64) {
-            const double v = a.V[(int64_t)i * a.ldv + j];
-            if (fabs(v) > best) {
-                best = fabs(v);
-                bi = i;
-                val = v;
+        for (int i0 = lane; i0 < a.n; i0 += 4 * 64) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + 64 * u;
+                v[u] = a.V[(int64_t)(i < a.n ? i : a.n - 1) * a.ldv + j];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + 64 * u;
+                if (i < a.n && fabs(v[u]) > best) {
+                    best = fabs(v[u]);
+                    bi = i;
+                    val = v[u];
+                }
             }
         }
         for (int o = 32; o > 0; o >>= 1) {
@@ -685,9 +694,21 @@ __device__ __forceinline__ void select_factor_body(const SelectArgs& a, double* 
         if (lane == 0) sign_s[j] = val < 0.0 ? -1 : 1;
     }
     __syncthreads();
-    for (int64_t idx = tid; idx < (int64_t)a.n * r; idx += blockDim.x) {
+    const int64_t total = (int64_t)a.n * r;
+    for (int64_t base = tid; base < total; base += 4 * (int64_t)blockDim.x) {
+        double vv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t idx = base + q * (int64_t)blockDim.x;
+            const int64_t ii = idx < total ? idx : total - 1;
+            vv[q] = a.V[(ii / r) * a.ldv + ii % r];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+        const int64_t idx = base + q * (int64_t)blockDim.x;
+        if (idx >= total) break;
         const int i = (int)(idx / r), j = (int)(idx % r);
-        const double u = sign_s[j] * a.V[(int64_t)i * a.ldv + j];
+        const double u = sign_s[j] * vv[q];
         if (a.ufac_f64) ((double*)a.ufac)[idx] = u;
         else ((float*)a.ufac)[idx] = (float)u;
         const int64_t t = (int64_t)j * a.n + i;  // U^T, r x n
@@ -700,6 +721,7 @@ __device__ __forceinline__ void select_factor_body(const SelectArgs& a, double* 
                 a.Mth[t] = hh;
                 a.Mtl[t] = (__bf16)(f - (float)hh);
             }
+        }
         }
     }
 }
@@ -723,7 +745,7 @@ __global__ __launch_bounds__(256) void k_select_factor(SelectArgs a) {
 //   B = Q1^T Z = W diag(theta) W^T (one-wavefront Jacobi), V = Q1 W, then the
 //   rank choice, sign rule and factor output of select_factor_body.
 constexpr int S32 = 32;
-constexpr int GX_ROWS = 8;    // rows of G per workgroup of k_gemm_gx
+constexpr int GX_ROWS = 16;   // rows of G per workgroup of k_gemm_gx
 constexpr int GX_SPLIT = 4;   // K chunks; the consumer adds the partial products
 constexpr int OT = 512;       // threads of the orthonormalisation workgroup
 constexpr int OW = OT / 64;   // its wavefronts
@@ -734,49 +756,51 @@ constexpr size_t RR_LDS = (size_t)(RW * S32 * S32 + 2 * S32 * (S32 + 1)) * sizeo
 
 // part[s] (n x 32) = G[:, K_s] X[K_s, :], K_s the s-th of GX_SPLIT chunks of
 // [0, n).  X == nullptr: X[k][j] = hash_unit((32 k + j) * C + salt).  One
-// wavefront per workgroup; lane = (row pair, column pair).
+// wavefront per (16-row tile, chunk) on v_mfma_f64_16x16x4f64, eight K steps'
+// loads in flight.
 __global__ __launch_bounds__(64) void k_gemm_gx(const double* __restrict__ G, const double* __restrict__ X,
                                                 double* __restrict__ part, int n, uint64_t salt) {
     const int lane = threadIdx.x;
-    const int q = lane >> 4, c = (lane & 15) * 2;
-    const int r0 = blockIdx.x * GX_ROWS + 2 * q;
+    const int kr = lane >> 4, cl = lane & 15;
+    const int r0 = blockIdx.x * GX_ROWS;
     const int s = blockIdx.y;
-    const int chunk = (int)ceil_div(n, GX_SPLIT);
+    const int chunk = (int)ceil_div(ceil_div(n, GX_SPLIT), 4) * 4;
     const int k0 = min(n, s * chunk), k1 = min(n, k0 + chunk);
-    const double* ga = G + (int64_t)min(r0, n - 1) * n;
-    const double* gb = G + (int64_t)min(r0 + 1, n - 1) * n;
-    double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
-    if (X) {
-#pragma unroll 4
-        for (int k = k0; k < k1; ++k) {
-            const double x0 = X[(int64_t)k * S32 + c], x1 = X[(int64_t)k * S32 + c + 1];
-            const double g0 = ga[k], g1 = gb[k];
-            a00 += g0 * x0;
-            a01 += g0 * x1;
-            a10 += g1 * x0;
-            a11 += g1 * x1;
+    const int ra = min(r0 + cl, n - 1);
+    const double* grow = G + (int64_t)ra * n;
+    f64x4 acc0 = f64x4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+    for (int kb = k0; kb < k1; kb += 32) {
+        double av[8], b0[8], b1[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int k = kb + 4 * t + kr;
+            const bool in = k < k1;
+            const int kk = in ? k : k0;
+            const double m = in ? 1.0 : 0.0;
+            av[t] = m * grow[kk];
+            if (X) {
+                b0[t] = X[(int64_t)kk * S32 + cl];
+                b1[t] = X[(int64_t)kk * S32 + 16 + cl];
+            } else {
+                const uint64_t key = (uint64_t)kk * S32 + cl;
+                b0[t] = hash_unit(key * 0x2545F4914F6CDD1Dull + salt);
+                b1[t] = hash_unit((key + 16) * 0x2545F4914F6CDD1Dull + salt);
+            }
         }
-    } else {
-#pragma unroll 4
-        for (int k = k0; k < k1; ++k) {
-            const uint64_t key = (uint64_t)k * S32 + c;
-            const double x0 = hash_unit(key * 0x2545F4914F6CDD1Dull + salt);
-            const double x1 = hash_unit((key + 1) * 0x2545F4914F6CDD1Dull + salt);
-            const double g0 = ga[k], g1 = gb[k];
-            a00 += g0 * x0;
-            a01 += g0 * x1;
-            a10 += g1 * x0;
-            a11 += g1 * x1;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], b0[t], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], b1[t], acc1, 0, 0, 0);
         }
     }
     double* out = part + (int64_t)s * n * S32;
-    if (r0 < n) {
-        out[(int64_t)r0 * S32 + c] = a00;
-        out[(int64_t)r0 * S32 + c + 1] = a01;
-    }
-    if (r0 + 1 < n) {
-        out[(int64_t)(r0 + 1) * S32 + c] = a10;
-        out[(int64_t)(r0 + 1) * S32 + c + 1] = a11;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = r0 + mfma16_row<PREC_F64>(lane, e);
+        if (r < n) {
+            out[(int64_t)r * S32 + cl] = acc0[e];
+            out[(int64_t)r * S32 + 16 + cl] = acc1[e];
+        }
     }
 }
 
@@ -934,6 +958,47 @@ __device__ __forceinline__ bool chol_inv32_wave(double (*C)[S32 + 1], double (*R
     return true;
 }
 
+// Out[r][j] = sum_k X[r][k] B[k][col(j)] for an n x 32 X (the sum of NP partial
+// arrays spaced n x 32 apart) and B 32 x 32 in LDS; col(j) = colmap[j] or j.
+// v_mfma_f64_16x16x4f64 on 16-row tiles, wavefront w of NW taking tiles w,
+// w + NW, ...; B in registers.  Out may be the first array of X: a tile's
+// rows are all loaded before any of them is stored.
+template <int NP, int NW>
+__device__ __forceinline__ void apply32(const double* X, double* Out, int n, const double (*B)[S32 + 1],
+                                        const int* colmap) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kr = lane >> 4, cl = lane & 15;
+    const int64_t ps = (int64_t)n * S32;
+    const int c0 = colmap ? colmap[cl] : cl, c1 = colmap ? colmap[16 + cl] : 16 + cl;
+    double bop[8][2];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+        bop[ks][0] = B[4 * ks + kr][c0];
+        bop[ks][1] = B[4 * ks + kr][c1];
+    }
+    for (int r0 = 16 * wave; r0 < n; r0 += 16 * NW) {
+        const int ra = r0 + cl;
+        const int64_t rowoff = (int64_t)(ra < n ? ra : n - 1) * S32;
+        double aop[8];
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) aop[ks] = parts_at<NP>(X, ps, rowoff + 4 * ks + kr);
+        f64x4 acc0 = f64x4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[ks], bop[ks][0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[ks], bop[ks][1], acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = r0 + mfma16_row<PREC_F64>(lane, e);
+            if (r < n) {
+                Out[(int64_t)r * S32 + cl] = acc0[e];
+                Out[(int64_t)r * S32 + 16 + cl] = acc1[e];
+            }
+        }
+    }
+}
+
 // One Cholesky QR pass: Y <- X R^{-1}, R^T R = X^T X (+ shift I), X the sum of
 // NP partial arrays of which Y is the first (in place).  Returns false,
 // uniformly, on a failed pivot.  The product X R^{-1} runs on
@@ -942,7 +1007,7 @@ template <int NP>
 __device__ __forceinline__ bool cholqr_pass(double* __restrict__ Y, int n, bool shifted, double* part_lds,
                                             double (*C)[S32 + 1], double (*Rinv)[S32 + 1], double* invd, double* spare,
                                             int* ok_s) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     cross32<OW, NP, NP>(Y, Y, n, part_lds, C);
     if (tid < 64) {
         if (shifted) {
@@ -960,35 +1025,7 @@ __device__ __forceinline__ bool cholqr_pass(double* __restrict__ Y, int n, bool 
     }
     __syncthreads();
     if (!*ok_s) return false;
-    const int kr = lane >> 4, cl = lane & 15;
-    const int64_t ps = (int64_t)n * S32;
-    double bop[8][2];
-#pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-        bop[ks][0] = Rinv[4 * ks + kr][cl];
-        bop[ks][1] = Rinv[4 * ks + kr][16 + cl];
-    }
-    for (int r0 = 16 * wave; r0 < n; r0 += 16 * OW) {
-        const int ra = r0 + cl;
-        const int64_t rowoff = (int64_t)(ra < n ? ra : n - 1) * S32;
-        double aop[8];
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) aop[ks] = parts_at<NP>(Y, ps, rowoff + 4 * ks + kr);
-        f64x4 acc0 = f64x4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
-#pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[ks], bop[ks][0], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[ks], bop[ks][1], acc1, 0, 0, 0);
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int r = r0 + mfma16_row<PREC_F64>(lane, e);
-            if (r < n) {
-                Y[(int64_t)r * S32 + cl] = acc0[e];
-                Y[(int64_t)r * S32 + 16 + cl] = acc1[e];
-            }
-        }
-    }
+    apply32<NP, OW>(Y, Y, n, Rinv, nullptr);
     __syncthreads();
     return true;
 }
@@ -1191,6 +1228,7 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
     __shared__ int jflag;
     __shared__ double jspare[64];
     __shared__ int col_of[S32];
+    __shared__ double lam_s[S32];
     __shared__ double red[17];
     __shared__ int sign_s[S32];
     __shared__ int r_s;
@@ -1235,33 +1273,20 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
         }
         col_of[r] = tid;
         lam[r] = li;
+        lam_s[r] = li;
     }
     __syncthreads();
-    // V = Q W[:, col_of]: thread (row i, half h) keeps the row of Q in registers
-    for (int idx = tid; idx < 2 * n; idx += RT) {
-        const int i = idx >> 1, h = (idx & 1) * (S32 / 2);
-        double qr[S32];
-#pragma unroll
-        for (int c = 0; c < S32; c += 2) {
-            const double2 v = *reinterpret_cast<const double2*>(Q + (int64_t)i * S32 + c);
-            qr[c] = v.x;
-            qr[c + 1] = v.y;
-        }
-        for (int jj = 0; jj < S32 / 2; ++jj) {
-            const int col = col_of[h + jj];
-            double s = 0.0;
-#pragma unroll
-            for (int c = 0; c < S32; ++c) s += qr[c] * Wm[c][col];
-            V[(int64_t)i * S32 + h + jj] = s;
-        }
-    }
+    // V = Q W[:, col_of]
+    apply32<1, RW>(Q, V, n, Wm, col_of);
     if (tid == 0) {
         bk->sweeps[a.k] = sweeps_s;
         bk->eig_ok = conv_s;
     }
     __threadfence();
     __syncthreads();
-    select_factor_body(a, red, sign_s, r_s);
+    SelectArgs al = a;
+    al.lam = lam_s;  // the Ritz values from LDS
+    select_factor_body(al, red, sign_s, r_s);
 }
 
 bool sub32_ready() {
