@@ -211,6 +211,9 @@ def main():
                     help="field: the 512^3 headline (default); the others print their own line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison path")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before timing, copy a float32 buffer of this many MiB once (untimed): the reference "
+                         "dispatch that scales HBM byte counters in a profiled run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the ST-HOSVD here runs on a single MI355X "
@@ -236,6 +239,15 @@ def main():
            [torch.empty(n * n, dtype=torch.float32, device="cuda") for n in dims])
     print("bench: field %s generated, %d steps + %d warmup" % (dims, args.steps, args.warmup), file=sys.stderr,
           flush=True)
+    if args.calib_copy_mib > 0:
+        n_el = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("bench: calibration copy of %d MiB done" % args.calib_copy_mib, file=sys.stderr, flush=True)
+        del src, dst
 
     ms_bf, res_bf = time_path(atc, torch, x, args.eps, "bf16x3", args.steps, args.warmup, ws, out)
     t_bf = res_bf[-1]

@@ -13,6 +13,8 @@
 // (BK x 64) slab of Y in LDS (Y stored column-major so each lane reads its
 // MFMA operand contiguously).  The kernel reads the tensor exactly once and
 // is bound by HBM bandwidth for small m_out.
+#include <type_traits>
+
 #include "atc_internal.hpp"
 
 namespace atc {
@@ -201,6 +203,160 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm(const typename ElemOf<P>::T* _
     }
 }
 
+// Wide variant for the contiguous-R layout (R >= 256, R % 4 == 0) and small
+// m_out (<= 16 MT): a workgroup owns 256 consecutive columns of one slice and
+// every output row, so the tensor is read once, in coalesced float4 rows.  The
+// next 32-row slab of Y (and of M, split into bf16 hi/lo on the fly for the
+// bf16x3 form) is loaded into registers while the current one is multiplied;
+// Y is staged in LDS column-major, eight rows of a column per 16-byte store.
+template <int P, int MT>
+__global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__ Y, int n, int64_t R, int m_out,
+                                                       int64_t tpl, const float* __restrict__ M32,
+                                                       float* __restrict__ Z) {
+    constexpr int W = 256, BK = 32, MR = 16 * MT;
+    constexpr int YP = (P == PREC_BF16X3) ? BK + 8 : BK + 4;  // padded row of a staged column
+    struct SmB {
+        __bf16 yh[W][BK + 8], yl[W][BK + 8], mh[MR][BK + 8], ml[MR][BK + 8];
+    };
+    struct SmF {
+        float yf[W][BK + 4], mf[MR][BK + 4];
+    };
+    typedef typename std::conditional<P == PREC_BF16X3, SmB, SmF>::type Sm;
+    __shared__ Sm sm;
+    (void)YP;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t ct = blockIdx.x;
+    const int64_t l = ct / tpl;
+    const int64_t c0 = (ct - l * tpl) * W;
+    const float* ybase = Y + l * (int64_t)n * R + c0;
+    const int cg = tid & 63, rg = tid >> 6;  // columns c0 + 4 cg .. + 3, slab rows 8 rg .. + 7
+    const bool colok = c0 + 4 * cg < R;
+    float4 yv[8];
+    float mv[MT][8];
+    auto load = [&](int i0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int i = i0 + 8 * rg + e;
+            yv[e] = (colok && i < n) ? *reinterpret_cast<const float4*>(ybase + (int64_t)i * R + 4 * cg)
+                                     : float4{0.f, 0.f, 0.f, 0.f};
+        }
+        // M: MR rows x 32 k, eight consecutive k per (thread, row block)
+#pragma unroll
+        for (int q = 0; q < MT; ++q) {
+            const int idx = tid + NTHREADS * q;  // < MR * 4 = 64 MT
+            const int mr = idx >> 2, kq = (idx & 3) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int i = i0 + kq + e;
+                mv[q][e] = (idx < MR * 4 && mr < m_out && i < n) ? M32[(int64_t)mr * n + i] : 0.f;
+            }
+        }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float f[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) f[e] = q == 0 ? yv[e].x : q == 1 ? yv[e].y : q == 2 ? yv[e].z : yv[e].w;
+            if constexpr (P == PREC_BF16X3) {
+                bf16x8 hv, lv;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const __bf16 h = (__bf16)f[e];
+                    hv[e] = h;
+                    lv[e] = (__bf16)(f[e] - (float)h);
+                }
+                *reinterpret_cast<bf16x8*>(&sm.yh[4 * cg + q][8 * rg]) = hv;
+                *reinterpret_cast<bf16x8*>(&sm.yl[4 * cg + q][8 * rg]) = lv;
+            } else {
+                *reinterpret_cast<float4*>(&sm.yf[4 * cg + q][8 * rg]) = float4{f[0], f[1], f[2], f[3]};
+                *reinterpret_cast<float4*>(&sm.yf[4 * cg + q][8 * rg + 4]) = float4{f[4], f[5], f[6], f[7]};
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < MT; ++q) {
+            const int idx = tid + NTHREADS * q;
+            if (idx >= MR * 4) continue;
+            const int mr = idx >> 2, kq = (idx & 3) * 8;
+            if constexpr (P == PREC_BF16X3) {
+                bf16x8 hv, lv;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const __bf16 h = (__bf16)mv[q][e];
+                    hv[e] = h;
+                    lv[e] = (__bf16)(mv[q][e] - (float)h);
+                }
+                *reinterpret_cast<bf16x8*>(&sm.mh[mr][kq]) = hv;
+                *reinterpret_cast<bf16x8*>(&sm.ml[mr][kq]) = lv;
+            } else {
+                *reinterpret_cast<float4*>(&sm.mf[mr][kq]) = float4{mv[q][0], mv[q][1], mv[q][2], mv[q][3]};
+                *reinterpret_cast<float4*>(&sm.mf[mr][kq + 4]) = float4{mv[q][4], mv[q][5], mv[q][6], mv[q][7]};
+            }
+        }
+    };
+    const int wc = wave * 64;  // this wavefront's 64 columns
+    f32x4 acc[MT][4];
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    load(0);
+    for (int i0 = 0; i0 < n; i0 += BK) {
+        __syncthreads();
+        stage();
+        __syncthreads();
+        if (i0 + BK < n) load(i0 + BK);
+        if constexpr (P == PREC_BF16X3) {
+            const int kq = 8 * (lane >> 4);
+            bf16x8 bh[4], bl[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                bh[b] = *reinterpret_cast<const bf16x8*>(&sm.yh[wc + 16 * b + (lane & 15)][kq]);
+                bl[b] = *reinterpret_cast<const bf16x8*>(&sm.yl[wc + 16 * b + (lane & 15)][kq]);
+            }
+#pragma unroll
+            for (int a = 0; a < MT; ++a) {
+                const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sm.mh[16 * a + (lane & 15)][kq]);
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(&sm.ml[16 * a + (lane & 15)][kq]);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[b], acc[a][b], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k4 = 0; k4 < BK; k4 += 4) {
+                const int kk = k4 + (lane >> 4);
+                float bv[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bv[b] = sm.yf[wc + 16 * b + (lane & 15)][kk];
+#pragma unroll
+                for (int a = 0; a < MT; ++a) {
+                    const float av = sm.mf[16 * a + (lane & 15)][kk];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[b], acc[a][b], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float* zbase = Z + l * (int64_t)m_out * R + c0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t c = wc + 16 * b + (lane & 15);
+        if (c0 + c >= R) continue;
+#pragma unroll
+        for (int a = 0; a < MT; ++a)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = 16 * a + mfma16_row<PREC_F32>(lane, v);
+                if (j < m_out) zbase[(int64_t)j * R + c] = acc[a][b][v];
+            }
+    }
+}
+
 template <int P, int LAYOUT>
 hipError_t launch_ttm_t(const TtmPlan& t, const void* Y, const void* M, const void* Mh, const void* Ml, void* Z,
                         hipStream_t st) {
@@ -251,6 +407,21 @@ TtmPlan ttm_plan(int prec, int64_t L, int n, int64_t R, int m_out) {
 
 hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, const void* Mh, const void* Ml,
                       void* Z, hipStream_t st) {
+    if (prec != PREC_F64 && t.layout == LAYOUT_KC && t.R >= 256 && t.R % 4 == 0 && t.m_out <= 64) {
+        const int64_t tpl = ceil_div(t.R, (int64_t)256);
+        const dim3 grid((unsigned)(t.L * tpl));
+        const float* y = (const float*)Y;
+        const float* m = (const float*)M;
+        float* z = (float*)Z;
+        if (prec == PREC_BF16X3) {
+            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 2>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z);
+            else hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 4>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z);
+        } else {
+            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 2>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z);
+            else hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 4>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z);
+        }
+        return hipGetLastError();
+    }
     switch (prec) {
         case PREC_F64: return launch_ttm_p<PREC_F64>(t, Y, M, Mh, Ml, Z, st);
         case PREC_F32: return launch_ttm_p<PREC_F32>(t, Y, M, Mh, Ml, Z, st);
