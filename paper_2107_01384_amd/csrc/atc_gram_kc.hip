@@ -88,7 +88,7 @@ __device__ inline void kc_store(KcSmem<P>& sm, bool second, int row, int col, co
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void k_gram_kc(const float* __restrict__ X, int n, int64_t L, int64_t R,
+__global__ __launch_bounds__(256, 2) void k_gram_kc(const float* __restrict__ X, int n, int64_t L, int64_t R,
                                                  int64_t steps, int nsplit, int tiles, int npairs,
                                                  float* __restrict__ part, double* __restrict__ dpart) {
     __shared__ KcSmem<P> sm;
