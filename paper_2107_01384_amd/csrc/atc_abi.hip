@@ -209,6 +209,43 @@ struct PhaseEvents {
 };
 thread_local PhaseEvents g_phase;
 
+// Pinned host word block the selection kernels report into, so that the host
+// learns each mode's rank without draining the stream (see wait_selection).
+struct PinnedFlags {
+    HostFlags* h = nullptr;  // host view
+    HostFlags* d = nullptr;  // device view
+    int32_t seq = 0;
+    bool init() {
+        if (h) return true;
+        void* p = nullptr;
+        if (hipHostMalloc(&p, sizeof(HostFlags), hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) return false;
+        void* dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, p, 0) != hipSuccess) {
+            (void)hipHostFree(p);
+            return false;
+        }
+        h = (HostFlags*)p;
+        d = (HostFlags*)dp;
+        memset(h, 0, sizeof(*h));
+        return true;
+    }
+};
+thread_local PinnedFlags g_flags;
+
+// Spins until the selection kernel reports sequence number `expect`; gives up
+// with an error when the stream has drained without the report.
+hipError_t wait_selection(const volatile HostFlags* f, int32_t expect, hipStream_t st) {
+    for (uint64_t it = 0;; ++it) {
+        if (__atomic_load_n(&f->seq, __ATOMIC_ACQUIRE) == expect) return hipSuccess;
+        if ((it & 1023) == 1023) {
+            const hipError_t q = hipStreamQuery(st);
+            if (q == hipSuccess) return __atomic_load_n(&f->seq, __ATOMIC_ACQUIRE) == expect ? hipSuccess : hipErrorUnknown;
+            if (q != hipErrorNotReady) return q;
+        }
+        __builtin_ia32_pause();
+    }
+}
+
 double event_ms(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.0;
@@ -265,6 +302,8 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
     for (int k = 0; k < d; ++k) cur[k] = shape->dims[k];
     const void* src = x;
     DevBook hb;
+    HostFlags hf{};
+    if (!g_flags.init()) return fail(ATC_ERR_DEVICE, "hipHostMalloc of the report block failed");
     int paths[ATC_MAX_DIMS] = {0};
     for (int i = 0; i < d; ++i) {
         const int k = order[i];
@@ -307,6 +346,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         sa.Mth = prec == PREC_BF16X3 ? w.Mth : nullptr;
         sa.Mtl = prec == PREC_BF16X3 ? w.Mtl : nullptr;
         sa.guard = SUBSPACE_GUARD;
+        sa.hflags = g_flags.d;
         int32_t* sweeps_dev = &w.book->sweeps[k];
         int32_t* ok_dev = &w.book->eig_ok;
 
@@ -320,6 +360,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         int attempt = dense_first ? 2 : 0;
         for (;; ++attempt) {
             bool selected = false;
+            sa.seq = ++g_flags.seq;
             if (attempt == 0 && subspace32_available(n)) {
                 sa.ldv = 32;
                 sa.ncand = 32;
@@ -349,18 +390,24 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
                 paths[k] = 1;
             }
             if (!selected) HIP_TRY(launch_select_factor(sa, st));
-            HIP_TRY(hipMemcpyAsync(&hb, w.book, sizeof(DevBook), hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            if (hb.status != 0) return fail((atc_status)hb.status, "input |A|^2 is not finite");
-            if (!hb.need_dense) break;
+            HIP_TRY(wait_selection(g_flags.h, sa.seq, st));
+            {
+                const volatile HostFlags* f = g_flags.h;
+                hf.rank = f->rank;
+                hf.need_dense = f->need_dense;
+                hf.eig_ok = f->eig_ok;
+                hf.status = f->status;
+            }
+            if (hf.status != 0) return fail((atc_status)hf.status, "input |A|^2 is not finite");
+            if (!hf.need_dense) break;
             if (attempt >= 2) return fail(ATC_ERR_INTERNAL, "mode %d: dense eigensolver asked for more", k);
             if (attempt == 1 && opts->eig_path == 2)
                 return fail(ATC_ERR_UNSUPPORTED, "mode %d: rank needs more than %d Ritz pairs", k,
                             SUBSPACE_M - SUBSPACE_GUARD);
             HIP_TRY(hipMemcpyAsync(&w.book->need_dense, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
         }
-        if (!hb.eig_ok) return fail(ATC_ERR_NOT_CONVERGED, "mode %d: eigensolver hit %d sweeps", k, max_sweeps);
-        const int r = hb.rank[k];
+        if (!hf.eig_ok) return fail(ATC_ERR_NOT_CONVERGED, "mode %d: eigensolver hit %d sweeps", k, max_sweeps);
+        const int r = hf.rank;
         if (r < 1 || r > n) return fail(ATC_ERR_INTERNAL, "mode %d: rank %d outside [1, %d]", k, r, n);
         void* dst = (i == d - 1) ? core : w.buf[i % 2];
         const TtmPlan tp = ttm_plan(prec, L, n, R, r);

@@ -580,6 +580,20 @@ hipError_t run_subspace_eig(const double* G, int n, int m, int iters, int max_sw
 // ------------------------------------------------------- rank select + factor
 namespace {
 
+// Reports the selection outcome to the host (one thread): the fields, a
+// system-scope fence, then the sequence number the host waits for.
+__device__ inline void publish_selection(const SelectArgs& a, int rank) {
+    if (!a.hflags) return;
+    volatile HostFlags* h = a.hflags;
+    const DevBook* bk = a.book;
+    h->rank = rank;
+    h->need_dense = bk->need_dense;
+    h->eig_ok = bk->eig_ok;
+    h->status = bk->status;
+    __threadfence_system();
+    h->seq = a.seq;
+}
+
 // Rank choice (Section 4.1.3), sign rule and factor output for one mode, run
 // by a whole workgroup (any multiple of 64 threads).  red: 17 doubles, sign_s:
 // n ints, r_s: 1 int, all in LDS.
@@ -654,6 +668,7 @@ __device__ __forceinline__ void select_factor_body(const SelectArgs& a, double* 
             bk->rank[a.k] = r;
         }
         r_s = r;
+        publish_selection(a, r);
     }
     __syncthreads();
     if (bk->need_dense) return;
@@ -737,11 +752,13 @@ __global__ __launch_bounds__(256) void k_select_factor(SelectArgs a) {
 // Orthogonal iteration with a Rayleigh-Ritz finish:
 //   Y0 = G Omega          split-K FP64 product on many workgroups (Omega is a
 //                         counter-based pseudo-random matrix made in the kernel)
-//   Q0 = orth(Y0)         one shifted Cholesky QR pass, then two plain ones, in
-//                         one workgroup (the columns of Y0 spread like the
+//   Q0 = orth(Y0)         a shifted Cholesky QR pass, then a plain one, in one
+//                         workgroup (the columns of Y0 spread like the
 //                         eigenvalues of G, far beyond what plain Cholesky QR
 //                         can orthonormalise)
-//   Q1 = orth(G Q0), Z = G Q1
+//   Q1 = orth(G Q0)       the same two passes, then the series C^{-1/2} = I - E/2
+//                         + 3 E^2 / 8 of C = Q^T Q = I + E, which also checks |E|
+//   Z = G Q1
 //   B = Q1^T Z = W diag(theta) W^T (one-wavefront Jacobi), V = Q1 W, then the
 //   rank choice, sign rule and factor output of select_factor_body.
 constexpr int S32 = 32;
@@ -898,62 +915,62 @@ __device__ __forceinline__ void cross32(const double* __restrict__ P, const doub
     __syncthreads();
 }
 
-// Upper Cholesky factor R of C (32 x 32 in LDS, symmetric; R overwrites the
-// upper triangle) and its inverse, by one wavefront.  Lane b (mod 32) owns
-// column b; the two half-wavefronts split the rows of each update; loads go
-// out eight at a time before the stores.  Rinv (LDS) receives R^{-1} (upper
-// triangular, zeros below), rows from the bottom.  Returns false (on every
-// lane) when a pivot is not positive and finite.  spare: 64 doubles of LDS.
-__device__ __forceinline__ bool chol_inv32_wave(double (*C)[S32 + 1], double (*Rinv)[S32 + 1], double* invd,
-                                                double* spare) {
-    const int lane = threadIdx.x & 63, b = lane & 31, h = lane >> 5;
-    for (int j = 0; j < S32; ++j) {
-        const double d = C[j][j];
-        if (!(d > 0.0 && d < INFINITY)) return false;
-        const double r = rsqrt_nr(d);
-        const double rjb = (b == j) ? d * r : C[j][b] * r;  // R[j][b] for b >= j
-        wave_sync();
-        if (h == 0 && b >= j) C[j][b] = rjb;
-        if (lane == 0) invd[j] = r;
-        wave_sync();
-        // C[a][b] -= R[j][a] R[j][b] for j < a <= b; half h takes a = j + 1 + h + 2t
-        for (int a0 = j + 1 + h; a0 < S32; a0 += 16) {
-            double ra[8], ca[8];
+// Upper Cholesky factor R of C (32 x 32, LDS, symmetric) and its inverse, by
+// one wavefront: lane b (mod 32) keeps column b in registers and the other
+// lanes' entries arrive by readlane.  The steps are unrolled through templates
+// so every register index is static; a scheduling barrier after each
+// broadcast-and-update keeps the compiler from hoisting all broadcasts of a
+// step at once.  Rinv (LDS) receives R^{-1} (upper triangular, zeros below).
+// Returns false (on every lane) when a pivot is not positive and finite.
+template <int J>
+__device__ __forceinline__ void chol_step(double (&c)[S32], int lane, bool& ok, double* invd) {
+    if constexpr (J < S32) {
+        const double d = lane_bcast(c[J], J);
+        ok = ok && (d > 0.0) && (d < INFINITY);
+        const double r = ok ? rsqrt_nr(d) : 0.0;
+        if (lane == 0) invd[J] = r;
+        const double rjb = c[J] * r;  // R[J][b]
+        c[J] = rjb;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int aa = min(a0 + 2 * t, S32 - 1);
-                ra[t] = C[j][aa];
-                ca[t] = C[aa][b];
-            }
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int aa = a0 + 2 * t;
-                // branch-free store: entries outside the triangle go to the spare slot
-                double* dst = (aa < S32 && aa <= b) ? &C[aa][b] : &spare[lane];
-                *dst = ca[t] - ra[t] * rjb;
-            }
+        for (int a = J + 1; a < S32; ++a) {
+            c[a] -= lane_bcast(rjb, a) * rjb;
+            __builtin_amdgcn_sched_barrier(0);
         }
-        wave_sync();
+        chol_step<J + 1>(c, lane, ok, invd);
     }
-    // R X = I: X[i][b] = (delta_ib - sum_{k > i} R[i][k] X[k][b]) / R[i][i]
-    for (int i = S32 - 1; i >= 0; --i) {
+}
+
+// Column b of X = R^{-1} from R X = I, rows from the bottom: R[I][k] (k > I) is
+// c[I] of lane k, and x[I] replaces c[I] once row I of R has been used.
+template <int I>
+__device__ __forceinline__ void rinv_step(double (&c)[S32], int lane, const double* invd) {
+    if constexpr (I >= 0) {
+        const int b = lane & 31;
         double t = 0.0;
-        for (int k0 = i + 1 + h; k0 < S32; k0 += 16) {
-            double rk[8], xk[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int k = k0 + 2 * q;
-                const int kk = min(k, S32 - 1);
-                rk[q] = k < S32 ? C[i][kk] : 0.0;
-                xk[q] = Rinv[kk][b];
-            }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) t += rk[q] * xk[q];
+        for (int k = I + 1; k < S32; ++k) {
+            t += lane_bcast(c[I], k) * c[k];
+            __builtin_amdgcn_sched_barrier(0);
         }
-        t += __shfl_xor(t, 32);
-        const double inv = invd[i];
-        if (h == 0) Rinv[i][b] = (i == b) ? inv : ((b > i) ? -t * inv : 0.0);
-        wave_sync();
+        const double inv = invd[I];
+        c[I] = (I == b) ? inv : ((I < b) ? -t * inv : 0.0);
+        rinv_step<I - 1>(c, lane, invd);
+    }
+}
+
+__device__ __forceinline__ bool chol_inv32_wave(const double (*C)[S32 + 1], double (*Rinv)[S32 + 1], double* invd) {
+    const int lane = threadIdx.x & 63, b = lane & 31;
+    double c[S32];
+#pragma unroll
+    for (int a = 0; a < S32; ++a) c[a] = C[a][b];
+    bool ok = true;
+    chol_step<0>(c, lane, ok, invd);
+    if (!ok) return false;
+    wave_sync();
+    rinv_step<S32 - 1>(c, lane, invd);
+    if (lane < S32) {
+#pragma unroll
+        for (int i = 0; i < S32; ++i) Rinv[i][b] = c[i];
     }
     return true;
 }
@@ -1020,7 +1037,7 @@ __device__ __forceinline__ bool cholqr_pass(double* __restrict__ Y, int n, bool 
             if (tid < S32) C[tid][tid] += sh;
             wave_sync();
         }
-        const bool ok = chol_inv32_wave(C, Rinv, invd, spare);
+        const bool ok = chol_inv32_wave(C, Rinv, invd);
         if (tid == 0) *ok_s = ok ? 1 : 0;
     }
     __syncthreads();
@@ -1030,11 +1047,48 @@ __device__ __forceinline__ bool cholqr_pass(double* __restrict__ Y, int n, bool 
     return true;
 }
 
-// Basis of the columns of Y = sum of nparts arrays (n x 32 each, spaced n x 32
-// apart), written over the first array: one shifted Cholesky QR pass (a
-// well-conditioned basis of the same span), and with full != 0 two more plain
-// passes (orthonormal to working precision).  *ok = 1 on success (first != 0)
-// or *ok &= success (first == 0).
+// Final orthonormalisation of an almost orthonormal Y (n x 32, global, in
+// place): C = Y^T Y = I + E, Y <- Y (I - E/2 + 3 E^2 / 8), the series of
+// C^{-1/2} to second order (error about |E|^3).  Returns false, uniformly,
+// without touching Y, when max |E_ij| > 1e-4 (the caller then runs a
+// Cholesky QR pass instead).
+__device__ __forceinline__ bool series_pass(double* __restrict__ Y, int n, double* part_lds, double (*C)[S32 + 1],
+                                            double (*X)[S32 + 1], int* ok_s) {
+    const int tid = threadIdx.x;
+    cross32<OW, 1, 1>(Y, Y, n, part_lds, C);
+    // E = C - I in place; max |E| by wavefront 0
+    for (int e = tid; e < S32 * S32; e += OT) {
+        const int i = e >> 5, j = e & 31;
+        if (i == j) C[i][j] -= 1.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        double m = 0.0;
+        for (int e = tid; e < S32 * S32; e += 64) m = fmax(m, fabs(C[e >> 5][e & 31]));
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+        if (tid == 0) *ok_s = (m <= 1e-4) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!*ok_s) return false;
+    // X = I - E/2 + 3/8 E^2 (E symmetric)
+    for (int e = tid; e < S32 * S32; e += OT) {
+        const int i = e >> 5, j = e & 31;
+        double t = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < S32; ++k) t += C[i][k] * C[k][j];
+        X[i][j] = (i == j ? 1.0 : 0.0) - 0.5 * C[i][j] + 0.375 * t;
+    }
+    __syncthreads();
+    apply32<1, OW>(Y, Y, n, X, nullptr);
+    __syncthreads();
+    return true;
+}
+
+// Orthonormal basis of the columns of Y = sum of nparts arrays (n x 32 each,
+// spaced n x 32 apart), written over the first array: a shifted Cholesky QR
+// pass and a plain one; with full != 0 (the Rayleigh-Ritz basis) also the
+// verified series correction.  *ok = 1 on success (first != 0) or *ok &=
+// success (first == 0).
 __global__ __launch_bounds__(OT) void k_orth32(double* __restrict__ Y, int nparts, int n, int full, int first,
                                                int32_t* __restrict__ ok) {
     extern __shared__ double lds[];
@@ -1045,10 +1099,18 @@ __global__ __launch_bounds__(OT) void k_orth32(double* __restrict__ Y, int npart
     __shared__ double spare[64];
     __shared__ int ok_s;
     const int tid = threadIdx.x;
+    // shifted pass (condition number down to about 5e-6 of the input's), then a
+    // plain pass (orthonormal to about u cond^2)
     bool good = nparts == GX_SPLIT ? cholqr_pass<GX_SPLIT>(Y, n, true, part_lds, C, Rinv, invd, spare, &ok_s)
                                    : cholqr_pass<1>(Y, n, true, part_lds, C, Rinv, invd, spare, &ok_s);
-    if (full) good = good && cholqr_pass<1>(Y, n, false, part_lds, C, Rinv, invd, spare, &ok_s) &&
-                     cholqr_pass<1>(Y, n, false, part_lds, C, Rinv, invd, spare, &ok_s);
+    good = good && cholqr_pass<1>(Y, n, false, part_lds, C, Rinv, invd, spare, &ok_s);
+    if (full && good) {
+        // final basis: the series correction, which also verifies |Y^T Y - I|;
+        // one more plain pass if that is not yet small, else report failure
+        if (!series_pass(Y, n, part_lds, C, Rinv, &ok_s))
+            good = cholqr_pass<1>(Y, n, false, part_lds, C, Rinv, invd, spare, &ok_s) &&
+                   series_pass(Y, n, part_lds, C, Rinv, &ok_s);
+    }
     if (tid == 0) *ok = first ? (good ? 1 : 0) : ((*ok && good) ? 1 : 0);
 }
 
@@ -1236,7 +1298,10 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
     const int tid = threadIdx.x;
     DevBook* bk = a.book;
     if (!*orth_ok) {
-        if (tid == 0) bk->need_dense = 1;
+        if (tid == 0) {
+            bk->need_dense = 1;
+            publish_selection(a, 0);
+        }
         return;
     }
     if (nparts == GX_SPLIT) cross32<RW, 1, GX_SPLIT>(Q, Z, n, part_lds, Bm);
@@ -1351,8 +1416,7 @@ hipError_t run_subspace32_select(const double* G, int n, int iters, int max_swee
     const int steps = iters < 1 ? 1 : iters;
     for (int it = 0; it < steps; ++it) {
         // P1[0] <- orthonormal basis of the (summed) product, then P2 <- G P1[0]
-        // intermediate bases only need to be well conditioned; the last one
-        // (the Rayleigh-Ritz basis) is orthonormal
+        // the last basis (the Rayleigh-Ritz one) gets the verified final correction
         hipLaunchKernelGGL(k_orth32, dim3(1), dim3(OT), ORTH_LDS, st, P1, GX_SPLIT, n, it + 1 == steps ? 1 : 0,
                            it == 0 ? 1 : 0, ok);
         if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -140,6 +140,14 @@ hipError_t run_subspace_eig(const double* G, int n, int m, int iters, int max_sw
                             hipStream_t st);
 
 // Rank choice, sign rule and factor output for mode position i (of d) on mode k.
+// Outcome of a selection kernel that the host polls for: pinned host memory,
+// written by the kernel with seq last (after a system-scope fence).
+struct HostFlags {
+    int32_t seq;
+    int32_t rank, need_dense, eig_ok, status;
+    int32_t pad[3];
+};
+
 struct SelectArgs {
     const double* lam;    // descending eigenvalues (ncand of them)
     const double* V;      // n x ncand, column j <-> lam[j]
@@ -160,6 +168,8 @@ struct SelectArgs {
     float* Mt32;          // U^T, r x n, FP32
     __bf16* Mth;          // hi/lo split of Mt32
     __bf16* Mtl;
+    HostFlags* hflags;    // null: no host report
+    int32_t seq;          // value written to hflags->seq
 };
 hipError_t launch_select_factor(const SelectArgs& a, hipStream_t st);
 
