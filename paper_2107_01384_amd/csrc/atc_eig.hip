@@ -771,16 +771,16 @@ constexpr int RW = RT / 64;
 constexpr size_t ORTH_LDS = (size_t)(OW * S32 * S32 + 2 * S32 * (S32 + 1)) * sizeof(double);
 constexpr size_t RR_LDS = (size_t)(RW * S32 * S32 + 2 * S32 * (S32 + 1)) * sizeof(double);
 
-// part[s] (n x 32) = G[:, K_s] X[K_s, :], K_s the s-th of GX_SPLIT chunks of
-// [0, n).  X == nullptr: X[k][j] = hash_unit((32 k + j) * C + salt).  One
-// wavefront per (16-row tile, chunk) on v_mfma_f64_16x16x4f64, eight K steps'
-// loads in flight.
-__global__ __launch_bounds__(64) void k_gemm_gx(const double* __restrict__ G, const double* __restrict__ X,
-                                                double* __restrict__ part, int n, uint64_t salt) {
-    const int lane = threadIdx.x;
+// Y (n x 32) = G X, X == nullptr: X[k][j] = hash_unit((32 k + j) * C + salt).
+// One workgroup of GX_SPLIT wavefronts per 16-row tile; wavefront w takes the
+// w-th K chunk on v_mfma_f64_16x16x4f64 (eight K steps' loads in flight) and
+// the partial tiles are added in LDS in wavefront order.
+__global__ __launch_bounds__(64 * GX_SPLIT) void k_gemm_gx(const double* __restrict__ G, const double* __restrict__ X,
+                                                           double* __restrict__ Y, int n, uint64_t salt) {
+    __shared__ double red[GX_SPLIT][GX_ROWS][S32 + 1];
+    const int lane = threadIdx.x & 63, s = threadIdx.x >> 6;
     const int kr = lane >> 4, cl = lane & 15;
     const int r0 = blockIdx.x * GX_ROWS;
-    const int s = blockIdx.y;
     const int chunk = (int)ceil_div(ceil_div(n, GX_SPLIT), 4) * 4;
     const int k0 = min(n, s * chunk), k1 = min(n, k0 + chunk);
     const int ra = min(r0 + cl, n - 1);
@@ -810,14 +810,19 @@ __global__ __launch_bounds__(64) void k_gemm_gx(const double* __restrict__ G, co
             acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], b1[t], acc1, 0, 0, 0);
         }
     }
-    double* out = part + (int64_t)s * n * S32;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int r = r0 + mfma16_row<PREC_F64>(lane, e);
-        if (r < n) {
-            out[(int64_t)r * S32 + cl] = acc0[e];
-            out[(int64_t)r * S32 + 16 + cl] = acc1[e];
-        }
+        const int r = mfma16_row<PREC_F64>(lane, e);
+        red[s][r][cl] = acc0[e];
+        red[s][r][16 + cl] = acc1[e];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < GX_ROWS * S32; e += 64 * GX_SPLIT) {
+        const int r = e / S32, c = e % S32;
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < GX_SPLIT; ++w) t += red[w][r][c];
+        if (r0 + r < n) Y[(int64_t)(r0 + r) * S32 + c] = t;
     }
 }
 
@@ -863,7 +868,7 @@ __device__ __forceinline__ double parts_at(const double* __restrict__ X, int64_t
 template <int NW, int NPP, int NPY>
 __device__ __forceinline__ void cross32(const double* __restrict__ P, const double* __restrict__ Y, int n,
                                         double* part_lds, double (*C)[S32 + 1]) {
-    constexpr int UNR = 4;
+    constexpr int UNR = (NW >= 8) ? 16 : 8;  // row groups whose loads go out together
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kr = lane >> 4, cl = lane & 15;
     const int64_t ps = (int64_t)n * S32;
@@ -983,6 +988,7 @@ __device__ __forceinline__ bool chol_inv32_wave(const double (*C)[S32 + 1], doub
 template <int NP, int NW>
 __device__ __forceinline__ void apply32(const double* X, double* Out, int n, const double (*B)[S32 + 1],
                                         const int* colmap) {
+    constexpr int TPW = 4;  // tiles per wavefront whose loads go out together (n <= 64 NW covered in one pass)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kr = lane >> 4, cl = lane & 15;
     const int64_t ps = (int64_t)n * S32;
@@ -993,24 +999,31 @@ __device__ __forceinline__ void apply32(const double* X, double* Out, int n, con
         bop[ks][0] = B[4 * ks + kr][c0];
         bop[ks][1] = B[4 * ks + kr][c1];
     }
-    for (int r0 = 16 * wave; r0 < n; r0 += 16 * NW) {
-        const int ra = r0 + cl;
-        const int64_t rowoff = (int64_t)(ra < n ? ra : n - 1) * S32;
-        double aop[8];
+    for (int rb = 16 * wave; rb < n; rb += 16 * NW * TPW) {
+        double aop[TPW][8];
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) aop[ks] = parts_at<NP>(X, ps, rowoff + 4 * ks + kr);
-        f64x4 acc0 = f64x4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+        for (int t = 0; t < TPW; ++t) {
+            const int ra = rb + 16 * NW * t + cl;
+            const int64_t rowoff = (int64_t)(ra < n ? ra : n - 1) * S32;
 #pragma unroll
-        for (int ks = 0; ks < 8; ++ks) {
-            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[ks], bop[ks][0], acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[ks], bop[ks][1], acc1, 0, 0, 0);
+            for (int ks = 0; ks < 8; ++ks) aop[t][ks] = parts_at<NP>(X, ps, rowoff + 4 * ks + kr);
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int r = r0 + mfma16_row<PREC_F64>(lane, e);
-            if (r < n) {
-                Out[(int64_t)r * S32 + cl] = acc0[e];
-                Out[(int64_t)r * S32 + 16 + cl] = acc1[e];
+        for (int t = 0; t < TPW; ++t) {
+            const int r0 = rb + 16 * NW * t;
+            f64x4 acc0 = f64x4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[t][ks], bop[ks][0], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[t][ks], bop[ks][1], acc1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = r0 + mfma16_row<PREC_F64>(lane, e);
+                if (r < n) {
+                    Out[(int64_t)r * S32 + cl] = acc0[e];
+                    Out[(int64_t)r * S32 + 16 + cl] = acc1[e];
+                }
             }
         }
     }
@@ -1099,18 +1112,20 @@ __global__ __launch_bounds__(OT) void k_orth32(double* __restrict__ Y, int npart
     __shared__ double spare[64];
     __shared__ int ok_s;
     const int tid = threadIdx.x;
-    // shifted pass (condition number down to about 5e-6 of the input's), then a
-    // plain pass (orthonormal to about u cond^2)
-    bool good = nparts == GX_SPLIT ? cholqr_pass<GX_SPLIT>(Y, n, true, part_lds, C, Rinv, invd, spare, &ok_s)
-                                   : cholqr_pass<1>(Y, n, true, part_lds, C, Rinv, invd, spare, &ok_s);
-    good = good && cholqr_pass<1>(Y, n, false, part_lds, C, Rinv, invd, spare, &ok_s);
-    if (full && good) {
-        // final basis: the series correction, which also verifies |Y^T Y - I|;
-        // one more plain pass if that is not yet small, else report failure
-        if (!series_pass(Y, n, part_lds, C, Rinv, &ok_s))
-            good = cholqr_pass<1>(Y, n, false, part_lds, C, Rinv, invd, spare, &ok_s) &&
-                   series_pass(Y, n, part_lds, C, Rinv, &ok_s);
+    // pass 0 shifted (condition number down to about 5e-6 of the input's), pass
+    // 1 plain (orthonormal to about u cond^2); for the final basis the series
+    // correction, which also verifies |Y^T Y - I|, and if that is not yet small
+    // a pass 2 and the series again.  One call site each keeps one inlined copy.
+    (void)nparts;
+    bool good = true, done = false;
+    for (int pass = 0; pass < 3 && good && !done; ++pass) {
+        good = cholqr_pass<1>(Y, n, pass == 0, part_lds, C, Rinv, invd, spare, &ok_s);
+        if (!good || pass == 0) continue;
+        if (!full) done = true;
+        else if (series_pass(Y, n, part_lds, C, Rinv, &ok_s)) done = true;
+        else if (pass == 2) good = false;
     }
+    good = good && done;
     if (tid == 0) *ok = first ? (good ? 1 : 0) : ((*ok && good) ? 1 : 0);
 }
 
@@ -1304,8 +1319,8 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
         }
         return;
     }
-    if (nparts == GX_SPLIT) cross32<RW, 1, GX_SPLIT>(Q, Z, n, part_lds, Bm);
-    else cross32<RW, 1, 1>(Q, Z, n, part_lds, Bm);
+    (void)nparts;
+    cross32<RW, 1, 1>(Q, Z, n, part_lds, Bm);
     for (int e = tid; e < S32 * S32; e += RT) {
         const int i = e >> 5, j = e & 31;
         Wm[i][j] = 0.5 * (Bm[i][j] + Bm[j][i]);
@@ -1400,33 +1415,34 @@ hipError_t launch_select_factor(const SelectArgs& a, hipStream_t st) {
 
 bool subspace32_available(int n) { return n >= 2 * S32 && n <= 512 && sub32_ready(); }
 
-size_t subspace32_ws_doubles(int n) { return (size_t)2 * GX_SPLIT * n * S32 + 8; }
+size_t subspace32_ws_doubles(int n) { return (size_t)2 * n * S32 + 8; }
 
 hipError_t run_subspace32_select(const double* G, int n, int iters, int max_sweeps, double* ws, const SelectArgs& sa,
                                  hipStream_t st) {
     if (!subspace32_available(n)) return hipErrorInvalidValue;
     if (sa.ncand != S32 || sa.ldv != S32 || !sa.subspace) return hipErrorInvalidValue;
-    double* P1 = ws;                                  // GX_SPLIT x n x 32
-    double* P2 = P1 + (size_t)GX_SPLIT * n * S32;     // GX_SPLIT x n x 32
-    int32_t* ok = reinterpret_cast<int32_t*>(P2 + (size_t)GX_SPLIT * n * S32);
-    const dim3 gg((unsigned)ceil_div(n, GX_ROWS), GX_SPLIT);
+    double* P1 = ws;                   // n x 32
+    double* P2 = P1 + (size_t)n * S32;  // n x 32
+    int32_t* ok = reinterpret_cast<int32_t*>(P2 + (size_t)n * S32);
+    const dim3 gg((unsigned)ceil_div(n, GX_ROWS));
+    const dim3 gb(64 * GX_SPLIT);
     hipError_t e;
-    hipLaunchKernelGGL(k_gemm_gx, gg, dim3(64), 0, st, G, (const double*)nullptr, P1, n, (uint64_t)0x5eed);
+    hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)nullptr, P1, n, (uint64_t)0x5eed);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int steps = iters < 1 ? 1 : iters;
     for (int it = 0; it < steps; ++it) {
-        // P1[0] <- orthonormal basis of the (summed) product, then P2 <- G P1[0]
-        // the last basis (the Rayleigh-Ritz one) gets the verified final correction
-        hipLaunchKernelGGL(k_orth32, dim3(1), dim3(OT), ORTH_LDS, st, P1, GX_SPLIT, n, it + 1 == steps ? 1 : 0,
+        // P1 <- orthonormal basis of its columns, then P2 <- G P1; the last basis
+        // (the Rayleigh-Ritz one) gets the verified final correction
+        hipLaunchKernelGGL(k_orth32, dim3(1), dim3(OT), ORTH_LDS, st, P1, 1, n, it + 1 == steps ? 1 : 0,
                            it == 0 ? 1 : 0, ok);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_gemm_gx, gg, dim3(64), 0, st, G, (const double*)P1, P2, n, (uint64_t)0);
+        hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)P1, P2, n, (uint64_t)0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         std::swap(P1, P2);
     }
-    // P2[0] holds the basis, P1 the parts of G times it
-    hipLaunchKernelGGL(k_rr32_select, dim3(1), dim3(RT), RR_LDS, st, (const double*)P2, (const double*)P1, GX_SPLIT,
-                       n, max_sweeps, (const int32_t*)ok, sa);
+    // P2 holds the basis, P1 = G times it
+    hipLaunchKernelGGL(k_rr32_select, dim3(1), dim3(RT), RR_LDS, st, (const double*)P2, (const double*)P1, 1, n,
+                       max_sweeps, (const int32_t*)ok, sa);
     return hipGetLastError();
 }
 
