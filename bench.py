@@ -49,6 +49,23 @@ def algorithmic_flops(dims, ranks, order):
     return gram, ttm
 
 
+def measured_traffic():
+    """HBM bytes per launch of the first-mode Gram kernel from the committed counter
+    record (profiles/gram_kc_first_mode_traffic.json), or None when that record is
+    missing or was taken on a different version of the kernel source."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    rec_path = os.path.join(here, "profiles", "gram_kc_first_mode_traffic.json")
+    try:
+        with open(rec_path) as f:
+            rec = json.load(f)
+        with open(os.path.join(here, rec["source"]), "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None
+    return rec["traffic_bytes_per_launch"] if digest == rec["source_sha256"] else None
+
+
 def time_path(atc, torch, x, eps, precision, steps, warmup, ws, out):
     for _ in range(warmup):
         atc.sthosvd(x, eps, precision, workspace=ws, out=out, profile=True)
@@ -269,8 +286,8 @@ def main():
     # dominant MFMA kernel: the first mode's Gram matrix; bf16 operations = 3 per FP32-equivalent product
     achieved = 3.0 * gram[k0] / (gram_ms[k0] * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
-                "kernel": "k_gram<bf16x3, contiguous-R> mode %d" % k0, "kernel_ms": round(gram_ms[k0], 4)}
+                "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": measured_traffic(),
+                "kernel": "k_gram_kc<bf16x3> (first mode)", "kernel_ms": round(gram_ms[k0], 4)}
 
     fp32 = None
     if not args.no_fp32:

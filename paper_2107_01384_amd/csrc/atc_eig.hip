@@ -679,15 +679,15 @@ __device__ __forceinline__ void select_factor_body(const SelectArgs& a, double* 
         double best = -1.0;
         int bi = 0x7fffffff;
         double val = 0.0;
-        for (int i0 = lane; i0 < a.n; i0 += 4 * 64) {
-            double v[4];
+        for (int i0 = lane; i0 < a.n; i0 += 8 * 64) {
+            double v[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const int i = i0 + 64 * u;
                 v[u] = a.V[(int64_t)(i < a.n ? i : a.n - 1) * a.ldv + j];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
                 const int i = i0 + 64 * u;
                 if (i < a.n && fabs(v[u]) > best) {
                     best = fabs(v[u]);
@@ -709,34 +709,40 @@ __device__ __forceinline__ void select_factor_body(const SelectArgs& a, double* 
         if (lane == 0) sign_s[j] = val < 0.0 ? -1 : 1;
     }
     __syncthreads();
-    const int64_t total = (int64_t)a.n * r;
-    for (int64_t base = tid; base < total; base += 4 * (int64_t)blockDim.x) {
-        double vv[4];
+    // factor output: 32-lane column groups (no division per element); the
+    // user factor is row-major n x r, the mode-product operand U^T is r x n
+    const int lanes_per_row = 32;
+    const int rows_per_pass = blockDim.x / lanes_per_row;
+    const int jl = tid % lanes_per_row;
+    constexpr int RB = 8;  // rows whose loads go out together
+    for (int i0 = tid / lanes_per_row; i0 < a.n; i0 += RB * rows_per_pass) {
+        for (int j = jl; j < r; j += lanes_per_row) {
+            double vv[RB];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t idx = base + q * (int64_t)blockDim.x;
-            const int64_t ii = idx < total ? idx : total - 1;
-            vv[q] = a.V[(ii / r) * a.ldv + ii % r];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-        const int64_t idx = base + q * (int64_t)blockDim.x;
-        if (idx >= total) break;
-        const int i = (int)(idx / r), j = (int)(idx % r);
-        const double u = sign_s[j] * vv[q];
-        if (a.ufac_f64) ((double*)a.ufac)[idx] = u;
-        else ((float*)a.ufac)[idx] = (float)u;
-        const int64_t t = (int64_t)j * a.n + i;  // U^T, r x n
-        if (a.Mt64) a.Mt64[t] = u;
-        if (a.Mt32) {
-            const float f = (float)u;
-            a.Mt32[t] = f;
-            if (a.Mth) {
-                const __bf16 hh = (__bf16)f;
-                a.Mth[t] = hh;
-                a.Mtl[t] = (__bf16)(f - (float)hh);
+            for (int q = 0; q < RB; ++q) {
+                const int i = i0 + q * rows_per_pass;
+                vv[q] = a.V[(int64_t)(i < a.n ? i : a.n - 1) * a.ldv + j];
             }
-        }
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const int i = i0 + q * rows_per_pass;
+                if (i >= a.n) break;
+                const double u = sign_s[j] * vv[q];
+                const int64_t idx = (int64_t)i * r + j;
+                if (a.ufac_f64) ((double*)a.ufac)[idx] = u;
+                else ((float*)a.ufac)[idx] = (float)u;
+                const int64_t t = (int64_t)j * a.n + i;  // U^T, r x n
+                if (a.Mt64) a.Mt64[t] = u;
+                if (a.Mt32) {
+                    const float f = (float)u;
+                    a.Mt32[t] = f;
+                    if (a.Mth) {
+                        const __bf16 hh = (__bf16)f;
+                        a.Mth[t] = hh;
+                        a.Mtl[t] = (__bf16)(f - (float)hh);
+                    }
+                }
+            }
         }
     }
 }

@@ -21,8 +21,6 @@
 // A workgroup accumulates one split (a few thousand terms) in FP32 and
 // writes an FP32 partial tile; the reduction adds the splits in FP64 in a
 // fixed order.
-#include <stdlib.h>
-
 #include "atc_internal.hpp"
 
 namespace atc {
@@ -266,234 +264,6 @@ __global__ __launch_bounds__(256, 2) void k_gram_kc(const float* __restrict__ X,
     }
 }
 
-// ---- pipelined variant: HBM -> LDS directly (global_load_lds_dwordx4), S
-// stages in flight, fp32 in LDS, split into bf16 hi/lo as fragments are read.
-// Stage layout: A (and B) tile 128 rows x 32 floats, row-major, the eight
-// 16-byte chunks of a row XOR-swizzled by (row & 7) so that the 32 rows a
-// fragment read touches fall in different banks.  A load instruction of
-// wavefront w in round q fills 1 KB: rows 8 (4 q + w) .. + 7, chunk c' of
-// row r taken from chunk c' ^ (r & 7) of the source.  Masked chunks read a
-// zero quad in global memory, so every LDS byte of a stage is written.
-__device__ const float kc_zero_quad[4] = {0.f, 0.f, 0.f, 0.f};
-
-// s_waitcnt immediate that waits until at most n vector-memory loads are
-// outstanding (expcnt and lgkmcnt left unconstrained).
-__host__ __device__ constexpr int kc_vmcnt(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14); }
-
-template <int S>
-__device__ __forceinline__ void kc_wait_newer(int64_t newer, bool diag) {
-    // newer = steps issued after the one about to be used that may stay in flight
-    if (newer >= S - 2) {
-        if (diag) __builtin_amdgcn_s_waitcnt(kc_vmcnt(4 * (S - 2)));
-        else __builtin_amdgcn_s_waitcnt(kc_vmcnt(8 * (S - 2)));
-    } else {
-        __builtin_amdgcn_s_waitcnt(kc_vmcnt(0));
-    }
-}
-
-__device__ __forceinline__ float4 kc_lds4(const float* tile, int row, int chunk) {
-    return *reinterpret_cast<const float4*>(tile + row * KC_BK + 4 * (chunk ^ (row & 7)));
-}
-
-__device__ __forceinline__ void kc_split8(const float4& f0, const float4& f1, bf16x8& hi, bf16x8& lo) {
-    const float x[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const __bf16 h = (__bf16)x[e];
-        hi[e] = h;
-        lo[e] = (__bf16)(x[e] - (float)h);
-    }
-}
-
-template <int P, int S>
-__global__ __launch_bounds__(256, (S <= 2 ? 2 : 1)) void k_gram_kc_pipe(const float* __restrict__ X, int n, int64_t L,
-                                                                         int64_t R, int64_t steps, int nsplit,
-                                                                         int tiles, int npairs,
-                                                                         float* __restrict__ part,
-                                                                         double* __restrict__ dpart) {
-    extern __shared__ float kc_stage[];  // S x (A, B) tiles of KC_BM x KC_BK floats
-    constexpr int TILEF = KC_BM * KC_BK;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int b = blockIdx.x;
-    const int xcd = b & 7, slot = b >> 3;
-    const int pair = slot % npairs;
-    const int split = (slot / npairs) * 8 + xcd;
-    if (split >= nsplit) return;
-    int ti, tj;
-    kc_decode_pair(pair, tiles, ti, tj);
-    const bool diag = ti == tj;
-    const int row0 = ti * KC_BM, col0 = tj * KC_BM;
-    const int64_t s0 = steps * split / nsplit, s1 = steps * (split + 1) / nsplit;
-    const int64_t spl = ceil_div(R, KC_BK);
-    (void)L;
-
-    auto issue = [&](int64_t s, int st) {
-        const int64_t l = s / spl;
-        const int64_t r = (s - l * spl) * KC_BK;
-        float* sa = kc_stage + st * 2 * TILEF;
-        float* sb = sa + TILEF;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int blk = q * 4 + wave;
-            const int row = blk * 8 + (lane >> 3);
-            const int c = (lane & 7) ^ (row & 7);
-            const int64_t rr = r + 4 * c;
-            const int ga = row0 + row;
-            const float* srca = (ga < n && rr < R) ? X + (l * n + ga) * R + rr : kc_zero_quad;
-            __builtin_amdgcn_global_load_lds((const void*)srca, (void*)(sa + blk * 256), 16, 0, 0);
-            if (!diag) {
-                const int gb = col0 + row;
-                const float* srcb = (gb < n && rr < R) ? X + (l * n + gb) * R + rr : kc_zero_quad;
-                __builtin_amdgcn_global_load_lds((const void*)srcb, (void*)(sb + blk * 256), 16, 0, 0);
-            }
-        }
-    };
-
-    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-    f32x16 acc[2][2], tot[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                acc[a][c][v] = 0.f;
-                tot[a][c][v] = 0.f;
-            }
-    double dsq = 0.0;  // diagonal tile: exact sum of squares of row tid / 2, half tid % 2
-    constexpr int FLUSH_STEPS = FLUSH_TERMS / KC_BK;
-    int since_flush = 0;
-
-#pragma unroll
-    for (int j = 0; j < S - 1; ++j)
-        if (s0 + j < s1) issue(s0 + j, j);
-    for (int64_t s = s0; s < s1; ++s) {
-        kc_wait_newer<S>(s1 - 1 - s, diag);
-        __syncthreads();
-        const int st = (int)((s - s0) % S);
-        if (s + S - 1 < s1) issue(s + S - 1, (int)((s + S - 1 - s0) % S));
-        const float* ta = kc_stage + st * 2 * TILEF;
-        const float* tb = diag ? ta : ta + TILEF;
-        if (diag) {
-            const int row = tid >> 1, h = (tid & 1) * 4;
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const float4 v = kc_lds4(ta, row, h + c);
-                const double x0 = v.x, x1 = v.y, x2 = v.z, x3 = v.w;
-                dsq += x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3;
-            }
-        }
-#pragma unroll
-        for (int sl = 0; sl < KC_BK / 16; ++sl) {
-            if constexpr (P == PREC_BF16X3) {
-                const int c1 = sl * 4 + 2 * (lane >> 5);
-                bf16x8 ah[2], al[2], bh[2], bl[2];
-#pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    const int rr = wr + a * 32 + (lane & 31);
-                    kc_split8(kc_lds4(ta, rr, c1), kc_lds4(ta, rr, c1 + 1), ah[a], al[a]);
-                }
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const int cc = wc + c * 32 + (lane & 31);
-                    kc_split8(kc_lds4(tb, cc, c1), kc_lds4(tb, cc, c1 + 1), bh[c], bl[c]);
-                }
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-#pragma unroll
-                    for (int a = 0; a < 2; ++a) {
-                        acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[c], acc[a][c], 0, 0, 0);
-                        acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[c], acc[a][c], 0, 0, 0);
-                        acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[c], acc[a][c], 0, 0, 0);
-                    }
-            } else {
-#pragma unroll
-                for (int kk = 0; kk < 16; kk += 2) {
-                    const int k = sl * 16 + kk + (lane >> 5);
-                    const int ch = k >> 2, ke = k & 3;
-                    float av[2], bv[2];
-#pragma unroll
-                    for (int a = 0; a < 2; ++a) {
-                        const int rr = wr + a * 32 + (lane & 31);
-                        av[a] = ta[rr * KC_BK + 4 * (ch ^ (rr & 7)) + ke];
-                    }
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const int cc = wc + c * 32 + (lane & 31);
-                        bv[c] = tb[cc * KC_BK + 4 * (ch ^ (cc & 7)) + ke];
-                    }
-#pragma unroll
-                    for (int a = 0; a < 2; ++a)
-#pragma unroll
-                        for (int c = 0; c < 2; ++c)
-                            acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a], bv[c], acc[a][c], 0, 0, 0);
-                }
-            }
-        }
-        if (++since_flush == FLUSH_STEPS) {
-            since_flush = 0;
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    tot[a][c] += acc[a][c];
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) acc[a][c][v] = 0.f;
-                }
-        }
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) tot[a][c] += acc[a][c];
-    float* out = part + ((int64_t)split * npairs + pair) * (KC_BM * KC_BM);
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int i = wr + a * 32 + mfma32_row(lane, v);
-                const int j = wc + c * 32 + (lane & 31);
-                out[i * KC_BM + j] = tot[a][c][v];
-            }
-    if (diag) {
-        const double sum = dsq + __shfl_xor(dsq, 1);
-        const int row = row0 + (tid >> 1);
-        if ((tid & 1) == 0 && row < n) dpart[(int64_t)split * n + row] = sum;
-    }
-}
-
-template <int S>
-constexpr size_t kc_pipe_lds() { return (size_t)S * 2 * KC_BM * KC_BK * sizeof(float); }
-
-template <int S>
-bool kc_pipe_ready() {
-    static int state = 0;
-    if (state == 0) {
-        const bool a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_kc_pipe<PREC_BF16X3, S>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kc_pipe_lds<S>()) == hipSuccess;
-        const bool c = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gram_kc_pipe<PREC_F32, S>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kc_pipe_lds<S>()) == hipSuccess;
-        state = (a && c) ? 1 : -1;
-    }
-    return state == 1;
-}
-
-template <int S>
-hipError_t launch_kc_pipe(int prec, const GramKcPlan& g, const float* X, float* part, double* dpart, hipStream_t st) {
-    if (!kc_pipe_ready<S>()) return hipErrorInvalidValue;
-    const int blocks = g.nsplit * g.npairs;
-    if (prec == PREC_BF16X3)
-        hipLaunchKernelGGL((k_gram_kc_pipe<PREC_BF16X3, S>), dim3(blocks), dim3(256), kc_pipe_lds<S>(), st, X, g.n, g.L,
-                           g.R, g.steps, g.nsplit, g.tiles, g.npairs, part, dpart);
-    else
-        hipLaunchKernelGGL((k_gram_kc_pipe<PREC_F32, S>), dim3(blocks), dim3(256), kc_pipe_lds<S>(), st, X, g.n, g.L,
-                           g.R, g.steps, g.nsplit, g.tiles, g.npairs, part, dpart);
-    return hipGetLastError();
-}
-
 __global__ void k_gram_kc_reduce(const float* __restrict__ part, const double* __restrict__ dpart, int nsplit,
                                  int npairs, int tiles, int n, double* __restrict__ G) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -548,10 +318,6 @@ hipError_t launch_gram_kc(int prec, const GramKcPlan& g, const float* X, float* 
                           hipStream_t st) {
     if (!g.ok) return hipErrorInvalidValue;
     const int blocks = g.nsplit * g.npairs;  // nsplit is a multiple of 8
-    static const int pipe = getenv("ATC_GRAM_PIPE") ? atoi(getenv("ATC_GRAM_PIPE")) : 0;
-    if (pipe == 2) return launch_kc_pipe<2>(prec, g, X, part, dpart, st);
-    if (pipe == 3) return launch_kc_pipe<3>(prec, g, X, part, dpart, st);
-    if (pipe == 4) return launch_kc_pipe<4>(prec, g, X, part, dpart, st);
     if (prec == PREC_BF16X3)
         hipLaunchKernelGGL(k_gram_kc<PREC_BF16X3>, dim3(blocks), dim3(256), 0, st, X, g.n, g.L, g.R, g.steps,
                            g.nsplit, g.tiles, g.npairs, part, dpart);
