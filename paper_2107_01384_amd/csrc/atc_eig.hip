@@ -1160,48 +1160,86 @@ __device__ inline bool rot2(double app, double aqq, double apq, double tol2, dou
 
 // Cyclic Jacobi on the symmetric A (32 x 32, LDS; only the upper triangle is
 // read or written), rotations accumulated in W (32 x 32, LDS).  Called by
-// every thread of a workgroup of at least 5 wavefronts.  Wavefront 0 runs the
-// sweeps: per round of the round-robin ordering lanes 0-15 compute the
-// rotations of the 16 pairs into the rotation log, then every lane rotates its
-// 2 x 2 blocks (pair k, pair l), k <= l (loads first, stores last; the
-// diagonal blocks set exactly).  A round with no rotation is skipped.
-// Wavefronts 1-4 meanwhile apply the previous sweep's log to 8 rows of W each;
-// one workgroup barrier per sweep.  log: 2 x 31 x 16 double2 (c, s); dd: 16
-// double2 (new diagonal); pq: 16 ints; flag: 1 int; spare: 64 doubles, all LDS.
+// every thread of a workgroup of at least 6 wavefronts.  Wavefront 0 runs the
+// sweeps over the round-robin ordering: in each round lanes 0-15 compute the
+// rotation of pair `lane` into the rotation log and write that pair's 2 x 2
+// diagonal block exactly (new diagonal, zero coupling), while every lane
+// holds two of the 120 off-diagonal blocks (pair k, pair l), k < l, whose
+// LDS offsets come from a per-round table, so their loads go out before the
+// rotations are computed; after one wavefront sync the lanes read the two
+// rotations each block needs and store it.  A round with no rotation is
+// skipped.  Wavefronts 1, 2, 3 and 5 (off wavefront 0's SIMD) meanwhile
+// apply the previous sweep's log to 8 rows of W each; one workgroup barrier
+// per sweep.  log: 2 x 31 x 16 double2 (c, s); ptab: 31 x 16 ints; btab:
+// 31 x 128 uint4 (62 KB); flag: 1 int; all LDS.  Unused block slots point at
+// the padding column of A, which nothing reads.
 __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 + 1], int max_sweeps, double2* log,
-                                         double2* dd, int* pq, int* flag, double* spare, int& sweeps_out,
-                                         bool& conv_out) {
-    constexpr int H = S32 / 2;
-    constexpr int NB = H * (H + 1) / 2;  // 136 blocks
-    constexpr int LOGR = (S32 - 1) * H;  // records per sweep
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                         int* ptab, uint4* btab, int* flag, int& sweeps_out, bool& conv_out) {
+    constexpr int H = S32 / 2;             // pairs per round
+    constexpr int NR = S32 - 1;            // rounds per sweep
+    constexpr int NOFF = H * (H - 1) / 2;  // off-diagonal blocks per round
+    constexpr int SL = 128;                // block slots per round, two per lane
+    constexpr int LOGR = NR * H;           // rotation records per sweep
+    static_assert(NOFF <= SL && SL - NOFF <= S32, "block slots");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double tol = (double)S32 * 0x1p-53;
     const double tol2 = tol * tol;
-    int kt[3], lt[3];
-    bool vt[3];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        int idx = lane + 64 * t;
-        vt[t] = idx < NB;
-        int k = 0;
-        if (vt[t])
-            while (idx >= H - k) {
-                idx -= H - k;
-                ++k;
-            }
-        kt[t] = vt[t] ? k : 0;
-        lt[t] = vt[t] ? k + idx : 0;
+    char* const abase = reinterpret_cast<char*>(&A[0][0]);
+    for (int e = tid; e < LOGR; e += blockDim.x) {
+        int p, q;
+        round_robin_pair(e / H, e % H, S32, p, q);
+        ptab[e] = p | (q << 8);
     }
-    // canonical (upper triangle) element
-    auto U = [&](int x, int y) -> double& { return x < y ? A[x][y] : A[y][x]; };
-    // wavefronts 1-4: rows 8 (wave - 1) + lane / 8, pairs lane % 8 and lane % 8 + 8
+    // block slot b < NOFF -> (k, l), k < l, in row-major order of the strict upper triangle
+    auto block_kl = [](int b, int& k, int& l) {
+        k = 0;
+        while (b >= H - 1 - k) {
+            b -= H - 1 - k;
+            ++k;
+        }
+        l = k + 1 + b;
+    };
+    __syncthreads();
+    for (int e = tid; e < NR * SL; e += blockDim.x) {
+        const int r = e / SL, b = e % SL;
+        uint4 o;
+        if (b < NOFF) {
+            int k, l;
+            block_kl(b, k, l);
+            const int c1 = ptab[r * H + k], c2 = ptab[r * H + l];
+            const int p = c1 & 255, q = c1 >> 8, p2 = c2 & 255, q2 = c2 >> 8;
+            auto off = [](int x, int y) -> unsigned {
+                return (unsigned)((x < y ? x * (S32 + 1) + y : y * (S32 + 1) + x) * (int)sizeof(double));
+            };
+            o = make_uint4(off(p, p2), off(p, q2), off(q, p2), off(q, q2));
+        } else {
+            const unsigned pad = (unsigned)(((b - NOFF) * (S32 + 1) + S32) * (int)sizeof(double));
+            o = make_uint4(pad, pad, pad, pad);
+        }
+        btab[e] = o;
+    }
+    int kt[2], lt[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int b = lane + 64 * t;
+        if (b < NOFF) {
+            block_kl(b, kt[t], lt[t]);
+        } else {
+            kt[t] = 0;
+            lt[t] = 0;
+        }
+    }
+    __syncthreads();
+    auto at = [&](unsigned off) -> double& { return *reinterpret_cast<double*>(abase + off); };
+    // wavefronts 1, 2, 3, 5: rows 8 j + lane / 8 (j = 0..3), pairs lane % 8 and lane % 8 + 8
+    const bool w_apply = wave == 1 || wave == 2 || wave == 3 || wave == 5;
     auto apply_log = [&](const double2* lg) {
-        const int i = 8 * (wave - 1) + (lane >> 3);
+        const int j = wave == 5 ? 3 : wave - 1;
+        const int i = 8 * j + (lane >> 3);
         const int k0 = lane & 7;
-        for (int round = 0; round < S32 - 1; ++round) {
-            int p0, q0, p1, q1;
-            round_robin_pair(round, k0, S32, p0, q0);
-            round_robin_pair(round, k0 + 8, S32, p1, q1);
+        for (int round = 0; round < NR; ++round) {
+            const int c0 = ptab[round * H + k0], c1 = ptab[round * H + k0 + 8];
+            const int p0 = c0 & 255, q0 = c0 >> 8, p1 = c1 & 255, q1 = c1 >> 8;
             const double2 r0 = lg[round * H + k0], r1 = lg[round * H + k0 + 8];
             const double x0 = W[i][p0], y0 = W[i][q0], x1 = W[i][p1], y1 = W[i][q1];
             // (c, s) = (1, 0) for a pair that did not rotate: the same values back
@@ -1218,70 +1256,58 @@ __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 +
         double2* lg = log + (sweeps & 1) * LOGR;
         if (wave == 0) {
             bool any = false;
-            for (int round = 0; round < S32 - 1; ++round) {
+            uint4 ad[2] = {btab[lane], btab[64 + lane]};
+            int me = ptab[lane & (H - 1)];
+            for (int round = 0; round < NR; ++round) {
+                double x[2][4];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    x[t][0] = at(ad[t].x);
+                    x[t][1] = at(ad[t].y);
+                    x[t][2] = at(ad[t].z);
+                    x[t][3] = at(ad[t].w);
+                }
+                const int mp = me & 255, mq = me >> 8;
+                const double app = A[mp][mp], aqq = A[mq][mq], apq = A[mp][mq];
+                const int rn = round + 1 < NR ? round + 1 : 0;
+                const uint4 nad0 = btab[rn * SL + lane], nad1 = btab[rn * SL + 64 + lane];
+                const int nme = ptab[rn * H + (lane & (H - 1))];
                 bool r = false;
                 if (lane < H) {
-                    int p, q;
-                    round_robin_pair(round, lane, S32, p, q);
                     double c, s, dp, dq;
-                    r = rot2(A[p][p], A[q][q], A[p][q], tol2, c, s, dp, dq);
+                    r = rot2(app, aqq, apq, tol2, c, s, dp, dq);
                     lg[round * H + lane] = double2{c, s};
-                    dd[lane] = double2{dp, dq};
-                    pq[lane] = p | (q << 8);
+                    A[mp][mp] = dp;
+                    A[mq][mq] = dq;
+                    A[mp][mq] = r ? 0.0 : apq;
                 }
-                if (__ballot(r) == 0) continue;
-                any = true;
-                wave_sync();
-                double2 ck[3], cl[3], dk[3];
-                int pk[3], pl[3];
+                if (__ballot(r) != 0) {
+                    any = true;
+                    wave_sync();
+                    double2 ck[2], cl[2];
 #pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    ck[t] = lg[round * H + kt[t]];
-                    cl[t] = lg[round * H + lt[t]];
-                    dk[t] = dd[kt[t]];
-                    pk[t] = pq[kt[t]];
-                    pl[t] = pq[lt[t]];
-                }
-                double x[3][4];
-#pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    const int p = pk[t] & 255, q = pk[t] >> 8, p2 = pl[t] & 255, q2 = pl[t] >> 8;
-                    x[t][0] = U(p, p2);
-                    x[t][1] = U(p, q2);
-                    x[t][2] = U(q, p2);
-                    x[t][3] = U(q, q2);
-                }
-                wave_sync();
-                // branch-free stores (a branch would let the compiler sink the
-                // loads above into it); blocks a lane does not own go to spare
-#pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    const int p = pk[t] & 255, q = pk[t] >> 8, p2 = pl[t] & 255, q2 = pl[t] >> 8;
-                    const double c1 = ck[t].x, s1 = ck[t].y, c2 = cl[t].x, s2 = cl[t].y;
-                    const double ra = c1 * x[t][0] - s1 * x[t][2], rb = c1 * x[t][1] - s1 * x[t][3];
-                    const double rc = s1 * x[t][0] + c1 * x[t][2], rd = s1 * x[t][1] + c1 * x[t][3];
-                    double n0 = c2 * ra - s2 * rb, n1 = s2 * ra + c2 * rb;
-                    double n2 = c2 * rc - s2 * rd, n3 = s2 * rc + c2 * rd;
-                    if (kt[t] == lt[t]) {  // the rotated pair itself: exact new diagonal
-                        const bool rot_k = s1 != 0.0;
-                        n0 = rot_k ? dk[t].x : x[t][0];
-                        n1 = rot_k ? 0.0 : x[t][1];
-                        n2 = n1;
-                        n3 = rot_k ? dk[t].y : x[t][3];
+                    for (int t = 0; t < 2; ++t) {
+                        ck[t] = lg[round * H + kt[t]];
+                        cl[t] = lg[round * H + lt[t]];
                     }
-                    double* d0 = vt[t] ? &U(p, p2) : &spare[lane];
-                    double* d1 = vt[t] ? &U(p, q2) : &spare[lane];
-                    double* d2 = vt[t] ? &U(q, p2) : &spare[lane];
-                    double* d3 = vt[t] ? &U(q, q2) : &spare[lane];
-                    *d0 = n0;
-                    *d1 = n1;
-                    *d2 = n2;
-                    *d3 = n3;
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const double c1 = ck[t].x, s1 = ck[t].y, c2 = cl[t].x, s2 = cl[t].y;
+                        const double ra = c1 * x[t][0] - s1 * x[t][2], rb = c1 * x[t][1] - s1 * x[t][3];
+                        const double rc = s1 * x[t][0] + c1 * x[t][2], rd = s1 * x[t][1] + c1 * x[t][3];
+                        at(ad[t].x) = c2 * ra - s2 * rb;
+                        at(ad[t].y) = s2 * ra + c2 * rb;
+                        at(ad[t].z) = c2 * rc - s2 * rd;
+                        at(ad[t].w) = s2 * rc + c2 * rd;
+                    }
+                    wave_sync();
                 }
-                wave_sync();
+                ad[0] = nad0;
+                ad[1] = nad1;
+                me = nme;
             }
             if (lane == 0) *flag = any ? 1 : 0;
-        } else if (wave <= 4 && sweeps > 0) {
+        } else if (w_apply && sweeps > 0) {
             apply_log(log + ((sweeps - 1) & 1) * LOGR);
         }
         __syncthreads();
@@ -1289,7 +1315,7 @@ __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 +
         ++sweeps;
         __syncthreads();
     }
-    if (wave >= 1 && wave <= 4 && sweeps > 0) apply_log(log + ((sweeps - 1) & 1) * LOGR);
+    if (w_apply && sweeps > 0) apply_log(log + ((sweeps - 1) & 1) * LOGR);
     __syncthreads();
     sweeps_out = sweeps;
     conv_out = conv;
@@ -1306,10 +1332,8 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
     double(*Bm)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + RW * S32 * S32);
     double(*Wm)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + RW * S32 * S32 + S32 * (S32 + 1));
     __shared__ double2 jlog[2 * (S32 - 1) * (S32 / 2)];
-    __shared__ double2 jdd[S32 / 2];
-    __shared__ int jpq[S32 / 2];
+    __shared__ int jptab[(S32 - 1) * (S32 / 2)];
     __shared__ int jflag;
-    __shared__ double jspare[64];
     __shared__ int col_of[S32];
     __shared__ double lam_s[S32];
     __shared__ double red[17];
@@ -1341,7 +1365,9 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
     {
         int sw;
         bool cv;
-        jacobi32(Bm, Wm, max_sweeps, jlog, jdd, jpq, &jflag, jspare, sw, cv);
+        // the cross-product partials are dead here: their space holds the block table
+        static_assert(RW * S32 * S32 * sizeof(double) >= (S32 - 1) * 128 * sizeof(uint4), "block table");
+        jacobi32(Bm, Wm, max_sweeps, jlog, jptab, reinterpret_cast<uint4*>(part_lds), &jflag, sw, cv);
         if (tid == 0) {
             sweeps_s = sw;
             conv_s = cv ? 1 : 0;
