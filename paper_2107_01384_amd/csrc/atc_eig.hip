@@ -926,64 +926,56 @@ __device__ __forceinline__ void cross32(const double* __restrict__ P, const doub
     __syncthreads();
 }
 
-// Upper Cholesky factor R of C (32 x 32, LDS, symmetric) and its inverse, by
-// one wavefront: lane b (mod 32) keeps column b in registers and the other
-// lanes' entries arrive by readlane.  The steps are unrolled through templates
-// so every register index is static; a scheduling barrier after each
-// broadcast-and-update keeps the compiler from hoisting all broadcasts of a
-// step at once.  Rinv (LDS) receives R^{-1} (upper triangular, zeros below).
-// Returns false (on every lane) when a pivot is not positive and finite.
+// R^{-1} for the upper Cholesky factor R of C (32 x 32, LDS, symmetric), by one
+// wavefront, without forming R: the row operations that reduce C to the
+// identity (right-looking Cholesky, R^T R = C) are applied to the identity as
+// well, which leaves R^{-T} = L^{-1} (column-oriented forward substitution).
+// Lanes 0-31 keep column b = lane of the trailing matrix in registers, lanes
+// 32-63 column b = lane - 32 of the identity being transformed.  At step J
+// every lane publishes its v[J] in rowbuf (64 doubles, LDS; the upper half is
+// never read), all lanes read row J of the trailing matrix back as uniform
+// loads, d = C'[J][J] gives r = d^{-1/2}, and each lane subtracts
+// rowbuf[a] v[J] / d from v[a], a > J.  v[J] r of an identity lane is final
+// (entry J of row b of R^{-1}, exact zero below the diagonal) and goes to
+// Rinv at once; the other lanes store into the padding column of Rinv.  No
+// branches: the steps are unrolled through templates so every register index
+// is static.  Returns false (on every lane) when a pivot is not positive and
+// finite.
 template <int J>
-__device__ __forceinline__ void chol_step(double (&c)[S32], int lane, bool& ok, double* invd) {
+__device__ __forceinline__ void cinv_step(double (&v)[S32], double* rowbuf, double (*Rinv)[S32 + 1], bool idl, int b,
+                                          bool& ok) {
     if constexpr (J < S32) {
-        const double d = lane_bcast(c[J], J);
+        const int lane = threadIdx.x & 63;
+        rowbuf[lane] = v[J];
+        wave_sync();
+        double rb[S32 - J];
+#pragma unroll
+        for (int a = J; a < S32; ++a) rb[a - J] = rowbuf[a];
+        const double d = rb[0];
         ok = ok && (d > 0.0) && (d < INFINITY);
-        const double r = ok ? rsqrt_nr(d) : 0.0;
-        if (lane == 0) invd[J] = r;
-        const double rjb = c[J] * r;  // R[J][b]
-        c[J] = rjb;
+        double r = rsqrt_nr(d);
+        r = ok ? r : 0.0;
+        const double s = v[J] * (r * r);
+        *(idl ? &Rinv[b][J] : &Rinv[b][S32]) = v[J] * r;
 #pragma unroll
-        for (int a = J + 1; a < S32; ++a) {
-            c[a] -= lane_bcast(rjb, a) * rjb;
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        chol_step<J + 1>(c, lane, ok, invd);
+        for (int a = J + 1; a < S32; ++a) v[a] -= rb[a - J] * s;
+        cinv_step<J + 1>(v, rowbuf, Rinv, idl, b, ok);
     }
 }
 
-// Column b of X = R^{-1} from R X = I, rows from the bottom: R[I][k] (k > I) is
-// c[I] of lane k, and x[I] replaces c[I] once row I of R has been used.
-template <int I>
-__device__ __forceinline__ void rinv_step(double (&c)[S32], int lane, const double* invd) {
-    if constexpr (I >= 0) {
-        const int b = lane & 31;
-        double t = 0.0;
-#pragma unroll
-        for (int k = I + 1; k < S32; ++k) {
-            t += lane_bcast(c[I], k) * c[k];
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        const double inv = invd[I];
-        c[I] = (I == b) ? inv : ((I < b) ? -t * inv : 0.0);
-        rinv_step<I - 1>(c, lane, invd);
-    }
-}
-
-__device__ __forceinline__ bool chol_inv32_wave(const double (*C)[S32 + 1], double (*Rinv)[S32 + 1], double* invd) {
+__device__ __forceinline__ bool chol_inv32_wave(const double (*C)[S32 + 1], double (*Rinv)[S32 + 1],
+                                                double* rowbuf) {
     const int lane = threadIdx.x & 63, b = lane & 31;
-    double c[S32];
+    const bool idl = lane >= S32;
+    double v[S32];
 #pragma unroll
-    for (int a = 0; a < S32; ++a) c[a] = C[a][b];
-    bool ok = true;
-    chol_step<0>(c, lane, ok, invd);
-    if (!ok) return false;
-    wave_sync();
-    rinv_step<S32 - 1>(c, lane, invd);
-    if (lane < S32) {
-#pragma unroll
-        for (int i = 0; i < S32; ++i) Rinv[i][b] = c[i];
+    for (int a = 0; a < S32; ++a) {
+        const double c = C[a][b];
+        v[a] = idl ? (a == b ? 1.0 : 0.0) : c;
     }
-    return true;
+    bool ok = true;
+    cinv_step<0>(v, rowbuf, Rinv, idl, b, ok);
+    return ok;
 }
 
 // Out[r][j] = sum_k X[r][k] B[k][col(j)] for an n x 32 X (the sum of NP partial
@@ -1041,7 +1033,7 @@ __device__ __forceinline__ void apply32(const double* X, double* Out, int n, con
 // v_mfma_f64_16x16x4f64, 16-row tiles per wavefront, R^{-1} held in registers.
 template <int NP>
 __device__ __forceinline__ bool cholqr_pass(double* __restrict__ Y, int n, bool shifted, double* part_lds,
-                                            double (*C)[S32 + 1], double (*Rinv)[S32 + 1], double* invd, double* spare,
+                                            double (*C)[S32 + 1], double (*Rinv)[S32 + 1], double* rowbuf,
                                             int* ok_s) {
     const int tid = threadIdx.x;
     cross32<OW, NP, NP>(Y, Y, n, part_lds, C);
@@ -1056,7 +1048,7 @@ __device__ __forceinline__ bool cholqr_pass(double* __restrict__ Y, int n, bool 
             if (tid < S32) C[tid][tid] += sh;
             wave_sync();
         }
-        const bool ok = chol_inv32_wave(C, Rinv, invd);
+        const bool ok = chol_inv32_wave(C, Rinv, rowbuf);
         if (tid == 0) *ok_s = ok ? 1 : 0;
     }
     __syncthreads();
@@ -1114,8 +1106,7 @@ __global__ __launch_bounds__(OT) void k_orth32(double* __restrict__ Y, int npart
     double* part_lds = lds;
     double(*C)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + OW * S32 * S32);
     double(*Rinv)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + OW * S32 * S32 + S32 * (S32 + 1));
-    __shared__ double invd[S32];
-    __shared__ double spare[64];
+    __shared__ double rowbuf[64];
     __shared__ int ok_s;
     const int tid = threadIdx.x;
     // pass 0 shifted (condition number down to about 5e-6 of the input's), pass
@@ -1125,7 +1116,7 @@ __global__ __launch_bounds__(OT) void k_orth32(double* __restrict__ Y, int npart
     (void)nparts;
     bool good = true, done = false;
     for (int pass = 0; pass < 3 && good && !done; ++pass) {
-        good = cholqr_pass<1>(Y, n, pass == 0, part_lds, C, Rinv, invd, spare, &ok_s);
+        good = cholqr_pass<1>(Y, n, pass == 0, part_lds, C, Rinv, rowbuf, &ok_s);
         if (!good || pass == 0) continue;
         if (!full) done = true;
         else if (series_pass(Y, n, part_lds, C, Rinv, &ok_s)) done = true;
