@@ -595,85 +595,117 @@ __device__ inline void publish_selection(const SelectArgs& a, int rank) {
 }
 
 // Rank choice (Section 4.1.3), sign rule and factor output for one mode, run
-// by a whole workgroup (any multiple of 64 threads).  red: 17 doubles, sign_s:
-// n ints, r_s: 1 int, all in LDS.
-__device__ __forceinline__ void select_factor_body(const SelectArgs& a, double* red, int* sign_s, int& r_s) {
+// by a whole workgroup (any multiple of 64 threads).  The pieces: gram_trace
+// (every thread), choose_rank (thread 0: budget, rank, book, host flags),
+// store_factor (one entry of the user factor and of the mode-product operand)
+// and sign_factor_from_v (sign rule and factor output from V in global memory).
+
+// trace of G (fixed-order block sum); red: 17 doubles of LDS
+__device__ __forceinline__ double gram_trace(const SelectArgs& a, double* red) {
+    double part = 0.0;
+    for (int i = threadIdx.x; i < a.n; i += blockDim.x) part += a.G[(int64_t)i * a.n + i];
+    return block_sum(part, red);
+}
+
+// Thread 0 only: the rank from the eigenvalues (or Ritz values) a.lam and the
+// trace; the book entries, the host flags.  r_s <- rank, dense_s <- 1 when the
+// subspace does not hold enough Ritz pairs (the caller then stops: the host
+// moves to a larger eigensolver).
+__device__ __forceinline__ void choose_rank(const SelectArgs& a, double tr, int& r_s, int& dense_s) {
+    DevBook* bk = a.book;
+    if (a.pos == 0) {
+        bk->norm2 = tr;
+        bk->S = a.rtmss * a.eps2 * tr;
+        bk->used = 0.0;
+        if (!isfinite(tr)) bk->status = ATC_ERR_NONFINITE_INPUT;
+    }
+    bk->trace[a.k] = tr;
+    const double b = (a.rule == ATC_RANK_EQUAL) ? bk->S / a.d : (bk->S - bk->used) / (a.d - a.pos);
+    int r = a.n;
+    double tail_r = 0.0;
+    if (!a.subspace) {
+        // tail(r) = sum_{j >= r} lam_j, added from the smallest upward; the
+        // eigenvalues are not clamped, so rounding-level negative values of
+        // an FP32-accurate Gram matrix offset the positive ones
+        double acc = 0.0;
+        int best = a.n;
+        double best_tail = 0.0;
+        for (int j = a.n - 1; j >= 0; --j) {
+            if (acc <= b) {  // acc = tail at r = j + 1
+                best = j + 1;
+                best_tail = acc;
+            }
+            acc += a.lam[j];
+        }
+        r = best;
+        tail_r = best_tail;
+        if (a.fixed_rank > 0) {
+            r = a.fixed_rank;
+            double t = 0.0;
+            for (int j = a.n - 1; j >= r; --j) t += a.lam[j];
+            tail_r = t;
+        }
+    } else {
+        // tail(r) = trace - sum_{j < r} theta_j (an upper bound of the true tail)
+        double pre = 0.0;
+        int found = -1;
+        for (int j = 0; j < a.ncand; ++j) {
+            pre += a.lam[j];
+            const double t = tr - pre;
+            if (found < 0 && t <= b) {
+                found = j + 1;
+                tail_r = t > 0.0 ? t : 0.0;
+            }
+            if (a.fixed_rank > 0 && j + 1 == a.fixed_rank) {
+                found = a.fixed_rank;
+                tail_r = t > 0.0 ? t : 0.0;
+                break;
+            }
+        }
+        if (found < 0 || found > a.ncand - a.guard || !(a.lam[found - 1] > 0.0)) {
+            bk->need_dense = 1;
+            found = a.ncand < a.n ? a.ncand : a.n;
+        }
+        r = found;
+    }
+    const int dense = bk->need_dense;
+    if (dense == 0) {
+        bk->used += tail_r;
+        bk->tail[a.k] = tail_r;
+        bk->budget[a.k] = b;
+        bk->rank[a.k] = r;
+    }
+    r_s = r;
+    dense_s = dense;
+    publish_selection(a, r);
+}
+
+// Entry (i, j) of the factor, u with its sign applied: the user factor is
+// row-major n x r, the mode-product operand U^T is r x n (FP64, or FP32 with
+// its bf16 hi / lo split).
+__device__ __forceinline__ void store_factor(const SelectArgs& a, int i, int j, int r, double u) {
+    const int64_t idx = (int64_t)i * r + j;
+    if (a.ufac_f64) ((double*)a.ufac)[idx] = u;
+    else ((float*)a.ufac)[idx] = (float)u;
+    const int64_t t = (int64_t)j * a.n + i;
+    if (a.Mt64) a.Mt64[t] = u;
+    if (a.Mt32) {
+        const float f = (float)u;
+        a.Mt32[t] = f;
+        if (a.Mth) {
+            const __bf16 hh = (__bf16)f;
+            a.Mth[t] = hh;
+            a.Mtl[t] = (__bf16)(f - (float)hh);
+        }
+    }
+}
+
+// Sign rule (largest-magnitude entry of each kept column positive, first row
+// on ties) and factor output for the leading r columns of V (global, n x ldv).
+// sign_s: r ints of LDS.
+__device__ __forceinline__ void sign_factor_from_v(const SelectArgs& a, int r, int* sign_s) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    DevBook* bk = a.book;
-    // trace of G (fixed-order block sum)
-    double part = 0.0;
-    for (int i = tid; i < a.n; i += blockDim.x) part += a.G[(int64_t)i * a.n + i];
-    const double tr = block_sum(part, red);
-    if (tid == 0) {
-        if (a.pos == 0) {
-            bk->norm2 = tr;
-            bk->S = a.rtmss * a.eps2 * tr;
-            bk->used = 0.0;
-            if (!isfinite(tr)) bk->status = ATC_ERR_NONFINITE_INPUT;
-        }
-        bk->trace[a.k] = tr;
-        const double b = (a.rule == ATC_RANK_EQUAL) ? bk->S / a.d : (bk->S - bk->used) / (a.d - a.pos);
-        int r = a.n;
-        double tail_r = 0.0;
-        if (!a.subspace) {
-            // tail(r) = sum_{j >= r} lam_j, added from the smallest upward; the
-            // eigenvalues are not clamped, so rounding-level negative values of
-            // an FP32-accurate Gram matrix offset the positive ones
-            double acc = 0.0;
-            int best = a.n;
-            double best_tail = 0.0;
-            for (int j = a.n - 1; j >= 0; --j) {
-                if (acc <= b) {  // acc = tail at r = j + 1
-                    best = j + 1;
-                    best_tail = acc;
-                }
-                acc += a.lam[j];
-            }
-            r = best;
-            tail_r = best_tail;
-            if (a.fixed_rank > 0) {
-                r = a.fixed_rank;
-                double t = 0.0;
-                for (int j = a.n - 1; j >= r; --j) t += a.lam[j];
-                tail_r = t;
-            }
-        } else {
-            // tail(r) = trace - sum_{j < r} theta_j (an upper bound of the true tail)
-            double pre = 0.0;
-            int found = -1;
-            for (int j = 0; j < a.ncand; ++j) {
-                pre += a.lam[j];
-                const double t = tr - pre;
-                if (found < 0 && t <= b) {
-                    found = j + 1;
-                    tail_r = t > 0.0 ? t : 0.0;
-                }
-                if (a.fixed_rank > 0 && j + 1 == a.fixed_rank) {
-                    found = a.fixed_rank;
-                    tail_r = t > 0.0 ? t : 0.0;
-                    break;
-                }
-            }
-            if (found < 0 || found > a.ncand - a.guard || !(a.lam[found - 1] > 0.0)) {
-                bk->need_dense = 1;
-                found = a.ncand < a.n ? a.ncand : a.n;
-            }
-            r = found;
-        }
-        if (bk->need_dense == 0) {
-            bk->used += tail_r;
-            bk->tail[a.k] = tail_r;
-            bk->budget[a.k] = b;
-            bk->rank[a.k] = r;
-        }
-        r_s = r;
-        publish_selection(a, r);
-    }
-    __syncthreads();
-    if (bk->need_dense) return;
-    const int r = r_s;
-    // sign rule: largest-magnitude entry of each kept column positive (first row on ties);
     // one wave per column, lanes scan rows, then a fixed-order shuffle reduction
     for (int j = wave; j < r; j += nw) {
         double best = -1.0;
@@ -709,8 +741,7 @@ __device__ __forceinline__ void select_factor_body(const SelectArgs& a, double* 
         if (lane == 0) sign_s[j] = val < 0.0 ? -1 : 1;
     }
     __syncthreads();
-    // factor output: 32-lane column groups (no division per element); the
-    // user factor is row-major n x r, the mode-product operand U^T is r x n
+    // 32-lane column groups (no division per element)
     const int lanes_per_row = 32;
     const int rows_per_pass = blockDim.x / lanes_per_row;
     const int jl = tid % lanes_per_row;
@@ -727,24 +758,20 @@ __device__ __forceinline__ void select_factor_body(const SelectArgs& a, double* 
             for (int q = 0; q < RB; ++q) {
                 const int i = i0 + q * rows_per_pass;
                 if (i >= a.n) break;
-                const double u = sign_s[j] * vv[q];
-                const int64_t idx = (int64_t)i * r + j;
-                if (a.ufac_f64) ((double*)a.ufac)[idx] = u;
-                else ((float*)a.ufac)[idx] = (float)u;
-                const int64_t t = (int64_t)j * a.n + i;  // U^T, r x n
-                if (a.Mt64) a.Mt64[t] = u;
-                if (a.Mt32) {
-                    const float f = (float)u;
-                    a.Mt32[t] = f;
-                    if (a.Mth) {
-                        const __bf16 hh = (__bf16)f;
-                        a.Mth[t] = hh;
-                        a.Mtl[t] = (__bf16)(f - (float)hh);
-                    }
-                }
+                store_factor(a, i, j, r, sign_s[j] * vv[q]);
             }
         }
     }
+}
+
+// red: 17 doubles, sign_s: n ints, r_s: 1 int, all in LDS.
+__device__ __forceinline__ void select_factor_body(const SelectArgs& a, double* red, int* sign_s, int& r_s) {
+    __shared__ int dense_s;
+    const double tr = gram_trace(a, red);
+    if (threadIdx.x == 0) choose_rank(a, tr, r_s, dense_s);
+    __syncthreads();
+    if (dense_s) return;
+    sign_factor_from_v(a, r_s, sign_s);
 }
 
 __global__ __launch_bounds__(256) void k_select_factor(SelectArgs a) {
@@ -765,8 +792,8 @@ __global__ __launch_bounds__(256) void k_select_factor(SelectArgs a) {
 //   Q1 = orth(G Q0)       the same two passes, then the series C^{-1/2} = I - E/2
 //                         + 3 E^2 / 8 of C = Q^T Q = I + E, which also checks |E|
 //   Z = G Q1
-//   B = Q1^T Z = W diag(theta) W^T (one-wavefront Jacobi), V = Q1 W, then the
-//   rank choice, sign rule and factor output of select_factor_body.
+//   B = Q1^T Z = W diag(theta) W^T (one-wavefront Jacobi), the rank choice
+//   from theta, then V = Q1 W in registers, its sign rule and the factor output.
 constexpr int S32 = 32;
 constexpr int GX_ROWS = 16;   // rows of G per workgroup of k_gemm_gx
 constexpr int GX_SPLIT = 4;   // K chunks; the consumer adds the partial products
@@ -1095,12 +1122,11 @@ __device__ __forceinline__ bool series_pass(double* __restrict__ Y, int n, doubl
     return true;
 }
 
-// Orthonormal basis of the columns of Y = sum of nparts arrays (n x 32 each,
-// spaced n x 32 apart), written over the first array: a shifted Cholesky QR
-// pass and a plain one; with full != 0 (the Rayleigh-Ritz basis) also the
+// Orthonormal basis of the columns of Y (n x 32, global), in place: a shifted
+// Cholesky QR pass and a plain one; with full != 0 (the Rayleigh-Ritz basis) also the
 // verified series correction.  *ok = 1 on success (first != 0) or *ok &=
 // success (first == 0).
-__global__ __launch_bounds__(OT) void k_orth32(double* __restrict__ Y, int nparts, int n, int full, int first,
+__global__ __launch_bounds__(OT) void k_orth32(double* __restrict__ Y, int n, int full, int first,
                                                int32_t* __restrict__ ok) {
     extern __shared__ double lds[];
     double* part_lds = lds;
@@ -1113,7 +1139,6 @@ __global__ __launch_bounds__(OT) void k_orth32(double* __restrict__ Y, int npart
     // 1 plain (orthonormal to about u cond^2); for the final basis the series
     // correction, which also verifies |Y^T Y - I|, and if that is not yet small
     // a pass 2 and the series again.  One call site each keeps one inlined copy.
-    (void)nparts;
     bool good = true, done = false;
     for (int pass = 0; pass < 3 && good && !done; ++pass) {
         good = cholqr_pass<1>(Y, n, pass == 0, part_lds, C, Rinv, rowbuf, &ok_s);
@@ -1312,11 +1337,114 @@ __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 +
     conv_out = conv;
 }
 
-// Rayleigh-Ritz on span(Q) (Q n x 32 orthonormal, Z = G Q given as nparts
-// partial arrays), then rank choice and factor output.  When either
+// Best-|v| candidate of one column for the sign rule.
+struct SignCand {
+    double best, val;
+    int row, pad;
+};
+
+// Merges candidate (ob, oi, ov) into (best, bi, val): larger |v| wins, the
+// smaller row on ties (the first row, whatever the order of the merges).
+__device__ __forceinline__ void sign_merge(double& best, int& bi, double& val, double ob, int oi, double ov) {
+    if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+        val = ov;
+    }
+}
+
+// V = Q W[:, colmap] for n <= 16 RW TPW rows, on v_mfma_f64_16x16x4f64 as in
+// apply32, kept in the accumulators: the sign rule over the leading r columns
+// (per-wavefront candidates in LDS, merged in wavefront order) and the factor
+// output come straight from registers, so V never goes to memory.  cand: RW x
+// 32 records, sign_s: 32 ints, both LDS.
+__device__ __forceinline__ void rr_factor_out(const SelectArgs& a, const double* __restrict__ Q, int n,
+                                              const double (*B)[S32 + 1], const int* colmap, int r, SignCand* cand,
+                                              int* sign_s) {
+    constexpr int TPW = 4;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kr = lane >> 4, cl = lane & 15;
+    const int c0 = colmap[cl], c1 = colmap[16 + cl];
+    double bop[8][2];
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+        bop[ks][0] = B[4 * ks + kr][c0];
+        bop[ks][1] = B[4 * ks + kr][c1];
+    }
+    double aop[TPW][8];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int ra = 16 * wave + 16 * RW * t + cl;
+        const int64_t rowoff = (int64_t)(ra < n ? ra : n - 1) * S32;
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) aop[t][ks] = Q[rowoff + 4 * ks + kr];
+    }
+    f64x4 acc[TPW][2];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        acc[t][0] = f64x4{0.0, 0.0, 0.0, 0.0};
+        acc[t][1] = acc[t][0];
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[t][ks], bop[ks][0], acc[t][0], 0, 0, 0);
+            acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[t][ks], bop[ks][1], acc[t][1], 0, 0, 0);
+        }
+    }
+    // sign candidates of columns cl (h = 0) and 16 + cl (h = 1)
+    double best[2] = {-1.0, -1.0}, val[2] = {0.0, 0.0};
+    int bi[2] = {0x7fffffff, 0x7fffffff};
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = 16 * wave + 16 * RW * t + mfma16_row<PREC_F64>(lane, e);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double v = acc[t][h][e];
+                if (row < n) sign_merge(best[h], bi[h], val[h], fabs(v), row, v);
+            }
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        for (int o = 16; o < 64; o <<= 1) {
+            const double ob = __shfl_xor(best[h], o);
+            const int oi = __shfl_xor(bi[h], o);
+            const double ov = __shfl_xor(val[h], o);
+            sign_merge(best[h], bi[h], val[h], ob, oi, ov);
+        }
+        if (lane < 16) cand[wave * S32 + 16 * h + cl] = SignCand{best[h], val[h], bi[h], 0};
+    }
+    __syncthreads();
+    if (tid < S32) {
+        SignCand c = cand[tid];
+        for (int w = 1; w < RW; ++w) {
+            const SignCand o = cand[w * S32 + tid];
+            sign_merge(c.best, c.row, c.val, o.best, o.row, o.val);
+        }
+        sign_s[tid] = c.val < 0.0 ? -1 : 1;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = 16 * wave + 16 * RW * t + mfma16_row<PREC_F64>(lane, e);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int j = 16 * h + cl;
+                if (row < n && j < r) store_factor(a, row, j, r, sign_s[j] * acc[t][h][e]);
+            }
+        }
+    }
+}
+
+// Rayleigh-Ritz on span(Q) (Q n x 32 orthonormal, Z = G Q), then rank choice
+// and factor output: B = Q^T Z = W diag(theta) W^T, the rank from theta and
+// trace(G), and V = Q W straight into the factor (rr_factor_out).  When either
 // orthonormalisation failed the mode is handed to the next eigensolver.
 __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q, const double* __restrict__ Z,
-                                                    int nparts, int n, int max_sweeps,
+                                                    int n, int max_sweeps,
                                                     const int32_t* __restrict__ orth_ok, SelectArgs a) {
     extern __shared__ double lds[];
     double* part_lds = lds;
@@ -1329,7 +1457,7 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
     __shared__ double lam_s[S32];
     __shared__ double red[17];
     __shared__ int sign_s[S32];
-    __shared__ int r_s;
+    __shared__ int r_s, dense_s;
     __shared__ int sweeps_s, conv_s;
     const int tid = threadIdx.x;
     DevBook* bk = a.book;
@@ -1340,7 +1468,7 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
         }
         return;
     }
-    (void)nparts;
+    const double tr = gram_trace(a, red);
     cross32<RW, 1, 1>(Q, Z, n, part_lds, Bm);
     for (int e = tid; e < S32 * S32; e += RT) {
         const int i = e >> 5, j = e & 31;
@@ -1366,7 +1494,6 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
     }
     __syncthreads();
     double* lam = const_cast<double*>(a.lam);
-    double* V = const_cast<double*>(a.V);
     if (tid < S32) {
         const double li = Bm[tid][tid];
         int r = 0;
@@ -1378,18 +1505,19 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
         lam[r] = li;
         lam_s[r] = li;
     }
-    __syncthreads();
-    // V = Q W[:, col_of]
-    apply32<1, RW>(Q, V, n, Wm, col_of);
     if (tid == 0) {
         bk->sweeps[a.k] = sweeps_s;
         bk->eig_ok = conv_s;
     }
-    __threadfence();
     __syncthreads();
     SelectArgs al = a;
     al.lam = lam_s;  // the Ritz values from LDS
-    select_factor_body(al, red, sign_s, r_s);
+    if (tid == 0) choose_rank(al, tr, r_s, dense_s);
+    __syncthreads();
+    if (dense_s) return;
+    // V = Q W[:, col_of], sign rule and factor output (the partials' space is free again)
+    static_assert(RW * S32 * S32 * sizeof(double) >= RW * S32 * sizeof(SignCand), "sign candidates");
+    rr_factor_out(al, Q, n, Wm, col_of, r_s, reinterpret_cast<SignCand*>(part_lds), sign_s);
 }
 
 bool sub32_ready() {
@@ -1456,7 +1584,7 @@ hipError_t run_subspace32_select(const double* G, int n, int iters, int max_swee
     for (int it = 0; it < steps; ++it) {
         // P1 <- orthonormal basis of its columns, then P2 <- G P1; the last basis
         // (the Rayleigh-Ritz one) gets the verified final correction
-        hipLaunchKernelGGL(k_orth32, dim3(1), dim3(OT), ORTH_LDS, st, P1, 1, n, it + 1 == steps ? 1 : 0,
+        hipLaunchKernelGGL(k_orth32, dim3(1), dim3(OT), ORTH_LDS, st, P1, n, it + 1 == steps ? 1 : 0,
                            it == 0 ? 1 : 0, ok);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)P1, P2, n, (uint64_t)0);
@@ -1464,7 +1592,7 @@ hipError_t run_subspace32_select(const double* G, int n, int iters, int max_swee
         std::swap(P1, P2);
     }
     // P2 holds the basis, P1 = G times it
-    hipLaunchKernelGGL(k_rr32_select, dim3(1), dim3(RT), RR_LDS, st, (const double*)P2, (const double*)P1, 1, n,
+    hipLaunchKernelGGL(k_rr32_select, dim3(1), dim3(RT), RR_LDS, st, (const double*)P2, (const double*)P1, n,
                        max_sweeps, (const int32_t*)ok, sa);
     return hipGetLastError();
 }
