@@ -1151,17 +1151,24 @@ __global__ __launch_bounds__(OT) void k_orth32(double* __restrict__ Y, int n, in
     if (tid == 0) *ok = first ? (good ? 1 : 0) : ((*ok && good) ? 1 : 0);
 }
 
+// Whether the pair (p, q) is rotated: |a_pq| > tol sqrt(|a_pp a_qq|) (the
+// relative test of schur2, squared) and |a_pq| > floor.
+__device__ __forceinline__ bool rot2_needed(double app, double aqq, double apq, double tol2, double floor2) {
+    const double a2 = apq * apq;
+    return a2 > tol2 * fabs(app * aqq) && a2 > floor2;
+}
+
 // Jacobi rotation for the pair (p, q) as in schur2, with fewer long-latency
-// operations: the threshold |a_pq| > tol sqrt(|a_pp a_qq|) is tested squared,
-// and with d = a_qq - a_pp, g = 2 a_pq, h = hypot(d, g), u = (1 + |d| / h) / 2:
-// c = sqrt(u), s = sign(d) g / (2 h c), t = s / c (the smaller angle).
-__device__ inline bool rot2(double app, double aqq, double apq, double tol2, double& c, double& s, double& dp,
-                            double& dq) {
+// operations: with d = a_qq - a_pp, g = 2 a_pq, h = hypot(d, g), u = (1 + |d|
+// / h) / 2: c = sqrt(u), s = sign(d) g / (2 h c), t = s / c (the smaller
+// angle).  Pairs that fail rot2_needed keep (c, s) = (1, 0).
+__device__ inline bool rot2(double app, double aqq, double apq, double tol2, double floor2, double& c, double& s,
+                            double& dp, double& dq) {
     c = 1.0;
     s = 0.0;
     dp = app;
     dq = aqq;
-    if (!(apq * apq > tol2 * fabs(app * aqq))) return false;
+    if (!rot2_needed(app, aqq, apq, tol2, floor2)) return false;
     const double d = aqq - app, g = 2.0 * apq;
     const double rh = rsqrt_nr(d * d + g * g);   // 1 / h
     const double u = 0.5 + 0.5 * fabs(d) * rh;   // cos^2 of the angle
@@ -1177,7 +1184,9 @@ __device__ inline bool rot2(double app, double aqq, double apq, double tol2, dou
 // Cyclic Jacobi on the symmetric A (32 x 32, LDS; only the upper triangle is
 // read or written), rotations accumulated in W (32 x 32, LDS).  Called by
 // every thread of a workgroup of at least 6 wavefronts.  Wavefront 0 runs the
-// sweeps over the round-robin ordering: in each round lanes 0-15 compute the
+// sweeps over the round-robin ordering.  A sweep starts with a test of all 496
+// pairs (rot2_needed); when none needs a rotation the matrix has converged and
+// the sweep is not run.  Otherwise in each round lanes 0-15 compute the
 // rotation of pair `lane` into the rotation log and write that pair's 2 x 2
 // diagonal block exactly (new diagonal, zero coupling), while every lane
 // holds two of the 120 off-diagonal blocks (pair k, pair l), k < l, whose
@@ -1186,7 +1195,11 @@ __device__ inline bool rot2(double app, double aqq, double apq, double tol2, dou
 // rotations each block needs and store it.  A round with no rotation is
 // skipped.  Wavefronts 1, 2, 3 and 5 (off wavefront 0's SIMD) meanwhile
 // apply the previous sweep's log to 8 rows of W each; one workgroup barrier
-// per sweep.  log: 2 x 31 x 16 double2 (c, s); ptab: 31 x 16 ints; btab:
+// per sweep.  Besides the relative test, an off-diagonal entry below u
+// trace(A) (u = 2^-53) is left alone: it is under the rounding error the
+// entries of A = Q^T G Q carry already, and rotating it away costs a sweep
+// without changing the result at that accuracy.  log: 2 x 31 x 16 double2
+// (c, s); ptab: 31 x 16 ints; btab:
 // 31 x 128 uint4 (62 KB); flag: 1 int; all LDS.  Unused block slots point at
 // the padding column of A, which nothing reads.
 __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 + 1], int max_sweeps, double2* log,
@@ -1200,6 +1213,10 @@ __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 +
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double tol = (double)S32 * 0x1p-53;
     const double tol2 = tol * tol;
+    double trace = 0.0;
+    for (int i = 0; i < S32; ++i) trace += A[i][i];
+    const double floor = 0x1p-53 * fabs(trace);
+    const double floor2 = floor * floor;
     char* const abase = reinterpret_cast<char*>(&A[0][0]);
     for (int e = tid; e < LOGR; e += blockDim.x) {
         int p, q;
@@ -1271,10 +1288,15 @@ __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 +
     while (!conv && sweeps < max_sweeps) {
         double2* lg = log + (sweeps & 1) * LOGR;
         if (wave == 0) {
+            bool need = false;
+            for (int e = lane; e < LOGR; e += 64) {
+                const int c = ptab[e], p = c & 255, q = c >> 8;
+                need = need || rot2_needed(A[p][p], A[q][q], A[p][q], tol2, floor2);
+            }
             bool any = false;
             uint4 ad[2] = {btab[lane], btab[64 + lane]};
             int me = ptab[lane & (H - 1)];
-            for (int round = 0; round < NR; ++round) {
+            for (int round = 0; round < NR && __ballot(need) != 0; ++round) {
                 double x[2][4];
 #pragma unroll
                 for (int t = 0; t < 2; ++t) {
@@ -1291,7 +1313,7 @@ __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 +
                 bool r = false;
                 if (lane < H) {
                     double c, s, dp, dq;
-                    r = rot2(app, aqq, apq, tol2, c, s, dp, dq);
+                    r = rot2(app, aqq, apq, tol2, floor2, c, s, dp, dq);
                     lg[round * H + lane] = double2{c, s};
                     A[mp][mp] = dp;
                     A[mq][mq] = dq;
@@ -1331,7 +1353,9 @@ __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 +
         ++sweeps;
         __syncthreads();
     }
-    if (w_apply && sweeps > 0) apply_log(log + ((sweeps - 1) & 1) * LOGR);
+    // the last sweep's log: applied already when that sweep was followed by
+    // the converged one (whose log is unused: not written, or all (1, 0))
+    if (!conv && w_apply && sweeps > 0) apply_log(log + ((sweeps - 1) & 1) * LOGR);
     __syncthreads();
     sweeps_out = sweeps;
     conv_out = conv;
