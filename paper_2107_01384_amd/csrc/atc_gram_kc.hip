@@ -23,6 +23,8 @@
 // fixed order.
 #include "atc_internal.hpp"
 
+#include <type_traits>
+
 namespace atc {
 namespace {
 
@@ -264,6 +266,191 @@ __global__ __launch_bounds__(256, 2) void k_gram_kc(const float* __restrict__ X,
     }
 }
 
+// ---------------------------------------------------------------------------
+// bf16x3 variant for full tiles (n % 128 == 0, R % 32 == 0): the same work
+// decomposition and accumulation as k_gram_kc, with
+//   * LDS rows of 32 bf16 (64 bytes) without padding; the four 16-byte chunks
+//     of row r sit at chunk ^ ((r >> 2) & 3), so the 16 rows one ds_read_b128
+//     group touches cover all 64 banks;
+//   * two LDS stages: step s+1 is stored into the other stage while step s is
+//     multiplied, one workgroup barrier per step;
+//   * the split x = hi + lo from one packed conversion per pair (hi), the
+//     exact difference, and one packed conversion per pair (lo);
+//   * no row or K masking, and the chunk's first products take a zero
+//     accumulator instead of clearing it.
+struct K3Stage {
+    uint4 ah[KC_BM][4], al[KC_BM][4], bh[KC_BM][4], bl[KC_BM][4];
+};
+
+__device__ __forceinline__ int k3_chunk(int row, int c) { return c ^ ((row >> 2) & 3); }
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// hi / lo bf16 pairs of (x, y): hi = bf16(x), lo = bf16(x - hi)
+__device__ __forceinline__ void k3_split2(float x, float y, uint32_t& hi, uint32_t& lo) {
+    const bf16x2 h = {(__bf16)x, (__bf16)y};
+    const uint32_t hu = __builtin_bit_cast(uint32_t, h);
+    const float hx = __uint_as_float(hu << 16), hy = __uint_as_float(hu & 0xffff0000u);
+    const bf16x2 l = {(__bf16)(x - hx), (__bf16)(y - hy)};
+    hi = hu;
+    lo = __builtin_bit_cast(uint32_t, l);
+}
+
+__global__ __launch_bounds__(256, 2) void k_gram_kc3(const float* __restrict__ X, int n, int64_t L, int64_t R,
+                                                  int64_t steps, int nsplit, int tiles, int npairs,
+                                                  float* __restrict__ part, double* __restrict__ dpart) {
+    __shared__ K3Stage sm[2];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int b = blockIdx.x;
+    const int xcd = b & 7, slot = b >> 3;
+    const int pair = slot % npairs;
+    const int split = (slot / npairs) * 8 + xcd;
+    if (split >= nsplit) return;
+    int ti, tj;
+    kc_decode_pair(pair, tiles, ti, tj);
+    const bool diag = ti == tj;
+    const int row0 = ti * KC_BM, col0 = tj * KC_BM;
+    const int64_t s0 = steps * split / nsplit, s1 = steps * (split + 1) / nsplit;
+    const int64_t spl = R / KC_BK;  // K steps per slice l
+
+    // loader: 8 threads per row (4 floats each), rows lr + 32 i
+    const int lr = tid >> 3, lc = (tid & 7) * 4;
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    typedef const v4f __attribute__((address_space(1)))* gf4;
+    const int64_t rowstep = (int64_t)32 * R;
+    int64_t l0 = s0 / spl, kpos = (s0 - l0 * spl) * KC_BK;  // slice and K offset of the next load
+    const float* pa = X + (l0 * n + row0 + lr) * R + kpos + lc;
+    const float* pb = X + (l0 * n + col0 + lr) * R + kpos + lc;
+    const int64_t wrap = (int64_t)(n - 1) * R;  // from one slice's row end to the next slice's row start
+    v4f ra[4], rb[4];
+    auto load = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ra[i] = *(gf4)(pa + i * rowstep);
+            if (!diag) rb[i] = *(gf4)(pb + i * rowstep);
+        }
+        pa += KC_BK;
+        pb += KC_BK;
+        kpos += KC_BK;
+        if (kpos == R) {
+            kpos = 0;
+            pa += wrap;
+            pb += wrap;
+        }
+    };
+    // store of the loaded rows into stage st (hi / lo), diagonal sums of squares
+    double dsq[4] = {0.0, 0.0, 0.0, 0.0};
+    const int cst = lc >> 3, half = (lc >> 2) & 1;
+    auto store = [&](K3Stage& S) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = lr + 32 * i;
+            const int ch = k3_chunk(row, cst);
+            uint2 h, l;
+            k3_split2(ra[i].x, ra[i].y, h.x, l.x);
+            k3_split2(ra[i].z, ra[i].w, h.y, l.y);
+            reinterpret_cast<uint2*>(&S.ah[row][ch])[half] = h;
+            reinterpret_cast<uint2*>(&S.al[row][ch])[half] = l;
+            if (!diag) {
+                k3_split2(rb[i].x, rb[i].y, h.x, l.x);
+                k3_split2(rb[i].z, rb[i].w, h.y, l.y);
+                reinterpret_cast<uint2*>(&S.bh[row][ch])[half] = h;
+                reinterpret_cast<uint2*>(&S.bl[row][ch])[half] = l;
+            } else {
+                const double x0 = ra[i].x, x1 = ra[i].y, x2 = ra[i].z, x3 = ra[i].w;
+                dsq[i] += x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3;
+            }
+        }
+    };
+
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    f32x16 acc[2][2], tot[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) tot[a][c][v] = 0.f;
+    const f32x16 zero16 = {};
+    // products of one K step from stage S; ZC: the first slice starts from zero
+    auto mma = [&](const K3Stage& S, auto zc) {
+        constexpr bool ZC = decltype(zc)::value;
+#pragma unroll
+        for (int sl = 0; sl < KC_BK / 16; ++sl) {
+            const int cq = 2 * sl + (lane >> 5);
+            bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int rr = wr + a * 32 + (lane & 31);
+                ah[a] = __builtin_bit_cast(bf16x8, S.ah[rr][k3_chunk(rr, cq)]);
+                al[a] = __builtin_bit_cast(bf16x8, S.al[rr][k3_chunk(rr, cq)]);
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int cc = wc + c * 32 + (lane & 31);
+                const int ch = k3_chunk(cc, cq);
+                bh[c] = __builtin_bit_cast(bf16x8, diag ? S.ah[cc][ch] : S.bh[cc][ch]);
+                bl[c] = __builtin_bit_cast(bf16x8, diag ? S.al[cc][ch] : S.bl[cc][ch]);
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const f32x16 c0 = (ZC && sl == 0) ? zero16 : acc[a][c];
+                    acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[c], c0, 0, 0, 0);
+                    acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[c], acc[a][c], 0, 0, 0);
+                    acc[a][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[c], acc[a][c], 0, 0, 0);
+                }
+        }
+    };
+    constexpr int FLUSH_STEPS = FLUSH_TERMS / KC_BK;
+    int since = 0;
+    if (s0 < s1) {
+        load();
+        store(sm[0]);
+    }
+    __syncthreads();
+    for (int64_t s = s0; s < s1; ++s) {
+        const int cur = (int)((s - s0) & 1);
+        const bool more = s + 1 < s1;
+        if (more) load();
+        if (since == 0) mma(sm[cur], std::true_type{});
+        else mma(sm[cur], std::false_type{});
+        if (++since == FLUSH_STEPS || !more) {
+            since = 0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) tot[a][c] += acc[a][c];
+        }
+        if (more) store(sm[cur ^ 1]);
+        __syncthreads();
+    }
+    float* out = part + ((int64_t)split * npairs + pair) * (KC_BM * KC_BM);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = wr + a * 32 + mfma32_row(lane, v);
+                const int j = wc + c * 32 + (lane & 31);
+                out[i * KC_BM + j] = tot[a][c][v];
+            }
+    if (diag) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            double sq = dsq[i];
+            sq += __shfl_xor(sq, 1);
+            sq += __shfl_xor(sq, 2);
+            sq += __shfl_xor(sq, 4);
+            const int row = row0 + lr + 32 * i;
+            if ((tid & 7) == 0) dpart[(int64_t)split * n + row] = sq;
+        }
+    }
+}
+
 __global__ void k_gram_kc_reduce(const float* __restrict__ part, const double* __restrict__ dpart, int nsplit,
                                  int npairs, int tiles, int n, double* __restrict__ G) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -318,7 +505,10 @@ hipError_t launch_gram_kc(int prec, const GramKcPlan& g, const float* X, float* 
                           hipStream_t st) {
     if (!g.ok) return hipErrorInvalidValue;
     const int blocks = g.nsplit * g.npairs;  // nsplit is a multiple of 8
-    if (prec == PREC_BF16X3)
+    if (prec == PREC_BF16X3 && g.n % KC_BM == 0 && g.R % KC_BK == 0)
+        hipLaunchKernelGGL(k_gram_kc3, dim3(blocks), dim3(256), 0, st, X, g.n, g.L, g.R, g.steps, g.nsplit, g.tiles,
+                           g.npairs, part, dpart);
+    else if (prec == PREC_BF16X3)
         hipLaunchKernelGGL(k_gram_kc<PREC_BF16X3>, dim3(blocks), dim3(256), 0, st, X, g.n, g.L, g.R, g.steps,
                            g.nsplit, g.tiles, g.npairs, part, dpart);
     else
