@@ -292,7 +292,7 @@ def main():
     achieved = 3.0 * gram[k0] / (gram_ms[k0] * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": measured_traffic(),
-                "kernel": "k_gram_kc<bf16x3> (first mode)", "kernel_ms": round(gram_ms[k0], 4)}
+                "kernel": "k_gram_kc3 (bf16x3, first mode)", "kernel_ms": round(gram_ms[k0], 4)}
 
     fp32 = None
     if not args.no_fp32:

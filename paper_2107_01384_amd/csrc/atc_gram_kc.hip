@@ -289,7 +289,8 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 // hi / lo bf16 pairs of (x, y): hi = bf16(x), lo = bf16(x - hi)
 __device__ __forceinline__ void k3_split2(float x, float y, uint32_t& hi, uint32_t& lo) {
     const bf16x2 h = {(__bf16)x, (__bf16)y};
-    const uint32_t hu = __builtin_bit_cast(uint32_t, h);
+    uint32_t hu = __builtin_bit_cast(uint32_t, h);
+    asm volatile("" : "+v"(hu));  // keeps the compiler from converting x a second time for hx
     const float hx = __uint_as_float(hu << 16), hy = __uint_as_float(hu & 0xffff0000u);
     const bf16x2 l = {(__bf16)(x - hx), (__bf16)(y - hy)};
     hi = hu;
@@ -365,6 +366,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_kc3(const float* __restrict__ X
     };
 
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    const bool lower = diag && wr > wc;
     f32x16 acc[2][2], tot[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -415,8 +417,13 @@ __global__ __launch_bounds__(256, 2) void k_gram_kc3(const float* __restrict__ X
         const int cur = (int)((s - s0) & 1);
         const bool more = s + 1 < s1;
         if (more) load();
-        if (since == 0) mma(sm[cur], std::true_type{});
-        else mma(sm[cur], std::false_type{});
+        if (lower) {
+            // the strictly lower quarter of a diagonal tile is never read
+        } else if (since == 0) {
+            mma(sm[cur], std::true_type{});
+        } else {
+            mma(sm[cur], std::false_type{});
+        }
         if (++since == FLUSH_STEPS || !more) {
             since = 0;
 #pragma unroll
@@ -429,7 +436,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_kc3(const float* __restrict__ X
     }
     float* out = part + ((int64_t)split * npairs + pair) * (KC_BM * KC_BM);
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2 && !lower; ++a)
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
