@@ -173,24 +173,37 @@ size_t carve_sthosvd(const atc_shape* s, char* base, SthosvdWs* w) {
     return c.off;
 }
 
+// Start / end events of one call (created once per thread).  stop() records
+// the end event; elapsed() is valid once the stream has been synchronised.
 struct StreamTimer {
     hipEvent_t a = nullptr, b = nullptr;
     bool ok = false;
-    explicit StreamTimer(hipStream_t st) {
-        ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
-             hipEventRecord(a, st) == hipSuccess;
+    bool start(hipStream_t st) {
+        if (!a && (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)) return ok = false;
+        return ok = hipEventRecord(a, st) == hipSuccess;
     }
-    double stop(hipStream_t st) {
+    void stop(hipStream_t st) { ok = ok && hipEventRecord(b, st) == hipSuccess; }
+    double elapsed() const {
         float ms = 0.f;
-        if (ok && hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess)
-            hipEventElapsedTime(&ms, a, b);
+        if (ok) (void)hipEventElapsedTime(&ms, a, b);
         return ms;
     }
-    ~StreamTimer() {
-        if (a) hipEventDestroy(a);
-        if (b) hipEventDestroy(b);
+};
+thread_local StreamTimer g_timer;
+
+// Host copy of the device bookkeeping record in pinned memory (an
+// asynchronous device-to-host copy into pageable memory would be staged).
+struct PinnedBook {
+    DevBook* h = nullptr;
+    bool init() {
+        if (h) return true;
+        void* p = nullptr;
+        if (hipHostMalloc(&p, sizeof(DevBook), hipHostMallocDefault) != hipSuccess) return false;
+        h = (DevBook*)p;
+        return true;
     }
 };
+thread_local PinnedBook g_book;
 
 // Per-mode phase events (Gram, reduction, eigensolver + rank choice, mode
 // product), created once per thread and reused.
@@ -296,7 +309,8 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
     if (prof && !g_phase.init()) return fail(ATC_ERR_DEVICE, "hipEventCreate failed");
     auto mark = [&](int i, int j) -> hipError_t { return prof ? hipEventRecord(g_phase.ev[i][j], st) : hipSuccess; };
 
-    StreamTimer timer(st);
+    if (!g_book.init()) return fail(ATC_ERR_DEVICE, "hipHostMalloc failed");
+    g_timer.start(st);
     HIP_TRY(hipMemsetAsync(w.book, 0, sizeof(DevBook), st));
     int64_t cur[ATC_MAX_DIMS];
     for (int k = 0; k < d; ++k) cur[k] = shape->dims[k];
@@ -418,9 +432,11 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         cur[k] = r;
         src = dst;
     }
-    HIP_TRY(hipMemcpyAsync(&hb, w.book, sizeof(DevBook), hipMemcpyDeviceToHost, st));
-    const double ms = timer.stop(st);
+    HIP_TRY(hipMemcpyAsync(g_book.h, w.book, sizeof(DevBook), hipMemcpyDeviceToHost, st));
+    g_timer.stop(st);
     HIP_TRY(hipStreamSynchronize(st));
+    hb = *g_book.h;
+    const double ms = g_timer.elapsed();
     if (result) {
         memset(result, 0, sizeof(*result));
         for (int i = 0; i < d; ++i) {
