@@ -103,7 +103,7 @@ typedef struct {
     double budget[ATC_MAX_DIMS];   /* budget share per mode */
     int32_t eig_path[ATC_MAX_DIMS];/* 1 = dense Jacobi, 2 = subspace iteration */
     int32_t eig_sweeps[ATC_MAX_DIMS];
-    double elapsed_ms;             /* device time of the call, stream events */
+    double elapsed_ms;             /* with opts.profile: device time of the call (stream events), else 0 */
     /* with opts.profile, per processed mode (natural index): Gram kernel,
      * split-K reduction, eigensolver + rank choice, mode-product kernel */
     double gram_ms[ATC_MAX_DIMS];
@@ -132,8 +132,13 @@ size_t atc_sthosvd_workspace_size(const atc_shape* shape, const atc_sthosvd_opts
  *  factors  host array of d device pointers; factors[k] receives U_k as a
  *           row-major n_k x r_k matrix of the input dtype; capacity n_k^2.
  *  result   host pointer, filled on success.
- * The call returns after the work has completed (it reads each r_k back to
- * size the next step).
+ * The call returns once every r_k is known (the selection kernels report each
+ * rank and the result figures through pinned host memory, and the host sizes
+ * the next step from them); the last mode product may still be running on
+ * `stream`.  core and factors are complete in stream order, like the output
+ * of a kernel launch: synchronise the stream, or keep later work on it,
+ * before reading them, and keep workspace alive until then.  With
+ * opts.profile the call waits for the stream (the phase times need it).
  */
 atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_opts* opts,
                        void* core, void* const* factors, atc_result* result,

@@ -196,7 +196,9 @@ def sthosvd(x: torch.Tensor, rel_error: float = 1e-3, precision: str = "native",
             rule: str = "adaptive", fixed_ranks=None, max_sweeps: int = 0, eig_path: int = 0,
             workspace: Optional[torch.Tensor] = None, stream=None, profile: bool = False,
             out: Optional[tuple] = None) -> Tucker:
-    """ST-HOSVD of x (GPU tensor) to relative error rel_error; see atc_sthosvd in include/atc.h."""
+    """ST-HOSVD of x (GPU tensor) to relative error rel_error; see atc_sthosvd in include/atc.h.
+    The ranks and figures of the result are final on return; core and factors
+    are written in the order of `stream` (torch's current stream by default)."""
     lib = load()
     _require_gpu(x, "x")
     dims = list(x.shape)

@@ -191,19 +191,6 @@ struct StreamTimer {
 };
 thread_local StreamTimer g_timer;
 
-// Host copy of the device bookkeeping record in pinned memory (an
-// asynchronous device-to-host copy into pageable memory would be staged).
-struct PinnedBook {
-    DevBook* h = nullptr;
-    bool init() {
-        if (h) return true;
-        void* p = nullptr;
-        if (hipHostMalloc(&p, sizeof(DevBook), hipHostMallocDefault) != hipSuccess) return false;
-        h = (DevBook*)p;
-        return true;
-    }
-};
-thread_local PinnedBook g_book;
 
 // Per-mode phase events (Gram, reduction, eigensolver + rank choice, mode
 // product), created once per thread and reused.
@@ -309,14 +296,14 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
     if (prof && !g_phase.init()) return fail(ATC_ERR_DEVICE, "hipEventCreate failed");
     auto mark = [&](int i, int j) -> hipError_t { return prof ? hipEventRecord(g_phase.ev[i][j], st) : hipSuccess; };
 
-    if (!g_book.init()) return fail(ATC_ERR_DEVICE, "hipHostMalloc failed");
-    g_timer.start(st);
+    if (prof) g_timer.start(st);
     HIP_TRY(hipMemsetAsync(w.book, 0, sizeof(DevBook), st));
     int64_t cur[ATC_MAX_DIMS];
     for (int k = 0; k < d; ++k) cur[k] = shape->dims[k];
     const void* src = x;
-    DevBook hb;
     HostFlags hf{};
+    double rep_tail[ATC_MAX_DIMS] = {}, rep_budget[ATC_MAX_DIMS] = {}, rep_norm2 = 0.0, rep_used = 0.0;
+    int32_t rep_sweeps[ATC_MAX_DIMS] = {};
     if (!g_flags.init()) return fail(ATC_ERR_DEVICE, "hipHostMalloc of the report block failed");
     int paths[ATC_MAX_DIMS] = {0};
     for (int i = 0; i < d; ++i) {
@@ -411,6 +398,11 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
                 hf.need_dense = f->need_dense;
                 hf.eig_ok = f->eig_ok;
                 hf.status = f->status;
+                hf.sweeps = f->sweeps;
+                hf.tail = f->tail;
+                hf.budget = f->budget;
+                hf.norm2 = f->norm2;
+                hf.used = f->used;
             }
             if (hf.status != 0) return fail((atc_status)hf.status, "input |A|^2 is not finite");
             if (!hf.need_dense) break;
@@ -421,6 +413,11 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
             HIP_TRY(hipMemcpyAsync(&w.book->need_dense, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
         }
         if (!hf.eig_ok) return fail(ATC_ERR_NOT_CONVERGED, "mode %d: eigensolver hit %d sweeps", k, max_sweeps);
+        rep_tail[k] = hf.tail;
+        rep_budget[k] = hf.budget;
+        rep_sweeps[k] = hf.sweeps;
+        rep_norm2 = hf.norm2;
+        rep_used = hf.used;
         const int r = hf.rank;
         if (r < 1 || r > n) return fail(ATC_ERR_INTERNAL, "mode %d: rank %d outside [1, %d]", k, r, n);
         void* dst = (i == d - 1) ? core : w.buf[i % 2];
@@ -432,21 +429,24 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         cur[k] = r;
         src = dst;
     }
-    HIP_TRY(hipMemcpyAsync(g_book.h, w.book, sizeof(DevBook), hipMemcpyDeviceToHost, st));
-    g_timer.stop(st);
-    HIP_TRY(hipStreamSynchronize(st));
-    hb = *g_book.h;
-    const double ms = g_timer.elapsed();
+    // every figure of the result came with the host reports; only profiling
+    // waits for the last mode product (the outputs are stream-ordered)
+    double ms = 0.0;
+    if (prof) {
+        g_timer.stop(st);
+        HIP_TRY(hipStreamSynchronize(st));
+        ms = g_timer.elapsed();
+    }
     if (result) {
         memset(result, 0, sizeof(*result));
         for (int i = 0; i < d; ++i) {
             const int k = order[i];
-            result->ranks[k] = hb.rank[k];
+            result->ranks[k] = cur[k];
             result->order[i] = order[i];
-            result->tail[k] = hb.tail[k];
-            result->budget[k] = hb.budget[k];
+            result->tail[k] = rep_tail[k];
+            result->budget[k] = rep_budget[k];
             result->eig_path[k] = paths[k];
-            result->eig_sweeps[k] = hb.sweeps[k];
+            result->eig_sweeps[k] = rep_sweeps[k];
             if (prof) {
                 hipEvent_t* e = g_phase.ev[i];
                 result->gram_ms[k] = event_ms(e[0], e[1]);
@@ -455,8 +455,8 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
                 result->ttm_ms[k] = event_ms(e[3], e[4]);
             }
         }
-        result->norm2 = hb.norm2;
-        result->sse_pred = hb.used;
+        result->norm2 = rep_norm2;
+        result->sse_pred = rep_used;
         result->elapsed_ms = ms;
     }
     return ATC_OK;

@@ -590,6 +590,11 @@ __device__ inline void publish_selection(const SelectArgs& a, int rank) {
     h->need_dense = bk->need_dense;
     h->eig_ok = bk->eig_ok;
     h->status = bk->status;
+    h->sweeps = bk->sweeps[a.k];
+    h->tail = bk->tail[a.k];
+    h->budget = bk->budget[a.k];
+    h->norm2 = bk->norm2;
+    h->used = bk->used;
     __threadfence_system();
     h->seq = a.seq;
 }

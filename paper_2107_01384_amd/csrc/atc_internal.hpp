@@ -144,8 +144,9 @@ hipError_t run_subspace_eig(const double* G, int n, int m, int iters, int max_sw
 // written by the kernel with seq last (after a system-scope fence).
 struct HostFlags {
     int32_t seq;
-    int32_t rank, need_dense, eig_ok, status;
-    int32_t pad[3];
+    int32_t rank, need_dense, eig_ok, status, sweeps;
+    int32_t pad[2];
+    double tail, budget, norm2, used;  // this mode's book entries, |A|^2, discarded energy so far
 };
 
 struct SelectArgs {
