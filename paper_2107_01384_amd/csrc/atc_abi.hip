@@ -306,6 +306,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
     int32_t rep_sweeps[ATC_MAX_DIMS] = {};
     if (!g_flags.init()) return fail(ATC_ERR_DEVICE, "hipHostMalloc of the report block failed");
     int paths[ATC_MAX_DIMS] = {0};
+    int lazy[ATC_MAX_DIMS], nlazy = 0;  // modes kept whole, rotated at the end
     for (int i = 0; i < d; ++i) {
         const int k = order[i];
         const int64_t L = prod(cur, 0, k), R = prod(cur, k + 1, d);
@@ -317,6 +318,12 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
             HIP_TRY(launch_gram_kc(prec, kp, (const float*)src, (float*)w.part, w.dpart, st));
             HIP_TRY(mark(i, 1));
             HIP_TRY(launch_gram_kc_reduce(kp, (const float*)w.part, w.dpart, w.G, st));
+            HIP_TRY(mark(i, 2));
+        } else if (gram_tall_applicable(prec, n, R) && reinterpret_cast<uintptr_t>(src) % 16 == 0) {
+            // short last mode: FP64 MFMA over rows streamed through LDS (reduction included)
+            HIP_TRY(mark(i, 0));
+            HIP_TRY(launch_gram_tall((const float*)src, n, L, w.part, w.part_cap, w.G, st));
+            HIP_TRY(mark(i, 1));
             HIP_TRY(mark(i, 2));
         } else {
             const GramPlan gp = gram_plan(prec, L, n, n, R, true, w.part_cap);
@@ -420,14 +427,41 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         rep_used = hf.used;
         const int r = hf.rank;
         if (r < 1 || r > n) return fail(ATC_ERR_INTERNAL, "mode %d: rank %d outside [1, %d]", k, r, n);
-        void* dst = (i == d - 1) ? core : w.buf[i % 2];
+        cur[k] = r;
+        if (r == n && i + 1 < d) {
+            // nothing discarded: the projection is a rotation of mode k, which
+            // leaves every later Gram matrix unchanged, so it is applied to the
+            // final core instead of the full tensor (Alg. 1 computes the same core)
+            lazy[nlazy++] = k;
+            HIP_TRY(mark(i, 3));
+            HIP_TRY(mark(i, 4));
+            continue;
+        }
+        void* dst = (i == d - 1) ? core : (src == w.buf[0] ? w.buf[1] : w.buf[0]);
         const TtmPlan tp = ttm_plan(prec, L, n, R, r);
         const void* M = f64 ? (const void*)w.Mt64 : (const void*)w.Mt32;
         HIP_TRY(mark(i, 3));
         HIP_TRY(launch_ttm(prec, tp, src, M, w.Mth, w.Mtl, dst, st));
         HIP_TRY(mark(i, 4));
-        cur[k] = r;
         src = dst;
+    }
+    if (nlazy > 0) {
+        // the deferred rotations, on the core (a copy of it in w.buf[1] first)
+        const int64_t nc = prod(cur, 0, d);
+        const size_t esz = f64 ? sizeof(double) : sizeof(float);
+        HIP_TRY(hipMemcpyAsync(w.buf[1], core, (size_t)nc * esz, hipMemcpyDeviceToDevice, st));
+        for (int j = 0; j < nlazy; ++j) {
+            const int k = lazy[j];
+            const int nk = (int)cur[k];
+            HIP_TRY(launch_prepare_matrix(prec, factors[k], f64 ? 1 : 0, nk, nk, 1, f64 ? w.Mt64 : nullptr,
+                                          f64 ? nullptr : w.Mt32, prec == PREC_BF16X3 ? w.Mth : nullptr,
+                                          prec == PREC_BF16X3 ? w.Mtl : nullptr, st));
+            const TtmPlan tp = ttm_plan(prec, prod(cur, 0, k), nk, prod(cur, k + 1, d), nk);
+            const void* M = f64 ? (const void*)w.Mt64 : (const void*)w.Mt32;
+            const void* in = w.buf[(j + 1) % 2];
+            void* out = (j == nlazy - 1) ? core : w.buf[j % 2];
+            HIP_TRY(launch_ttm(prec, tp, in, M, w.Mth, w.Mtl, out, st));
+        }
     }
     // every figure of the result came with the host reports; only profiling
     // waits for the last mode product (the outputs are stream-ordered)

@@ -381,4 +381,89 @@ hipError_t launch_gram_reduce(const GramPlan& g, const double* part, double* C, 
     return hipGetLastError();
 }
 
+
+// ------------------------------------------------------------ tall and narrow
+// Gram matrix of an (L, n, 1) view with n <= 16: L rows of n floats back to
+// back (the last mode of a row-major tensor when it is short, e.g. the 13
+// variables of a 4-way field).  The generic tiles would be almost all padding
+// here; instead each workgroup streams a contiguous range of rows through LDS
+// (chunks of TALL_ROWS rows, float4 loads of the contiguous floats) and every
+// wave runs v_mfma_f64_16x16x4f64 over 4 rows per instruction: lane l feeds
+// X[row + l / 16][l % 16] (0 beyond n) as both operands (A = X^T, B = X).
+// FP32 products are exact in FP64 and accumulate in FP64, so this mode's Gram
+// matrix (and |A|^2 when it is processed first) carries no rounding bias.
+// Each workgroup writes its n x n partial; k_gram_tall_reduce adds them in
+// workgroup order.
+constexpr int TALL_ROWS = 512;
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_gram_tall(const float* __restrict__ X, int n, int64_t L,
+                                                   int64_t rows_per_wg, double* __restrict__ part) {
+    __shared__ float4 buf4[TALL_ROWS * 16 / 4];
+    __shared__ double red[4][16][17];
+    const float* buf = reinterpret_cast<const float*>(buf4);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+    const int64_t r1 = r0 + rows_per_wg < L ? r0 + rows_per_wg : L;
+    const int col = lane & 15, rsub = lane >> 4;
+    f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int64_t c0 = r0; c0 < r1; c0 += TALL_ROWS) {
+        const int cnt = (int)(r1 - c0 < TALL_ROWS ? r1 - c0 : TALL_ROWS);
+        const int nf = cnt * n;
+        const float* src = X + c0 * n;  // 16-byte aligned: c0 is a multiple of 4
+        const int nf4 = nf >> 2;
+        for (int e = tid; e < nf4; e += 256) buf4[e] = reinterpret_cast<const float4*>(src)[e];
+        for (int e = (nf4 << 2) + tid; e < nf; e += 256) reinterpret_cast<float*>(buf4)[e] = src[e];
+        __syncthreads();
+        for (int q = 4 * wave; q < cnt; q += 16) {
+            const int row = q + rsub;
+            const double v = (row < cnt && col < n) ? (double)buf[row * n + col] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[wave][mfma16_row<PREC_F64>(lane, e)][col] = acc[e];
+    __syncthreads();
+    for (int e = tid; e < n * n; e += 256) {
+        const int i = e / n, j = e % n;
+        part[(int64_t)blockIdx.x * n * n + e] = ((red[0][i][j] + red[1][i][j]) + red[2][i][j]) + red[3][i][j];
+    }
+}
+
+__global__ void k_gram_tall_reduce(const double* __restrict__ part, int nblocks, int n, double* __restrict__ G) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * n * n + e];
+    G[e] = s;
+}
+
+}  // namespace
+
+bool gram_tall_applicable(int prec, int n, int64_t R) { return prec != PREC_F64 && R == 1 && n >= 1 && n <= 16; }
+
+int gram_tall_blocks(int64_t L) {
+    const int64_t want = 1024;  // four workgroups per CU
+    return (int)(L < want * TALL_ROWS / 8 ? ceil_div(L, (int64_t)TALL_ROWS / 8) : want);
+}
+
+hipError_t launch_gram_tall(const float* X, int n, int64_t L, double* part, size_t part_capacity_bytes, double* G,
+                            hipStream_t st) {
+    if (n < 1 || n > 16 || L < 1) return hipErrorInvalidValue;
+    if (reinterpret_cast<uintptr_t>(X) % 16 != 0) return hipErrorInvalidValue;
+    const int nb = gram_tall_blocks(L);
+    int64_t per = ceil_div(L, (int64_t)nb);
+    per = ceil_div(per, (int64_t)4) * 4;  // chunk starts stay 16-byte aligned
+    const int blocks = (int)ceil_div(L, per);
+    if ((size_t)blocks * n * n * sizeof(double) > part_capacity_bytes) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gram_tall, dim3(blocks), dim3(256), 0, st, X, n, L, per, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gram_tall_reduce, dim3((unsigned)ceil_div(n * n, 256)), dim3(256), 0, st,
+                       (const double*)part, blocks, n, G);
+    return hipGetLastError();
+}
+
 }  // namespace atc

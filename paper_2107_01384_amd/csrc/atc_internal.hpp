@@ -85,6 +85,13 @@ hipError_t launch_gram(int prec, const GramPlan& g, const void* X, const void* Y
 // symmetric plans write both triangles from the upper one.
 hipError_t launch_gram_reduce(const GramPlan& g, const double* part, double* C, hipStream_t st);
 
+// Gram matrix of a float32 (L, n, 1) view with n <= 16 (rows of n floats back
+// to back, X 16-byte aligned) into G (n x n FP64): FP64 MFMA with exact
+// products, partials (one n x n per workgroup) in part.
+bool gram_tall_applicable(int prec, int n, int64_t R);
+hipError_t launch_gram_tall(const float* X, int n, int64_t L, double* part, size_t part_capacity_bytes, double* G,
+                            hipStream_t st);
+
 // Gram matrix of a float32 (L, n, R) view with contiguous R (R >= 32, R % 4 == 0):
 // 128 x 128 MFMA tiles, split-K, FP32 partial tiles + FP64 exact diagonal.
 struct GramKcPlan {

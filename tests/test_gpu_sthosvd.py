@@ -160,3 +160,28 @@ def test_deterministic_bits():
     assert torch.equal(a.core, b.core)
     for fa, fb in zip(a.factors, b.factors):
         assert torch.equal(fa, fb)
+
+
+@pytest.mark.parametrize("precision", ["native", "bf16x3"])
+def test_tall_short_last_mode(precision):
+    """A 13-long last mode over 589,824 rows (several LDS chunks per workgroup,
+    rows of 13 floats): the first processed Gram matrix comes from FP64 MFMA
+    with exact products, so |A|^2 and that mode's discarded energy match an
+    FP64 Gram matrix formed here to rounding, and the rank to the letter."""
+    x = synth.field((4096, 144, 13), 13)
+    eps = 1e-3
+    t = _run(x, eps, torch.float32, precision=precision)
+    rows = x.reshape(-1, 13).astype(np.float64)
+    g = rows.T @ rows
+    norm2 = float(np.trace(g))
+    assert abs(t.norm2 - norm2) <= 1e-12 * norm2
+    lam = np.sort(np.linalg.eigvalsh(g))[::-1]
+    tails = np.concatenate([np.cumsum(lam[::-1])[::-1], [0.0]])  # tails[r] = sum_{j >= r} lam_j
+    budget = eps * eps * norm2 / 3
+    r = int(np.nonzero(tails[1:] <= budget)[0][0]) + 1
+    assert t.order[0] == 2
+    assert t.ranks[2] == r, (t.ranks, r)
+    assert abs(t.tails[2] - tails[r]) <= 1e-9 * norm2
+    err = gpu_rel_error(x, t)
+    log("  tall last mode: ranks", t.ranks, "err %.4e" % err)
+    assert err <= 1.02 * eps
