@@ -394,7 +394,7 @@ hipError_t launch_gram_reduce(const GramPlan& g, const double* part, double* C, 
 // matrix (and |A|^2 when it is processed first) carries no rounding bias.
 // Each workgroup writes its n x n partial; k_gram_tall_reduce adds them in
 // workgroup order.
-constexpr int TALL_ROWS = 512;
+constexpr int TALL_ROWS = 256;
 
 namespace {
 
@@ -402,29 +402,43 @@ __global__ __launch_bounds__(256) void k_gram_tall(const float* __restrict__ X, 
                                                    int64_t rows_per_wg, double* __restrict__ part) {
     __shared__ float4 buf4[TALL_ROWS * 16 / 4];
     __shared__ double red[4][16][17];
-    const float* buf = reinterpret_cast<const float*>(buf4);
+    float* const buf = reinterpret_cast<float*>(buf4);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
     const int64_t r1 = r0 + rows_per_wg < L ? r0 + rows_per_wg : L;
     const int col = lane & 15, rsub = lane >> 4;
-    f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int colc = col < n ? col : n - 1;
+    // four independent accumulators (rows 4 wave + 16 u + 64 m, u = 0..3)
+    // keep several MFMAs in flight; the workgroups resident on a CU overlap
+    // one another's loads.  No branches around loads: masked lanes read a
+    // clamped address and select zero.
+    f64x4 acc0 = f64x4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0, acc2 = acc0, acc3 = acc0;
     for (int64_t c0 = r0; c0 < r1; c0 += TALL_ROWS) {
         const int cnt = (int)(r1 - c0 < TALL_ROWS ? r1 - c0 : TALL_ROWS);
-        const int nf = cnt * n;
-        const float* src = X + c0 * n;  // 16-byte aligned: c0 is a multiple of 4
-        const int nf4 = nf >> 2;
-        for (int e = tid; e < nf4; e += 256) buf4[e] = reinterpret_cast<const float4*>(src)[e];
-        for (int e = (nf4 << 2) + tid; e < nf; e += 256) reinterpret_cast<float*>(buf4)[e] = src[e];
+        const int nf = cnt * n, nf4 = nf >> 2;
+        const float4* src4 = reinterpret_cast<const float4*>(X + c0 * n);  // c0 % 4 == 0: 16-byte aligned
+        for (int e = tid; e < nf4; e += 256) buf4[e] = src4[e];
+        const int et = (nf4 << 2) + tid;
+        if (et < nf) buf[et] = X[c0 * n + et];
         __syncthreads();
-        for (int q = 4 * wave; q < cnt; q += 16) {
-            const int row = q + rsub;
-            const double v = (row < cnt && col < n) ? (double)buf[row * n + col] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+        for (int q = 4 * wave; q < cnt; q += 64) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int row = q + 16 * u + rsub;
+                const float raw = buf[(row < cnt ? row : cnt - 1) * n + colc];
+                v[u] = (row < cnt && col < n) ? (double)raw : 0.0;
+            }
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[0], v[0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[1], v[1], acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[2], v[2], acc2, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(v[3], v[3], acc3, 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) red[wave][mfma16_row<PREC_F64>(lane, e)][col] = acc[e];
+    for (int e = 0; e < 4; ++e)
+        red[wave][mfma16_row<PREC_F64>(lane, e)][col] = ((acc0[e] + acc1[e]) + acc2[e]) + acc3[e];
     __syncthreads();
     for (int e = tid; e < n * n; e += 256) {
         const int i = e / n, j = e % n;
@@ -432,12 +446,22 @@ __global__ __launch_bounds__(256) void k_gram_tall(const float* __restrict__ X, 
     }
 }
 
-__global__ void k_gram_tall_reduce(const double* __restrict__ part, int nblocks, int n, double* __restrict__ G) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * n) return;
+// G[e] = sum of the nblocks partials of entry e: one workgroup per entry, each
+// thread a strided subset, then a fixed-order tree in LDS.
+__global__ __launch_bounds__(256) void k_gram_tall_reduce(const double* __restrict__ part, int nblocks, int n,
+                                                          double* __restrict__ G) {
+    __shared__ double sred[256];
+    const int e = blockIdx.x, tid = threadIdx.x;
+    const int nn = n * n;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * n * n + e];
-    G[e] = s;
+    for (int b = tid; b < nblocks; b += 256) s += part[(int64_t)b * nn + e];
+    sred[tid] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) sred[tid] += sred[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) G[e] = sred[0];
 }
 
 }  // namespace
@@ -445,7 +469,7 @@ __global__ void k_gram_tall_reduce(const double* __restrict__ part, int nblocks,
 bool gram_tall_applicable(int prec, int n, int64_t R) { return prec != PREC_F64 && R == 1 && n >= 1 && n <= 16; }
 
 int gram_tall_blocks(int64_t L) {
-    const int64_t want = 1024;  // four workgroups per CU
+    const int64_t want = 1536;  // six workgroups per CU
     return (int)(L < want * TALL_ROWS / 8 ? ceil_div(L, (int64_t)TALL_ROWS / 8) : want);
 }
 
@@ -461,8 +485,8 @@ hipError_t launch_gram_tall(const float* X, int n, int64_t L, double* part, size
     hipLaunchKernelGGL(k_gram_tall, dim3(blocks), dim3(256), 0, st, X, n, L, per, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gram_tall_reduce, dim3((unsigned)ceil_div(n * n, 256)), dim3(256), 0, st,
-                       (const double*)part, blocks, n, G);
+    hipLaunchKernelGGL(k_gram_tall_reduce, dim3((unsigned)(n * n)), dim3(256), 0, st, (const double*)part, blocks, n,
+                       G);
     return hipGetLastError();
 }
 
