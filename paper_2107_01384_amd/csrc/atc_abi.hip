@@ -161,8 +161,9 @@ size_t carve_sthosvd(const atc_shape* s, char* base, SthosvdWs* w) {
     t.lam = (double*)c.take((size_t)nmax * 8);
     t.V = (double*)c.take(n2 * 8);
     t.jac = (double*)c.take(nmax > 64 ? (size_t)2 * mpad * mpad * 8 : 0);
-    t.sub = (double*)c.take(nmax > 64 ? std::max(subspace_ws_doubles(nmax, SUBSPACE_M),
-                                                 subspace32_ws_doubles(std::min(nmax, 512))) * 8
+    t.sub = (double*)c.take(nmax > 64 ? std::max({subspace_ws_doubles(nmax, SUBSPACE_M),
+                                                  subspace32_ws_doubles(std::min(nmax, 512)),
+                                                  subspace64b_ws_doubles(std::min(nmax, 512))}) * 8
                                       : 0);
     t.Mt64 = (double*)c.take(s->dtype == ATC_F64 ? n2 * 8 : 0);
     t.Mt32 = (float*)c.take(s->dtype == ATC_F32 ? n2 * 4 : 0);
@@ -375,6 +376,15 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
                 sa.subspace = 1;
                 paths[k] = 2;
                 HIP_TRY(run_subspace32_select(w.G, n, SUBSPACE_ITERS, max_sweeps, w.sub, sa, st));
+                selected = true;
+            } else if (attempt == 1 && subspace32_available(n)) {
+                sa.ldv = 64;
+                sa.ncand = 64;
+                sa.subspace = 1;
+                sa.lam = w.lam;
+                sa.V = w.V;
+                paths[k] = 2;
+                HIP_TRY(run_subspace64_select(w.G, n, max_sweeps, w.sub, w.lam, w.V, sweeps_dev, ok_dev, sa, st));
                 selected = true;
             } else if (attempt < 2) {
                 const int m = attempt == 0 ? std::min(SUBSPACE_M / 2, n) : std::min(SUBSPACE_M, n);

@@ -1014,10 +1014,11 @@ __device__ __forceinline__ bool chol_inv32_wave(const double (*C)[S32 + 1], doub
 // arrays spaced n x 32 apart) and B 32 x 32 in LDS; col(j) = colmap[j] or j.
 // v_mfma_f64_16x16x4f64 on 16-row tiles, wavefront w of NW taking tiles w,
 // w + NW, ...; B in registers.  Out may be the first array of X: a tile's
-// rows are all loaded before any of them is stored.
+// rows are all loaded before any of them is stored.  With Sub (n x 32,
+// global; may be Out) Out receives Sub - X B instead.
 template <int NP, int NW>
 __device__ __forceinline__ void apply32(const double* X, double* Out, int n, const double (*B)[S32 + 1],
-                                        const int* colmap) {
+                                        const int* colmap, const double* Sub = nullptr) {
     constexpr int TPW = 4;  // tiles per wavefront whose loads go out together (n <= 64 NW covered in one pass)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kr = lane >> 4, cl = lane & 15;
@@ -1051,8 +1052,9 @@ __device__ __forceinline__ void apply32(const double* X, double* Out, int n, con
             for (int e = 0; e < 4; ++e) {
                 const int r = r0 + mfma16_row<PREC_F64>(lane, e);
                 if (r < n) {
-                    Out[(int64_t)r * S32 + cl] = acc0[e];
-                    Out[(int64_t)r * S32 + 16 + cl] = acc1[e];
+                    const int64_t o = (int64_t)r * S32 + cl;
+                    Out[o] = Sub ? Sub[o] - acc0[e] : acc0[e];
+                    Out[o + 16] = Sub ? Sub[o + 16] - acc1[e] : acc1[e];
                 }
             }
         }
@@ -1593,6 +1595,92 @@ hipError_t launch_select_factor(const SelectArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+namespace {
+
+// ------------------------------------------- subspace path, m = 64, n <= 512
+// The same orthogonal iteration with a 64-column block kept as two 32-column
+// halves Pa, Pb (each n x 32): every power step orthonormalises Pa (k_orth32),
+// removes its span from Pb twice (k_proj32: Pb -= Pa (Pa^T Pb)), then
+// orthonormalises Pb, so [Pa Pb] is orthonormal; the Rayleigh-Ritz matrix B =
+// [Pa Pb]^T G [Pa Pb] (k_rr64_prep) goes to the 64-wide LDS Jacobi, V =
+// [Pa Pb] W (k_combine64), and launch_select_factor takes the rank.
+
+// Pb -= Pa (Pa^T Pb), twice (classical Gram-Schmidt of the block, repeated).
+__global__ __launch_bounds__(OT) void k_proj32(const double* __restrict__ Pa, double* __restrict__ Pb, int n) {
+    extern __shared__ double lds[];
+    double* part_lds = lds;
+    double(*C)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + OW * S32 * S32);
+    for (int pass = 0; pass < 2; ++pass) {
+        cross32<OW, 1, 1>(Pa, Pb, n, part_lds, C);
+        apply32<1, OW>(Pa, Pb, n, C, nullptr, Pb);
+        __syncthreads();
+    }
+}
+
+// B (64 x 64, row-major, symmetrised) = [Qa Qb]^T [Za Zb]; when either
+// orthonormalisation failed, the mode is handed to the next eigensolver.
+__global__ __launch_bounds__(RT) void k_rr64_prep(const double* __restrict__ Qa, const double* __restrict__ Qb,
+                                                  const double* __restrict__ Za, const double* __restrict__ Zb,
+                                                  int n, const int32_t* __restrict__ orth_ok,
+                                                  DevBook* __restrict__ book, double* __restrict__ B) {
+    extern __shared__ double lds[];
+    double* part_lds = lds;
+    double(*C)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + RW * S32 * S32);
+    __shared__ double full[2 * S32][2 * S32 + 1];
+    const int tid = threadIdx.x;
+    if (!*orth_ok) {
+        if (tid == 0) book->need_dense = 1;
+        return;
+    }
+    for (int blk = 0; blk < 4; ++blk) {
+        const double* P = (blk >> 1) ? Qb : Qa;
+        const double* Z = (blk & 1) ? Zb : Za;
+        cross32<RW, 1, 1>(P, Z, n, part_lds, C);
+        for (int e = tid; e < S32 * S32; e += RT) {
+            const int i = e >> 5, j = e & 31;
+            full[32 * (blk >> 1) + i][32 * (blk & 1) + j] = C[i][j];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < 4 * S32 * S32; e += RT) {
+        const int i = e >> 6, j = e & 63;
+        B[e] = 0.5 * (full[i][j] + full[j][i]);
+    }
+}
+
+// V[i][j] = sum_c Qa[i][c] W[c][j] + Qb[i][c] W[32 + c][j]  (n x 64, W 64 x 64).
+__global__ __launch_bounds__(256) void k_combine64(const double* __restrict__ Qa, const double* __restrict__ Qb,
+                                                   const double* __restrict__ W, double* __restrict__ V, int n) {
+    __shared__ double w[2 * S32][2 * S32];
+    for (int e = threadIdx.x; e < 4 * S32 * S32; e += 256) w[e >> 6][e & 63] = W[e];
+    __syncthreads();
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)n * 64) return;
+    const int i = (int)(idx >> 6), j = (int)(idx & 63);
+    const double* qa = Qa + (int64_t)i * S32;
+    const double* qb = Qb + (int64_t)i * S32;
+    double t = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < S32; ++c) t += qa[c] * w[c][j];
+#pragma unroll 8
+    for (int c = 0; c < S32; ++c) t += qb[c] * w[S32 + c][j];
+    V[idx] = t;
+}
+
+bool sub64_ready() {
+    static int state = 0;
+    if (state == 0) {
+        const bool a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_proj32),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)ORTH_LDS) == hipSuccess;
+        const bool b = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rr64_prep),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)RR_LDS) == hipSuccess;
+        state = (a && b) ? 1 : -1;
+    }
+    return state == 1;
+}
+
+}  // namespace
+
 bool subspace32_available(int n) { return n >= 2 * S32 && n <= 512 && sub32_ready(); }
 
 size_t subspace32_ws_doubles(int n) { return (size_t)2 * n * S32 + 8; }
@@ -1624,6 +1712,55 @@ hipError_t run_subspace32_select(const double* G, int n, int iters, int max_swee
     hipLaunchKernelGGL(k_rr32_select, dim3(1), dim3(RT), RR_LDS, st, (const double*)P2, (const double*)P1, n,
                        max_sweeps, (const int32_t*)ok, sa);
     return hipGetLastError();
+}
+
+size_t subspace64b_ws_doubles(int n) { return (size_t)4 * n * S32 + 2 * 64 * 64 + 8; }
+
+hipError_t run_subspace64_select(const double* G, int n, int max_sweeps, double* ws, double* lam, double* V,
+                                 int32_t* sweeps_dev, int32_t* ok_dev, const SelectArgs& sa, hipStream_t st) {
+    if (!subspace32_available(n) || !sub64_ready()) return hipErrorInvalidValue;
+    if (sa.ncand != 64 || sa.ldv != 64 || !sa.subspace) return hipErrorInvalidValue;
+    double* Pa = ws;
+    double* Pb = Pa + (size_t)n * S32;
+    double* Za = Pb + (size_t)n * S32;
+    double* Zb = Za + (size_t)n * S32;
+    double* B = Zb + (size_t)n * S32;     // 64 x 64
+    double* W = B + 64 * 64;              // 64 x 64
+    int32_t* ok = reinterpret_cast<int32_t*>(W + 64 * 64);
+    const dim3 gg((unsigned)ceil_div(n, GX_ROWS));
+    const dim3 gb(64 * GX_SPLIT);
+    hipError_t e;
+    hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)nullptr, Pa, n, (uint64_t)0x5eed);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)nullptr, Pb, n, (uint64_t)0x64b5eed);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    constexpr int steps = 2;
+    for (int it = 0; it < steps; ++it) {
+        const int full = it + 1 == steps ? 1 : 0;
+        hipLaunchKernelGGL(k_orth32, dim3(1), dim3(OT), ORTH_LDS, st, Pa, n, full, 1, ok);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_proj32, dim3(1), dim3(OT), ORTH_LDS, st, (const double*)Pa, Pb, n);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_orth32, dim3(1), dim3(OT), ORTH_LDS, st, Pb, n, full, 0, ok);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)Pa, Za, n, (uint64_t)0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)Pb, Zb, n, (uint64_t)0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (it + 1 < steps) {
+            std::swap(Pa, Za);
+            std::swap(Pb, Zb);
+        }
+    }
+    hipLaunchKernelGGL(k_rr64_prep, dim3(1), dim3(RT), RR_LDS, st, (const double*)Pa, (const double*)Pb,
+                       (const double*)Za, (const double*)Zb, n, (const int32_t*)ok, sa.book, B);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_eig_jacobi_lds(B, 64, 64, max_sweeps, lam, W, 64, sweeps_dev, ok_dev, st)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_combine64, dim3((unsigned)ceil_div((int64_t)n * 64, 256)), dim3(256), 0, st,
+                       (const double*)Pa, (const double*)Pb, (const double*)W, V, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_select_factor(sa, st);
 }
 
 hipError_t launch_prepare_matrix(int prec, const void* U, int src_f64, int rows, int cols, int transpose,

@@ -185,3 +185,22 @@ def test_tall_short_last_mode(precision):
     err = gpu_rel_error(x, t)
     log("  tall last mode: ranks", t.ranks, "err %.4e" % err)
     assert err <= 1.02 * eps
+
+
+@pytest.mark.parametrize("precision", ["native", "bf16x3"])
+def test_subspace_64_path(precision):
+    """Ranks above the m = 32 subspace's reach (24) on modes of 64 < n <= 512:
+    the m = 64 path (two orthonormalised 32-column halves, 64 x 64 Rayleigh-Ritz)
+    must give the oracle's ranks to the letter on a known-rank tensor."""
+    x, _, _ = synth.known_rank_tucker((150, 120, 100), (40, 36, 30), seed=64, rel_noise=1e-4)
+    x = x.astype(np.float32)
+    eps = 1e-2
+    t_o = oracle.sthosvd(x.astype(np.float64), eps)
+    t_g = _run(x, eps, torch.float32, precision=precision)
+    err = gpu_rel_error(x, t_g)
+    log("  m = 64 path: ranks gpu", t_g.ranks, "oracle", t_o.ranks, "paths", t_g.eig_path, "err %.4e" % err)
+    assert t_o.ranks == [40, 36, 30]
+    assert t_g.ranks == t_o.ranks
+    assert t_g.eig_path == [2, 2, 2]
+    assert err <= 1.02 * eps
+    assert recon_rel_diff(x, t_g, t_o) <= 0.1 * eps
