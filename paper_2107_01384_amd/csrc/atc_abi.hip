@@ -308,6 +308,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
     if (!g_flags.init()) return fail(ATC_ERR_DEVICE, "hipHostMalloc of the report block failed");
     int paths[ATC_MAX_DIMS] = {0};
     int lazy[ATC_MAX_DIMS], nlazy = 0;  // modes kept whole, rotated at the end
+    bool wide_hint = false;             // the previous subspace mode needed m = 64
     for (int i = 0; i < d; ++i) {
         const int k = order[i];
         const int64_t L = prod(cur, 0, k), R = prod(cur, k + 1, d);
@@ -366,7 +367,10 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         // FP32-grade Gram matrix carries, not to FP64) unless eig_path forces it.
         const int32_t zero = 0;
         const bool dense_first = n <= 64 || opts->eig_path == 1 || (f64 && opts->eig_path != 2);
-        int attempt = dense_first ? 2 : 0;
+        // a mode after one whose rank needed the m = 64 subspace starts there
+        // (ranks of neighbouring modes tend to be alike; m = 64 is never less
+        // accurate, only slower when m = 32 would have done)
+        int attempt = dense_first ? 2 : (wide_hint && subspace32_available(n) ? 1 : 0);
         for (;; ++attempt) {
             bool selected = false;
             sa.seq = ++g_flags.seq;
@@ -430,6 +434,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
             HIP_TRY(hipMemcpyAsync(&w.book->need_dense, &zero, sizeof(zero), hipMemcpyHostToDevice, st));
         }
         if (!hf.eig_ok) return fail(ATC_ERR_NOT_CONVERGED, "mode %d: eigensolver hit %d sweeps", k, max_sweeps);
+        if (n > 64) wide_hint = attempt >= 1;
         rep_tail[k] = hf.tail;
         rep_budget[k] = hf.budget;
         rep_sweeps[k] = hf.sweeps;
