@@ -275,18 +275,8 @@ __device__ bool blk_jacobi(int n, int max_sweeps, BatchSmem<BK>& sm) {
                     p = q;
                     q = t;
                 }
-                const double app = A[p][p], aqq = A[q][q], apq = A[p][q];
-                double c = 1.0, s = 0.0, dp = app, dq = aqq;
-                if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app)) * sqrt(fabs(aqq))) {
-                    const double tau = (aqq - app) / (2.0 * apq);
-                    const double t = fabs(tau) > 1e150 ? 0.5 / tau
-                                                       : (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    s = t * c;
-                    dp = app - t * apq;
-                    dq = aqq + t * apq;
-                    sm.flag = 1;
-                }
+                double c, s, dp, dq;
+                if (schur2_rs(A[p][p], A[q][q], A[p][q], tol, c, s, dp, dq)) sm.flag = 1;
                 sm.pp[tid] = p;
                 sm.qq[tid] = q;
                 sm.cs[tid] = c;

@@ -127,7 +127,7 @@ __global__ __launch_bounds__((MAXM / 2) * (MAXM / 2)) void k_eig_jacobi_lds(
                 int p, q;
                 round_robin_pair(round, tid, m, p, q);
                 double c, s, dp, dq;
-                if (schur2(A[p][p], A[q][q], A[p][q], tol, c, s, dp, dq)) rotated = 1;
+                if (schur2_rs(A[p][p], A[q][q], A[p][q], tol, c, s, dp, dq)) rotated = 1;
                 pp[tid] = p;
                 qq[tid] = q;
                 cs[tid] = c;

@@ -54,6 +54,37 @@ constexpr int FLUSH_TERMS = 128;  // FP32 accumulation chunk before the FP64 add
 template <int P> struct KDepth { static constexpr int value = 32; };
 template <> struct KDepth<PREC_F64> { static constexpr int value = 16; };
 
+// The Jacobi rotation of a symmetric pair (p, q), rotated when |a_pq| > tol
+// sqrt(|a_pp a_qq|), by the smaller angle, with two
+// reciprocal square roots instead of two divisions and two square roots:
+// d = a_qq - a_pp, g = 2 a_pq, h = hypot(d, g), u = (1 + |d| / h) / 2,
+// c = sqrt(u), s = sign(d) g / (2 h c), t = s / c.  Each reciprocal square
+// root gets one Newton step to working precision.
+__device__ inline double rsqrt_nr1(double z) {
+    const double r = rsqrt(z);
+    return r * (1.5 - 0.5 * z * r * r);
+}
+__device__ inline bool schur2_rs(double app, double aqq, double apq, double tol, double& c, double& s, double& dp,
+                                 double& dq) {
+    c = 1.0;
+    s = 0.0;
+    dp = app;
+    dq = aqq;
+    if (!(apq * apq > tol * tol * fabs(app * aqq))) return false;
+    const double d = aqq - app, g = 2.0 * apq;
+    const double hh = d * d + g * g;
+    if (!(hh > 0.0) || !(hh < INFINITY)) return false;  // squares out of range: leave the pair
+    const double rh = rsqrt_nr1(hh);
+    const double u = 0.5 + 0.5 * fabs(d) * rh;
+    const double rc = rsqrt_nr1(u);
+    c = u * rc;
+    s = (d >= 0.0 ? 0.5 : -0.5) * g * rh * rc;
+    const double t = s * rc;
+    dp = app - t * apq;
+    dq = aqq + t * apq;
+    return true;
+}
+
 // Output row held in register v by `lane` for the 16 x 16 MFMA blocks (the
 // column is lane % 16): the FP32-accumulating f32 / bf16 forms hold rows
 // 4*(lane/16) + v, the f64 form holds rows lane/16 + 4*v (measured on gfx950).
