@@ -255,6 +255,32 @@ __device__ bool blk_jacobi(int n, int max_sweeps, BatchSmem<BK>& sm) {
     }
     __syncthreads();
     const double tol = (double)n * 0x1p-53;
+    // this thread's share of the round's work, fixed for the whole solve: up
+    // to 3 of the h (h + 1) / 2 blocks (k, l), k <= l, and up to 8 of the m h
+    // (row, pair) entries of the eigenvector update (codes k | l << 8 and
+    // i | k << 8, -1 for none), so the rounds need no division
+    constexpr int NBK = (BMAX / 2) * (BMAX / 2 + 1) / 2 / BT + 1;
+    constexpr int NVR = BMAX * (BMAX / 2) / BT;
+    int blk[NBK], vrk[NVR];
+    {
+        int b = 0, k = 0, l = 0;  // enumerate the upper triangle in order
+        for (int j = 0; j < NBK; ++j) {
+            const int want = tid + BT * j;
+            while (b < want && k < h) {
+                ++b;
+                if (++l == h) {
+                    ++k;
+                    l = k;
+                }
+            }
+            blk[j] = (want < h * (h + 1) / 2 && k < h) ? (k | (l << 8)) : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < NVR; ++j) {
+            const int idx = tid + BT * j;
+            vrk[j] = idx < m * h ? ((idx / h) | ((idx % h) << 8)) : -1;
+        }
+    }
     int sweeps = 0;
     bool converged = m < 2;
     while (!converged && sweeps < max_sweeps) {
@@ -286,9 +312,10 @@ __device__ bool blk_jacobi(int n, int max_sweeps, BatchSmem<BK>& sm) {
             }
             __syncthreads();
             // 2x2 blocks (k <= l) of the rotation pairs, mirrored
-            for (int idx = tid; idx < h * h; idx += BT) {
-                const int k = idx / h, l = idx % h;
-                if (k > l) continue;
+#pragma unroll
+            for (int j = 0; j < NBK; ++j) {
+                if (blk[j] < 0) continue;
+                const int k = blk[j] & 255, l = blk[j] >> 8;
                 const int p = sm.pp[k], q = sm.qq[k];
                 const double c1 = sm.cs[k], s1 = sm.sn[k];
                 if (k == l) {
@@ -317,8 +344,10 @@ __device__ bool blk_jacobi(int n, int max_sweeps, BatchSmem<BK>& sm) {
                 A[p2][q] = nc;
                 A[q2][q] = nd;
             }
-            for (int idx = tid; idx < m * h; idx += BT) {
-                const int i = idx / h, k = idx % h;
+#pragma unroll
+            for (int j = 0; j < NVR; ++j) {
+                if (vrk[j] < 0) continue;
+                const int i = vrk[j] & 255, k = vrk[j] >> 8;
                 const double s1 = sm.sn[k];
                 if (s1 == 0.0) continue;
                 const double c1 = sm.cs[k];
