@@ -25,6 +25,7 @@
 // discarded energy and the error bound still holds; a rank that reaches into
 // the last `guard` Ritz pairs sends the mode to a larger m or the dense path.
 #include <math.h>
+#include <stdlib.h>
 
 #include "atc_internal.hpp"
 
@@ -809,16 +810,14 @@ constexpr int RW = RT / 64;
 constexpr size_t ORTH_LDS = (size_t)(OW * S32 * S32 + 2 * S32 * (S32 + 1)) * sizeof(double);
 constexpr size_t RR_LDS = (size_t)(RW * S32 * S32 + 2 * S32 * (S32 + 1)) * sizeof(double);
 
-// Y (n x 32) = G X, X == nullptr: X[k][j] = hash_unit((32 k + j) * C + salt).
-// One workgroup of GX_SPLIT wavefronts per 16-row tile; wavefront w takes the
-// w-th K chunk on v_mfma_f64_16x16x4f64 (eight K steps' loads in flight) and
-// the partial tiles are added in LDS in wavefront order.
-__global__ __launch_bounds__(64 * GX_SPLIT) void k_gemm_gx(const double* __restrict__ G, const double* __restrict__ X,
-                                                           double* __restrict__ Y, int n, uint64_t salt) {
-    __shared__ double red[GX_SPLIT][GX_ROWS][S32 + 1];
-    const int lane = threadIdx.x & 63, s = threadIdx.x >> 6;
+// Rows r0 .. r0 + 15 of G X over the s-th of GX_SPLIT K chunks into red (16 x
+// 33, LDS), one wavefront, on v_mfma_f64_16x16x4f64 (eight K steps' loads in
+// flight).  X == nullptr: X[k][j] = hash_unit((32 k + j) * C + salt).  Rows
+// past n repeat row n - 1 (their results are not stored).
+__device__ __forceinline__ void gx_partial(const double* __restrict__ G, const double* __restrict__ X, int n,
+                                           uint64_t salt, int r0, int s, double (*red)[S32 + 1]) {
+    const int lane = threadIdx.x & 63;
     const int kr = lane >> 4, cl = lane & 15;
-    const int r0 = blockIdx.x * GX_ROWS;
     const int chunk = (int)ceil_div(ceil_div(n, GX_SPLIT), 4) * 4;
     const int k0 = min(n, s * chunk), k1 = min(n, k0 + chunk);
     const int ra = min(r0 + cl, n - 1);
@@ -851,9 +850,20 @@ __global__ __launch_bounds__(64 * GX_SPLIT) void k_gemm_gx(const double* __restr
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int r = mfma16_row<PREC_F64>(lane, e);
-        red[s][r][cl] = acc0[e];
-        red[s][r][16 + cl] = acc1[e];
+        red[r][cl] = acc0[e];
+        red[r][16 + cl] = acc1[e];
     }
+}
+
+// Y (n x 32) = G X (gx_partial).  One workgroup of GX_SPLIT wavefronts per
+// 16-row tile; wavefront w takes the w-th K chunk and the partial tiles are
+// added in LDS in wavefront order.
+__global__ __launch_bounds__(64 * GX_SPLIT) void k_gemm_gx(const double* __restrict__ G, const double* __restrict__ X,
+                                                           double* __restrict__ Y, int n, uint64_t salt) {
+    __shared__ double red[GX_SPLIT][GX_ROWS][S32 + 1];
+    const int s = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * GX_ROWS;
+    gx_partial(G, X, n, salt, r0, s, red[s]);
     __syncthreads();
     for (int e = threadIdx.x; e < GX_ROWS * S32; e += 64 * GX_SPLIT) {
         const int r = e / S32, c = e % S32;
@@ -903,10 +913,11 @@ __device__ __forceinline__ double parts_at(const double* __restrict__ X, int64_t
 // v_mfma_f64_16x16x4f64 over groups of four rows (rows 4w, 4w + 4 NW, ...; four
 // groups' loads in flight), every element loaded once per wavefront; the NW
 // partial products pass through part_lds and are added in wavefront order.
-template <int NW, int NPP, int NPY>
+template <int NW, int NPP, int NPY, int UNR_ = 0>
 __device__ __forceinline__ void cross32(const double* __restrict__ P, const double* __restrict__ Y, int n,
                                         double* part_lds, double (*C)[S32 + 1]) {
-    constexpr int UNR = (NW >= 8) ? 16 : 8;  // row groups whose loads go out together
+    // row groups whose loads go out together (1 for a 32-row slab)
+    constexpr int UNR = UNR_ ? UNR_ : ((NW >= 8) ? 16 : 8);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kr = lane >> 4, cl = lane & 15;
     const int64_t ps = (int64_t)n * S32;
@@ -995,7 +1006,9 @@ __device__ __forceinline__ void cinv_step(double (&v)[S32], double* rowbuf, doub
     }
 }
 
-__device__ __forceinline__ bool chol_inv32_wave(const double (*C)[S32 + 1], double (*Rinv)[S32 + 1],
+// Not inlined: a call site of its own keeps its unrolled steps from raising the
+// register pressure of the caller.
+__device__ __attribute__((noinline)) bool chol_inv32_wave(const double (*C)[S32 + 1], double (*Rinv)[S32 + 1],
                                                 double* rowbuf) {
     const int lane = threadIdx.x & 63, b = lane & 31;
     const bool idl = lane >= S32;
@@ -1016,10 +1029,9 @@ __device__ __forceinline__ bool chol_inv32_wave(const double (*C)[S32 + 1], doub
 // w + NW, ...; B in registers.  Out may be the first array of X: a tile's
 // rows are all loaded before any of them is stored.  With Sub (n x 32,
 // global; may be Out) Out receives Sub - X B instead.
-template <int NP, int NW>
+template <int NP, int NW, int TPW = 4>  // TPW: tiles per wavefront whose loads go out together
 __device__ __forceinline__ void apply32(const double* X, double* Out, int n, const double (*B)[S32 + 1],
                                         const int* colmap, const double* Sub = nullptr) {
-    constexpr int TPW = 4;  // tiles per wavefront whose loads go out together (n <= 64 NW covered in one pass)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kr = lane >> 4, cl = lane & 15;
     const int64_t ps = (int64_t)n * S32;
@@ -1551,6 +1563,360 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
     rr_factor_out(al, Q, n, Wm, col_of, r_s, reinterpret_cast<SignCand*>(part_lds), sign_s);
 }
 
+// ------------------------------- subspace path, m = 32, one cooperative launch
+// The orthogonal iteration and Rayleigh-Ritz step of k_gemm_gx / k_orth32 /
+// k_rr32_select in one launch of ceil(n / 32) workgroups, workgroup b owning
+// rows 32 b .. 32 b + 31 of the n x 32 blocks.  The 32 x 32 products Y^T Y and
+// Q^T Z are formed per slab and summed over the workgroups through global
+// partial arrays in workgroup order, so every workgroup holds the same matrix
+// bit for bit and computes the same Cholesky factor, series correction and
+// Jacobi eigenvectors by itself (no broadcast step).  Only the products G X
+// read every row of X and wait for all workgroups.  The launch is cooperative
+// (all workgroups resident), which the grid barrier relies on.
+
+constexpr int GRID_ROWS = 32;                 // rows per workgroup
+constexpr int GRID_MAXB = 512 / GRID_ROWS;    // workgroups for n <= 512
+constexpr unsigned GRID_SPIN_LIMIT = 1u << 20;  // polls before a wait gives up
+
+// Global scratch of the cooperative path (inside the subspace workspace).
+struct Sub32Grid {
+    double* P1;       // n x 32
+    double* P2;       // n x 32
+    double* part;     // 2 x GRID_MAXB x 1024: per-workgroup 32 x 32 products, two alternating sets
+    double* cand;     // GRID_MAXB x 32 x 3: sign candidates (|v|, v, row)
+    unsigned* sync;   // [0] arrivals, [1] rank, [2] need_dense, [3] a wait gave up; zeroed before the launch
+};
+
+// Grid barrier: every wavefront drains its stores, thread 0 makes the
+// workgroup's stores visible at device scope (release), adds its arrival and
+// polls until `target` arrivals, then makes the other workgroups' stores
+// visible (acquire).  The wait is bounded: a workgroup that gives up records
+// it and goes on, so every wavefront still reaches the end of the kernel.
+__device__ __forceinline__ void grid_sync(unsigned* sync, unsigned target) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned spins = 0;
+        while (__hip_atomic_load(&sync[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > GRID_SPIN_LIMIT) {
+                __hip_atomic_store(&sync[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// Per-workgroup state of the cooperative path.
+struct GridCtx {
+    Sub32Grid g;
+    int n, b, nb, row0, nr;
+    unsigned arrivals;  // barriers passed so far times nb
+    int parity;         // partial set of the next exchange
+    __device__ void sync() {
+        arrivals += (unsigned)nb;
+        grid_sync(g.sync, arrivals);
+    }
+};
+
+// C (LDS) = sum over workgroups, in workgroup order, of P_b^T Z_b (each
+// workgroup's nr rows of P and Z); the same value in every workgroup.
+__device__ __forceinline__ void cross_grid(GridCtx& x, const double* P, const double* Z, double* part_lds,
+                                           double (*C)[S32 + 1]) {
+    const int tid = threadIdx.x;
+    cross32<RW, 1, 1, 1>(P, Z, x.nr, part_lds, C);
+    double* slot = x.g.part + (size_t)x.parity * GRID_MAXB * (S32 * S32);
+    x.parity ^= 1;
+    for (int e = tid; e < S32 * S32; e += RT) slot[(size_t)x.b * (S32 * S32) + e] = C[e >> 5][e & 31];
+    x.sync();
+    for (int e = tid; e < S32 * S32; e += RT) {
+        double v[GRID_MAXB];
+#pragma unroll
+        for (int o = 0; o < GRID_MAXB; ++o) v[o] = slot[(size_t)(o < x.nb ? o : 0) * (S32 * S32) + e];
+        double t = 0.0;
+#pragma unroll
+        for (int o = 0; o < GRID_MAXB; ++o)
+            if (o < x.nb) t += v[o];
+        C[e >> 5][e & 31] = t;
+    }
+    __syncthreads();
+}
+
+// Rows row0 .. row0 + 31 of G X into Y (X == nullptr: the hash matrix of
+// salt): wavefront w takes row tile w & 1 and K chunk w >> 1; the chunks are
+// added in order.  red: 2 x GX_SPLIT x 16 x 33 doubles of LDS.
+__device__ __forceinline__ void gx_rows32(const GridCtx& x, const double* __restrict__ G, const double* X,
+                                          uint64_t salt, double* Y, double* red_lds) {
+    static_assert(RW == 2 * GX_SPLIT, "two row tiles of GX_SPLIT chunks");
+    const int tid = threadIdx.x, wave = tid >> 6;
+    auto red = reinterpret_cast<double(*)[GX_SPLIT][GX_ROWS][S32 + 1]>(red_lds);
+    gx_partial(G, X, x.n, salt, x.row0 + GX_ROWS * (wave & 1), wave >> 1, red[wave & 1][wave >> 1]);
+    __syncthreads();
+    for (int e = tid; e < 2 * GX_ROWS * S32; e += RT) {
+        const int rt = e / (GX_ROWS * S32), r = (e / S32) % GX_ROWS, c = e % S32;
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < GX_SPLIT; ++w) t += red[rt][w][r][c];
+        const int row = x.row0 + GX_ROWS * rt + r;
+        if (row < x.n) Y[(int64_t)row * S32 + c] = t;
+    }
+    __syncthreads();
+}
+
+// One Cholesky QR pass on the workgroup's rows Y (in place), as cholqr_pass.
+__device__ __forceinline__ bool cholqr_grid(GridCtx& x, double* Y, bool shifted, double* part_lds,
+                                            double (*C)[S32 + 1], double (*Rinv)[S32 + 1], double* rowbuf,
+                                            int* ok_s) {
+    const int tid = threadIdx.x;
+    cross_grid(x, Y, Y, part_lds, C);
+    if (tid < 64) {
+        if (shifted) {
+            double fro = 0.0;
+            for (int j = 0; j < S32; ++j) fro += C[j][j];
+            const double sh = 11.0 * ((double)x.n * S32 + (double)S32 * (S32 + 1)) * 0x1p-53 * fro;
+            wave_sync();
+            if (tid < S32) C[tid][tid] += sh;
+            wave_sync();
+        }
+        const bool ok = chol_inv32_wave(C, Rinv, rowbuf);
+        if (tid == 0) *ok_s = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!*ok_s) return false;
+    apply32<1, RW, 1>(Y, Y, x.nr, Rinv, nullptr);
+    __syncthreads();
+    return true;
+}
+
+// The series correction of series_pass on the workgroup's rows.
+__device__ __forceinline__ bool series_grid(GridCtx& x, double* Y, double* part_lds, double (*C)[S32 + 1],
+                                            double (*X)[S32 + 1], int* ok_s) {
+    const int tid = threadIdx.x;
+    cross_grid(x, Y, Y, part_lds, C);
+    for (int e = tid; e < S32 * S32; e += RT) {
+        const int i = e >> 5, j = e & 31;
+        if (i == j) C[i][j] -= 1.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+        double m = 0.0;
+        for (int e = tid; e < S32 * S32; e += 64) m = fmax(m, fabs(C[e >> 5][e & 31]));
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+        if (tid == 0) *ok_s = (m <= 1e-4) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!*ok_s) return false;
+    for (int e = tid; e < S32 * S32; e += RT) {
+        const int i = e >> 5, j = e & 31;
+        double t = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < S32; ++k) t += C[i][k] * C[k][j];
+        X[i][j] = (i == j ? 1.0 : 0.0) - 0.5 * C[i][j] + 0.375 * t;
+    }
+    __syncthreads();
+    apply32<1, RW, 1>(Y, Y, x.nr, X, nullptr);
+    __syncthreads();
+    return true;
+}
+
+// The orthonormalisation of k_orth32 on the workgroup's rows of Y.
+__device__ __forceinline__ bool orth_grid(GridCtx& x, double* Y, bool full, double* part_lds, double (*C)[S32 + 1],
+                                          double (*R)[S32 + 1], double* rowbuf, int* ok_s) {
+    bool good = true, done = false;
+    for (int pass = 0; pass < 3 && good && !done; ++pass) {
+        good = cholqr_grid(x, Y, pass == 0, part_lds, C, R, rowbuf, ok_s);
+        if (!good || pass == 0) continue;
+        if (!full) done = true;
+        else if (series_grid(x, Y, part_lds, C, R, ok_s)) done = true;
+        else if (pass == 2) good = false;
+    }
+    return good && done;
+}
+
+__global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G, int n, int steps, int max_sweeps,
+                                                   Sub32Grid g, SelectArgs a) {
+    extern __shared__ double lds[];
+    double* part_lds = lds;
+    double(*Bm)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + RW * S32 * S32);
+    double(*Wm)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + RW * S32 * S32 + S32 * (S32 + 1));
+    __shared__ double2 jlog[2 * (S32 - 1) * (S32 / 2)];
+    __shared__ int jptab[(S32 - 1) * (S32 / 2)];
+    __shared__ int jflag;
+    __shared__ double rowbuf[64];
+    __shared__ int col_of[S32];
+    __shared__ double lam_s[S32];
+    __shared__ double red[17];
+    __shared__ int sign_s[S32];
+    __shared__ SignCand wcand[2][S32];
+    __shared__ int ok_s, r_s, dense_s;
+    static_assert(2 * GX_SPLIT * GX_ROWS * (S32 + 1) <= RW * S32 * S32, "product partials fit");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    GridCtx x;
+    x.g = g;
+    x.n = n;
+    x.b = blockIdx.x;
+    x.nb = gridDim.x;
+    x.row0 = GRID_ROWS * x.b;
+    x.nr = min(GRID_ROWS, n - x.row0);
+    x.arrivals = 0;
+    x.parity = 0;
+    DevBook* bk = a.book;
+    double tr = 0.0;
+    if (x.b == 0) tr = gram_trace(a, red);
+    // power steps: P1 <- orth(P1), P2 <- G P1, swap
+    double* P1 = g.P1;
+    double* P2 = g.P2;
+    gx_rows32(x, G, nullptr, 0x5eed, P1, part_lds);
+    bool good = true;
+    for (int it = 0; it < steps && good; ++it) {
+        double* Yb = P1 + (int64_t)x.row0 * S32;
+        good = orth_grid(x, Yb, it + 1 == steps, part_lds, Bm, Wm, rowbuf, &ok_s);
+        if (!good) break;
+        x.sync();
+        gx_rows32(x, G, P1, 0, P2, part_lds);
+        double* t = P1;
+        P1 = P2;
+        P2 = t;
+    }
+    if (!good) {
+        // the same outcome in every workgroup: hand the mode to the next eigensolver
+        if (x.b == 0 && tid == 0) {
+            bk->need_dense = 1;
+            publish_selection(a, 0);
+        }
+        return;
+    }
+    // P2: the basis Q, P1 = G Q.  B = Q^T Z, symmetrised; Jacobi in every workgroup
+    const double* Qb = P2 + (int64_t)x.row0 * S32;
+    cross_grid(x, Qb, P1 + (int64_t)x.row0 * S32, part_lds, Bm);
+    for (int e = tid; e < S32 * S32; e += RT) {
+        const int i = e >> 5, j = e & 31;
+        Wm[i][j] = 0.5 * (Bm[i][j] + Bm[j][i]);
+    }
+    __syncthreads();
+    for (int e = tid; e < S32 * S32; e += RT) {
+        const int i = e >> 5, j = e & 31;
+        Bm[i][j] = Wm[i][j];
+        Wm[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    int sw;
+    bool cv;
+    static_assert(RW * S32 * S32 * sizeof(double) >= (S32 - 1) * 128 * sizeof(uint4), "block table");
+    jacobi32(Bm, Wm, max_sweeps, jlog, jptab, reinterpret_cast<uint4*>(part_lds), &jflag, sw, cv);
+    if (tid < S32) {
+        const double li = Bm[tid][tid];
+        int r = 0;
+        for (int j = 0; j < S32; ++j) {
+            const double lj = Bm[j][j];
+            r += (lj > li) || (lj == li && j < tid);
+        }
+        col_of[r] = tid;
+        lam_s[r] = li;
+        if (x.b == 0) const_cast<double*>(a.lam)[r] = li;
+    }
+    __syncthreads();
+    SelectArgs al = a;
+    al.lam = lam_s;
+    if (x.b == 0 && tid == 0) {
+        bk->sweeps[a.k] = sw;
+        bk->eig_ok = cv ? 1 : 0;
+        if (__hip_atomic_load(&g.sync[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) bk->status = ATC_ERR_INTERNAL;
+        choose_rank(al, tr, r_s, dense_s);
+        __hip_atomic_store(&g.sync[1], (unsigned)r_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&g.sync[2], (unsigned)dense_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // V_b = Q_b W[:, col_of] in the accumulators of wavefronts 0 and 1 (16 rows each)
+    const int kr = lane >> 4, cl = lane & 15;
+    const bool vw = wave < 2;
+    f64x4 acc0 = f64x4{0.0, 0.0, 0.0, 0.0}, acc1 = acc0;
+    const int rbase = x.row0 + 16 * (wave & 1);
+    if (vw) {
+        const int c0 = col_of[cl], c1 = col_of[16 + cl];
+        const int ra = min(rbase + cl, n - 1);
+#pragma unroll
+        for (int ks = 0; ks < 8; ++ks) {
+            const double av = P2[(int64_t)ra * S32 + 4 * ks + kr];
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Wm[4 * ks + kr][c0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Wm[4 * ks + kr][c1], acc1, 0, 0, 0);
+        }
+        double best[2] = {-1.0, -1.0}, val[2] = {0.0, 0.0};
+        int bi[2] = {0x7fffffff, 0x7fffffff};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = rbase + mfma16_row<PREC_F64>(lane, e);
+            if (row < n) {
+                sign_merge(best[0], bi[0], val[0], fabs(acc0[e]), row, acc0[e]);
+                sign_merge(best[1], bi[1], val[1], fabs(acc1[e]), row, acc1[e]);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            for (int o = 16; o < 64; o <<= 1) {
+                const double ob = __shfl_xor(best[h], o);
+                const int oi = __shfl_xor(bi[h], o);
+                const double ov = __shfl_xor(val[h], o);
+                sign_merge(best[h], bi[h], val[h], ob, oi, ov);
+            }
+            if (lane < 16) wcand[wave][16 * h + cl] = SignCand{best[h], val[h], bi[h], 0};
+        }
+    }
+    __syncthreads();
+    if (tid < S32) {
+        SignCand c = wcand[0][tid];
+        const SignCand o = wcand[1][tid];
+        sign_merge(c.best, c.row, c.val, o.best, o.row, o.val);
+        double* gc = g.cand + ((size_t)x.b * S32 + tid) * 3;
+        gc[0] = c.best;
+        gc[1] = c.val;
+        gc[2] = (double)c.row;
+    }
+    x.sync();
+    const int r = (int)__hip_atomic_load(&g.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int dense = (int)__hip_atomic_load(&g.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (dense) return;
+    if (tid < S32) {
+        double best = -1.0, val = 0.0;
+        int bi = 0x7fffffff;
+        for (int o = 0; o < x.nb; ++o) {
+            const double* gc = g.cand + ((size_t)o * S32 + tid) * 3;
+            sign_merge(best, bi, val, gc[0], (int)gc[2], gc[1]);
+        }
+        sign_s[tid] = val < 0.0 ? -1 : 1;
+    }
+    __syncthreads();
+    if (vw) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = rbase + mfma16_row<PREC_F64>(lane, e);
+            if (row < n) {
+                if (cl < r) store_factor(al, row, cl, r, sign_s[cl] * acc0[e]);
+                if (16 + cl < r) store_factor(al, row, 16 + cl, r, sign_s[16 + cl] * acc1[e]);
+            }
+        }
+    }
+}
+
+// The cooperative path needs cooperative launches and its LDS; ATC_SUB32_KERNELS=1
+// in the environment (read at every call) selects the kernel-per-step path.
+bool sub32_grid_ready() {
+    static int state = 0;
+    if (state == 0) {
+        int dev = 0, coop = 0;
+        const bool a = hipGetDevice(&dev) == hipSuccess &&
+                       hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess && coop;
+        const bool b = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sub32_grid),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)RR_LDS) == hipSuccess;
+        state = (a && b) ? 1 : -1;
+    }
+    const char* env = getenv("ATC_SUB32_KERNELS");
+    return state == 1 && !(env && env[0] == '1');
+}
+
 bool sub32_ready() {
     static int state = 0;
     if (state == 0) {
@@ -1683,7 +2049,11 @@ bool sub64_ready() {
 
 bool subspace32_available(int n) { return n >= 2 * S32 && n <= 512 && sub32_ready(); }
 
-size_t subspace32_ws_doubles(int n) { return (size_t)2 * n * S32 + 8; }
+// P1, P2 (n x 32 each), 8 doubles of flags, then the cooperative path's
+// partial products, sign candidates and barrier words.
+size_t subspace32_ws_doubles(int n) {
+    return (size_t)2 * n * S32 + 8 + (size_t)2 * GRID_MAXB * S32 * S32 + (size_t)GRID_MAXB * S32 * 3 + 8;
+}
 
 hipError_t run_subspace32_select(const double* G, int n, int iters, int max_sweeps, double* ws, const SelectArgs& sa,
                                  hipStream_t st) {
@@ -1692,12 +2062,29 @@ hipError_t run_subspace32_select(const double* G, int n, int iters, int max_swee
     double* P1 = ws;                   // n x 32
     double* P2 = P1 + (size_t)n * S32;  // n x 32
     int32_t* ok = reinterpret_cast<int32_t*>(P2 + (size_t)n * S32);
+    const int steps = iters < 1 ? 1 : iters;
+    hipError_t e;
+    if (sub32_grid_ready()) {
+        Sub32Grid g;
+        g.P1 = P1;
+        g.P2 = P2;
+        g.part = P2 + (size_t)n * S32 + 8;
+        g.cand = g.part + (size_t)2 * GRID_MAXB * S32 * S32;
+        g.sync = reinterpret_cast<unsigned*>(g.cand + (size_t)GRID_MAXB * S32 * 3);
+        if ((e = launch_zero(g.sync, 8 * sizeof(unsigned), st)) != hipSuccess) return e;
+        const int nb = (int)ceil_div(n, GRID_ROWS);
+        int n_ = n, steps_ = steps, sweeps_ = max_sweeps;
+        SelectArgs sa_ = sa;
+        void* args[] = {(void*)&G, (void*)&n_, (void*)&steps_, (void*)&sweeps_, (void*)&g, (void*)&sa_};
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sub32_grid), dim3(nb), dim3(RT), args,
+                                       (unsigned)RR_LDS, st);
+        if (e == hipSuccess) return hipSuccess;
+        (void)hipGetLastError();  // not launched: the kernel-per-step path below
+    }
     const dim3 gg((unsigned)ceil_div(n, GX_ROWS));
     const dim3 gb(64 * GX_SPLIT);
-    hipError_t e;
     hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)nullptr, P1, n, (uint64_t)0x5eed);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int steps = iters < 1 ? 1 : iters;
     for (int it = 0; it < steps; ++it) {
         // P1 <- orthonormal basis of its columns, then P2 <- G P1; the last basis
         // (the Rayleigh-Ritz one) gets the verified final correction

@@ -204,3 +204,36 @@ def test_subspace_64_path(precision):
     assert t_g.eig_path == [2, 2, 2]
     assert err <= 1.02 * eps
     assert recon_rel_diff(x, t_g, t_o) <= 0.1 * eps
+
+
+@pytest.mark.parametrize("shape", [(90, 80, 70), (512, 20, 24), (300, 65, 33)])
+def test_subspace_one_launch_and_kernel_chain_agree(shape, monkeypatch):
+    """The m = 32 subspace path as one cooperative launch (default) and as a
+    chain of kernels (ATC_SUB32_KERNELS=1) run the same iteration from the same
+    start block: same ranks, tails and kept subspaces up to rounding order.
+    Workgroups of 32 rows: 16 of them for n = 512, a last one of 26, 12 and 1
+    rows for n = 90, 300 and 65."""
+    x = synth.field(shape, 5)
+    monkeypatch.delenv("ATC_SUB32_KERNELS", raising=False)
+    t_c = _run(x, 1e-3, torch.float32, eig_path=2)
+    monkeypatch.setenv("ATC_SUB32_KERNELS", "1")
+    t_k = _run(x, 1e-3, torch.float32, eig_path=2)
+    monkeypatch.delenv("ATC_SUB32_KERNELS")
+    log("one launch", t_c.ranks, t_c.eig_path, "kernels", t_k.ranks, t_k.eig_path)
+    sub = [k for k, n in enumerate(shape) if 64 < n <= 512]  # n <= 64 goes to the dense solver
+    assert sub, shape
+    for k in sub:
+        assert t_c.eig_path[k] == 2 and t_k.eig_path[k] == 2, (t_c.eig_path, t_k.eig_path)
+    assert t_c.ranks == t_k.ranks
+    for k in range(len(shape)):
+        assert abs(t_c.tails[k] - t_k.tails[k]) <= 1e-9 * t_c.norm2
+        gap = projector_gap(np64(t_c.factors[k]), np64(t_k.factors[k]))
+        log("  mode", k, "projector gap %.2e" % gap)
+        assert gap < 1e-7
+        # the sign rule picks the same rows: columns agree to rounding
+        assert np.max(np.abs(np64(t_c.factors[k]) - np64(t_k.factors[k]))) < 1e-6
+    xc = oracle.reconstruct(np64(t_c.core), [np64(f) for f in t_c.factors])
+    xk = oracle.reconstruct(np64(t_k.core), [np64(f) for f in t_k.factors])
+    assert np.sqrt(oracle.norm2(xc - xk) / oracle.norm2(x)) < 1e-6
+    ok, how = rank_parity(t_c, oracle.sthosvd(x, 1e-3), 0.1)
+    assert ok, how
