@@ -617,7 +617,8 @@ __device__ __forceinline__ double gram_trace(const SelectArgs& a, double* red) {
 // trace; the book entries, the host flags.  r_s <- rank, dense_s <- 1 when the
 // subspace does not hold enough Ritz pairs (the caller then stops: the host
 // moves to a larger eigensolver).
-__device__ __forceinline__ void choose_rank(const SelectArgs& a, double tr, int& r_s, int& dense_s) {
+__device__ __forceinline__ void choose_rank(const SelectArgs& a, double tr, int& r_s, int& dense_s,
+                                            bool publish = true) {
     DevBook* bk = a.book;
     if (a.pos == 0) {
         bk->norm2 = tr;
@@ -683,7 +684,7 @@ __device__ __forceinline__ void choose_rank(const SelectArgs& a, double tr, int&
     }
     r_s = r;
     dense_s = dense;
-    publish_selection(a, r);
+    if (publish) publish_selection(a, r);
 }
 
 // Entry (i, j) of the factor, u with its sign applied: the user factor is
@@ -1647,22 +1648,69 @@ __device__ __forceinline__ void cross_grid(GridCtx& x, const double* P, const do
 }
 
 // Rows row0 .. row0 + 31 of G X into Y (X == nullptr: the hash matrix of
-// salt): wavefront w takes row tile w & 1 and K chunk w >> 1; the chunks are
-// added in order.  red: 2 x GX_SPLIT x 16 x 33 doubles of LDS.
+// salt, as in gx_partial, when HASH): wavefront w takes the w-th of RW K
+// chunks for all 32 rows and columns, in batches of eight K steps whose loads
+// go out together (two memory latencies per product for n = 512), then the
+// chunks are added in order through LDS.  red_lds: RW x 32 x 32 doubles.
+template <bool HASH>
 __device__ __forceinline__ void gx_rows32(const GridCtx& x, const double* __restrict__ G, const double* X,
                                           uint64_t salt, double* Y, double* red_lds) {
-    static_assert(RW == 2 * GX_SPLIT, "two row tiles of GX_SPLIT chunks");
-    const int tid = threadIdx.x, wave = tid >> 6;
-    auto red = reinterpret_cast<double(*)[GX_SPLIT][GX_ROWS][S32 + 1]>(red_lds);
-    gx_partial(G, X, x.n, salt, x.row0 + GX_ROWS * (wave & 1), wave >> 1, red[wave & 1][wave >> 1]);
+    constexpr int KB = 8;  // K steps of four per batch
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int kr = lane >> 4, cl = lane & 15;
+    const int n = x.n;
+    const int chunk = (int)ceil_div(ceil_div(n, RW), 4) * 4;
+    const int k0 = min(n, wave * chunk), k1 = min(n, k0 + chunk);
+    const double* g0 = G + (int64_t)min(x.row0 + cl, n - 1) * n;
+    const double* g1 = G + (int64_t)min(x.row0 + 16 + cl, n - 1) * n;
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int kb = k0; kb < k1; kb += 4 * KB) {
+        double a0[KB], a1[KB], b0[KB], b1[KB];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+            const int k = kb + 4 * t + kr;
+            const bool in = k < k1;
+            const int kk = in ? k : k0;
+            const double m = in ? 1.0 : 0.0;
+            a0[t] = m * g0[kk];
+            a1[t] = m * g1[kk];
+            if constexpr (HASH) {
+                const uint64_t key = (uint64_t)kk * S32 + cl;
+                b0[t] = hash_unit(key * 0x2545F4914F6CDD1Dull + salt);
+                b1[t] = hash_unit((key + 16) * 0x2545F4914F6CDD1Dull + salt);
+            } else {
+                b0[t] = X[(int64_t)kk * S32 + cl];
+                b1[t] = X[(int64_t)kk * S32 + 16 + cl];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[t], b0[t], acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[t], b1[t], acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[t], b0[t], acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[t], b1[t], acc[1][1], 0, 0, 0);
+        }
+    }
+    double* mine = red_lds + wave * (S32 * S32);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                mine[(16 * u + mfma16_row<PREC_F64>(lane, e)) * S32 + 16 * v + cl] = acc[u][v][e];
     __syncthreads();
-    for (int e = tid; e < 2 * GX_ROWS * S32; e += RT) {
-        const int rt = e / (GX_ROWS * S32), r = (e / S32) % GX_ROWS, c = e % S32;
+    for (int e = tid; e < S32 * S32; e += RT) {
         double t = 0.0;
 #pragma unroll
-        for (int w = 0; w < GX_SPLIT; ++w) t += red[rt][w][r][c];
-        const int row = x.row0 + GX_ROWS * rt + r;
-        if (row < x.n) Y[(int64_t)row * S32 + c] = t;
+        for (int w = 0; w < RW; ++w) t += red_lds[w * (S32 * S32) + e];
+        const int row = x.row0 + (e >> 5);
+        if (row < n) Y[(int64_t)row * S32 + (e & 31)] = t;
     }
     __syncthreads();
 }
@@ -1753,7 +1801,6 @@ __global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G,
     __shared__ int sign_s[S32];
     __shared__ SignCand wcand[2][S32];
     __shared__ int ok_s, r_s, dense_s;
-    static_assert(2 * GX_SPLIT * GX_ROWS * (S32 + 1) <= RW * S32 * S32, "product partials fit");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     GridCtx x;
     x.g = g;
@@ -1770,14 +1817,14 @@ __global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G,
     // power steps: P1 <- orth(P1), P2 <- G P1, swap
     double* P1 = g.P1;
     double* P2 = g.P2;
-    gx_rows32(x, G, nullptr, 0x5eed, P1, part_lds);
+    gx_rows32<true>(x, G, nullptr, 0x5eed, P1, part_lds);
     bool good = true;
     for (int it = 0; it < steps && good; ++it) {
         double* Yb = P1 + (int64_t)x.row0 * S32;
         good = orth_grid(x, Yb, it + 1 == steps, part_lds, Bm, Wm, rowbuf, &ok_s);
         if (!good) break;
         x.sync();
-        gx_rows32(x, G, P1, 0, P2, part_lds);
+        gx_rows32<false>(x, G, P1, 0, P2, part_lds);
         double* t = P1;
         P1 = P2;
         P2 = t;
@@ -1826,7 +1873,7 @@ __global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G,
         bk->sweeps[a.k] = sw;
         bk->eig_ok = cv ? 1 : 0;
         if (__hip_atomic_load(&g.sync[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) bk->status = ATC_ERR_INTERNAL;
-        choose_rank(al, tr, r_s, dense_s);
+        choose_rank(al, tr, r_s, dense_s, false);  // reported to the host at the end
         __hip_atomic_store(&g.sync[1], (unsigned)r_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&g.sync[2], (unsigned)dense_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1878,14 +1925,24 @@ __global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G,
     x.sync();
     const int r = (int)__hip_atomic_load(&g.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int dense = (int)__hip_atomic_load(&g.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (dense) return;
+    if (dense) {
+        if (x.b == 0 && tid == 0) publish_selection(a, r);
+        return;
+    }
     if (tid < S32) {
+        double cb[GRID_MAXB], cv_[GRID_MAXB], cr[GRID_MAXB];
+#pragma unroll
+        for (int o = 0; o < GRID_MAXB; ++o) {
+            const double* gc = g.cand + ((size_t)(o < x.nb ? o : 0) * S32 + tid) * 3;
+            cb[o] = gc[0];
+            cv_[o] = gc[1];
+            cr[o] = gc[2];
+        }
         double best = -1.0, val = 0.0;
         int bi = 0x7fffffff;
-        for (int o = 0; o < x.nb; ++o) {
-            const double* gc = g.cand + ((size_t)o * S32 + tid) * 3;
-            sign_merge(best, bi, val, gc[0], (int)gc[2], gc[1]);
-        }
+#pragma unroll
+        for (int o = 0; o < GRID_MAXB; ++o)
+            if (o < x.nb) sign_merge(best, bi, val, cb[o], (int)cr[o], cv_[o]);
         sign_s[tid] = val < 0.0 ? -1 : 1;
     }
     __syncthreads();
@@ -1899,6 +1956,7 @@ __global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G,
             }
         }
     }
+    if (x.b == 0 && tid == 0) publish_selection(a, r);
 }
 
 // The cooperative path needs cooperative launches and its LDS; ATC_SUB32_KERNELS=1
