@@ -39,6 +39,7 @@ constexpr int MAX_MODE = 4096;       // longest mode the eigensolvers accept
 constexpr int SUBSPACE_M = 64;       // subspace size of the leading-eigenpair path
 constexpr int SUBSPACE_ITERS = 2;    // power steps before the Rayleigh-Ritz projection
 constexpr int SUBSPACE_GUARD = 8;    // Ritz pairs the chosen rank must leave unused
+constexpr int S32_RANKS = 32;        // Ritz pairs of the m = 32 subspace path
 constexpr int DEFAULT_SWEEPS = 60;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -371,6 +372,9 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         // (ranks of neighbouring modes tend to be alike; m = 64 is never less
         // accurate, only slower when m = 32 would have done)
         int attempt = dense_first ? 2 : (wide_hint && subspace32_available(n) ? 1 : 0);
+        const void* M = f64 ? (const void*)w.Mt64 : (const void*)w.Mt32;
+        void* const dst = (i == d - 1) ? core : (src == w.buf[0] ? w.buf[1] : w.buf[0]);
+        bool queued = false;  // mode product queued with the device-side rank
         for (;; ++attempt) {
             bool selected = false;
             sa.seq = ++g_flags.seq;
@@ -381,6 +385,15 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
                 paths[k] = 2;
                 HIP_TRY(run_subspace32_select(w.G, n, SUBSPACE_ITERS, max_sweeps, w.sub, sa, st));
                 selected = true;
+                // the mode product with the rank the kernel chose, queued before the
+                // host reads it (this path's ranks stay below 32 - guard < n, so
+                // there is no deferred rotation); when the selection hands the
+                // mode on, the rank slot holds 0 and the product writes nothing
+                const TtmPlan tp = ttm_plan(prec, L, n, R, S32_RANKS - SUBSPACE_GUARD);
+                HIP_TRY(mark(i, 3));
+                HIP_TRY(launch_ttm(prec, tp, src, M, w.Mth, w.Mtl, dst, st, &w.book->rank[k]));
+                HIP_TRY(mark(i, 4));
+                queued = true;
             } else if (attempt == 1 && subspace32_available(n)) {
                 sa.ldv = 64;
                 sa.ncand = 64;
@@ -427,6 +440,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
             }
             if (hf.status != 0) return fail((atc_status)hf.status, "input |A|^2 is not finite");
             if (!hf.need_dense) break;
+            queued = false;
             if (attempt >= 2) return fail(ATC_ERR_INTERNAL, "mode %d: dense eigensolver asked for more", k);
             if (attempt == 1 && opts->eig_path == 2)
                 return fail(ATC_ERR_UNSUPPORTED, "mode %d: rank needs more than %d Ritz pairs", k,
@@ -443,6 +457,11 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         const int r = hf.rank;
         if (r < 1 || r > n) return fail(ATC_ERR_INTERNAL, "mode %d: rank %d outside [1, %d]", k, r, n);
         cur[k] = r;
+        if (queued) {
+            if (r >= n) return fail(ATC_ERR_INTERNAL, "mode %d: rank %d of the subspace path", k, r);
+            src = dst;
+            continue;
+        }
         if (r == n && i + 1 < d) {
             // nothing discarded: the projection is a rotation of mode k, which
             // leaves every later Gram matrix unchanged, so it is applied to the
@@ -452,9 +471,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
             HIP_TRY(mark(i, 4));
             continue;
         }
-        void* dst = (i == d - 1) ? core : (src == w.buf[0] ? w.buf[1] : w.buf[0]);
         const TtmPlan tp = ttm_plan(prec, L, n, R, r);
-        const void* M = f64 ? (const void*)w.Mt64 : (const void*)w.Mt32;
         HIP_TRY(mark(i, 3));
         HIP_TRY(launch_ttm(prec, tp, src, M, w.Mth, w.Mtl, dst, st));
         HIP_TRY(mark(i, 4));

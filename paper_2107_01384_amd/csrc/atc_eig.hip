@@ -1585,7 +1585,7 @@ struct Sub32Grid {
     double* P2;       // n x 32
     double* part;     // 2 x GRID_MAXB x 1024: per-workgroup 32 x 32 products, two alternating sets
     double* cand;     // GRID_MAXB x 32 x 3: sign candidates (|v|, v, row)
-    unsigned* sync;   // [0] arrivals, [1] rank, [2] need_dense, [3] a wait gave up; zeroed before the launch
+    unsigned* sync;   // DevBook::grid: [0] arrivals, [1] rank, [2] need_dense, [3] a wait gave up, [4] exits
 };
 
 // Grid barrier: every wavefront drains its stores, thread 0 makes the
@@ -1785,8 +1785,8 @@ __device__ __forceinline__ bool orth_grid(GridCtx& x, double* Y, bool full, doub
     return good && done;
 }
 
-__global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G, int n, int steps, int max_sweeps,
-                                                   Sub32Grid g, SelectArgs a) {
+__device__ __forceinline__ void sub32_grid_body(const double* __restrict__ G, int n, int steps, int max_sweeps,
+                                                const Sub32Grid& g, const SelectArgs& a) {
     extern __shared__ double lds[];
     double* part_lds = lds;
     double(*Bm)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + RW * S32 * S32);
@@ -1869,11 +1869,14 @@ __global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G,
     __syncthreads();
     SelectArgs al = a;
     al.lam = lam_s;
-    if (x.b == 0 && tid == 0) {
+    if (x.b == 0 && tid == RT - 64) {
+        // the rank choice and host report by the last wavefront of workgroup 0,
+        // while wavefronts 0 and 1 form V_b; the host can queue the mode
+        // product while this kernel finishes
         bk->sweeps[a.k] = sw;
         bk->eig_ok = cv ? 1 : 0;
         if (__hip_atomic_load(&g.sync[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) bk->status = ATC_ERR_INTERNAL;
-        choose_rank(al, tr, r_s, dense_s, false);  // reported to the host at the end
+        choose_rank(al, tr, r_s, dense_s);
         __hip_atomic_store(&g.sync[1], (unsigned)r_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&g.sync[2], (unsigned)dense_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1925,10 +1928,7 @@ __global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G,
     x.sync();
     const int r = (int)__hip_atomic_load(&g.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int dense = (int)__hip_atomic_load(&g.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (dense) {
-        if (x.b == 0 && tid == 0) publish_selection(a, r);
-        return;
-    }
+    if (dense) return;
     if (tid < S32) {
         double cb[GRID_MAXB], cv_[GRID_MAXB], cr[GRID_MAXB];
 #pragma unroll
@@ -1956,7 +1956,22 @@ __global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G,
             }
         }
     }
-    if (x.b == 0 && tid == 0) publish_selection(a, r);
+}
+
+// The body above, then the last workgroup to finish clears the barrier words
+// for the next launch (every workgroup has passed its last wait by then).
+__global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G, int n, int steps, int max_sweeps,
+                                                   Sub32Grid g, SelectArgs a) {
+    sub32_grid_body(G, n, steps, max_sweeps, g, a);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned done = __hip_atomic_fetch_add(&g.sync[4], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done + 1 == gridDim.x) {
+            __hip_atomic_store(&g.sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&g.sync[3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&g.sync[4], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // The cooperative path needs cooperative launches and its LDS; ATC_SUB32_KERNELS=1
@@ -2108,9 +2123,9 @@ bool sub64_ready() {
 bool subspace32_available(int n) { return n >= 2 * S32 && n <= 512 && sub32_ready(); }
 
 // P1, P2 (n x 32 each), 8 doubles of flags, then the cooperative path's
-// partial products, sign candidates and barrier words.
+// partial products and sign candidates.
 size_t subspace32_ws_doubles(int n) {
-    return (size_t)2 * n * S32 + 8 + (size_t)2 * GRID_MAXB * S32 * S32 + (size_t)GRID_MAXB * S32 * 3 + 8;
+    return (size_t)2 * n * S32 + 8 + (size_t)2 * GRID_MAXB * S32 * S32 + (size_t)GRID_MAXB * S32 * 3;
 }
 
 hipError_t run_subspace32_select(const double* G, int n, int iters, int max_sweeps, double* ws, const SelectArgs& sa,
@@ -2128,8 +2143,7 @@ hipError_t run_subspace32_select(const double* G, int n, int iters, int max_swee
         g.P2 = P2;
         g.part = P2 + (size_t)n * S32 + 8;
         g.cand = g.part + (size_t)2 * GRID_MAXB * S32 * S32;
-        g.sync = reinterpret_cast<unsigned*>(g.cand + (size_t)GRID_MAXB * S32 * 3);
-        if ((e = launch_zero(g.sync, 8 * sizeof(unsigned), st)) != hipSuccess) return e;
+        g.sync = &sa.book->grid[0];
         const int nb = (int)ceil_div(n, GRID_ROWS);
         int n_ = n, steps_ = steps, sweeps_ = max_sweeps;
         SelectArgs sa_ = sa;

@@ -41,6 +41,10 @@ struct DevBook {
     int32_t need_dense;  // subspace basis too small for the chosen rank
     int32_t eig_ok;      // last eigensolve converged
     int32_t pad;
+    // words of the cooperative subspace kernel: barrier arrivals, rank,
+    // need_dense, a wait that gave up, workgroups done; zero between launches
+    // (the book is cleared per call and the kernel's last workgroup resets them)
+    uint32_t grid[8];
 };
 
 // ------------------------------------------------------------ small helpers
@@ -155,8 +159,10 @@ struct TtmPlan {
     int64_t tiles_per_l;
 };
 TtmPlan ttm_plan(int prec, int64_t L, int n, int64_t R, int m_out);
+// m_dev (optional): the output rows are min(t.m_out, *m_dev), read on the
+// device (a rank chosen by a kernel earlier on the stream); none when < 1.
 hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, const void* Mh,
-                      const void* Ml, void* Z, hipStream_t st);
+                      const void* Ml, void* Z, hipStream_t st, const int32_t* m_dev = nullptr);
 
 // Symmetric eigensolvers (FP64).  Outputs lam (descending; not clamped, so a
 // tail sum over rounding-level eigenvalues of an FP32-accurate Gram matrix

@@ -69,9 +69,12 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm(const typename ElemOf<P>::T* _
                                                   int64_t R, int m_out, int64_t tpl, int planes,
                                                   const double* __restrict__ M64, const float* __restrict__ M32,
                                                   const __bf16* __restrict__ Mh, const __bf16* __restrict__ Ml,
-                                                  typename ElemOf<P>::T* __restrict__ Z) {
+                                                  typename ElemOf<P>::T* __restrict__ Z,
+                                                  const int32_t* __restrict__ m_dev) {
     using T = typename ElemOf<P>::T;
     constexpr int BK = KDepth<P>::value;
+    if (m_dev) m_out = min(m_out, *m_dev);  // the rank chosen on the device
+    if (m_out < 1) return;
     constexpr int E = TILE * BK / NTHREADS;
     __shared__ TtmSmem<P> sm;
 
@@ -212,8 +215,10 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm(const typename ElemOf<P>::T* _
 template <int P, int MT>
 __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__ Y, int n, int64_t R, int m_out,
                                                        int64_t tpl, const float* __restrict__ M32,
-                                                       float* __restrict__ Z) {
+                                                       float* __restrict__ Z, const int32_t* __restrict__ m_dev) {
     constexpr int W = 256, BK = 32, MR = 16 * MT;
+    if (m_dev) m_out = min(m_out, *m_dev);  // the rank chosen on the device
+    if (m_out < 1) return;
     constexpr int YP = (P == PREC_BF16X3) ? BK + 8 : BK + 4;  // padded row of a staged column
     struct SmB {
         __bf16 yh[W][BK + 8], yl[W][BK + 8], mh[MR][BK + 8], ml[MR][BK + 8];
@@ -359,22 +364,22 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
 
 template <int P, int LAYOUT>
 hipError_t launch_ttm_t(const TtmPlan& t, const void* Y, const void* M, const void* Mh, const void* Ml, void* Z,
-                        hipStream_t st) {
+                        const int32_t* m_dev, hipStream_t st) {
     using T = typename ElemOf<P>::T;
     dim3 grid((unsigned)t.ctiles, t.jtiles);
     hipLaunchKernelGGL((k_ttm<P, LAYOUT>), grid, dim3(NTHREADS), 0, st, (const T*)Y, t.L, t.n, t.R, t.m_out,
                        t.tiles_per_l, t.planes, (const double*)M, (const float*)M, (const __bf16*)Mh,
-                       (const __bf16*)Ml, (T*)Z);
+                       (const __bf16*)Ml, (T*)Z, m_dev);
     return hipGetLastError();
 }
 
 template <int P>
 hipError_t launch_ttm_p(const TtmPlan& t, const void* Y, const void* M, const void* Mh, const void* Ml, void* Z,
-                        hipStream_t st) {
+                        const int32_t* m_dev, hipStream_t st) {
     switch (t.layout) {
-        case LAYOUT_KC: return launch_ttm_t<P, LAYOUT_KC>(t, Y, M, Mh, Ml, Z, st);
-        case LAYOUT_NC: return launch_ttm_t<P, LAYOUT_NC>(t, Y, M, Mh, Ml, Z, st);
-        default: return launch_ttm_t<P, LAYOUT_SR>(t, Y, M, Mh, Ml, Z, st);
+        case LAYOUT_KC: return launch_ttm_t<P, LAYOUT_KC>(t, Y, M, Mh, Ml, Z, m_dev, st);
+        case LAYOUT_NC: return launch_ttm_t<P, LAYOUT_NC>(t, Y, M, Mh, Ml, Z, m_dev, st);
+        default: return launch_ttm_t<P, LAYOUT_SR>(t, Y, M, Mh, Ml, Z, m_dev, st);
     }
 }
 
@@ -406,7 +411,7 @@ TtmPlan ttm_plan(int prec, int64_t L, int n, int64_t R, int m_out) {
 }
 
 hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, const void* Mh, const void* Ml,
-                      void* Z, hipStream_t st) {
+                      void* Z, hipStream_t st, const int32_t* m_dev) {
     if (prec != PREC_F64 && t.layout == LAYOUT_KC && t.R >= 256 && t.R % 4 == 0 && t.m_out <= 64) {
         const int64_t tpl = ceil_div(t.R, (int64_t)256);
         const dim3 grid((unsigned)(t.L * tpl));
@@ -414,18 +419,18 @@ hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, 
         const float* m = (const float*)M;
         float* z = (float*)Z;
         if (prec == PREC_BF16X3) {
-            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 2>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z);
-            else hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 4>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z);
+            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 2>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z, m_dev);
+            else hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 4>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z, m_dev);
         } else {
-            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 2>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z);
-            else hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 4>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z);
+            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 2>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z, m_dev);
+            else hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 4>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z, m_dev);
         }
         return hipGetLastError();
     }
     switch (prec) {
-        case PREC_F64: return launch_ttm_p<PREC_F64>(t, Y, M, Mh, Ml, Z, st);
-        case PREC_F32: return launch_ttm_p<PREC_F32>(t, Y, M, Mh, Ml, Z, st);
-        default: return launch_ttm_p<PREC_BF16X3>(t, Y, M, Mh, Ml, Z, st);
+        case PREC_F64: return launch_ttm_p<PREC_F64>(t, Y, M, Mh, Ml, Z, m_dev, st);
+        case PREC_F32: return launch_ttm_p<PREC_F32>(t, Y, M, Mh, Ml, Z, m_dev, st);
+        default: return launch_ttm_p<PREC_BF16X3>(t, Y, M, Mh, Ml, Z, m_dev, st);
     }
 }
 
