@@ -891,11 +891,6 @@ __device__ inline double lane_bcast(double v, int src) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// 1 / sqrt(z) to working precision: hardware-assisted estimate plus one Newton step.
-__device__ inline double rsqrt_nr(double z) {
-    double r = rsqrt(z);
-    return r * (1.5 - 0.5 * z * r * r);
-}
 
 // Row r of an n x 32 matrix held as NP partial arrays spaced n x 32 apart
 // (their sum), element c.
@@ -975,35 +970,39 @@ __device__ __forceinline__ void cross32(const double* __restrict__ P, const doub
 // identity (right-looking Cholesky, R^T R = C) are applied to the identity as
 // well, which leaves R^{-T} = L^{-1} (column-oriented forward substitution).
 // Lanes 0-31 keep column b = lane of the trailing matrix in registers, lanes
-// 32-63 column b = lane - 32 of the identity being transformed.  At step J
-// every lane publishes its v[J] in rowbuf (64 doubles, LDS; the upper half is
-// never read), all lanes read row J of the trailing matrix back as uniform
-// loads, d = C'[J][J] gives r = d^{-1/2}, and each lane subtracts
-// rowbuf[a] v[J] / d from v[a], a > J.  v[J] r of an identity lane is final
+// 32-63 column b = lane - 32 of the identity being transformed.  Every lane
+// publishes its v[J] in rowbuf (64 doubles, LDS; the upper half is never read)
+// and all lanes read row J of the trailing matrix back as uniform loads; at
+// step J, d = C'[J][J] gives r = d^{-1/2} and each lane subtracts
+// rowbuf[a] v[J] / d from v[a], a > J, v[J + 1] first so that row J + 1 is
+// published while the rest are updated.  v[J] r of an identity lane is final
 // (entry J of row b of R^{-1}, exact zero below the diagonal) and goes to
 // Rinv at once; the other lanes store into the padding column of Rinv.  No
 // branches: the steps are unrolled through templates so every register index
 // is static.  Returns false (on every lane) when a pivot is not positive and
 // finite.
 template <int J>
-__device__ __forceinline__ void cinv_step(double (&v)[S32], double* rowbuf, double (*Rinv)[S32 + 1], bool idl, int b,
-                                          bool& ok) {
-    if constexpr (J < S32) {
-        const int lane = threadIdx.x & 63;
-        rowbuf[lane] = v[J];
+__device__ __forceinline__ void cinv_step(double (&v)[S32], const double (&rb)[S32 - J], double* rowbuf,
+                                          double (*Rinv)[S32 + 1], bool idl, int b, bool& ok) {
+    const int lane = threadIdx.x & 63;
+    const double d = rb[0];
+    ok = ok && (d >= 0x1p-1022) && (d < INFINITY);  // a positive normal pivot
+    double r = rsqrt_pos(d);
+    r = ok ? r : 0.0;
+    const double s = v[J] * (r * r);
+    *(idl ? &Rinv[b][J] : &Rinv[b][S32]) = v[J] * r;
+    if constexpr (J + 1 < S32) {
+        // v[J + 1] first: the next row goes out through LDS while the other
+        // entries of this step are updated
+        v[J + 1] -= rb[1] * s;
+        rowbuf[lane] = v[J + 1];
         wave_sync();
-        double rb[S32 - J];
+        double nb[S32 - J - 1];
 #pragma unroll
-        for (int a = J; a < S32; ++a) rb[a - J] = rowbuf[a];
-        const double d = rb[0];
-        ok = ok && (d > 0.0) && (d < INFINITY);
-        double r = rsqrt_nr(d);
-        r = ok ? r : 0.0;
-        const double s = v[J] * (r * r);
-        *(idl ? &Rinv[b][J] : &Rinv[b][S32]) = v[J] * r;
+        for (int a = J + 1; a < S32; ++a) nb[a - J - 1] = rowbuf[a];
 #pragma unroll
-        for (int a = J + 1; a < S32; ++a) v[a] -= rb[a - J] * s;
-        cinv_step<J + 1>(v, rowbuf, Rinv, idl, b, ok);
+        for (int a = J + 2; a < S32; ++a) v[a] -= rb[a - J] * s;
+        cinv_step<J + 1>(v, nb, rowbuf, Rinv, idl, b, ok);
     }
 }
 
@@ -1020,7 +1019,12 @@ __device__ __attribute__((noinline)) bool chol_inv32_wave(const double (*C)[S32 
         v[a] = idl ? (a == b ? 1.0 : 0.0) : c;
     }
     bool ok = true;
-    cinv_step<0>(v, rowbuf, Rinv, idl, b, ok);
+    rowbuf[lane] = v[0];
+    wave_sync();
+    double rb[S32];
+#pragma unroll
+    for (int a = 0; a < S32; ++a) rb[a] = rowbuf[a];
+    cinv_step<0>(v, rb, rowbuf, Rinv, idl, b, ok);
     return ok;
 }
 
@@ -1190,9 +1194,11 @@ __device__ inline bool rot2(double app, double aqq, double apq, double tol2, dou
     dq = aqq;
     if (!rot2_needed(app, aqq, apq, tol2, floor2)) return false;
     const double d = aqq - app, g = 2.0 * apq;
-    const double rh = rsqrt_nr(d * d + g * g);   // 1 / h
+    const double hh = d * d + g * g;
+    if (!(hh >= 0x1p-1022) || !(hh < INFINITY)) return false;  // squares out of range: leave the pair
+    const double rh = rsqrt_pos(hh);  // 1 / h
     const double u = 0.5 + 0.5 * fabs(d) * rh;   // cos^2 of the angle
-    const double rc = rsqrt_nr(u);               // 1 / c
+    const double rc = rsqrt_pos(u);              // 1 / c
     c = u * rc;
     s = (d >= 0.0 ? 0.5 : -0.5) * g * rh * rc;
     const double t = s * rc;
@@ -1655,7 +1661,7 @@ __device__ __forceinline__ void cross_grid(GridCtx& x, const double* P, const do
 template <bool HASH>
 __device__ __forceinline__ void gx_rows32(const GridCtx& x, const double* __restrict__ G, const double* X,
                                           uint64_t salt, double* Y, double* red_lds) {
-    constexpr int KB = 8;  // K steps of four per batch
+    constexpr int KB = 16;  // K steps of four per batch
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int kr = lane >> 4, cl = lane & 15;
     const int n = x.n;

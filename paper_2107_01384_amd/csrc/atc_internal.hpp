@@ -62,11 +62,15 @@ template <> struct KDepth<PREC_F64> { static constexpr int value = 16; };
 // sqrt(|a_pp a_qq|), by the smaller angle, with two
 // reciprocal square roots instead of two divisions and two square roots:
 // d = a_qq - a_pp, g = 2 a_pq, h = hypot(d, g), u = (1 + |d| / h) / 2,
-// c = sqrt(u), s = sign(d) g / (2 h c), t = s / c.  Each reciprocal square
-// root gets one Newton step to working precision.
-__device__ inline double rsqrt_nr1(double z) {
-    const double r = rsqrt(z);
-    return r * (1.5 - 0.5 * z * r * r);
+// c = sqrt(u), s = sign(d) g / (2 h c), t = s / c.
+
+// 1 / sqrt(z) for positive, normal, finite z: the hardware estimate y0
+// (v_rsq_f64) and one correction from the series (1 - e)^(-1/2) = 1 + e/2 +
+// 3e^2/8 + ..., e = 1 - z y0^2, whose truncation error is O(e^3).
+__device__ inline double rsqrt_pos(double z) {
+    const double y0 = __builtin_amdgcn_rsq(z);
+    const double e = fma(-z * y0, y0, 1.0);
+    return fma(y0 * e, fma(e, 0.375, 0.5), y0);
 }
 __device__ inline bool schur2_rs(double app, double aqq, double apq, double tol, double& c, double& s, double& dp,
                                  double& dq) {
@@ -77,10 +81,10 @@ __device__ inline bool schur2_rs(double app, double aqq, double apq, double tol,
     if (!(apq * apq > tol * tol * fabs(app * aqq))) return false;
     const double d = aqq - app, g = 2.0 * apq;
     const double hh = d * d + g * g;
-    if (!(hh > 0.0) || !(hh < INFINITY)) return false;  // squares out of range: leave the pair
-    const double rh = rsqrt_nr1(hh);
+    if (!(hh >= 0x1p-1022) || !(hh < INFINITY)) return false;  // squares out of range: leave the pair
+    const double rh = rsqrt_pos(hh);
     const double u = 0.5 + 0.5 * fabs(d) * rh;
-    const double rc = rsqrt_nr1(u);
+    const double rc = rsqrt_pos(u);
     c = u * rc;
     s = (d >= 0.0 ? 0.5 : -0.5) * g * rh * rc;
     const double t = s * rc;
