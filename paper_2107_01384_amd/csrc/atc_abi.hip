@@ -438,7 +438,10 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
                 hf.norm2 = f->norm2;
                 hf.used = f->used;
             }
-            if (hf.status != 0) return fail((atc_status)hf.status, "input |A|^2 is not finite");
+            if (hf.status != 0)
+                return fail((atc_status)hf.status, hf.status == ATC_ERR_NONFINITE_INPUT
+                                                       ? "input |A|^2 is not finite"
+                                                       : "mode eigensolver: a grid barrier wait gave up");
             if (!hf.need_dense) break;
             queued = false;
             if (attempt >= 2) return fail(ATC_ERR_INTERNAL, "mode %d: dense eigensolver asked for more", k);

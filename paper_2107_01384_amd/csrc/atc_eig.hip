@@ -1544,6 +1544,9 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
     }
     __syncthreads();
     double* lam = const_cast<double*>(a.lam);
+    // every slot of col_of a valid column even when NaN Ritz values tie
+    if (tid < S32) col_of[tid] = tid;
+    __syncthreads();
     if (tid < S32) {
         const double li = Bm[tid][tid];
         int r = 0;
@@ -1583,7 +1586,7 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
 
 constexpr int GRID_ROWS = 32;                 // rows per workgroup
 constexpr int GRID_MAXB = 512 / GRID_ROWS;    // workgroups for n <= 512
-constexpr unsigned GRID_SPIN_LIMIT = 1u << 20;  // polls before a wait gives up
+constexpr unsigned GRID_SPIN_LIMIT = 1u << 20;  // polls before a wait gives up (default)
 
 // Global scratch of the cooperative path (inside the subspace workspace).
 struct Sub32Grid {
@@ -1592,6 +1595,7 @@ struct Sub32Grid {
     double* part;     // 2 x GRID_MAXB x 1024: per-workgroup 32 x 32 products, two alternating sets
     double* cand;     // GRID_MAXB x 32 x 3: sign candidates (|v|, v, row)
     unsigned* sync;   // DevBook::grid: [0] arrivals, [1] rank, [2] need_dense, [3] a wait gave up, [4] exits
+    unsigned spin_limit;  // polls before a wait gives up
 };
 
 // Grid barrier: every wavefront drains its stores, thread 0 makes the
@@ -1599,16 +1603,17 @@ struct Sub32Grid {
 // polls until `target` arrivals, then makes the other workgroups' stores
 // visible (acquire).  The wait is bounded: a workgroup that gives up records
 // it and goes on, so every wavefront still reaches the end of the kernel.
-__device__ __forceinline__ void grid_sync(unsigned* sync, unsigned target) {
+__device__ __forceinline__ void grid_sync(unsigned* sync, unsigned target, unsigned spin_limit) {
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
-        while (__hip_atomic_load(&sync[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        // a limit of 0 gives up without looking (forces the failure path)
+        while (spin_limit == 0 || __hip_atomic_load(&sync[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
-            if (++spins > GRID_SPIN_LIMIT) {
+            if (++spins > spin_limit) {
                 __hip_atomic_store(&sync[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
@@ -1626,7 +1631,7 @@ struct GridCtx {
     int parity;         // partial set of the next exchange
     __device__ void sync() {
         arrivals += (unsigned)nb;
-        grid_sync(g.sync, arrivals);
+        grid_sync(g.sync, arrivals, g.spin_limit);
     }
 };
 
@@ -1839,6 +1844,8 @@ __device__ __forceinline__ void sub32_grid_body(const double* __restrict__ G, in
         // the same outcome in every workgroup: hand the mode to the next eigensolver
         if (x.b == 0 && tid == 0) {
             bk->need_dense = 1;
+            if (__hip_atomic_load(&g.sync[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                bk->status = ATC_ERR_INTERNAL;  // not a failed basis: a wait gave up
             publish_selection(a, 0);
         }
         return;
@@ -1861,6 +1868,9 @@ __device__ __forceinline__ void sub32_grid_body(const double* __restrict__ G, in
     bool cv;
     static_assert(RW * S32 * S32 * sizeof(double) >= (S32 - 1) * 128 * sizeof(uint4), "block table");
     jacobi32(Bm, Wm, max_sweeps, jlog, jptab, reinterpret_cast<uint4*>(part_lds), &jflag, sw, cv);
+    // every slot of col_of a valid column even when NaN Ritz values tie
+    if (tid < S32) col_of[tid] = tid;
+    __syncthreads();
     if (tid < S32) {
         const double li = Bm[tid][tid];
         int r = 0;
@@ -2150,6 +2160,10 @@ hipError_t run_subspace32_select(const double* G, int n, int iters, int max_swee
         g.part = P2 + (size_t)n * S32 + 8;
         g.cand = g.part + (size_t)2 * GRID_MAXB * S32 * S32;
         g.sync = &sa.book->grid[0];
+        // ATC_GRID_SPIN_LIMIT (tests): a small limit makes the waits give up,
+        // which the mode must report as an error without hanging
+        const char* lim = getenv("ATC_GRID_SPIN_LIMIT");
+        g.spin_limit = lim ? (unsigned)strtoul(lim, nullptr, 10) : GRID_SPIN_LIMIT;
         const int nb = (int)ceil_div(n, GRID_ROWS);
         int n_ = n, steps_ = steps, sweeps_ = max_sweeps;
         SelectArgs sa_ = sa;

@@ -237,3 +237,23 @@ def test_subspace_one_launch_and_kernel_chain_agree(shape, monkeypatch):
     assert np.sqrt(oracle.norm2(xc - xk) / oracle.norm2(x)) < 1e-6
     ok, how = rank_parity(t_c, oracle.sthosvd(x, 1e-3), 0.1)
     assert ok, how
+
+
+def test_grid_barrier_wait_gives_up_without_hanging(monkeypatch):
+    """The one-launch eigensolver's barrier waits are bounded: a limit of zero
+    polls (forced from the host) makes every wait give up at once, every
+    workgroup still runs to its end, the call reports an internal error instead
+    of hanging, and the next call (normal limit) gives the same bits as before."""
+    x = synth.field((160, 96, 80), 7)
+    ref = _run(x, 1e-3, torch.float32, eig_path=2)
+    monkeypatch.setenv("ATC_GRID_SPIN_LIMIT", "0")
+    with pytest.raises(atc.AtcError) as e:
+        _run(x, 1e-3, torch.float32, eig_path=2)
+    assert e.value.status == -7, e.value.status
+    monkeypatch.delenv("ATC_GRID_SPIN_LIMIT")
+    torch.cuda.synchronize()
+    again = _run(x, 1e-3, torch.float32, eig_path=2)
+    assert again.ranks == ref.ranks
+    assert torch.equal(again.core, ref.core)
+    for fa, fb in zip(again.factors, ref.factors):
+        assert torch.equal(fa, fb)
