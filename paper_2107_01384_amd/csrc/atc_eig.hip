@@ -99,7 +99,7 @@ __device__ inline double block_sum(double s, double* red) {
 template <int MAXM>
 __global__ __launch_bounds__((MAXM / 2) * (MAXM / 2)) void k_eig_jacobi_lds(
     const double* __restrict__ G, int n, int ldg, int max_sweeps, double* __restrict__ lam, double* __restrict__ V,
-    int ldv, int32_t* __restrict__ sweeps_out, int32_t* __restrict__ ok_out) {
+    int ldv, int32_t* __restrict__ sweeps_out, int32_t* __restrict__ ok_out, double floor_rel) {
     constexpr int H = MAXM / 2;
     __shared__ double A[MAXM][MAXM + 1];
     __shared__ double Vs[MAXM][MAXM + 1];
@@ -118,6 +118,10 @@ __global__ __launch_bounds__((MAXM / 2) * (MAXM / 2)) void k_eig_jacobi_lds(
     }
     __syncthreads();
     const double tol = (double)n * 0x1p-53;
+    // with floor_rel > 0 an entry at or below floor_rel |trace| is left alone
+    double trace = 0.0;
+    for (int i = 0; i < n; ++i) trace += A[i][i];
+    const double floor = floor_rel * fabs(trace);
     int sweeps = 0;
     bool converged = (m < 2);
     while (!converged && sweeps < max_sweeps) {
@@ -127,8 +131,8 @@ __global__ __launch_bounds__((MAXM / 2) * (MAXM / 2)) void k_eig_jacobi_lds(
             if (tid < h) {
                 int p, q;
                 round_robin_pair(round, tid, m, p, q);
-                double c, s, dp, dq;
-                if (schur2_rs(A[p][p], A[q][q], A[p][q], tol, c, s, dp, dq)) rotated = 1;
+                double c = 1.0, s = 0.0, dp = A[p][p], dq = A[q][q];
+                if (fabs(A[p][q]) > floor && schur2_rs(A[p][p], A[q][q], A[p][q], tol, c, s, dp, dq)) rotated = 1;
                 pp[tid] = p;
                 qq[tid] = q;
                 cs[tid] = c;
@@ -511,14 +515,14 @@ hipError_t orthonormalise(double* X, int n, int m, uint64_t salt, hipStream_t st
 }  // namespace
 
 hipError_t launch_eig_jacobi_lds(const double* G, int n, int ldg, int max_sweeps, double* lam, double* V, int ldv,
-                                 int32_t* sweeps_out, int32_t* ok_out, hipStream_t st) {
+                                 int32_t* sweeps_out, int32_t* ok_out, hipStream_t st, double floor_rel) {
     if (n < 1 || n > 64) return hipErrorInvalidValue;
     if (n <= 32)
         hipLaunchKernelGGL((k_eig_jacobi_lds<32>), dim3(1), dim3(256), 0, st, G, n, ldg, max_sweeps, lam, V, ldv,
-                           sweeps_out, ok_out);
+                           sweeps_out, ok_out, floor_rel);
     else
         hipLaunchKernelGGL((k_eig_jacobi_lds<64>), dim3(1), dim3(1024), 0, st, G, n, ldg, max_sweeps, lam, V, ldv,
-                           sweeps_out, ok_out);
+                           sweeps_out, ok_out, floor_rel);
     return hipGetLastError();
 }
 
@@ -2234,7 +2238,8 @@ hipError_t run_subspace64_select(const double* G, int n, int max_sweeps, double*
     hipLaunchKernelGGL(k_rr64_prep, dim3(1), dim3(RT), RR_LDS, st, (const double*)Pa, (const double*)Pb,
                        (const double*)Za, (const double*)Zb, n, (const int32_t*)ok, sa.book, B);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_eig_jacobi_lds(B, 64, 64, max_sweeps, lam, W, 64, sweeps_dev, ok_dev, st)) != hipSuccess)
+    // the Ritz problem of FP32-grade data: entries under u trace(B) left alone, as in jacobi32
+    if ((e = launch_eig_jacobi_lds(B, 64, 64, max_sweeps, lam, W, 64, sweeps_dev, ok_dev, st, 0x1p-53)) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_combine64, dim3((unsigned)ceil_div((int64_t)n * 64, 256)), dim3(256), 0, st,
                        (const double*)Pa, (const double*)Pb, (const double*)W, V, n);

@@ -175,7 +175,7 @@ hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, 
 // Dense one-workgroup Jacobi with the matrix in LDS, n <= 64.
 hipError_t launch_eig_jacobi_lds(const double* G, int n, int ldg, int max_sweeps, double* lam,
                                  double* V, int ldv, int32_t* sweeps_out, int32_t* ok_out,
-                                 hipStream_t st);
+                                 hipStream_t st, double floor_rel = 0.0);
 // Dense one-workgroup Jacobi in global memory, any n (slow; fallback).
 hipError_t launch_eig_jacobi_global(const double* G, int n, int max_sweeps, double* A_ws, double* lam,
                                     double* V, int32_t* sweeps_out, int32_t* ok_out, hipStream_t st);
