@@ -219,9 +219,12 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
     constexpr int W = 256, BK = 32, MR = 16 * MT;
     if (m_dev) m_out = min(m_out, *m_dev);  // the rank chosen on the device
     if (m_out < 1) return;
-    constexpr int YP = (P == PREC_BF16X3) ? BK + 8 : BK + 4;  // padded row of a staged column
+    constexpr int YP = (P == PREC_BF16X3) ? BK : BK + 4;  // row of a staged column
+    // bf16 columns staged without padding (37 KB of LDS: four workgroups per
+    // CU): the 16-byte chunk c of row r sits at c ^ ((r >> 1) ^ (r >> 3)) & 3,
+    // so the 16 consecutive rows an MFMA operand load reads hit distinct banks
     struct SmB {
-        __bf16 yh[W][BK + 8], yl[W][BK + 8], mh[MR][BK + 8], ml[MR][BK + 8];
+        __bf16 yh[W][BK], yl[W][BK], mh[MR][BK + 8], ml[MR][BK + 8];
     };
     struct SmF {
         float yf[W][BK + 4], mf[MR][BK + 4];
@@ -271,8 +274,10 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
                     hv[e] = h;
                     lv[e] = (__bf16)(f[e] - (float)h);
                 }
-                *reinterpret_cast<bf16x8*>(&sm.yh[4 * cg + q][8 * rg]) = hv;
-                *reinterpret_cast<bf16x8*>(&sm.yl[4 * cg + q][8 * rg]) = lv;
+                const int row = 4 * cg + q;
+                const int ch = rg ^ (((row >> 1) ^ (row >> 3)) & 3);
+                *reinterpret_cast<bf16x8*>(&sm.yh[row][8 * ch]) = hv;
+                *reinterpret_cast<bf16x8*>(&sm.yl[row][8 * ch]) = lv;
             } else {
                 *reinterpret_cast<float4*>(&sm.yf[4 * cg + q][8 * rg]) = float4{f[0], f[1], f[2], f[3]};
                 *reinterpret_cast<float4*>(&sm.yf[4 * cg + q][8 * rg + 4]) = float4{f[4], f[5], f[6], f[7]};
@@ -316,8 +321,10 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
             bf16x8 bh[4], bl[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                bh[b] = *reinterpret_cast<const bf16x8*>(&sm.yh[wc + 16 * b + (lane & 15)][kq]);
-                bl[b] = *reinterpret_cast<const bf16x8*>(&sm.yl[wc + 16 * b + (lane & 15)][kq]);
+                const int row = wc + 16 * b + (lane & 15);
+                const int yq = 8 * ((lane >> 4) ^ (((row >> 1) ^ (row >> 3)) & 3));
+                bh[b] = *reinterpret_cast<const bf16x8*>(&sm.yh[row][yq]);
+                bl[b] = *reinterpret_cast<const bf16x8*>(&sm.yl[row][yq]);
             }
 #pragma unroll
             for (int a = 0; a < MT; ++a) {
