@@ -462,24 +462,51 @@ __global__ __launch_bounds__(256, 2) void k_gram_kc3(const float* __restrict__ X
     }
 }
 
-__global__ void k_gram_kc_reduce(const float* __restrict__ part, const double* __restrict__ dpart, int nsplit,
-                                 int npairs, int tiles, int n, double* __restrict__ G) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)n * n) return;
-    const int a = (int)(idx / n), b = (int)(idx % n);
-    if (a > b) return;
+// G (n x n, FP64, both triangles) from the split partials: one workgroup of
+// 256 threads per 16 x 16 block of the upper triangle of blocks.  A thread
+// loads its entry's partials of 32 splits at once and adds them in split
+// order (diagonal: the exact FP64 sums of squares); the block is stored, and
+// through LDS its transpose, both with 16-entry rows.
+constexpr int RDB = 16;   // reduction block edge
+constexpr int RDS = 32;   // splits loaded together
+__global__ __launch_bounds__(256) void k_gram_kc_reduce(const float* __restrict__ part,
+                                                        const double* __restrict__ dpart, int nsplit, int npairs,
+                                                        int tiles, int n, double* __restrict__ G) {
+    __shared__ double tb[RDB][RDB + 1];
+    const int nbk = (n + RDB - 1) / RDB;
+    int t = blockIdx.x, bi = 0;
+    while (t >= nbk - bi) {  // block (bi, bj), bi <= bj, in row-major order of the upper triangle
+        t -= nbk - bi;
+        ++bi;
+    }
+    const int bj = bi + t;
+    const int ty = threadIdx.x / RDB, tx = threadIdx.x % RDB;
+    const int a = bi * RDB + ty, b = bj * RDB + tx;
+    const bool mine = a < n && b < n && a <= b;
     double s = 0.0;
-    if (a == b) {
-        for (int sp = 0; sp < nsplit; ++sp) s += dpart[(int64_t)sp * n + a];
-    } else {
+    if (mine) {
+        const bool diag = a == b;
         const int ti = a / KC_BM, tj = b / KC_BM;
         const int pair = kc_pair_index(ti, tj, tiles);
-        const int i = a % KC_BM, j = b % KC_BM;
-        for (int sp = 0; sp < nsplit; ++sp)
-            s += (double)part[((int64_t)sp * npairs + pair) * (KC_BM * KC_BM) + i * KC_BM + j];
+        const int64_t off = (int64_t)(a % KC_BM) * KC_BM + b % KC_BM;
+        for (int sp0 = 0; sp0 < nsplit; sp0 += RDS) {
+            double v[RDS];
+#pragma unroll
+            for (int u = 0; u < RDS; ++u) {
+                const int sp = min(sp0 + u, nsplit - 1);
+                v[u] = diag ? dpart[(int64_t)sp * n + a]
+                            : (double)part[((int64_t)sp * npairs + pair) * (KC_BM * KC_BM) + off];
+            }
+#pragma unroll
+            for (int u = 0; u < RDS; ++u)
+                if (sp0 + u < nsplit) s += v[u];
+        }
+        G[(int64_t)a * n + b] = s;
     }
-    G[(int64_t)a * n + b] = s;
-    G[(int64_t)b * n + a] = s;
+    tb[ty][tx] = s;
+    __syncthreads();
+    const int ra = bj * RDB + ty, cb = bi * RDB + tx;  // mirror of entry (cb, ra)
+    if (ra < n && cb < n && ra > cb) G[(int64_t)ra * n + cb] = tb[tx][ty];
 }
 
 }  // namespace
@@ -530,9 +557,9 @@ hipError_t launch_gram_kc(int prec, const GramKcPlan& g, const float* X, float* 
 
 hipError_t launch_gram_kc_reduce(const GramKcPlan& g, const float* part, const double* dpart, double* G,
                                  hipStream_t st) {
-    const int64_t total = (int64_t)g.n * g.n;
-    hipLaunchKernelGGL(k_gram_kc_reduce, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, part, dpart, g.nsplit,
-                       g.npairs, g.tiles, g.n, G);
+    const int64_t nbk = ceil_div(g.n, RDB);
+    hipLaunchKernelGGL(k_gram_kc_reduce, dim3((unsigned)(nbk * (nbk + 1) / 2)), dim3(256), 0, st, part, dpart,
+                       g.nsplit, g.npairs, g.tiles, g.n, G);
     return hipGetLastError();
 }
 
