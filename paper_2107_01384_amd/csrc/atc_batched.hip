@@ -255,6 +255,12 @@ __device__ bool blk_jacobi(int n, int max_sweeps, BatchSmem<BK>& sm) {
     }
     __syncthreads();
     const double tol = (double)n * 0x1p-53;
+    // entries at or below u |trace| are left alone: the Gram matrix of FP32
+    // data carries errors of that size already, and rotating them away costs
+    // sweeps without changing the result at that accuracy
+    double trace = 0.0;
+    for (int i = 0; i < n; ++i) trace += A[i][i];
+    const double floor = 0x1p-53 * fabs(trace);
     // this thread's share of the round's work, fixed for the whole solve: up
     // to 3 of the h (h + 1) / 2 blocks (k, l), k <= l, and up to 8 of the m h
     // (row, pair) entries of the eigenvector update (codes k | l << 8 and
@@ -284,6 +290,20 @@ __device__ bool blk_jacobi(int n, int max_sweeps, BatchSmem<BK>& sm) {
     int sweeps = 0;
     bool converged = m < 2;
     while (!converged && sweeps < max_sweeps) {
+        // a sweep is run only when some pair passes the rotation test
+        if (tid == 0) sm.flag = 0;
+        __syncthreads();
+        for (int e = tid; e < m * m; e += BT) {
+            const int p = e / m, q = e % m;
+            if (p < q && fabs(A[p][q]) > floor && A[p][q] * A[p][q] > tol * tol * fabs(A[p][p] * A[q][q]))
+                sm.flag = 1;
+        }
+        __syncthreads();
+        if (sm.flag == 0) {
+            converged = true;
+            break;
+        }
+        __syncthreads();
         if (tid == 0) sm.flag = 0;
         __syncthreads();
         for (int round = 0; round < m - 1; ++round) {
@@ -301,8 +321,8 @@ __device__ bool blk_jacobi(int n, int max_sweeps, BatchSmem<BK>& sm) {
                     p = q;
                     q = t;
                 }
-                double c, s, dp, dq;
-                if (schur2_rs(A[p][p], A[q][q], A[p][q], tol, c, s, dp, dq)) sm.flag = 1;
+                double c = 1.0, s = 0.0, dp = A[p][p], dq = A[q][q];
+                if (fabs(A[p][q]) > floor && schur2_rs(A[p][p], A[q][q], A[p][q], tol, c, s, dp, dq)) sm.flag = 1;
                 sm.pp[tid] = p;
                 sm.qq[tid] = q;
                 sm.cs[tid] = c;
