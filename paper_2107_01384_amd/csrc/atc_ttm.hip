@@ -369,6 +369,61 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
     }
 }
 
+// Mode product for a last, contiguous mode (R == 1) and m_out <= 32: Z[l][j] =
+// sum_i Y[l][i] M[j][i] (M = U^T, m_out x n, FP32).  One workgroup per 16 rows
+// l; wavefront w takes the w-th quarter of i in batches of 128 whose loads go
+// out together (one memory latency per batch instead of one per 32 rows of a
+// tile loop), v_mfma_f32_16x16x4f32 (FP32 products and sums), and the
+// quarters are added in wavefront order through LDS.
+__global__ __launch_bounds__(NTHREADS) void k_ttm_rows(const float* __restrict__ Y, int64_t L, int n, int m_out,
+                                                       const float* __restrict__ M32, float* __restrict__ Z,
+                                                       const int32_t* __restrict__ m_dev) {
+    if (m_dev) m_out = min(m_out, *m_dev);  // the rank chosen on the device
+    if (m_out < 1) return;
+    constexpr int KB = 32;  // K steps of four per batch
+    __shared__ float red[4][16][33];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t l0 = (int64_t)blockIdx.x * 16;
+    const int c = lane & 15, kr = lane >> 4;
+    const int chunk = ((n + 3) / 4 + 3) / 4 * 4;
+    const int k0 = min(n, wave * chunk), k1 = min(n, k0 + chunk);
+    const float* yrow = Y + min(l0 + c, L - 1) * (int64_t)n;
+    const float* m0 = M32 + (int64_t)min(c, m_out - 1) * n;
+    const float* m1 = M32 + (int64_t)min(16 + c, m_out - 1) * n;
+    const float w0 = c < m_out ? 1.f : 0.f, w1 = 16 + c < m_out ? 1.f : 0.f;
+    f32x4 acc0 = f32x4{0.f, 0.f, 0.f, 0.f}, acc1 = acc0;
+    for (int kb = k0; kb < k1; kb += 4 * KB) {
+        float a[KB], b0[KB], b1[KB];
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+            const int k = kb + 4 * t + kr;
+            const bool in = k < k1;
+            const int kk = in ? k : k0;
+            const float m = in ? 1.f : 0.f;
+            a[t] = m * yrow[kk];
+            b0[t] = w0 * m0[kk];
+            b1[t] = w1 * m1[kk];
+        }
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b0[t], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b1[t], acc1, 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = mfma16_row<PREC_F32>(lane, e);
+        red[wave][r][c] = acc0[e];
+        red[wave][r][16 + c] = acc1[e];
+    }
+    __syncthreads();
+    for (int e = tid; e < 16 * 32; e += NTHREADS) {
+        const int r = e >> 5, j = e & 31;
+        const float t = ((red[0][r][j] + red[1][r][j]) + red[2][r][j]) + red[3][r][j];
+        if (l0 + r < L && j < m_out) Z[(l0 + r) * m_out + j] = t;
+    }
+}
+
 template <int P, int LAYOUT>
 hipError_t launch_ttm_t(const TtmPlan& t, const void* Y, const void* M, const void* Mh, const void* Ml, void* Z,
                         const int32_t* m_dev, hipStream_t st) {
@@ -432,6 +487,12 @@ hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, 
             if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 2>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z, m_dev);
             else hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 4>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z, m_dev);
         }
+        return hipGetLastError();
+    }
+    // short slabs (few 64-row tiles for the tile kernel, latency-bound): rows kernel
+    if (prec != PREC_F64 && t.layout == LAYOUT_NC && t.R == 1 && t.m_out <= 32 && t.L < 8192) {
+        hipLaunchKernelGGL(k_ttm_rows, dim3((unsigned)ceil_div(t.L, 16)), dim3(NTHREADS), 0, st, (const float*)Y, t.L,
+                           t.n, t.m_out, (const float*)M, (float*)Z, m_dev);
         return hipGetLastError();
     }
     switch (prec) {
