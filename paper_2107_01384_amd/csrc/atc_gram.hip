@@ -349,8 +349,10 @@ GramPlan gram_plan(int prec, int64_t L, int nx, int ny, int64_t R, bool sym, siz
     g.tiles_y = (int)ceil_div(ny, TILE);
     g.npairs = sym ? g.tiles_x * (g.tiles_x + 1) / 2 : g.tiles_x * g.tiles_y;
     // enough workgroups to cover 256 CUs several times, at least 8 steps each
+    // (2 for short products, whose time is one memory latency per step)
     int64_t want = ceil_div(2048, g.npairs);
-    int64_t max_by_steps = g.steps / 8 > 0 ? g.steps / 8 : 1;
+    const int64_t min_steps = g.steps < 64 ? 2 : 8;
+    int64_t max_by_steps = g.steps / min_steps > 0 ? g.steps / min_steps : 1;
     int64_t max_by_mem = (int64_t)(part_capacity_bytes / ((size_t)g.npairs * TILE * TILE * sizeof(double)));
     int64_t ns = want;
     if (ns > max_by_steps) ns = max_by_steps;
