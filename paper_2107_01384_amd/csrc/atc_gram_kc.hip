@@ -463,12 +463,13 @@ __global__ __launch_bounds__(256, 2) void k_gram_kc3(const float* __restrict__ X
 }
 
 // G (n x n, FP64, both triangles) from the split partials: one workgroup of
-// 256 threads per 16 x 16 block of the upper triangle of blocks.  A thread
-// loads its entry's partials of 32 splits at once and adds them in split
-// order (diagonal: the exact FP64 sums of squares); the block is stored, and
-// through LDS its transpose, both with 16-entry rows.
-constexpr int RDB = 16;   // reduction block edge
-constexpr int RDS = 32;   // splits loaded together
+// 256 threads per 32 x 32 block of the upper triangle of blocks, a thread four
+// consecutive entries of one row.  It loads those entries' partials of 16
+// splits at once (one 16-byte load per split) and adds them in split order;
+// diagonal entries take the exact FP64 sums of squares instead.  The block is
+// stored, and through LDS its transpose, both with 32-byte row pieces.
+constexpr int RDB = 32;   // reduction block edge
+constexpr int RDS = 16;   // splits loaded together
 __global__ __launch_bounds__(256) void k_gram_kc_reduce(const float* __restrict__ part,
                                                         const double* __restrict__ dpart, int nsplit, int npairs,
                                                         int tiles, int n, double* __restrict__ G) {
@@ -480,33 +481,57 @@ __global__ __launch_bounds__(256) void k_gram_kc_reduce(const float* __restrict_
         ++bi;
     }
     const int bj = bi + t;
-    const int ty = threadIdx.x / RDB, tx = threadIdx.x % RDB;
-    const int a = bi * RDB + ty, b = bj * RDB + tx;
-    const bool mine = a < n && b < n && a <= b;
-    double s = 0.0;
-    if (mine) {
-        const bool diag = a == b;
-        const int ti = a / KC_BM, tj = b / KC_BM;
+    const int ty = threadIdx.x >> 3, tx = threadIdx.x & 7;
+    const int a = bi * RDB + ty, b0 = bj * RDB + 4 * tx;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (a < n && b0 < n) {
+        const int ti = a / KC_BM, tj = b0 / KC_BM;
         const int pair = kc_pair_index(ti, tj, tiles);
-        const int64_t off = (int64_t)(a % KC_BM) * KC_BM + b % KC_BM;
+        const int64_t off = (int64_t)(a % KC_BM) * KC_BM + b0 % KC_BM;  // four entries in one tile row
         for (int sp0 = 0; sp0 < nsplit; sp0 += RDS) {
-            double v[RDS];
+            float4 v[RDS];
 #pragma unroll
             for (int u = 0; u < RDS; ++u) {
                 const int sp = min(sp0 + u, nsplit - 1);
-                v[u] = diag ? dpart[(int64_t)sp * n + a]
-                            : (double)part[((int64_t)sp * npairs + pair) * (KC_BM * KC_BM) + off];
+                v[u] = *reinterpret_cast<const float4*>(part + ((int64_t)sp * npairs + pair) * (KC_BM * KC_BM) + off);
             }
 #pragma unroll
-            for (int u = 0; u < RDS; ++u)
-                if (sp0 + u < nsplit) s += v[u];
+            for (int u = 0; u < RDS; ++u) {
+                if (sp0 + u < nsplit) {
+                    s[0] += (double)v[u].x;
+                    s[1] += (double)v[u].y;
+                    s[2] += (double)v[u].z;
+                    s[3] += (double)v[u].w;
+                }
+            }
         }
-        G[(int64_t)a * n + b] = s;
+        const int e = a - b0;  // the diagonal entry of this row piece, if any
+        if (e >= 0 && e < 4) {
+            double d = 0.0;
+            for (int sp0 = 0; sp0 < nsplit; sp0 += RDS) {
+                double w[RDS];
+#pragma unroll
+                for (int u = 0; u < RDS; ++u) w[u] = dpart[(int64_t)min(sp0 + u, nsplit - 1) * n + a];
+#pragma unroll
+                for (int u = 0; u < RDS; ++u)
+                    if (sp0 + u < nsplit) d += w[u];
+            }
+            s[e] = d;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (b0 + q < n && a <= b0 + q) G[(int64_t)a * n + b0 + q] = s[q];
     }
-    tb[ty][tx] = s;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tb[ty][4 * tx + q] = s[q];
     __syncthreads();
-    const int ra = bj * RDB + ty, cb = bi * RDB + tx;  // mirror of entry (cb, ra)
-    if (ra < n && cb < n && ra > cb) G[(int64_t)ra * n + cb] = tb[tx][ty];
+    // mirror: row bj*32 + ty, columns bi*32 + 4 tx .. + 3 <- entries (column, row) of the block
+    const int ra = bj * RDB + ty, cb0 = bi * RDB + 4 * tx;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int cb = cb0 + q;
+        if (ra < n && cb < n && ra > cb) G[(int64_t)ra * n + cb] = tb[4 * tx + q][ty];
+    }
 }
 
 }  // namespace
