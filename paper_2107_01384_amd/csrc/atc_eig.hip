@@ -1327,6 +1327,13 @@ __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 +
             uint4 ad[2] = {btab[lane], btab[64 + lane]};
             int me = ptab[lane & (H - 1)];
             for (int round = 0; round < NR && __ballot(need) != 0; ++round) {
+                // the rotation's inputs go out first (LDS serves a wavefront's
+                // accesses in issue order), then the block loads and next-round
+                // tables, whose latency the rotation hides.  Every lane computes
+                // the rotation of pair lane % 16 (no branch to sink the loads
+                // into); lanes 0-15 store it.
+                const int mp = me & 255, mq = me >> 8;
+                const double app = A[mp][mp], aqq = A[mq][mq], apq = A[mp][mq];
                 double x[2][4];
 #pragma unroll
                 for (int t = 0; t < 2; ++t) {
@@ -1335,23 +1342,22 @@ __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 +
                     x[t][2] = at(ad[t].z);
                     x[t][3] = at(ad[t].w);
                 }
-                const int mp = me & 255, mq = me >> 8;
-                const double app = A[mp][mp], aqq = A[mq][mq], apq = A[mp][mq];
                 const int rn = round + 1 < NR ? round + 1 : 0;
                 const uint4 nad0 = btab[rn * SL + lane], nad1 = btab[rn * SL + 64 + lane];
                 const int nme = ptab[rn * H + (lane & (H - 1))];
-                bool r = false;
+                double c, s, dp, dq;
+                const bool rr = rot2(app, aqq, apq, tol2, floor2, c, s, dp, dq);
+                const bool r = rr && lane < H;
                 if (lane < H) {
-                    double c, s, dp, dq;
-                    r = rot2(app, aqq, apq, tol2, floor2, c, s, dp, dq);
                     lg[round * H + lane] = double2{c, s};
                     A[mp][mp] = dp;
                     A[mq][mq] = dq;
-                    A[mp][mq] = r ? 0.0 : apq;
+                    A[mp][mq] = rr ? 0.0 : apq;
                 }
                 if (__ballot(r) != 0) {
                     any = true;
-                    wave_sync();
+                    // no wait: a wavefront's LDS accesses complete in issue order,
+                    // so these loads see the log and blocks stored above
                     double2 ck[2], cl[2];
 #pragma unroll
                     for (int t = 0; t < 2; ++t) {
@@ -1368,7 +1374,6 @@ __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 +
                         at(ad[t].z) = c2 * rc - s2 * rd;
                         at(ad[t].w) = s2 * rc + c2 * rd;
                     }
-                    wave_sync();
                 }
                 ad[0] = nad0;
                 ad[1] = nad1;
