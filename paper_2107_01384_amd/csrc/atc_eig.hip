@@ -999,8 +999,7 @@ __device__ __forceinline__ void cinv_step(double (&v)[S32], const double (&rb)[S
         // v[J + 1] first: the next row goes out through LDS while the other
         // entries of this step are updated
         v[J + 1] -= rb[1] * s;
-        rowbuf[lane] = v[J + 1];
-        wave_sync();
+        rowbuf[lane] = v[J + 1];  // read back below in issue order (one wavefront)
         double nb[S32 - J - 1];
 #pragma unroll
         for (int a = J + 1; a < S32; ++a) nb[a - J - 1] = rowbuf[a];
@@ -1310,7 +1309,6 @@ __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 +
             W[i][q0] = r0.y * x0 + r0.x * y0;
             W[i][p1] = r1.x * x1 - r1.y * y1;
             W[i][q1] = r1.y * x1 + r1.x * y1;
-            wave_sync();
         }
     };
     int sweeps = 0;
