@@ -295,7 +295,7 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void k3_split2(float x, float y, uint32_t& hi, uint32_t& lo) {
     const bf16x2 h = {(__bf16)x, (__bf16)y};
     uint32_t hu = __builtin_bit_cast(uint32_t, h);
-    asm volatile("" : "+v"(hu));  // keeps the compiler from converting x a second time for hx
+    asm("" : "+v"(hu));  // keeps the compiler from converting x a second time for hx
     const float hx = __uint_as_float(hu << 16), hy = __uint_as_float(hu & 0xffff0000u);
     const bf16x2 l = {(__bf16)(x - hx), (__bf16)(y - hy)};
     hi = hu;
