@@ -1630,6 +1630,20 @@ __device__ __forceinline__ void grid_sync(unsigned* sync, unsigned target, unsig
     __syncthreads();
 }
 
+// End of a cooperative launch: the last workgroup to finish clears the
+// barrier words for the next launch (every workgroup has passed its last wait).
+__device__ __forceinline__ void grid_exit(unsigned* sync) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned done = __hip_atomic_fetch_add(&sync[4], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done + 1 == gridDim.x) {
+            __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sync[3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&sync[4], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 // Per-workgroup state of the cooperative path.
 struct GridCtx {
     Sub32Grid g;
@@ -1986,15 +2000,7 @@ __device__ __forceinline__ void sub32_grid_body(const double* __restrict__ G, in
 __global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G, int n, int steps, int max_sweeps,
                                                    Sub32Grid g, SelectArgs a) {
     sub32_grid_body(G, n, steps, max_sweeps, g, a);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned done = __hip_atomic_fetch_add(&g.sync[4], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (done + 1 == gridDim.x) {
-            __hip_atomic_store(&g.sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&g.sync[3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&g.sync[4], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    grid_exit(g.sync);
 }
 
 // The cooperative path needs cooperative launches and its LDS; ATC_SUB32_KERNELS=1
@@ -2129,6 +2135,103 @@ __global__ __launch_bounds__(256) void k_combine64(const double* __restrict__ Qa
     V[idx] = t;
 }
 
+// The power steps and the 64 x 64 Rayleigh-Ritz matrix of the m = 64 path in
+// one cooperative launch (the kernels k_gemm_gx, k_orth32, k_proj32 and
+// k_rr64_prep of the kernel chain, with the slab decomposition and fixed-order
+// exchanges of k_sub32_grid): on return B (64 x 64, row-major, symmetrised)
+// and the basis halves are in global memory and *ok says whether both
+// orthonormalisations succeeded (else book->need_dense is set).  With two
+// power steps the basis ends in the buffers passed as Za, Zb.
+__device__ __forceinline__ void sub64_grid_body(const double* __restrict__ G, int n, double* Pa, double* Pb,
+                                                double* Za, double* Zb, const Sub32Grid& g,
+                                                DevBook* __restrict__ book, double* __restrict__ B,
+                                                int32_t* __restrict__ ok) {
+    extern __shared__ double lds[];
+    double* part_lds = lds;
+    double(*C)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + RW * S32 * S32);
+    double(*R)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + RW * S32 * S32 + S32 * (S32 + 1));
+    __shared__ double full[2 * S32][2 * S32 + 1];
+    __shared__ double rowbuf[64];
+    __shared__ int ok_s;
+    const int tid = threadIdx.x;
+    GridCtx x;
+    x.g = g;
+    x.n = n;
+    x.b = blockIdx.x;
+    x.nb = gridDim.x;
+    x.row0 = GRID_ROWS * x.b;
+    x.nr = min(GRID_ROWS, n - x.row0);
+    x.arrivals = 0;
+    x.parity = 0;
+    const int64_t ro = (int64_t)x.row0 * S32;
+    gx_rows32<true>(x, G, nullptr, 0x5eed, Pa, part_lds);
+    gx_rows32<true>(x, G, nullptr, 0x64b5eed, Pb, part_lds);
+    constexpr int steps = 2;
+    bool good = true;
+    for (int it = 0; it < steps && good; ++it) {
+        const bool fin = it + 1 == steps;
+        good = orth_grid(x, Pa + ro, fin, part_lds, C, R, rowbuf, &ok_s);
+        if (!good) break;
+        for (int pass = 0; pass < 2; ++pass) {  // Pb -= Pa (Pa^T Pb), twice
+            cross_grid(x, Pa + ro, Pb + ro, part_lds, C);
+            apply32<1, RW, 1>(Pa + ro, Pb + ro, x.nr, C, nullptr, Pb + ro);
+            __syncthreads();
+        }
+        good = orth_grid(x, Pb + ro, fin, part_lds, C, R, rowbuf, &ok_s);
+        if (!good) break;
+        x.sync();
+        gx_rows32<false>(x, G, Pa, 0, Za, part_lds);
+        gx_rows32<false>(x, G, Pb, 0, Zb, part_lds);
+        if (!fin) {
+            double* t = Pa;
+            Pa = Za;
+            Za = t;
+            t = Pb;
+            Pb = Zb;
+            Zb = t;
+        }
+    }
+    if (!good) {
+        // the same outcome in every workgroup: hand the mode to the next eigensolver
+        if (x.b == 0 && tid == 0) {
+            book->need_dense = 1;
+            if (__hip_atomic_load(&g.sync[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                book->status = ATC_ERR_INTERNAL;  // not a failed basis: a wait gave up
+            *ok = 0;
+        }
+        return;
+    }
+    // B = [Pa Pb]^T [Za Zb], block by block, symmetrised by workgroup 0
+    for (int blk = 0; blk < 4; ++blk) {
+        const double* P = (blk >> 1) ? Pb : Pa;
+        const double* Z = (blk & 1) ? Zb : Za;
+        cross_grid(x, P + ro, Z + ro, part_lds, C);
+        for (int e = tid; e < S32 * S32; e += RT) {
+            const int i = e >> 5, j = e & 31;
+            full[32 * (blk >> 1) + i][32 * (blk & 1) + j] = C[i][j];
+        }
+        __syncthreads();
+    }
+    if (x.b == 0) {
+        for (int e = tid; e < 4 * S32 * S32; e += RT) {
+            const int i = e >> 6, j = e & 63;
+            B[e] = 0.5 * (full[i][j] + full[j][i]);
+        }
+        if (tid == 0) {
+            if (__hip_atomic_load(&g.sync[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                book->status = ATC_ERR_INTERNAL;
+            *ok = 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(RT) void k_sub64_grid(const double* __restrict__ G, int n, double* Pa, double* Pb,
+                                                   double* Za, double* Zb, Sub32Grid g, DevBook* __restrict__ book,
+                                                   double* __restrict__ B, int32_t* __restrict__ ok) {
+    sub64_grid_body(G, n, Pa, Pb, Za, Zb, g, book, B, ok);
+    grid_exit(g.sync);
+}
+
 bool sub64_ready() {
     static int state = 0;
     if (state == 0) {
@@ -2139,6 +2242,18 @@ bool sub64_ready() {
         state = (a && b) ? 1 : -1;
     }
     return state == 1;
+}
+
+bool sub64_grid_ready() {
+    static int state = 0;
+    if (state == 0)
+        state = sub32_grid_ready() && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sub64_grid),
+                                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                          (int)RR_LDS) == hipSuccess
+                    ? 1
+                    : -1;
+    const char* env = getenv("ATC_SUB32_KERNELS");
+    return state == 1 && !(env && env[0] == '1');
 }
 
 }  // namespace
@@ -2200,7 +2315,11 @@ hipError_t run_subspace32_select(const double* G, int n, int iters, int max_swee
     return hipGetLastError();
 }
 
-size_t subspace64b_ws_doubles(int n) { return (size_t)4 * n * S32 + 2 * 64 * 64 + 8; }
+// Pa, Pb, Za, Zb (n x 32 each), B and W (64 x 64), 8 doubles of flags, then
+// the cooperative path's partial products.
+size_t subspace64b_ws_doubles(int n) {
+    return (size_t)4 * n * S32 + 2 * 64 * 64 + 8 + (size_t)2 * GRID_MAXB * S32 * S32;
+}
 
 hipError_t run_subspace64_select(const double* G, int n, int max_sweeps, double* ws, double* lam, double* V,
                                  int32_t* sweeps_dev, int32_t* ok_dev, const SelectArgs& sa, hipStream_t st) {
@@ -2216,31 +2335,59 @@ hipError_t run_subspace64_select(const double* G, int n, int max_sweeps, double*
     const dim3 gg((unsigned)ceil_div(n, GX_ROWS));
     const dim3 gb(64 * GX_SPLIT);
     hipError_t e;
-    hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)nullptr, Pa, n, (uint64_t)0x5eed);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)nullptr, Pb, n, (uint64_t)0x64b5eed);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    constexpr int steps = 2;
-    for (int it = 0; it < steps; ++it) {
-        const int full = it + 1 == steps ? 1 : 0;
-        hipLaunchKernelGGL(k_orth32, dim3(1), dim3(OT), ORTH_LDS, st, Pa, n, full, 1, ok);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_proj32, dim3(1), dim3(OT), ORTH_LDS, st, (const double*)Pa, Pb, n);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_orth32, dim3(1), dim3(OT), ORTH_LDS, st, Pb, n, full, 0, ok);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)Pa, Za, n, (uint64_t)0);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)Pb, Zb, n, (uint64_t)0);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (it + 1 < steps) {
+    bool prepared = false;
+    if (sub64_grid_ready()) {
+        Sub32Grid g;
+        g.P1 = nullptr;
+        g.P2 = nullptr;
+        g.part = W + 64 * 64 + 8;
+        g.cand = nullptr;
+        g.sync = &sa.book->grid[0];
+        const char* lim = getenv("ATC_GRID_SPIN_LIMIT");
+        g.spin_limit = lim ? (unsigned)strtoul(lim, nullptr, 10) : GRID_SPIN_LIMIT;
+        const int nb = (int)ceil_div(n, GRID_ROWS);
+        int n_ = n;
+        DevBook* book = sa.book;
+        void* args[] = {(void*)&G, (void*)&n_, (void*)&Pa, (void*)&Pb, (void*)&Za,
+                        (void*)&Zb, (void*)&g,  (void*)&book, (void*)&B, (void*)&ok};
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sub64_grid), dim3(nb), dim3(RT), args,
+                                       (unsigned)RR_LDS, st);
+        if (e == hipSuccess) {
+            prepared = true;
+            // two power steps: the basis ends in the buffers passed as Za, Zb
             std::swap(Pa, Za);
             std::swap(Pb, Zb);
+        } else {
+            (void)hipGetLastError();  // not launched: the kernel-per-step path below
         }
     }
-    hipLaunchKernelGGL(k_rr64_prep, dim3(1), dim3(RT), RR_LDS, st, (const double*)Pa, (const double*)Pb,
-                       (const double*)Za, (const double*)Zb, n, (const int32_t*)ok, sa.book, B);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!prepared) {
+        hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)nullptr, Pa, n, (uint64_t)0x5eed);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)nullptr, Pb, n, (uint64_t)0x64b5eed);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        constexpr int steps = 2;
+        for (int it = 0; it < steps; ++it) {
+            const int full = it + 1 == steps ? 1 : 0;
+            hipLaunchKernelGGL(k_orth32, dim3(1), dim3(OT), ORTH_LDS, st, Pa, n, full, 1, ok);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_proj32, dim3(1), dim3(OT), ORTH_LDS, st, (const double*)Pa, Pb, n);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_orth32, dim3(1), dim3(OT), ORTH_LDS, st, Pb, n, full, 0, ok);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)Pa, Za, n, (uint64_t)0);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_gemm_gx, gg, gb, 0, st, G, (const double*)Pb, Zb, n, (uint64_t)0);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if (it + 1 < steps) {
+                std::swap(Pa, Za);
+                std::swap(Pb, Zb);
+            }
+        }
+        hipLaunchKernelGGL(k_rr64_prep, dim3(1), dim3(RT), RR_LDS, st, (const double*)Pa, (const double*)Pb,
+                           (const double*)Za, (const double*)Zb, n, (const int32_t*)ok, sa.book, B);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     // the Ritz problem of FP32-grade data: entries under u trace(B) left alone, as in jacobi32
     if ((e = launch_eig_jacobi_lds(B, 64, 64, max_sweeps, lam, W, 64, sweeps_dev, ok_dev, st, 0x1p-53)) != hipSuccess)
         return e;

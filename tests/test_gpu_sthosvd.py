@@ -239,6 +239,33 @@ def test_subspace_one_launch_and_kernel_chain_agree(shape, monkeypatch):
     assert ok, how
 
 
+@pytest.mark.parametrize("shape,ranks", [((150, 120, 100), (40, 36, 30)), ((500, 70, 90), (50, 40, 44))])
+def test_subspace_64_one_launch_and_kernel_chain_agree(shape, ranks, monkeypatch):
+    """The m = 64 path's power steps and Rayleigh-Ritz matrix as one cooperative
+    launch (default) and as a chain of kernels (ATC_SUB32_KERNELS=1): the same
+    ranks, tails and kept subspaces up to rounding order, and the oracle's
+    ranks.  Workgroups of 32 rows: 16 for n = 500 (the last one of 20 rows),
+    3 for n = 70 (the last of 6)."""
+    x, _, _ = synth.known_rank_tucker(shape, ranks, seed=65, rel_noise=1e-4)
+    x = x.astype(np.float32)
+    eps = 1e-2
+    monkeypatch.delenv("ATC_SUB32_KERNELS", raising=False)
+    t_c = _run(x, eps, torch.float32)
+    monkeypatch.setenv("ATC_SUB32_KERNELS", "1")
+    t_k = _run(x, eps, torch.float32)
+    monkeypatch.delenv("ATC_SUB32_KERNELS")
+    log("m = 64 one launch", t_c.ranks, t_c.eig_path, "kernels", t_k.ranks, t_k.eig_path)
+    assert t_c.eig_path == [2, 2, 2] and t_k.eig_path == [2, 2, 2]
+    assert t_c.ranks == t_k.ranks == list(ranks)
+    for k in range(len(shape)):
+        assert abs(t_c.tails[k] - t_k.tails[k]) <= 1e-9 * t_c.norm2
+        gap = projector_gap(np64(t_c.factors[k]), np64(t_k.factors[k]))
+        log("  mode", k, "projector gap %.2e" % gap)
+        assert gap < 1e-7
+        assert np.max(np.abs(np64(t_c.factors[k]) - np64(t_k.factors[k]))) < 1e-6
+    assert t_c.ranks == oracle.sthosvd(x.astype(np.float64), eps).ranks
+
+
 def test_grid_barrier_wait_gives_up_without_hanging(monkeypatch):
     """The one-launch eigensolver's barrier waits are bounded: a limit of zero
     polls (forced from the host) makes every wait give up at once, every
