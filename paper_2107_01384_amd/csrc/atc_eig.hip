@@ -512,6 +512,14 @@ hipError_t orthonormalise(double* X, int n, int m, uint64_t salt, hipStream_t st
     return hipGetLastError();
 }
 
+// The 64 x 64 Jacobi in slot order (defined with the m = 64 subspace path).
+constexpr int J64_THREADS = 512;
+__global__ __launch_bounds__(J64_THREADS) void k_jacobi64_slots(const double* __restrict__ G, int n, int ldg,
+                                                                int max_sweeps, double* __restrict__ lam,
+                                                                double* __restrict__ V, int ldv,
+                                                                int32_t* __restrict__ sweeps_out,
+                                                                int32_t* __restrict__ ok_out, double floor_rel);
+
 }  // namespace
 
 hipError_t launch_eig_jacobi_lds(const double* G, int n, int ldg, int max_sweeps, double* lam, double* V, int ldv,
@@ -521,7 +529,7 @@ hipError_t launch_eig_jacobi_lds(const double* G, int n, int ldg, int max_sweeps
         hipLaunchKernelGGL((k_eig_jacobi_lds<32>), dim3(1), dim3(256), 0, st, G, n, ldg, max_sweeps, lam, V, ldv,
                            sweeps_out, ok_out, floor_rel);
     else
-        hipLaunchKernelGGL((k_eig_jacobi_lds<64>), dim3(1), dim3(1024), 0, st, G, n, ldg, max_sweeps, lam, V, ldv,
+        hipLaunchKernelGGL(k_jacobi64_slots, dim3(1), dim3(J64_THREADS), 0, st, G, n, ldg, max_sweeps, lam, V, ldv,
                            sweeps_out, ok_out, floor_rel);
     return hipGetLastError();
 }
@@ -2113,6 +2121,203 @@ __global__ __launch_bounds__(RT) void k_rr64_prep(const double* __restrict__ Qa,
     for (int e = tid; e < 4 * S32 * S32; e += RT) {
         const int i = e >> 6, j = e & 63;
         B[e] = 0.5 * (full[i][j] + full[j][i]);
+    }
+}
+
+// ---------------------------------------------- 64 x 64 Jacobi, slot order
+// Cyclic Jacobi for 33 <= n <= 64 (zero-padded to 64) with the pairs of the
+// circle method: index 0 stays in slot 0, the other 63 indices move one step
+// along a fixed cycle of slots after every round, and the pairs of a round
+// are the slot pairs (2k, 2k + 1).  A is kept in slot order, so every lane
+// reads its 2 x 2 blocks at fixed offsets and writes the rotated block to
+// the slots its rows and columns move to (the fixed permutation j64_sigma);
+// after 63 rounds every index is back in its own slot.  Wavefronts 0-3 each
+// compute all 32 rotations of a round (lanes k and k + 32 take pair k) and
+// rotate two of the 496 off-diagonal blocks per lane; after a workgroup
+// barrier (every entry of the round has been read) the blocks go to their
+// new slots and wavefront 0 writes the 32 diagonal blocks (new diagonal,
+// zero coupling).  Wavefronts 4-7 rotate the columns of the eigenvector
+// matrix W by the same round's rotations between the same barriers.  A sweep
+// starts with the test of all 2016 pairs; none passing ends the iteration.
+// Only the upper triangle of A (in slot order) is read or written.
+__device__ __forceinline__ int j64_cyc(int j) { return j < 31 ? 2 * (j + 1) : 2 * (62 - j) + 1; }
+__device__ __forceinline__ int j64_pos(int s) { return (s & 1) ? 62 - (s >> 1) : (s >> 1) - 1; }  // s != 0
+__device__ __forceinline__ int j64_sigma(int s) { return s == 0 ? 0 : j64_cyc((j64_pos(s) + 1) % 63); }
+// the index in slot s during round r of a sweep
+__device__ __forceinline__ int j64_index(int r, int s) { return s == 0 ? 0 : j64_cyc((j64_pos(s) + 63 - r) % 63); }
+__device__ __forceinline__ unsigned j64_up(int x, int y) {
+    return (unsigned)((x < y ? x * 65 + y : y * 65 + x) * (int)sizeof(double));
+}
+
+__global__ __launch_bounds__(J64_THREADS) void k_jacobi64_slots(const double* __restrict__ G, int n, int ldg,
+                                                                int max_sweeps, double* __restrict__ lam,
+                                                                double* __restrict__ V, int ldv,
+                                                                int32_t* __restrict__ sweeps_out,
+                                                                int32_t* __restrict__ ok_out, double floor_rel) {
+    constexpr int M = 64, H = 32, NR = 63, NOFF = H * (H - 1) / 2;
+    __shared__ double A[M][M + 1];
+    __shared__ double W[M][M + 1];
+    __shared__ double2 xch[4][H];  // the round's rotations, one copy per block wavefront
+    __shared__ double2 rlog[H];    // the same for the eigenvector wavefronts
+    __shared__ int ptab[NR * H];   // indices (p | q << 8) of pair k in round r
+    __shared__ int need_s[4];
+    __shared__ int rank_of[M];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < M * M; e += J64_THREADS) {
+        const int i = e >> 6, j = e & 63;
+        A[i][j] = (i < n && j < n) ? G[(int64_t)i * ldg + j] : 0.0;
+        W[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    for (int e = tid; e < NR * H; e += J64_THREADS) {
+        const int r = e >> 5, k = e & 31;
+        ptab[e] = j64_index(r, 2 * k) | (j64_index(r, 2 * k + 1) << 8);
+    }
+    __syncthreads();
+    const double tol = (double)n * 0x1p-53;
+    const double tol2 = tol * tol;
+    double trace = 0.0;
+    for (int i = 0; i < n; ++i) trace += A[i][i];
+    const double floor = floor_rel * fabs(trace);
+    const double floor2 = floor * floor;
+    char* const abase = reinterpret_cast<char*>(&A[0][0]);
+    auto at = [&](unsigned off) -> double& { return *reinterpret_cast<double*>(abase + off); };
+    // block wavefronts: slots b = 64 wave + lane + 256 t; b < 496 is block (k, l), k < l, in
+    // row-major order of the strict upper triangle, the rest read and write the padding column
+    unsigned ld[2][4], st[2][4];
+    int kt[2], lt[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        int b = 64 * (wave & 3) + lane + 256 * t;
+        if (b < NOFF) {
+            int k = 0;
+            while (b >= H - 1 - k) {
+                b -= H - 1 - k;
+                ++k;
+            }
+            const int l = k + 1 + b;
+            kt[t] = k;
+            lt[t] = l;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = 2 * k + (e >> 1), y = 2 * l + (e & 1);
+                ld[t][e] = j64_up(x, y);
+                st[t][e] = j64_up(j64_sigma(x), j64_sigma(y));
+            }
+        } else {
+            kt[t] = 0;
+            lt[t] = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const unsigned pad = (unsigned)((4 * (b - NOFF) + e) * (M + 1) + M) * (unsigned)sizeof(double);
+                ld[t][e] = pad;
+                st[t][e] = pad;
+            }
+        }
+    }
+    const int kp = lane & (H - 1);
+    const unsigned o_pp = j64_up(2 * kp, 2 * kp), o_qq = j64_up(2 * kp + 1, 2 * kp + 1), o_pq = j64_up(2 * kp, 2 * kp + 1);
+    const int sp = j64_sigma(2 * kp), sq = j64_sigma(2 * kp + 1);
+    const unsigned s_pp = j64_up(sp, sp), s_qq = j64_up(sq, sq), s_pq = j64_up(sp, sq);
+    // eigenvector wavefronts: row lane of W, pairs 8 g .. 8 g + 7
+    const int g8 = 8 * (wave & 3);
+    int sweeps = 0;
+    bool conv = false;
+    while (true) {
+        if (wave < 4) {
+            bool need = false;
+            for (int e = 64 * wave + lane; e < NR * H; e += 256) {
+                const int c = ptab[e], p = c & 255, q = c >> 8;
+                need = need || rot2_needed(A[p][p], A[q][q], A[min(p, q)][max(p, q)], tol2, floor2);
+            }
+            const bool any = __ballot(need) != 0;
+            if (lane == 0) need_s[wave] = any ? 1 : 0;
+        }
+        __syncthreads();
+        const bool need = (need_s[0] | need_s[1] | need_s[2] | need_s[3]) != 0;
+        if (!need) {
+            conv = true;
+            break;
+        }
+        if (sweeps >= max_sweeps) break;
+        for (int round = 0; round < NR; ++round) {
+            if (wave < 4) {
+                const double app = at(o_pp), aqq = at(o_qq), apq = at(o_pq);
+                double x[2][4];
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) x[t][e] = at(ld[t][e]);
+                double c, s, dp, dq;
+                const bool rr = rot2(app, aqq, apq, tol2, floor2, c, s, dp, dq);
+                if (lane < H) {
+                    xch[wave][lane] = double2{c, s};
+                    if (wave == 0) rlog[lane] = double2{c, s};
+                }
+                // no wait: a wavefront's LDS accesses complete in issue order
+                double y[2][4];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const double2 ck = xch[wave][kt[t]], cl = xch[wave][lt[t]];
+                    const double c1 = ck.x, s1 = ck.y, c2 = cl.x, s2 = cl.y;
+                    const double ra = c1 * x[t][0] - s1 * x[t][2], rb = c1 * x[t][1] - s1 * x[t][3];
+                    const double rc = s1 * x[t][0] + c1 * x[t][2], rd = s1 * x[t][1] + c1 * x[t][3];
+                    y[t][0] = c2 * ra - s2 * rb;
+                    y[t][1] = s2 * ra + c2 * rb;
+                    y[t][2] = c2 * rc - s2 * rd;
+                    y[t][3] = s2 * rc + c2 * rd;
+                }
+                __syncthreads();  // every entry of this round has been read
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) at(st[t][e]) = y[t][e];
+                if (wave == 0 && lane < H) {
+                    at(s_pp) = dp;
+                    at(s_qq) = dq;
+                    at(s_pq) = rr ? 0.0 : apq;
+                }
+            } else {
+                double xv[8], yv[8];
+                int pv[8], qv[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int c = ptab[round * H + g8 + j];
+                    pv[j] = c & 255;
+                    qv[j] = c >> 8;
+                    xv[j] = W[lane][pv[j]];
+                    yv[j] = W[lane][qv[j]];
+                }
+                __syncthreads();  // this round's rotations are in rlog
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const double2 r = rlog[g8 + j];
+                    W[lane][pv[j]] = r.x * xv[j] - r.y * yv[j];
+                    W[lane][qv[j]] = r.y * xv[j] + r.x * yv[j];
+                }
+            }
+            __syncthreads();
+        }
+        ++sweeps;
+    }
+    // eigenvalues = diagonal (every index back in its own slot); descending, equal values by index
+    for (int i = tid; i < n; i += J64_THREADS) {
+        const double li = A[i][i];
+        int r = 0;
+        for (int j = 0; j < n; ++j) {
+            const double lj = A[j][j];
+            r += (lj > li) || (lj == li && j < i);
+        }
+        rank_of[i] = r;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += J64_THREADS) lam[rank_of[i]] = A[i][i];  // unclamped (see select)
+    for (int idx = tid; idx < n * n; idx += J64_THREADS) {
+        const int row = idx / n, i = idx % n;
+        V[(int64_t)row * ldv + rank_of[i]] = W[row][i];
+    }
+    if (tid == 0) {
+        if (sweeps_out) *sweeps_out = sweeps;
+        if (ok_out) *ok_out = conv ? 1 : 0;
     }
 }
 
