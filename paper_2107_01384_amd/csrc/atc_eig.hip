@@ -513,7 +513,7 @@ hipError_t orthonormalise(double* X, int n, int m, uint64_t salt, hipStream_t st
 }
 
 // The 64 x 64 Jacobi in slot order (defined with the m = 64 subspace path).
-constexpr int J64_THREADS = 512;
+constexpr int J64_THREADS = 256;
 __global__ __launch_bounds__(J64_THREADS) void k_jacobi64_slots(const double* __restrict__ G, int n, int ldg,
                                                                 int max_sweeps, double* __restrict__ lam,
                                                                 double* __restrict__ V, int ldv,
@@ -2131,18 +2131,21 @@ __global__ __launch_bounds__(RT) void k_rr64_prep(const double* __restrict__ Qa,
 // are the slot pairs (2k, 2k + 1).  A is kept in slot order, so every lane
 // reads its 2 x 2 blocks at fixed offsets and writes the rotated block to
 // the slots its rows and columns move to (the fixed permutation j64_sigma);
-// after 63 rounds every index is back in its own slot.  Wavefronts 0-3 each
-// compute all 32 rotations of a round (lanes k and k + 32 take pair k) and
-// rotate two of the 496 off-diagonal blocks per lane; after a workgroup
-// barrier (every entry of the round has been read) the blocks go to their
-// new slots and wavefront 0 writes the 32 diagonal blocks (new diagonal,
-// zero coupling).  Wavefronts 4-7 rotate the columns of the eigenvector
-// matrix W by the same round's rotations between the same barriers.  A sweep
-// starts with the test of all 2016 pairs; none passing ends the iteration.
-// Only the upper triangle of A (in slot order) is read or written.
-__device__ __forceinline__ int j64_cyc(int j) { return j < 31 ? 2 * (j + 1) : 2 * (62 - j) + 1; }
-__device__ __forceinline__ int j64_pos(int s) { return (s & 1) ? 62 - (s >> 1) : (s >> 1) - 1; }  // s != 0
-__device__ __forceinline__ int j64_sigma(int s) { return s == 0 ? 0 : j64_cyc((j64_pos(s) + 1) % 63); }
+// after 63 rounds every index is back in its own slot.  A round reads one
+// buffer and writes the other (every upper-triangle entry is written once),
+// so a round needs one workgroup barrier.  Wavefronts 0-2 each compute all 32
+// rotations of a round (lanes k and k + 32 take pair k) and rotate three of
+// the 496 off-diagonal blocks per lane into their new slots; wavefront 0
+// writes the 32 diagonal blocks (new diagonal, zero coupling).  Wavefront 3
+// holds the eigenvector matrix in registers, lane i its row i in slot order,
+// so a rotation and the move to the next slots use only compile-time
+// register indices; it applies a round's rotations (double-buffered in LDS)
+// while the other wavefronts compute the next round.  A sweep starts with
+// the test of all 2016 pairs; none passing ends the iteration.  Only the
+// upper triangle of A (in slot order) is read or written.
+__host__ __device__ constexpr int j64_cyc(int j) { return j < 31 ? 2 * (j + 1) : 2 * (62 - j) + 1; }
+__host__ __device__ constexpr int j64_pos(int s) { return (s & 1) ? 62 - (s >> 1) : (s >> 1) - 1; }  // s != 0
+__host__ __device__ constexpr int j64_sigma(int s) { return s == 0 ? 0 : j64_cyc((j64_pos(s) + 1) % 63); }
 // the index in slot s during round r of a sweep
 __device__ __forceinline__ int j64_index(int r, int s) { return s == 0 ? 0 : j64_cyc((j64_pos(s) + 63 - r) % 63); }
 __device__ __forceinline__ unsigned j64_up(int x, int y) {
@@ -2155,18 +2158,21 @@ __global__ __launch_bounds__(J64_THREADS) void k_jacobi64_slots(const double* __
                                                                 int32_t* __restrict__ sweeps_out,
                                                                 int32_t* __restrict__ ok_out, double floor_rel) {
     constexpr int M = 64, H = 32, NR = 63, NOFF = H * (H - 1) / 2;
-    __shared__ double A[M][M + 1];
-    __shared__ double W[M][M + 1];
-    __shared__ double2 xch[4][H];  // the round's rotations, one copy per block wavefront
-    __shared__ double2 rlog[H];    // the same for the eigenvector wavefronts
-    __shared__ int ptab[NR * H];   // indices (p | q << 8) of pair k in round r
-    __shared__ int need_s[4];
+    constexpr int BW = 3;                  // block wavefronts
+    constexpr int SPL = 3;                 // block slots per lane
+    constexpr int NSLOT = 64 * BW * SPL;   // 576: 496 blocks, 80 unused slots
+    static_assert(NSLOT >= NOFF && 4 * (NSLOT - NOFF) <= 5 * (M + 1), "unused slots fit rows 64-68");
+    __shared__ double Ab[2][M + 5][M + 1];  // this round's A and the next; rows 64-68: unused slots
+    __shared__ double2 xch[BW][H];        // the round's rotations, one copy per block wavefront
+    __shared__ double2 rlog[2][H];        // the same for the eigenvector wavefront, by round parity
+    __shared__ int ptab[NR * H];          // indices (p | q << 8) of pair k in round r
+    __shared__ int need_s[BW];
     __shared__ int rank_of[M];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    int cur = 0;  // the buffer that holds A
     for (int e = tid; e < M * M; e += J64_THREADS) {
         const int i = e >> 6, j = e & 63;
-        A[i][j] = (i < n && j < n) ? G[(int64_t)i * ldg + j] : 0.0;
-        W[i][j] = (i == j) ? 1.0 : 0.0;
+        Ab[0][i][j] = (i < n && j < n) ? G[(int64_t)i * ldg + j] : 0.0;
     }
     for (int e = tid; e < NR * H; e += J64_THREADS) {
         const int r = e >> 5, k = e & 31;
@@ -2176,18 +2182,16 @@ __global__ __launch_bounds__(J64_THREADS) void k_jacobi64_slots(const double* __
     const double tol = (double)n * 0x1p-53;
     const double tol2 = tol * tol;
     double trace = 0.0;
-    for (int i = 0; i < n; ++i) trace += A[i][i];
+    for (int i = 0; i < n; ++i) trace += Ab[0][i][i];
     const double floor = floor_rel * fabs(trace);
     const double floor2 = floor * floor;
-    char* const abase = reinterpret_cast<char*>(&A[0][0]);
-    auto at = [&](unsigned off) -> double& { return *reinterpret_cast<double*>(abase + off); };
-    // block wavefronts: slots b = 64 wave + lane + 256 t; b < 496 is block (k, l), k < l, in
-    // row-major order of the strict upper triangle, the rest read and write the padding column
-    unsigned ld[2][4], st[2][4];
-    int kt[2], lt[2];
+    // block wavefronts: slots b = 64 wave + lane + 192 t; b < 496 is block (k, l), k < l, in
+    // row-major order of the strict upper triangle, the rest read and write rows 64-68
+    unsigned ld[SPL][4], st[SPL][4];
+    int kt[SPL], lt[SPL];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        int b = 64 * (wave & 3) + lane + 256 * t;
+    for (int t = 0; t < SPL; ++t) {
+        int b = 64 * (wave < BW ? wave : 0) + lane + 64 * BW * t;
         if (b < NOFF) {
             int k = 0;
             while (b >= H - 1 - k) {
@@ -2208,9 +2212,9 @@ __global__ __launch_bounds__(J64_THREADS) void k_jacobi64_slots(const double* __
             lt[t] = 0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const unsigned pad = (unsigned)((4 * (b - NOFF) + e) * (M + 1) + M) * (unsigned)sizeof(double);
-                ld[t][e] = pad;
-                st[t][e] = pad;
+                const unsigned spare = (unsigned)(M * (M + 1) + 4 * (b - NOFF) + e) * (unsigned)sizeof(double);
+                ld[t][e] = spare;
+                st[t][e] = spare;
             }
         }
     }
@@ -2218,14 +2222,17 @@ __global__ __launch_bounds__(J64_THREADS) void k_jacobi64_slots(const double* __
     const unsigned o_pp = j64_up(2 * kp, 2 * kp), o_qq = j64_up(2 * kp + 1, 2 * kp + 1), o_pq = j64_up(2 * kp, 2 * kp + 1);
     const int sp = j64_sigma(2 * kp), sq = j64_sigma(2 * kp + 1);
     const unsigned s_pp = j64_up(sp, sp), s_qq = j64_up(sq, sq), s_pq = j64_up(sp, sq);
-    // eigenvector wavefronts: row lane of W, pairs 8 g .. 8 g + 7
-    const int g8 = 8 * (wave & 3);
+    // eigenvector wavefront: row `lane` of W in slot order (slot = index at a sweep's start)
+    double w[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) w[j] = (j == lane) ? 1.0 : 0.0;
     int sweeps = 0;
     bool conv = false;
     while (true) {
-        if (wave < 4) {
+        if (wave < BW) {
             bool need = false;
-            for (int e = 64 * wave + lane; e < NR * H; e += 256) {
+            double(*A)[M + 1] = Ab[cur];
+            for (int e = 64 * wave + lane; e < NR * H; e += 64 * BW) {
                 const int c = ptab[e], p = c & 255, q = c >> 8;
                 need = need || rot2_needed(A[p][p], A[q][q], A[min(p, q)][max(p, q)], tol2, floor2);
             }
@@ -2233,30 +2240,34 @@ __global__ __launch_bounds__(J64_THREADS) void k_jacobi64_slots(const double* __
             if (lane == 0) need_s[wave] = any ? 1 : 0;
         }
         __syncthreads();
-        const bool need = (need_s[0] | need_s[1] | need_s[2] | need_s[3]) != 0;
+        const bool need = (need_s[0] | need_s[1] | need_s[2]) != 0;
         if (!need) {
             conv = true;
             break;
         }
         if (sweeps >= max_sweeps) break;
-        for (int round = 0; round < NR; ++round) {
-            if (wave < 4) {
+        if (wave < BW) {
+            for (int round = 0; round < NR; ++round) {
+                char* const src = reinterpret_cast<char*>(&Ab[cur][0][0]);
+                char* const dst = reinterpret_cast<char*>(&Ab[cur ^ 1][0][0]);
+                auto at = [&](unsigned off) -> double& { return *reinterpret_cast<double*>(src + off); };
+                auto to = [&](unsigned off) -> double& { return *reinterpret_cast<double*>(dst + off); };
                 const double app = at(o_pp), aqq = at(o_qq), apq = at(o_pq);
-                double x[2][4];
+                double x[SPL][4];
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                for (int t = 0; t < SPL; ++t)
 #pragma unroll
                     for (int e = 0; e < 4; ++e) x[t][e] = at(ld[t][e]);
                 double c, s, dp, dq;
                 const bool rr = rot2(app, aqq, apq, tol2, floor2, c, s, dp, dq);
                 if (lane < H) {
                     xch[wave][lane] = double2{c, s};
-                    if (wave == 0) rlog[lane] = double2{c, s};
+                    if (wave == 0) rlog[round & 1][lane] = double2{c, s};
                 }
                 // no wait: a wavefront's LDS accesses complete in issue order
-                double y[2][4];
+                double y[SPL][4];
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
+                for (int t = 0; t < SPL; ++t) {
                     const double2 ck = xch[wave][kt[t]], cl = xch[wave][lt[t]];
                     const double c1 = ck.x, s1 = ck.y, c2 = cl.x, s2 = cl.y;
                     const double ra = c1 * x[t][0] - s1 * x[t][2], rb = c1 * x[t][1] - s1 * x[t][3];
@@ -2266,39 +2277,68 @@ __global__ __launch_bounds__(J64_THREADS) void k_jacobi64_slots(const double* __
                     y[t][2] = c2 * rc - s2 * rd;
                     y[t][3] = s2 * rc + c2 * rd;
                 }
-                __syncthreads();  // every entry of this round has been read
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                for (int t = 0; t < SPL; ++t)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) at(st[t][e]) = y[t][e];
+                    for (int e = 0; e < 4; ++e) to(st[t][e]) = y[t][e];
                 if (wave == 0 && lane < H) {
-                    at(s_pp) = dp;
-                    at(s_qq) = dq;
-                    at(s_pq) = rr ? 0.0 : apq;
+                    to(s_pp) = dp;
+                    to(s_qq) = dq;
+                    to(s_pq) = rr ? 0.0 : apq;
                 }
-            } else {
-                double xv[8], yv[8];
-                int pv[8], qv[8];
+                __syncthreads();  // the next buffer is complete; this one is free
+                cur ^= 1;
+            }
+        } else {
+            // unrolled by 7 (63 = 9 x 7): the register moves that bring the
+            // permuted columns back to the loop's registers come once per 7 rounds
+            for (int r7 = 0; r7 < NR; r7 += 7) {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int c = ptab[round * H + g8 + j];
-                    pv[j] = c & 255;
-                    qv[j] = c >> 8;
-                    xv[j] = W[lane][pv[j]];
-                    yv[j] = W[lane][qv[j]];
-                }
-                __syncthreads();  // this round's rotations are in rlog
+                for (int u = 0; u < 7; ++u) {
+                    const int round = r7 + u;
+                    // this round's rotations: written before the round's barrier, rewritten
+                    // two rounds later, after this wavefront has passed the next barrier
+                    __syncthreads();
+                    const double2* lg = rlog[round & 1];
+                    double2 ca[8], cb[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const double2 r = rlog[g8 + j];
-                    W[lane][pv[j]] = r.x * xv[j] - r.y * yv[j];
-                    W[lane][qv[j]] = r.y * xv[j] + r.x * yv[j];
+                    for (int j = 0; j < 8; ++j) {
+                        ca[j] = lg[j];
+                        cb[j] = lg[8 + j];
+                    }
+                    double wn[M];
+                    auto rotate8 = [&](const double2 (&cs)[8], int kb) {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            const int k = kb + j;
+                            const double xv = w[2 * k], yv = w[2 * k + 1];
+                            wn[j64_sigma(2 * k)] = cs[j].x * xv - cs[j].y * yv;
+                            wn[j64_sigma(2 * k + 1)] = cs[j].y * xv + cs[j].x * yv;
+                        }
+                    };
+                    rotate8(ca, 0);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) ca[j] = lg[16 + j];
+                    rotate8(cb, 8);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) cb[j] = lg[24 + j];
+                    rotate8(ca, 16);
+                    rotate8(cb, 24);
+#pragma unroll
+                    for (int j = 0; j < M; ++j) w[j] = wn[j];
                 }
             }
-            __syncthreads();
         }
+        if (wave == BW) cur ^= NR & 1;
         ++sweeps;
     }
+    double(*A)[M + 1] = Ab[cur];
+    double(*W)[M + 1] = Ab[cur ^ 1];  // the eigenvectors, in the free buffer
+    if (wave == BW) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) W[lane][j] = w[j];
+    }
+    __syncthreads();
     // eigenvalues = diagonal (every index back in its own slot); descending, equal values by index
     for (int i = tid; i < n; i += J64_THREADS) {
         const double li = A[i][i];
