@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "atc_internal.hpp"
+#include "atc_jacobi64.hpp"
 
 namespace atc {
 namespace {
@@ -48,8 +49,11 @@ template <int BK>
 struct BatchSmem {
     union {
         struct {
-            double A[BMAX][APAD];  // Gram matrix, then the Jacobi iterate
-            double V[BMAX][APAD];  // eigenvectors
+            // Gram matrix, then the Jacobi iterate; V the eigenvectors.  The
+            // slot-order Jacobi (n > 32) uses both as its two buffers of
+            // J64_ROWS rows and leaves the eigenvectors in V.
+            double A[J64_ROWS][APAD];
+            double V[J64_ROWS][APAD];
         } e;
         struct {                   // Gram staging (aliases A; V unused then)
             __bf16 xh[BMAX][BK + 8];
@@ -64,6 +68,7 @@ struct BatchSmem {
             float yf[BMAX][BK + 1];
         } t;
     } u;
+    J64Shared j64;
     double lam[BMAX];
     int col_of[BMAX];   // eigenvector column of the j-th largest eigenvalue
     int sgn[BMAX];
@@ -242,9 +247,34 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
 }
 
 // ---- cyclic Jacobi on sm.u.e.A (n <= 64) --------------------------------
+// The slot-order Jacobi as a call of its own: its eigenvector registers are
+// then not allocated next to the rest of the persistent kernel's state.
+__device__ __attribute__((noinline)) bool blk_jacobi64(int n, int max_sweeps, double (*A)[APAD], double (*V)[APAD],
+                                                       J64Shared* sh, int* sweeps) {
+    return jacobi64_slots(n, max_sweeps, 0x1p-53, A, V, *sh, V, *sweeps);
+}
+
 template <int BK>
 __device__ bool blk_jacobi(int n, int max_sweeps, BatchSmem<BK>& sm) {
     const int tid = threadIdx.x;
+    static_assert(APAD == J64_LD && BT == J64_THREADS, "slot-order Jacobi layout");
+    if (n > 32) {
+        // 33 <= n <= 64: the slot-order Jacobi (zero-padded to 64), same tests
+        int sweeps = 0;
+        const bool conv = blk_jacobi64(n, max_sweeps, sm.u.e.A, sm.u.e.V, &sm.j64, &sweeps);
+        for (int i = tid; i < n; i += BT) {
+            const double li = sm.j64.diag[i];
+            int r = 0;
+            for (int j = 0; j < n; ++j) {
+                const double lj = sm.j64.diag[j];
+                r += (lj > li) || (lj == li && j < i);
+            }
+            sm.lam[r] = li;
+            sm.col_of[r] = i;
+        }
+        __syncthreads();
+        return conv;
+    }
     const int m = n + (n & 1), h = m / 2;
     double (*A)[APAD] = sm.u.e.A;
     double (*Vm)[APAD] = sm.u.e.V;

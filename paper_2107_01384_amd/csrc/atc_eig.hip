@@ -28,6 +28,7 @@
 #include <stdlib.h>
 
 #include "atc_internal.hpp"
+#include "atc_jacobi64.hpp"
 
 namespace atc {
 namespace {
@@ -513,7 +514,6 @@ hipError_t orthonormalise(double* X, int n, int m, uint64_t salt, hipStream_t st
 }
 
 // The 64 x 64 Jacobi in slot order (defined with the m = 64 subspace path).
-constexpr int J64_THREADS = 256;
 __global__ __launch_bounds__(J64_THREADS) void k_jacobi64_slots(const double* __restrict__ G, int n, int ldg,
                                                                 int max_sweeps, double* __restrict__ lam,
                                                                 double* __restrict__ V, int ldv,
@@ -1184,38 +1184,6 @@ __global__ __launch_bounds__(OT) void k_orth32(double* __restrict__ Y, int n, in
     }
     good = good && done;
     if (tid == 0) *ok = first ? (good ? 1 : 0) : ((*ok && good) ? 1 : 0);
-}
-
-// Whether the pair (p, q) is rotated: |a_pq| > tol sqrt(|a_pp a_qq|) (the
-// relative test of schur2, squared) and |a_pq| > floor.
-__device__ __forceinline__ bool rot2_needed(double app, double aqq, double apq, double tol2, double floor2) {
-    const double a2 = apq * apq;
-    return a2 > tol2 * fabs(app * aqq) && a2 > floor2;
-}
-
-// Jacobi rotation for the pair (p, q) as in schur2, with fewer long-latency
-// operations: with d = a_qq - a_pp, g = 2 a_pq, h = hypot(d, g), u = (1 + |d|
-// / h) / 2: c = sqrt(u), s = sign(d) g / (2 h c), t = s / c (the smaller
-// angle).  Pairs that fail rot2_needed keep (c, s) = (1, 0).
-__device__ inline bool rot2(double app, double aqq, double apq, double tol2, double floor2, double& c, double& s,
-                            double& dp, double& dq) {
-    c = 1.0;
-    s = 0.0;
-    dp = app;
-    dq = aqq;
-    if (!rot2_needed(app, aqq, apq, tol2, floor2)) return false;
-    const double d = aqq - app, g = 2.0 * apq;
-    const double hh = d * d + g * g;
-    if (!(hh >= 0x1p-1022) || !(hh < INFINITY)) return false;  // squares out of range: leave the pair
-    const double rh = rsqrt_pos(hh);  // 1 / h
-    const double u = 0.5 + 0.5 * fabs(d) * rh;   // cos^2 of the angle
-    const double rc = rsqrt_pos(u);              // 1 / c
-    c = u * rc;
-    s = (d >= 0.0 ? 0.5 : -0.5) * g * rh * rc;
-    const double t = s * rc;
-    dp = app - t * apq;
-    dq = aqq + t * apq;
-    return true;
 }
 
 // Cyclic Jacobi on the symmetric A (32 x 32, LDS; only the upper triangle is
@@ -2124,236 +2092,39 @@ __global__ __launch_bounds__(RT) void k_rr64_prep(const double* __restrict__ Qa,
     }
 }
 
-// ---------------------------------------------- 64 x 64 Jacobi, slot order
-// Cyclic Jacobi for 33 <= n <= 64 (zero-padded to 64) with the pairs of the
-// circle method: index 0 stays in slot 0, the other 63 indices move one step
-// along a fixed cycle of slots after every round, and the pairs of a round
-// are the slot pairs (2k, 2k + 1).  A is kept in slot order, so every lane
-// reads its 2 x 2 blocks at fixed offsets and writes the rotated block to
-// the slots its rows and columns move to (the fixed permutation j64_sigma);
-// after 63 rounds every index is back in its own slot.  A round reads one
-// buffer and writes the other (every upper-triangle entry is written once),
-// so a round needs one workgroup barrier.  Wavefronts 0-2 each compute all 32
-// rotations of a round (lanes k and k + 32 take pair k) and rotate three of
-// the 496 off-diagonal blocks per lane into their new slots; wavefront 0
-// writes the 32 diagonal blocks (new diagonal, zero coupling).  Wavefront 3
-// holds the eigenvector matrix in registers, lane i its row i in slot order,
-// so a rotation and the move to the next slots use only compile-time
-// register indices; it applies a round's rotations (double-buffered in LDS)
-// while the other wavefronts compute the next round.  A sweep starts with
-// the test of all 2016 pairs; none passing ends the iteration.  Only the
-// upper triangle of A (in slot order) is read or written.
-__host__ __device__ constexpr int j64_cyc(int j) { return j < 31 ? 2 * (j + 1) : 2 * (62 - j) + 1; }
-__host__ __device__ constexpr int j64_pos(int s) { return (s & 1) ? 62 - (s >> 1) : (s >> 1) - 1; }  // s != 0
-__host__ __device__ constexpr int j64_sigma(int s) { return s == 0 ? 0 : j64_cyc((j64_pos(s) + 1) % 63); }
-// the index in slot s during round r of a sweep
-__device__ __forceinline__ int j64_index(int r, int s) { return s == 0 ? 0 : j64_cyc((j64_pos(s) + 63 - r) % 63); }
-__device__ __forceinline__ unsigned j64_up(int x, int y) {
-    return (unsigned)((x < y ? x * 65 + y : y * 65 + x) * (int)sizeof(double));
-}
-
+// The 64 x 64 Jacobi in slot order (jacobi64_slots) on one matrix: G (n x n,
+// row stride ldg, 33 <= n <= 64) in, eigenvalues descending in lam (equal
+// values by index), eigenvectors in the matching columns of V (row stride ldv).
 __global__ __launch_bounds__(J64_THREADS) void k_jacobi64_slots(const double* __restrict__ G, int n, int ldg,
                                                                 int max_sweeps, double* __restrict__ lam,
                                                                 double* __restrict__ V, int ldv,
                                                                 int32_t* __restrict__ sweeps_out,
                                                                 int32_t* __restrict__ ok_out, double floor_rel) {
-    constexpr int M = 64, H = 32, NR = 63, NOFF = H * (H - 1) / 2;
-    constexpr int BW = 3;                  // block wavefronts
-    constexpr int SPL = 3;                 // block slots per lane
-    constexpr int NSLOT = 64 * BW * SPL;   // 576: 496 blocks, 80 unused slots
-    static_assert(NSLOT >= NOFF && 4 * (NSLOT - NOFF) <= 5 * (M + 1), "unused slots fit rows 64-68");
-    __shared__ double Ab[2][M + 5][M + 1];  // this round's A and the next; rows 64-68: unused slots
-    __shared__ double2 xch[BW][H];        // the round's rotations, one copy per block wavefront
-    __shared__ double2 rlog[2][H];        // the same for the eigenvector wavefront, by round parity
-    __shared__ int ptab[NR * H];          // indices (p | q << 8) of pair k in round r
-    __shared__ int need_s[BW];
-    __shared__ int rank_of[M];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int cur = 0;  // the buffer that holds A
-    for (int e = tid; e < M * M; e += J64_THREADS) {
-        const int i = e >> 6, j = e & 63;
-        Ab[0][i][j] = (i < n && j < n) ? G[(int64_t)i * ldg + j] : 0.0;
-    }
-    for (int e = tid; e < NR * H; e += J64_THREADS) {
-        const int r = e >> 5, k = e & 31;
-        ptab[e] = j64_index(r, 2 * k) | (j64_index(r, 2 * k + 1) << 8);
+    __shared__ double Ab[2][J64_ROWS][J64_LD];
+    __shared__ J64Shared sh;
+    __shared__ int rank_of[64];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < n * n; e += J64_THREADS) {
+        const int i = e / n, j = e % n;
+        Ab[0][i][j] = G[(int64_t)i * ldg + j];
     }
     __syncthreads();
-    const double tol = (double)n * 0x1p-53;
-    const double tol2 = tol * tol;
-    double trace = 0.0;
-    for (int i = 0; i < n; ++i) trace += Ab[0][i][i];
-    const double floor = floor_rel * fabs(trace);
-    const double floor2 = floor * floor;
-    // block wavefronts: slots b = 64 wave + lane + 192 t; b < 496 is block (k, l), k < l, in
-    // row-major order of the strict upper triangle, the rest read and write rows 64-68
-    unsigned ld[SPL][4], st[SPL][4];
-    int kt[SPL], lt[SPL];
-#pragma unroll
-    for (int t = 0; t < SPL; ++t) {
-        int b = 64 * (wave < BW ? wave : 0) + lane + 64 * BW * t;
-        if (b < NOFF) {
-            int k = 0;
-            while (b >= H - 1 - k) {
-                b -= H - 1 - k;
-                ++k;
-            }
-            const int l = k + 1 + b;
-            kt[t] = k;
-            lt[t] = l;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int x = 2 * k + (e >> 1), y = 2 * l + (e & 1);
-                ld[t][e] = j64_up(x, y);
-                st[t][e] = j64_up(j64_sigma(x), j64_sigma(y));
-            }
-        } else {
-            kt[t] = 0;
-            lt[t] = 0;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const unsigned spare = (unsigned)(M * (M + 1) + 4 * (b - NOFF) + e) * (unsigned)sizeof(double);
-                ld[t][e] = spare;
-                st[t][e] = spare;
-            }
-        }
-    }
-    const int kp = lane & (H - 1);
-    const unsigned o_pp = j64_up(2 * kp, 2 * kp), o_qq = j64_up(2 * kp + 1, 2 * kp + 1), o_pq = j64_up(2 * kp, 2 * kp + 1);
-    const int sp = j64_sigma(2 * kp), sq = j64_sigma(2 * kp + 1);
-    const unsigned s_pp = j64_up(sp, sp), s_qq = j64_up(sq, sq), s_pq = j64_up(sp, sq);
-    // eigenvector wavefront: row `lane` of W in slot order (slot = index at a sweep's start)
-    double w[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j) w[j] = (j == lane) ? 1.0 : 0.0;
     int sweeps = 0;
-    bool conv = false;
-    while (true) {
-        if (wave < BW) {
-            bool need = false;
-            double(*A)[M + 1] = Ab[cur];
-            for (int e = 64 * wave + lane; e < NR * H; e += 64 * BW) {
-                const int c = ptab[e], p = c & 255, q = c >> 8;
-                need = need || rot2_needed(A[p][p], A[q][q], A[min(p, q)][max(p, q)], tol2, floor2);
-            }
-            const bool any = __ballot(need) != 0;
-            if (lane == 0) need_s[wave] = any ? 1 : 0;
-        }
-        __syncthreads();
-        const bool need = (need_s[0] | need_s[1] | need_s[2]) != 0;
-        if (!need) {
-            conv = true;
-            break;
-        }
-        if (sweeps >= max_sweeps) break;
-        if (wave < BW) {
-            for (int round = 0; round < NR; ++round) {
-                char* const src = reinterpret_cast<char*>(&Ab[cur][0][0]);
-                char* const dst = reinterpret_cast<char*>(&Ab[cur ^ 1][0][0]);
-                auto at = [&](unsigned off) -> double& { return *reinterpret_cast<double*>(src + off); };
-                auto to = [&](unsigned off) -> double& { return *reinterpret_cast<double*>(dst + off); };
-                const double app = at(o_pp), aqq = at(o_qq), apq = at(o_pq);
-                double x[SPL][4];
-#pragma unroll
-                for (int t = 0; t < SPL; ++t)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) x[t][e] = at(ld[t][e]);
-                double c, s, dp, dq;
-                const bool rr = rot2(app, aqq, apq, tol2, floor2, c, s, dp, dq);
-                if (lane < H) {
-                    xch[wave][lane] = double2{c, s};
-                    if (wave == 0) rlog[round & 1][lane] = double2{c, s};
-                }
-                // no wait: a wavefront's LDS accesses complete in issue order
-                double y[SPL][4];
-#pragma unroll
-                for (int t = 0; t < SPL; ++t) {
-                    const double2 ck = xch[wave][kt[t]], cl = xch[wave][lt[t]];
-                    const double c1 = ck.x, s1 = ck.y, c2 = cl.x, s2 = cl.y;
-                    const double ra = c1 * x[t][0] - s1 * x[t][2], rb = c1 * x[t][1] - s1 * x[t][3];
-                    const double rc = s1 * x[t][0] + c1 * x[t][2], rd = s1 * x[t][1] + c1 * x[t][3];
-                    y[t][0] = c2 * ra - s2 * rb;
-                    y[t][1] = s2 * ra + c2 * rb;
-                    y[t][2] = c2 * rc - s2 * rd;
-                    y[t][3] = s2 * rc + c2 * rd;
-                }
-#pragma unroll
-                for (int t = 0; t < SPL; ++t)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) to(st[t][e]) = y[t][e];
-                if (wave == 0 && lane < H) {
-                    to(s_pp) = dp;
-                    to(s_qq) = dq;
-                    to(s_pq) = rr ? 0.0 : apq;
-                }
-                __syncthreads();  // the next buffer is complete; this one is free
-                cur ^= 1;
-            }
-        } else {
-            // unrolled by 7 (63 = 9 x 7): the register moves that bring the
-            // permuted columns back to the loop's registers come once per 7 rounds
-            for (int r7 = 0; r7 < NR; r7 += 7) {
-#pragma unroll
-                for (int u = 0; u < 7; ++u) {
-                    const int round = r7 + u;
-                    // this round's rotations: written before the round's barrier, rewritten
-                    // two rounds later, after this wavefront has passed the next barrier
-                    __syncthreads();
-                    const double2* lg = rlog[round & 1];
-                    double2 ca[8], cb[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        ca[j] = lg[j];
-                        cb[j] = lg[8 + j];
-                    }
-                    double wn[M];
-                    auto rotate8 = [&](const double2 (&cs)[8], int kb) {
-#pragma unroll
-                        for (int j = 0; j < 8; ++j) {
-                            const int k = kb + j;
-                            const double xv = w[2 * k], yv = w[2 * k + 1];
-                            wn[j64_sigma(2 * k)] = cs[j].x * xv - cs[j].y * yv;
-                            wn[j64_sigma(2 * k + 1)] = cs[j].y * xv + cs[j].x * yv;
-                        }
-                    };
-                    rotate8(ca, 0);
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) ca[j] = lg[16 + j];
-                    rotate8(cb, 8);
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) cb[j] = lg[24 + j];
-                    rotate8(ca, 16);
-                    rotate8(cb, 24);
-#pragma unroll
-                    for (int j = 0; j < M; ++j) w[j] = wn[j];
-                }
-            }
-        }
-        if (wave == BW) cur ^= NR & 1;
-        ++sweeps;
-    }
-    double(*A)[M + 1] = Ab[cur];
-    double(*W)[M + 1] = Ab[cur ^ 1];  // the eigenvectors, in the free buffer
-    if (wave == BW) {
-#pragma unroll
-        for (int j = 0; j < M; ++j) W[lane][j] = w[j];
-    }
-    __syncthreads();
-    // eigenvalues = diagonal (every index back in its own slot); descending, equal values by index
+    const bool conv = jacobi64_slots(n, max_sweeps, floor_rel, Ab[0], Ab[1], sh, Ab[0], sweeps);
     for (int i = tid; i < n; i += J64_THREADS) {
-        const double li = A[i][i];
+        const double li = sh.diag[i];
         int r = 0;
         for (int j = 0; j < n; ++j) {
-            const double lj = A[j][j];
+            const double lj = sh.diag[j];
             r += (lj > li) || (lj == li && j < i);
         }
         rank_of[i] = r;
     }
     __syncthreads();
-    for (int i = tid; i < n; i += J64_THREADS) lam[rank_of[i]] = A[i][i];  // unclamped (see select)
+    for (int i = tid; i < n; i += J64_THREADS) lam[rank_of[i]] = sh.diag[i];  // unclamped (see select)
     for (int idx = tid; idx < n * n; idx += J64_THREADS) {
         const int row = idx / n, i = idx % n;
-        V[(int64_t)row * ldv + rank_of[i]] = W[row][i];
+        V[(int64_t)row * ldv + rank_of[i]] = Ab[0][row][i];
     }
     if (tid == 0) {
         if (sweeps_out) *sweeps_out = sweeps;
