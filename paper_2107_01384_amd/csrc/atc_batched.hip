@@ -50,7 +50,7 @@ struct BatchSmem {
     union {
         struct {
             // Gram matrix, then the Jacobi iterate; V the eigenvectors.  The
-            // slot-order Jacobi (n > 32) uses both as its two buffers of
+            // slot-order Jacobi (n > 16) uses both as its two buffers of
             // J64_ROWS rows and leaves the eigenvectors in V.
             double A[J64_ROWS][APAD];
             double V[J64_ROWS][APAD];
@@ -249,19 +249,21 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
 // ---- cyclic Jacobi on sm.u.e.A (n <= 64) --------------------------------
 // The slot-order Jacobi as a call of its own: its eigenvector registers are
 // then not allocated next to the rest of the persistent kernel's state.
-__device__ __attribute__((noinline)) bool blk_jacobi64(int n, int max_sweeps, double (*A)[APAD], double (*V)[APAD],
-                                                       J64Shared* sh, int* sweeps) {
-    return jacobi64_slots(n, max_sweeps, 0x1p-53, A, V, *sh, V, *sweeps);
+template <int M>
+__device__ __attribute__((noinline)) bool blk_jacobi_slots(int n, int max_sweeps, double (*A)[APAD],
+                                                           double (*V)[APAD], J64Shared* sh, int* sweeps) {
+    return jacobi_slots<M>(n, max_sweeps, 0x1p-53, A, V, *sh, V, *sweeps);
 }
 
 template <int BK>
 __device__ bool blk_jacobi(int n, int max_sweeps, BatchSmem<BK>& sm) {
     const int tid = threadIdx.x;
     static_assert(APAD == J64_LD && BT == J64_THREADS, "slot-order Jacobi layout");
-    if (n > 32) {
-        // 33 <= n <= 64: the slot-order Jacobi (zero-padded to 64), same tests
+    if (n > 16) {
+        // 17 <= n <= 64: the slot-order Jacobi (zero-padded to 32 or 64), same tests
         int sweeps = 0;
-        const bool conv = blk_jacobi64(n, max_sweeps, sm.u.e.A, sm.u.e.V, &sm.j64, &sweeps);
+        const bool conv = n > 32 ? blk_jacobi_slots<64>(n, max_sweeps, sm.u.e.A, sm.u.e.V, &sm.j64, &sweeps)
+                                 : blk_jacobi_slots<32>(n, max_sweeps, sm.u.e.A, sm.u.e.V, &sm.j64, &sweeps);
         for (int i = tid; i < n; i += BT) {
             const double li = sm.j64.diag[i];
             int r = 0;
