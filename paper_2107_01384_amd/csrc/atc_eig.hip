@@ -793,7 +793,8 @@ __device__ __forceinline__ void select_factor_body(const SelectArgs& a, double* 
     sign_factor_from_v(a, r_s, sign_s);
 }
 
-__global__ __launch_bounds__(256) void k_select_factor(SelectArgs a) {
+// 512 threads: the sign rule takes one wavefront per column (8 in flight)
+__global__ __launch_bounds__(512) void k_select_factor(SelectArgs a) {
     __shared__ int r_s;
     __shared__ double red[17];
     __shared__ int sign_s[4096];
@@ -2035,7 +2036,7 @@ __global__ void k_zero(uint32_t* p, size_t words) {
 
 hipError_t launch_select_factor(const SelectArgs& a, hipStream_t st) {
     if (a.n > 4096) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_select_factor, dim3(1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_select_factor, dim3(1), dim3(512), 0, st, a);
     return hipGetLastError();
 }
 

@@ -117,6 +117,21 @@ def test_f32_parity_fields(shape, eps, precision):
         assert diff <= 0.2 * eps
 
 
+def test_f64_known_rank_padded_jacobi():
+    """Modes of 33, 47 and 64 in FP64 go to the 64 x 64 slot-order Jacobi (the
+    first two zero-padded to 64): the oracle's ranks, tails to 1e-12 of the
+    squared norm and the kept subspaces to 1e-10 in projector norm."""
+    x, _, _ = synth.known_rank_tucker((33, 47, 64), (5, 7, 9), seed=33, rel_noise=1e-3)
+    t_o = oracle.sthosvd(x, 1e-2, order=[0, 1, 2])
+    t_g = _run(x, 1e-2, torch.float64, order=[0, 1, 2])
+    log("padded Jacobi: ranks", t_g.ranks, "sweeps", t_g.eig_sweeps)
+    assert t_g.ranks == t_o.ranks == [5, 7, 9]
+    assert t_g.eig_path == [1, 1, 1]
+    for k in range(3):
+        assert abs(t_g.tails[k] - t_o.tails[k]) <= 1e-12 * t_o.norm2
+        assert projector_gap(np64(t_g.factors[k]), t_o.factors[k]) < 1e-10
+
+
 def test_dense_and_subspace_paths_agree():
     x = synth.field((90, 80, 70), 11)
     t_o = oracle.sthosvd(x, 1e-3)
