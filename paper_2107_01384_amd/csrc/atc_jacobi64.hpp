@@ -1,4 +1,4 @@
-// Jacobi rotations and the 64 x 64 slot-order Jacobi eigensolver, shared by
+// Jacobi rotations and the slot-order Jacobi eigensolver (32 x 32, 64 x 64), shared by
 // the single-matrix eigensolvers (atc_eig.hip) and the batched kernel
 // (atc_batched.hip).  The eigenvalues of the symmetric Gram matrix are those
 // of Algorithm 1 (Section 3.2); Jacobi is one way to reach them in FP64.
@@ -61,7 +61,7 @@ __device__ inline bool rot2(double app, double aqq, double apq, double tol2, dou
 // the test of all pairs; none passing ends the iteration.  Only the upper
 // triangle of A (in slot order) is read or written.
 constexpr int J64_LD = 65;    // row stride of the buffers (doubles)
-constexpr int J64_ROWS = 69;  // rows 64-68: targets of the unused block slots
+constexpr int J64_ROWS = 69;  // unused block slots write rows M.. (64-68 for M = 64, 32 for M = 32)
 constexpr int J64_THREADS = 256;
 
 // slot of cycle position j, cycle position of slot s != 0, next slot of s
@@ -82,7 +82,7 @@ struct J64Shared {
     int need_s[3];
 };
 
-// Called by all J64_THREADS threads of a workgroup, n <= M.  A0, A1: J64_ROWS
+// Called by every thread of a workgroup of J64_THREADS threads, n <= M.  A0, A1: J64_ROWS
 // x J64_LD doubles each; on entry A0 holds the symmetric n x n matrix (upper
 // triangle read; entries of the leading M x M outside n x n are cleared
 // here).  On return sh.diag[i] is the eigenvalue of index i, Wout (J64_LD
