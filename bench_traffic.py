@@ -9,7 +9,11 @@ N MiB once before timing): FETCH_SIZE has read half the copied bytes on this
 GPU, WRITE_SIZE all of them.
 
 Usage (from the repository root, after the two profiled runs):
-  python -m paper_2107_01384_amd.profiling FETCH_DB WRITE_DB KERNEL CALIB_MIB OUT_JSON "COMMAND"
+  python bench_traffic.py FETCH_DB WRITE_DB KERNEL CALIB_MIB OUT_JSON "COMMAND" [SOURCE]
+
+SOURCE is the kernel's source file (default: the tiled Gram kernels); its
+SHA-256 goes into the record so that bench.py drops the figure once the source
+changes.
 """
 from __future__ import annotations
 
@@ -65,7 +69,7 @@ def summarize(fetch_db, write_db, kernel, calib_mib, out_json, command, source_f
     fk, wk = kernel_rows(fr, kernel), kernel_rows(wr, kernel)
     fetch = sum(r[2] for r in fk) / len(fk) * 1024.0 * ff
     write = sum(r[2] for r in wk) / len(wk) * 1024.0 * wf
-    rec = {"kernel": kernel, "source": os.path.relpath(source_file, os.path.dirname(HERE)),
+    rec = {"kernel": kernel, "source": os.path.relpath(source_file, HERE),
            "source_sha256": source_digest(source_file),
            "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
            "traffic_bytes_per_launch": round(fetch + write),
@@ -78,9 +82,10 @@ def summarize(fetch_db, write_db, kernel, calib_mib, out_json, command, source_f
 
 
 if __name__ == "__main__":
-    if len(sys.argv) != 7:
+    if len(sys.argv) not in (7, 8):
         print(__doc__, file=sys.stderr)
         sys.exit(2)
-    fdb, wdb, kern, mib, out, cmd = sys.argv[1:]
-    src = os.path.join(HERE, "csrc", "atc_gram_kc.hip")
+    fdb, wdb, kern, mib, out, cmd = sys.argv[1:7]
+    src = sys.argv[7] if len(sys.argv) == 8 else os.path.join(HERE, "paper_2107_01384_amd", "csrc",
+                                                                "atc_gram_kc.hip")
     print(json.dumps(summarize(fdb, wdb, kern, int(mib), out, cmd, src)))

@@ -25,7 +25,10 @@
  *    hold unspecified values).  atc_last_error() returns a thread-local
  *    message describing the last failure of the calling thread.  No C++
  *    exception and no abort crosses this boundary.
- *  * Calls are re-entrant on different streams with different workspaces.
+ *  * Calls are re-entrant across host threads (each on its own stream with its
+ *    own workspace).  atc_sthosvd returns only once the calling thread has
+ *    learnt every rank, so one host thread runs its single-tensor calls one
+ *    after another; the batched and reconstruction calls never wait.
  */
 #ifndef ATC_H_
 #define ATC_H_
@@ -59,9 +62,12 @@ typedef enum { ATC_F32 = 0, ATC_F64 = 1 } atc_dtype;
  *  BF16X3 : float32 input only.  Each operand a is split into
  *           a_hi = bf16(a), a_lo = bf16(a - a_hi); a*b is formed on the bf16
  *           matrix cores as hi*hi + hi*lo + lo*hi with FP32 accumulation
- *           (chunks summed in FP64 as above).  Gram tiles on the diagonal add
- *           lo*lo as well, so the diagonal (where the dropped lo*lo term would
- *           always be positive) carries no bias.
+ *           (chunks summed in FP64 as above).  The dropped lo*lo term would
+ *           always be positive on the Gram diagonal: the tiled kernels of
+ *           modes with a contiguous trailing extent and the batched kernel
+ *           replace the diagonal by the exact FP64 sum of squares of the
+ *           loaded floats (in both precisions); the generic-layout kernel adds
+ *           lo*lo on its diagonal tiles instead.
  * The eigensolver, rank choice and every tail sum are FP64 in both cases. */
 typedef enum { ATC_PREC_NATIVE = 0, ATC_PREC_BF16X3 = 1 } atc_precision;
 
@@ -161,18 +167,23 @@ typedef struct atc_batch_plan atc_batch_plan;
  * Plans the ST-HOSVD of many independent 3-way float32 blocks in one
  * persistent launch (each block treated exactly as atc_sthosvd would with
  * precision BF16X3 or NATIVE, mode order by increasing length).
- *  dims     host array, nblocks x 3 mode sizes, each in [1, 64].
- *  The plan fixes: input offsets (blocks packed back to back in block order),
- *  core slots (prod(dims) floats per block) and factor slots (n_k^2 floats per
- *  mode), the longest-first processing order and the launch configuration.
+ *  dims           host array, nblocks x 3 mode sizes, each in [1, 64].
+ *  input_offsets  host array of nblocks element offsets (>= 0) of each block
+ *                 in the caller's input arena (row-major block, prod(dims)
+ *                 floats from there), or NULL for blocks packed back to back
+ *                 in block order.
+ *  The plan fixes: the input offsets, core slots (prod(dims) floats per
+ *  block) and factor slots (n_k^2 floats per mode), the longest-first
+ *  processing order and the launch configuration.
  * The plan owns device memory until atc_batch_plan_destroy.
  */
-atc_status atc_batch_plan_create(const int32_t* dims, int64_t nblocks, const atc_sthosvd_opts* opts,
-                                 atc_batch_plan** plan);
+atc_status atc_batch_plan_create(const int32_t* dims, const int64_t* input_offsets, int64_t nblocks,
+                                 const atc_sthosvd_opts* opts, atc_batch_plan** plan);
 void atc_batch_plan_destroy(atc_batch_plan* plan);
 
-/* Sizes in elements (float32) of the input arena, core arena and factor
- * arena, and the workspace bytes; any pointer may be NULL. */
+/* Sizes in elements (float32) of the input arena (the end of the last block),
+ * core arena and factor arena, and the workspace bytes; any pointer may be
+ * NULL. */
 atc_status atc_batch_plan_info(const atc_batch_plan* plan, int64_t* input_elems, int64_t* core_elems,
                                int64_t* factor_elems, size_t* workspace_bytes);
 
@@ -248,6 +259,13 @@ const char* atc_status_string(atc_status s);
 const char* atc_last_error(void);
 /* Library version string, e.g. "atc-mi355x 0.1 gfx950". */
 const char* atc_version(void);
+
+/* Releases what the library holds for the calling thread outside plans and
+ * graphs: the pinned host block atc_sthosvd's selection kernels report ranks
+ * into and the HIP events of opts.profile.  Call once the thread's work on
+ * its streams has completed (e.g. before the process exits, while the HIP
+ * runtime is still up); a later call re-creates them.  Idempotent. */
+void atc_finalize(void);
 
 #ifdef __cplusplus
 }

@@ -218,6 +218,10 @@ def sthosvd(x, eps: float, order=None, rtmss: float = 1.0, rule: str = "adaptive
 
     x: array of any real dtype (converted to float64, exact for float32).
     eps: target relative error |A - A~| / |A| (Section 2.1, relative error).
+    fixed_ranks: per natural mode, a rank to keep instead of the budget rule, or
+    None for that mode to use the rule (the remaining budget is then shared as
+    usual, so a boundary-degenerate rank of another implementation can be
+    followed through the later modes).
     Returns a Tucker record: core (natural mode order), factors U_k (n_k x r_k).
     """
     if rule not in ("adaptive", "equal"):
@@ -246,7 +250,7 @@ def sthosvd(x, eps: float, order=None, rtmss: float = 1.0, rule: str = "adaptive
             b = (budget_total - used) / (d - i)
         else:
             b = budget_total / d
-        if fixed_ranks is not None:
+        if fixed_ranks is not None and fixed_ranks[k] is not None:
             r = int(fixed_ranks[k])
             r_tail = float(tail_sums(lam)[r])
         else:

@@ -14,6 +14,7 @@ Entry points (same names as the C ABI, minus the ``atc_`` prefix):
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -79,7 +80,7 @@ SIGNATURES = [
     ("atc_default_opts", None, [_P(Opts)]),
     ("atc_sthosvd_workspace_size", _SZ, [_P(Shape), _P(Opts)]),
     ("atc_sthosvd", _I32, [_VP, _P(Shape), _P(Opts), _VP, _P(_VP), _P(Result), _VP, _SZ, _VP]),
-    ("atc_batch_plan_create", _I32, [_P(_I32), _I64, _P(Opts), _P(_VP)]),
+    ("atc_batch_plan_create", _I32, [_P(_I32), _P(_I64), _I64, _P(Opts), _P(_VP)]),
     ("atc_batch_plan_destroy", None, [_VP]),
     ("atc_batch_plan_info", _I32, [_VP, _P(_I64), _P(_I64), _P(_I64), _P(_SZ)]),
     ("atc_batch_plan_offsets", _I32, [_VP, _P(_I64), _P(_I64), _P(_I64)]),
@@ -95,6 +96,7 @@ SIGNATURES = [
     ("atc_status_string", ctypes.c_char_p, [_I32]),
     ("atc_last_error", ctypes.c_char_p, []),
     ("atc_version", ctypes.c_char_p, []),
+    ("atc_finalize", None, []),
 ]
 
 _lib = None
@@ -113,7 +115,20 @@ def load(path: str = LIB_PATH):
         f.restype = res
         f.argtypes = args
     _lib = lib
+    atexit.register(_finalize)
     return lib
+
+
+def _finalize():
+    """At interpreter exit, before the HIP runtime shuts down: wait for the
+    device, then release the pinned report block and events of this thread."""
+    if _lib is None:
+        return
+    try:
+        if torch.cuda.is_initialized():
+            torch.cuda.synchronize()
+    finally:
+        _lib.atc_finalize()
 
 
 def _check(status: int):

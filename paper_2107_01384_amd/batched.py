@@ -14,14 +14,22 @@ class BatchPlan:
     """Owns an atc_batch_plan (block offsets, slots, processing order, launch choice)."""
 
     def __init__(self, dims, rel_error: float = 1e-3, precision: str = "bf16x3", rule: str = "adaptive",
-                 max_sweeps: int = 0):
+                 max_sweeps: int = 0, input_offsets=None):
+        """input_offsets: element offset of each block in the input arena (None:
+        blocks packed back to back in block order)."""
         lib = load()
         dims = np.ascontiguousarray(np.asarray(dims, dtype=np.int32).reshape(-1, 3))
         self.dims = dims
         self.nblocks = int(dims.shape[0])
         self.opts = make_opts(rel_error, precision, None, 1.0, rule, None, max_sweeps, 0)
+        offp = None
+        if input_offsets is not None:
+            self._offsets_in = np.ascontiguousarray(np.asarray(input_offsets, dtype=np.int64).reshape(-1))
+            if self._offsets_in.shape[0] != self.nblocks:
+                raise ValueError("input_offsets needs one entry per block")
+            offp = self._offsets_in.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
         h = ctypes.c_void_p()
-        _check(lib.atc_batch_plan_create(dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), self.nblocks,
+        _check(lib.atc_batch_plan_create(dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), offp, self.nblocks,
                                          ctypes.byref(self.opts), ctypes.byref(h)))
         self.handle = h
         ie, ce, fe = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

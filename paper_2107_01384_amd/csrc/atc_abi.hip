@@ -185,6 +185,12 @@ struct StreamTimer {
         return ok = hipEventRecord(a, st) == hipSuccess;
     }
     void stop(hipStream_t st) { ok = ok && hipEventRecord(b, st) == hipSuccess; }
+    void release() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        a = b = nullptr;
+        ok = false;
+    }
     double elapsed() const {
         float ms = 0.f;
         if (ok) (void)hipEventElapsedTime(&ms, a, b);
@@ -208,6 +214,12 @@ struct PhaseEvents {
         ready = true;
         return true;
     }
+    void release() {
+        if (!ready) return;
+        for (int i = 0; i < ATC_MAX_DIMS; ++i)
+            for (int j = 0; j < PER_MODE; ++j) (void)hipEventDestroy(ev[i][j]);
+        ready = false;
+    }
 };
 thread_local PhaseEvents g_phase;
 
@@ -230,6 +242,10 @@ struct PinnedFlags {
         d = (HostFlags*)dp;
         memset(h, 0, sizeof(*h));
         return true;
+    }
+    void release() {
+        if (h) (void)hipHostFree(h);
+        h = d = nullptr;
     }
 };
 thread_local PinnedFlags g_flags;
@@ -255,6 +271,10 @@ double event_ms(hipEvent_t a, hipEvent_t b) {
 }
 
 }  // namespace
+
+namespace atc {
+void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
+}  // namespace atc
 
 extern "C" {
 
@@ -845,11 +865,7 @@ atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks
             std::vector<int> last{n};
             const void* outp;
             // shrink T_n in mode n straight into dcore
-            const void* srcT = Tn;
-            if (srcT == bufs[1] || srcT == bufs[2] || srcT == bufs[0]) {
-                // copy-free: the chain reads srcT and writes dcore
-            }
-            e = shrink_chain(srcT, cur, last, dcore, &outp);
+            e = shrink_chain(Tn, cur, last, dcore, &outp);
             if (e != ATC_OK) return e;
         }
     }
@@ -892,6 +908,12 @@ const char* atc_status_string(atc_status s) {
 }
 
 const char* atc_last_error(void) { return g_last_error.c_str(); }
+
+void atc_finalize(void) {
+    g_flags.release();
+    g_phase.release();
+    g_timer.release();
+}
 
 const char* atc_version(void) { return "atc-mi355x 0.1 gfx950"; }
 

@@ -139,6 +139,11 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
             acc[a][b] = f32x4{0, 0, 0, 0};
             acc64[a][b] = f64x4{0, 0, 0, 0};
         }
+    // exact diagonal: FP64 sums of squares of the loaded floats, one per
+    // staging slot (row, kk) this thread fills (the same slots every step)
+    double dsq[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) dsq[e] = 0.0;
     constexpr int FLUSH_STEPS = FLUSH_TERMS / BK;
     int since = 0;
     for (int64_t s = 0; s < steps; ++s) {
@@ -164,6 +169,7 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
                 off = (l * n + row) * R + sr[e];
             }
             if (in) v = Y[off];
+            dsq[e] = fma((double)v, (double)v, dsq[e]);
             if (sok[e]) {
                 if (P == PREC_BF16X3) {
                     const __bf16 h = (__bf16)v;
@@ -194,7 +200,6 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
                         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
                         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
                         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bl[b], acc[a][b], 0, 0, 0);
                     }
             }
         } else {
@@ -237,11 +242,26 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
                 const int j = wc + b * 16 + (lane & 15);
                 sm.u.e.A[i][j] = acc64[a][b][v] + (double)acc[a][b][v];
             }
+    // per-slot squares into V (free until the eigensolver), laid out as the
+    // staging slots: row i's are D[i * BK + kk]
+    double* D = &sm.u.e.V[0][0];
+    static_assert(BMAX * BK <= J64_ROWS * APAD, "diagonal partials fit in V");
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if (sok[e]) D[srow[e] * BK + skk[e]] = dsq[e];
     __syncthreads();
-    // exact symmetry: the upper triangle wins
+    // exact symmetry: the upper triangle wins; the diagonal is the exact sum
+    // of squares (the products' rounding and the dropped lo*lo term of the
+    // split would otherwise bias every discarded-energy sum by the trace error)
+    const int kmax = LAYOUT == LAYOUT_SR ? planes * (int)R : BK;  // SR slots past the planes stay unwritten
     for (int idx = tid; idx < n * n; idx += BT) {
         const int i = idx / n, j = idx % n;
         if (i > j) sm.u.e.A[i][j] = sm.u.e.A[j][i];
+    }
+    if (tid < n) {
+        double d = 0.0;
+        for (int kk = 0; kk < kmax; ++kk) d += D[tid * BK + kk];
+        sm.u.e.A[tid][tid] = d;
     }
     __syncthreads();
 }
@@ -726,7 +746,6 @@ struct atc_graph {
 
 namespace {
 
-thread_local std::string g_batch_error;
 
 struct Candidate {
     int bk;
@@ -769,7 +788,7 @@ hipError_t launch_batched(const atc_batch_plan* p, int cand, const float* arena,
 }
 
 atc_status bfail(atc_status s, const char* msg) {
-    g_batch_error = msg;
+    set_last_error(msg);  // read back through atc_last_error()
     return s;
 }
 
@@ -789,8 +808,8 @@ std::string tune_key(const atc_batch_plan* p) {
 
 extern "C" {
 
-atc_status atc_batch_plan_create(const int32_t* dims, int64_t nblocks, const atc_sthosvd_opts* opts,
-                                 atc_batch_plan** plan) {
+atc_status atc_batch_plan_create(const int32_t* dims, const int64_t* input_offsets, int64_t nblocks,
+                                 const atc_sthosvd_opts* opts, atc_batch_plan** plan) {
     if (!plan) return bfail(ATC_ERR_INVALID_ARGUMENT, "plan is NULL");
     *plan = nullptr;
     if (!dims || nblocks < 1 || !opts) return bfail(ATC_ERR_INVALID_ARGUMENT, "dims, nblocks and opts required");
@@ -804,6 +823,9 @@ atc_status atc_batch_plan_create(const int32_t* dims, int64_t nblocks, const atc
         return bfail(ATC_ERR_UNSUPPORTED, "batched blocks use the default order and the budget rule");
     for (int64_t i = 0; i < 3 * nblocks; ++i)
         if (dims[i] < 1 || dims[i] > BMAX) return bfail(ATC_ERR_UNSUPPORTED, "block modes must lie in [1, 64]");
+    if (input_offsets)
+        for (int64_t b = 0; b < nblocks; ++b)
+            if (input_offsets[b] < 0) return bfail(ATC_ERR_INVALID_ARGUMENT, "negative input offset");
     atc_batch_plan* p = new (std::nothrow) atc_batch_plan();
     if (!p) return bfail(ATC_ERR_INTERNAL, "out of host memory");
     p->nblocks = nblocks;
@@ -817,14 +839,15 @@ atc_status atc_batch_plan_create(const int32_t* dims, int64_t nblocks, const atc
     p->core_off.resize(nblocks);
     p->fac_off.resize(nblocks);
     std::vector<BlockDesc> desc(nblocks);
-    int64_t io = 0, co = 0, fo = 0, maxsize = 1;
+    int64_t io = 0, co = 0, fo = 0, maxsize = 1, in_end = 0;
     for (int64_t b = 0; b < nblocks; ++b) {
         const int64_t n0 = dims[3 * b], n1 = dims[3 * b + 1], n2 = dims[3 * b + 2];
         const int64_t sz = n0 * n1 * n2;
-        p->in_off[b] = io;
+        const int64_t ib = input_offsets ? input_offsets[b] : io;  // caller's placement, else back to back
+        p->in_off[b] = ib;
         p->core_off[b] = co;
         p->fac_off[b] = fo;
-        desc[b].in_off = io;
+        desc[b].in_off = ib;
         desc[b].core_off = co;
         desc[b].fac_off = fo;
         desc[b].dims[0] = (int32_t)n0;
@@ -835,8 +858,9 @@ atc_status atc_batch_plan_create(const int32_t* dims, int64_t nblocks, const atc
         co += sz;
         fo += n0 * n0 + n1 * n1 + n2 * n2;
         maxsize = std::max(maxsize, sz);
+        in_end = std::max(in_end, ib + sz);
     }
-    p->in_elems = io;
+    p->in_elems = in_end;
     p->core_elems = co;
     p->fac_elems = fo;
     p->scratch_elems = (maxsize + 63) / 64 * 64;

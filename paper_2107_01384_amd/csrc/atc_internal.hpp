@@ -245,6 +245,9 @@ hipError_t run_subspace64_select(const double* G, int n, int max_sweeps, double*
 hipError_t launch_prepare_matrix(int prec, const void* U, int src_f64, int rows, int cols, int transpose,
                                  double* M64, float* M32, __bf16* Mh, __bf16* Ml, hipStream_t st);
 
+// Message returned by atc_last_error() on the calling thread.
+void set_last_error(const char* msg);
+
 // Zeroes n bytes with a kernel (capturable in a graph, unlike memset nodes).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 
