@@ -68,8 +68,13 @@ typedef enum { ATC_F32 = 0, ATC_F64 = 1 } atc_dtype;
  *           replace the diagonal by the exact FP64 sum of squares of the
  *           loaded floats (in both precisions); the generic-layout kernel adds
  *           lo*lo on its diagonal tiles instead.
- * The eigensolver, rank choice and every tail sum are FP64 in both cases. */
-typedef enum { ATC_PREC_NATIVE = 0, ATC_PREC_BF16X3 = 1 } atc_precision;
+ *  F64ACC : float32 input only: the 64-bit internal arithmetic option
+ *           (Section 5) for the Gram matrix, where the error target asks for
+ *           more than an FP32-accumulated Gram matrix holds (eps <= 1e-4):
+ *           operands widened to FP64, exact products, FP64 accumulation on
+ *           the FP64 matrix cores.  Projections stay FP32.
+ * The eigensolver, rank choice and every tail sum are FP64 in all cases. */
+typedef enum { ATC_PREC_NATIVE = 0, ATC_PREC_BF16X3 = 1, ATC_PREC_F64ACC = 2 } atc_precision;
 
 /* Per-mode share of the SSE budget S = rtmss * (rel_error * |A|)^2
  * (Section 4.1.3; the paper defers the rule to the ST-HOSVD literature).

@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(HERE, "libatc.so")
 MAX_DIMS = 8
 
 ATC_F32, ATC_F64 = 0, 1
-PRECISIONS = {"native": 0, "bf16x3": 1}
+PRECISIONS = {"native": 0, "bf16x3": 1, "f64acc": 2}
 RULES = {"adaptive": 0, "equal": 1}
 STATUS = {
     0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small", -4: "device error",

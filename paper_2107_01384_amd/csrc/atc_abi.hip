@@ -79,10 +79,12 @@ atc_status check_opts(const atc_shape* s, const atc_sthosvd_opts* o) {
     if (!(o->rel_error >= 0.0) || !std::isfinite(o->rel_error))
         return fail(ATC_ERR_INVALID_ARGUMENT, "rel_error must be finite and >= 0");
     if (!(o->rtmss >= 0.0 && o->rtmss <= 1.0)) return fail(ATC_ERR_INVALID_ARGUMENT, "rtmss must lie in [0, 1]");
-    if (o->precision != ATC_PREC_NATIVE && o->precision != ATC_PREC_BF16X3)
+    if (o->precision != ATC_PREC_NATIVE && o->precision != ATC_PREC_BF16X3 && o->precision != ATC_PREC_F64ACC)
         return fail(ATC_ERR_INVALID_ARGUMENT, "unknown precision %d", o->precision);
     if (o->precision == ATC_PREC_BF16X3 && s->dtype != ATC_F32)
         return fail(ATC_ERR_UNSUPPORTED, "BF16X3 precision needs float32 input");
+    if (o->precision == ATC_PREC_F64ACC && s->dtype != ATC_F32)
+        return fail(ATC_ERR_UNSUPPORTED, "F64ACC precision needs float32 input (float64 input is FP64 throughout)");
     if (o->rank_rule != ATC_RANK_ADAPTIVE && o->rank_rule != ATC_RANK_EQUAL)
         return fail(ATC_ERR_INVALID_ARGUMENT, "unknown rank rule %d", o->rank_rule);
     if (o->max_sweeps < 0) return fail(ATC_ERR_INVALID_ARGUMENT, "max_sweeps < 0");
@@ -112,10 +114,15 @@ void processing_order(const atc_shape* s, const atc_sthosvd_opts* o, int* order)
         std::stable_sort(order, order + d, [&](int a, int b) { return s->dims[a] < s->dims[b]; });
 }
 
+// Arithmetic of the Gram matrices
 int prec_of(const atc_shape* s, const atc_sthosvd_opts* o) {
     if (s->dtype == ATC_F64) return PREC_F64;
+    if (o->precision == ATC_PREC_F64ACC) return PREC_F64ACC;
     return o->precision == ATC_PREC_BF16X3 ? PREC_BF16X3 : PREC_F32;
 }
+
+// Arithmetic of the mode products (projections): F64ACC projects in FP32
+int ttm_prec_of(int gram_prec) { return gram_prec == PREC_F64ACC ? PREC_F32 : gram_prec; }
 
 size_t part_capacity(int nmax) {
     const size_t t = (size_t)ceil_div(nmax, TILE);
@@ -276,7 +283,7 @@ namespace atc {
 void set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
 }  // namespace atc
 
-extern "C" {
+// The entry points below keep the C linkage of their declarations in atc.h.
 
 void atc_default_opts(atc_sthosvd_opts* o) {
     if (!o) return;
@@ -308,7 +315,8 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
     SthosvdWs w;
     carve_sthosvd(shape, (char*)workspace, &w);
     hipStream_t st = (hipStream_t)stream;
-    const int prec = prec_of(shape, opts);
+    const int gprec = prec_of(shape, opts);
+    const int prec = ttm_prec_of(gprec);  // projections (and their operand copies)
     const bool f64 = shape->dtype == ATC_F64;
     const int max_sweeps = opts->max_sweeps > 0 ? opts->max_sweeps : DEFAULT_SWEEPS;
     int order[ATC_MAX_DIMS];
@@ -335,23 +343,23 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         const int64_t L = prod(cur, 0, k), R = prod(cur, k + 1, d);
         const int n = (int)cur[k];
         GramKcPlan kp{};
-        if (gram_kc_applicable(prec, R)) kp = gram_kc_plan(prec, L, n, R, w.part_cap, w.dpart_cap);
+        if (gram_kc_applicable(gprec, R)) kp = gram_kc_plan(gprec, L, n, R, w.part_cap, w.dpart_cap);
         if (kp.ok) {
             HIP_TRY(mark(i, 0));
-            HIP_TRY(launch_gram_kc(prec, kp, (const float*)src, (float*)w.part, w.dpart, st));
+            HIP_TRY(launch_gram_kc(gprec, kp, (const float*)src, (float*)w.part, w.dpart, st));
             HIP_TRY(mark(i, 1));
             HIP_TRY(launch_gram_kc_reduce(kp, (const float*)w.part, w.dpart, w.G, st));
             HIP_TRY(mark(i, 2));
-        } else if (gram_tall_applicable(prec, n, R) && reinterpret_cast<uintptr_t>(src) % 16 == 0) {
+        } else if (gram_tall_applicable(gprec, n, R) && reinterpret_cast<uintptr_t>(src) % 16 == 0) {
             // short last mode: FP64 MFMA over rows streamed through LDS (reduction included)
             HIP_TRY(mark(i, 0));
             HIP_TRY(launch_gram_tall((const float*)src, n, L, w.part, w.part_cap, w.G, st));
             HIP_TRY(mark(i, 1));
             HIP_TRY(mark(i, 2));
         } else {
-            const GramPlan gp = gram_plan(prec, L, n, n, R, true, w.part_cap);
+            const GramPlan gp = gram_plan(gprec, L, n, n, R, true, w.part_cap);
             HIP_TRY(mark(i, 0));
-            HIP_TRY(launch_gram(prec, gp, src, src, w.part, st));
+            HIP_TRY(launch_gram(gprec, gp, src, src, w.part, st));
             HIP_TRY(mark(i, 1));
             HIP_TRY(launch_gram_reduce(gp, w.part, w.G, st));
             HIP_TRY(mark(i, 2));
@@ -378,6 +386,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         sa.Mtl = prec == PREC_BF16X3 ? w.Mtl : nullptr;
         sa.guard = SUBSPACE_GUARD;
         sa.hflags = g_flags.d;
+        sa.publish_late = i == d - 1 ? 1 : 0;
         int32_t* sweeps_dev = &w.book->sweeps[k];
         int32_t* ok_dev = &w.book->eig_ok;
 
@@ -627,6 +636,14 @@ size_t carve_recon(const atc_shape* s, const int64_t* ranks, char* base, void** 
 }
 
 }  // namespace
+
+namespace atc {
+atc_status check_recon_args(const atc_shape* s, const int64_t* ranks) {
+    atc_status st = check_shape(s);
+    return st != ATC_OK ? st : check_ranks(s, ranks);
+}
+void recon_order(const atc_shape* s, const int64_t* ranks, int* order) { best_order(s->dims, ranks, s->ndim, order); }
+}  // namespace atc
 
 size_t atc_reconstruct_workspace_size(const atc_shape* shape, const int64_t* ranks) {
     if (check_shape(shape) != ATC_OK || check_ranks(shape, ranks) != ATC_OK) return 0;
@@ -917,4 +934,3 @@ void atc_finalize(void) {
 
 const char* atc_version(void) { return "atc-mi355x 0.1 gfx950"; }
 
-}  // extern "C"

@@ -1587,10 +1587,13 @@ struct Sub32Grid {
 // polls until `target` arrivals, then makes the other workgroups' stores
 // visible (acquire).  The wait is bounded: a workgroup that gives up records
 // it and goes on, so every wavefront still reaches the end of the kernel.
-__device__ __forceinline__ void grid_sync(unsigned* sync, unsigned target, unsigned spin_limit) {
+// Returns true in every thread of a workgroup whose wait gave up.
+__device__ __forceinline__ bool grid_sync(unsigned* sync, unsigned target, unsigned spin_limit) {
+    __shared__ int gave;
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
     if (threadIdx.x == 0) {
+        gave = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_fetch_add(&sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         unsigned spins = 0;
@@ -1599,12 +1602,14 @@ __device__ __forceinline__ void grid_sync(unsigned* sync, unsigned target, unsig
             __builtin_amdgcn_s_sleep(1);
             if (++spins > spin_limit) {
                 __hip_atomic_store(&sync[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                gave = 1;
                 break;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
+    return gave != 0;
 }
 
 // End of a cooperative launch: the last workgroup to finish clears the
@@ -1614,9 +1619,9 @@ __device__ __forceinline__ void grid_exit(unsigned* sync) {
     if (threadIdx.x == 0) {
         const unsigned done = __hip_atomic_fetch_add(&sync[4], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (done + 1 == gridDim.x) {
-            __hip_atomic_store(&sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sync[3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&sync[4], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // the rank words too: a workgroup that reads them after a wait that
+            // gave up then finds 0 (nothing to write), never a previous mode's
+            for (int w = 0; w < 5; ++w) __hip_atomic_store(&sync[w], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -1627,9 +1632,10 @@ struct GridCtx {
     int n, b, nb, row0, nr;
     unsigned arrivals;  // barriers passed so far times nb
     int parity;         // partial set of the next exchange
+    bool gave_up;       // one of this workgroup's waits gave up
     __device__ void sync() {
         arrivals += (unsigned)nb;
-        grid_sync(g.sync, arrivals, g.spin_limit);
+        gave_up = grid_sync(g.sync, arrivals, g.spin_limit) || gave_up;
     }
 };
 
@@ -1820,6 +1826,7 @@ __device__ __forceinline__ void sub32_grid_body(const double* __restrict__ G, in
     x.nr = min(GRID_ROWS, n - x.row0);
     x.arrivals = 0;
     x.parity = 0;
+    x.gave_up = false;
     DevBook* bk = a.book;
     double tr = 0.0;
     if (x.b == 0) tr = gram_trace(a, red);
@@ -1890,7 +1897,7 @@ __device__ __forceinline__ void sub32_grid_body(const double* __restrict__ G, in
         bk->sweeps[a.k] = sw;
         bk->eig_ok = cv ? 1 : 0;
         if (__hip_atomic_load(&g.sync[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) bk->status = ATC_ERR_INTERNAL;
-        choose_rank(al, tr, r_s, dense_s);
+        choose_rank(al, tr, r_s, dense_s, !a.publish_late);
         __hip_atomic_store(&g.sync[1], (unsigned)r_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&g.sync[2], (unsigned)dense_s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1940,6 +1947,18 @@ __device__ __forceinline__ void sub32_grid_body(const double* __restrict__ G, in
         gc[2] = (double)c.row;
     }
     x.sync();
+    if (x.gave_up) {
+        // this workgroup may hold a stale rank and the other workgroups'
+        // candidates may be missing: write nothing, record the failure (the
+        // host reads it with the next report, or below for the last mode)
+        if (tid == 0) bk->status = ATC_ERR_INTERNAL;
+    }
+    if (a.publish_late && x.b == 0 && tid == 0) {
+        if (x.gave_up || __hip_atomic_load(&g.sync[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            bk->status = ATC_ERR_INTERNAL;
+        publish_selection(al, r_s);
+    }
+    if (x.gave_up) return;
     const int r = (int)__hip_atomic_load(&g.sync[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int dense = (int)__hip_atomic_load(&g.sync[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (dense) return;
@@ -2180,6 +2199,7 @@ __device__ __forceinline__ void sub64_grid_body(const double* __restrict__ G, in
     x.nr = min(GRID_ROWS, n - x.row0);
     x.arrivals = 0;
     x.parity = 0;
+    x.gave_up = false;
     const int64_t ro = (int64_t)x.row0 * S32;
     gx_rows32<true>(x, G, nullptr, 0x5eed, Pa, part_lds);
     gx_rows32<true>(x, G, nullptr, 0x64b5eed, Pb, part_lds);

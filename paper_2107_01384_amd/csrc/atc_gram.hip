@@ -10,6 +10,8 @@
 // of K steps (split-K).  Each step stages a 64 x BK slab of both operands in
 // LDS; each wave computes a 32 x 32 quarter with 16 x 16 MFMA blocks.
 //   PREC_F64   : v_mfma_f64_16x16x4f64, FP64 accumulation.
+//   PREC_F64ACC: float32 input widened to FP64 in LDS, then as PREC_F64
+//                (every product exact, FP64 accumulation).
 //   PREC_F32   : v_mfma_f32_16x16x4f32, FP32 accumulation flushed into FP64
 //                registers every FLUSH_TERMS contracted terms.
 //   PREC_BF16X3: operands split on load into bf16 hi + lo; products
@@ -20,6 +22,8 @@
 // Each workgroup writes its FP64 partial tile; a second kernel sums the splits
 // in a fixed order, so the result is bit-reproducible.
 #include "atc_internal.hpp"
+
+#include <type_traits>
 
 namespace atc {
 namespace {
@@ -43,6 +47,7 @@ template <> struct GramSmem<PREC_F64> {
     double x[TILE][KDepth<PREC_F64>::value + 1];
     double y[TILE][KDepth<PREC_F64>::value + 1];
 };
+template <> struct GramSmem<PREC_F64ACC> : GramSmem<PREC_F64> {};
 template <> struct GramSmem<PREC_F32> {
     float x[TILE][KDepth<PREC_F32>::value + 1];
     float y[TILE][KDepth<PREC_F32>::value + 1];
@@ -115,7 +120,8 @@ __global__ __launch_bounds__(NTHREADS) void k_gram(const typename ElemOf<P>::T* 
                                                    int ny, int64_t L, int64_t R, int64_t steps, int nsplit,
                                                    int tiles_x, int tiles_y, int npairs, int planes,
                                                    double* __restrict__ part) {
-    using T = typename ElemOf<P>::T;
+    using T = typename ElemOf<P>::T;                                   // input element
+    using S = typename std::conditional<prec_f64_mfma(P), double, T>::type;  // LDS / MFMA operand
     constexpr int BK = KDepth<P>::value;
     constexpr int E = TILE * BK / NTHREADS;
     __shared__ GramSmem<P> sm;
@@ -150,7 +156,7 @@ __global__ __launch_bounds__(NTHREADS) void k_gram(const typename ElemOf<P>::T* 
                 sm.xh[rr][kk] = (__bf16)0.0f; sm.xl[rr][kk] = (__bf16)0.0f;
                 sm.yh[rr][kk] = (__bf16)0.0f; sm.yl[rr][kk] = (__bf16)0.0f;
             } else {
-                sm.x[rr][kk] = (T)0; sm.y[rr][kk] = (T)0;
+                sm.x[rr][kk] = (S)0; sm.y[rr][kk] = (S)0;
             }
         }
     }
@@ -191,8 +197,8 @@ __global__ __launch_bounds__(NTHREADS) void k_gram(const typename ElemOf<P>::T* 
                         sm.yl[q.row][q.kk] = (__bf16)(vy - (float)yh);
                     }
                 } else {
-                    sm.x[q.row][q.kk] = vx;
-                    if (!diag) sm.y[q.row][q.kk] = vy;
+                    sm.x[q.row][q.kk] = (S)vx;
+                    if (!diag) sm.y[q.row][q.kk] = (S)vy;
                 }
             }
         }
@@ -232,7 +238,7 @@ __global__ __launch_bounds__(NTHREADS) void k_gram(const typename ElemOf<P>::T* 
 #pragma unroll
             for (int k4 = 0; k4 < BK; k4 += 4) {
                 const int kk = k4 + (lane >> 4);
-                T av[2], bv[2];
+                S av[2], bv[2];
 #pragma unroll
                 for (int a = 0; a < 2; ++a) av[a] = sm.x[wr + a * 16 + (lane & 15)][kk];
 #pragma unroll
@@ -242,14 +248,14 @@ __global__ __launch_bounds__(NTHREADS) void k_gram(const typename ElemOf<P>::T* 
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
                     for (int b = 0; b < 2; ++b) {
-                        if constexpr (P == PREC_F64)
+                        if constexpr (prec_f64_mfma(P))
                             acc64[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc64[a][b], 0, 0, 0);
                         else
                             acc32[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc32[a][b], 0, 0, 0);
                     }
             }
         }
-        if constexpr (P != PREC_F64) {
+        if constexpr (!prec_f64_mfma(P)) {
             if (++since_flush == FLUSH_STEPS) {
                 since_flush = 0;
 #pragma unroll
@@ -263,7 +269,7 @@ __global__ __launch_bounds__(NTHREADS) void k_gram(const typename ElemOf<P>::T* 
             }
         }
     }
-    if constexpr (P != PREC_F64) {
+    if constexpr (!prec_f64_mfma(P)) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -327,7 +333,7 @@ hipError_t launch_gram_p(const GramPlan& g, const void* X, const void* Y, double
 
 GramPlan gram_plan(int prec, int64_t L, int nx, int ny, int64_t R, bool sym, size_t part_capacity_bytes) {
     GramPlan g{};
-    const int BK = prec == PREC_F64 ? KDepth<PREC_F64>::value : KDepth<PREC_F32>::value;
+    const int BK = prec_f64_mfma(prec) ? KDepth<PREC_F64>::value : KDepth<PREC_F32>::value;
     g.L = L;
     g.R = R;
     g.nx = nx;
@@ -370,6 +376,7 @@ hipError_t launch_gram(int prec, const GramPlan& g, const void* X, const void* Y
     switch (prec) {
         case PREC_F64: return launch_gram_p<PREC_F64>(g, X, Y, part, st);
         case PREC_F32: return launch_gram_p<PREC_F32>(g, X, Y, part, st);
+        case PREC_F64ACC: return launch_gram_p<PREC_F64ACC>(g, X, Y, part, st);
         default: return launch_gram_p<PREC_BF16X3>(g, X, Y, part, st);
     }
 }

@@ -536,7 +536,9 @@ __global__ __launch_bounds__(256) void k_gram_kc_reduce(const float* __restrict_
 
 }  // namespace
 
-bool gram_kc_applicable(int prec, int64_t R) { return prec != PREC_F64 && R >= KC_BK && R % 4 == 0; }
+bool gram_kc_applicable(int prec, int64_t R) {
+    return (prec == PREC_F32 || prec == PREC_BF16X3) && R >= KC_BK && R % 4 == 0;
+}
 
 GramKcPlan gram_kc_plan(int prec, int64_t L, int n, int64_t R, size_t part_capacity_bytes,
                         size_t dpart_capacity_bytes) {

@@ -16,7 +16,10 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Arithmetic of a contraction (Gram matrix or mode product).
-enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
+//  PREC_F64ACC: float32 operands widened to FP64 on their way to LDS, FP64
+//  MFMA products and accumulation (the Gram matrix of float32 data to FP64
+//  accuracy); the mode products of that path run as PREC_F32.
+enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2, PREC_F64ACC = 3 };
 
 // How the contracted index of an (L, n, R) view is walked:
 //  KC: R large, the R index is contiguous -> tiles step along R inside one l.
@@ -57,6 +60,10 @@ constexpr int FLUSH_TERMS = 128;  // FP32 accumulation chunk before the FP64 add
 
 template <int P> struct KDepth { static constexpr int value = 32; };
 template <> struct KDepth<PREC_F64> { static constexpr int value = 16; };
+template <> struct KDepth<PREC_F64ACC> { static constexpr int value = 16; };
+
+// FP64 MFMA arithmetic (FP64 input, or float32 input widened)
+__host__ __device__ constexpr bool prec_f64_mfma(int p) { return p == PREC_F64 || p == PREC_F64ACC; }
 
 // The Jacobi rotation of a symmetric pair (p, q), rotated when |a_pq| > tol
 // sqrt(|a_pp a_qq|), by the smaller angle, with two
@@ -98,7 +105,7 @@ __device__ inline bool schur2_rs(double app, double aqq, double apq, double tol,
 // 4*(lane/16) + v, the f64 form holds rows lane/16 + 4*v (measured on gfx950).
 template <int P>
 __device__ inline int mfma16_row(int lane, int v) {
-    return P == PREC_F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+    return prec_f64_mfma(P) ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
 }
 
 // ------------------------------------------------------------ launchers
@@ -219,6 +226,9 @@ struct SelectArgs {
     __bf16* Mtl;
     HostFlags* hflags;    // null: no host report
     int32_t seq;          // value written to hflags->seq
+    int32_t publish_late; // one-launch m = 32 path: report after the last grid barrier
+                          // (the last processed mode: nothing waits on it, and a
+                          // barrier wait that gave up is then still reported)
 };
 hipError_t launch_select_factor(const SelectArgs& a, hipStream_t st);
 
@@ -247,6 +257,12 @@ hipError_t launch_prepare_matrix(int prec, const void* U, int src_f64, int rows,
 
 // Message returned by atc_last_error() on the calling thread.
 void set_last_error(const char* msg);
+
+// Reconstruction helpers of the C ABI: argument checks (shape, then ranks
+// 1 <= r_k <= n_k; the last error is set on failure) and the decompression
+// order of Section 4.1.1 (exhaustive search, first lexicographic on ties).
+atc_status check_recon_args(const atc_shape* s, const int64_t* ranks);
+void recon_order(const atc_shape* s, const int64_t* ranks, int* order);
 
 // Zeroes n bytes with a kernel (capturable in a graph, unlike memset nodes).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);

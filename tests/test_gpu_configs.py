@@ -84,6 +84,18 @@ def test_field256_eps1e4(precision):
     _check_field(256, 1e-4, precision)
 
 
+def test_field256_eps1e4_f64acc():
+    """256^3 field at eps = 1e-4 with the FP64-accumulated Gram matrix (float32
+    data widened to FP64, exact products, FP64 MFMA accumulation; the 64-bit
+    internal arithmetic option of Section 5): the oracle's ranks (22, 18, 20)
+    exactly, tails within 1% of a mode budget of the oracle's."""
+    t_g, t_o = _check_field(256, 1e-4, "f64acc")
+    assert t_o.ranks == [22, 18, 20]
+    assert t_g.ranks == t_o.ranks
+    for k in range(3):
+        assert abs(t_g.tails[k] - t_o.tails[k]) <= 0.01 * t_o.budgets[k], (k, t_g.tails[k], t_o.tails[k])
+
+
 @pytest.mark.parametrize("precision", ["bf16x3", "native"])
 def test_field512(precision):
     """512^3 field at eps = 1e-3: the benchmark's launch (k_gram_kc3 on the

@@ -127,7 +127,7 @@ F32_CASES = [((24, 36, 40), 1e-2), ((33, 64, 13), 1e-3), ((48, 20, 29, 13), 1e-3
              ((16, 16, 16), 1e-4)]
 
 
-@pytest.mark.parametrize("precision", ["native", "bf16x3"])
+@pytest.mark.parametrize("precision", ["native", "bf16x3", "f64acc"])
 @pytest.mark.parametrize("shape,eps", F32_CASES)
 def test_f32_parity_fields(shape, eps, precision):
     if len(shape) == 3:
