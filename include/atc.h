@@ -101,7 +101,20 @@ typedef struct {
     int32_t max_sweeps;          /* eigensolver sweep cap; 0 = default (60) */
     int32_t eig_path;            /* 0 = automatic, 1 = force dense Jacobi, 2 = force subspace (n > 64) */
     int32_t profile;             /* nonzero: time each phase with stream events (atc_result.*_ms) */
-    int32_t reserved[5];
+    /* Precision guard (NATIVE and BF16X3 on float32 input).  The rounding of
+     * an FP32-accumulated Gram matrix has both signs; in the trailing
+     * eigenvalues its negative part is clamped away, which biases the
+     * discarded-energy sums upwards.  A mode gets an F64ACC Gram matrix when
+     *  - its budget share is below 2^-23 times the energy of the tensor the
+     *    Gram matrix is formed from (for d = 3 and rtmss = 1: rel_error below
+     *    about 6e-4), or
+     *  - its contraction (product of the other current mode sizes) has fewer
+     *    than 2048 terms, where that bias grows to a sizeable part of a
+     *    budget share (and FP64 costs little).
+     * Nonzero turns the guard off.  atc_result.gram_prec reports what each
+     * mode used. */
+    int32_t no_precision_guard;
+    int32_t reserved[4];
 } atc_sthosvd_opts;
 
 /* Host-side record of one ST-HOSVD call. */
@@ -121,6 +134,7 @@ typedef struct {
     double reduce_ms[ATC_MAX_DIMS];
     double eig_ms[ATC_MAX_DIMS];
     double ttm_ms[ATC_MAX_DIMS];
+    int32_t gram_prec[ATC_MAX_DIMS]; /* atc_precision of each mode's Gram matrix (natural index) */
 } atc_result;
 
 /* Fills *o with the defaults documented above (rel_error = 1e-3). */
@@ -180,6 +194,10 @@ typedef struct atc_batch_plan atc_batch_plan;
  *  The plan fixes: the input offsets, core slots (prod(dims) floats per
  *  block) and factor slots (n_k^2 floats per mode), the longest-first
  *  processing order and the launch configuration.
+ *  opts->precision (BF16X3 or NATIVE) is the arithmetic of the mode
+ *  products; the blocks' Gram matrices are always FP64-accumulated (their
+ *  contractions have at most 4096 terms: the short-contraction case of the
+ *  precision guard of atc_sthosvd_opts).
  * The plan owns device memory until atc_batch_plan_destroy.
  */
 atc_status atc_batch_plan_create(const int32_t* dims, const int64_t* input_offsets, int64_t nblocks,

@@ -28,6 +28,7 @@ MAX_DIMS = 8
 
 ATC_F32, ATC_F64 = 0, 1
 PRECISIONS = {"native": 0, "bf16x3": 1, "f64acc": 2}
+_PREC_NAMES = {v: k for k, v in PRECISIONS.items()}
 RULES = {"adaptive": 0, "equal": 1}
 STATUS = {
     0: "ok", -1: "invalid argument", -2: "unsupported", -3: "workspace too small", -4: "device error",
@@ -51,7 +52,7 @@ class Opts(ctypes.Structure):
         ("rank_rule", ctypes.c_int32), ("has_order", ctypes.c_int32), ("mode_order", ctypes.c_int32 * MAX_DIMS),
         ("has_fixed_ranks", ctypes.c_int32), ("fixed_ranks", ctypes.c_int32 * MAX_DIMS),
         ("max_sweeps", ctypes.c_int32), ("eig_path", ctypes.c_int32), ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("no_precision_guard", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -62,7 +63,7 @@ class Result(ctypes.Structure):
         ("eig_path", ctypes.c_int32 * MAX_DIMS), ("eig_sweeps", ctypes.c_int32 * MAX_DIMS),
         ("elapsed_ms", ctypes.c_double), ("gram_ms", ctypes.c_double * MAX_DIMS),
         ("reduce_ms", ctypes.c_double * MAX_DIMS), ("eig_ms", ctypes.c_double * MAX_DIMS),
-        ("ttm_ms", ctypes.c_double * MAX_DIMS),
+        ("ttm_ms", ctypes.c_double * MAX_DIMS), ("gram_prec", ctypes.c_int32 * MAX_DIMS),
     ]
 
 
@@ -161,7 +162,7 @@ def _shape(dims: Sequence[int], dtype: torch.dtype) -> Shape:
 
 def make_opts(rel_error: float = 1e-3, precision: str = "native", order=None, rtmss: float = 1.0,
               rule: str = "adaptive", fixed_ranks=None, max_sweeps: int = 0, eig_path: int = 0,
-              profile: bool = False) -> Opts:
+              profile: bool = False, precision_guard: bool = True) -> Opts:
     o = Opts()
     load().atc_default_opts(ctypes.byref(o))
     o.rel_error = float(rel_error)
@@ -179,6 +180,7 @@ def make_opts(rel_error: float = 1e-3, precision: str = "native", order=None, rt
     o.max_sweeps = int(max_sweeps)
     o.eig_path = int(eig_path)
     o.profile = 1 if profile else 0
+    o.no_precision_guard = 0 if precision_guard else 1
     return o
 
 
@@ -196,6 +198,7 @@ class Tucker:
     eig_sweeps: List[int]
     elapsed_ms: float
     phase_ms: dict
+    gram_prec: List[str]
 
 
 def sthosvd_workspace_size(dims, dtype=torch.float32, **opt_kw) -> int:
@@ -210,7 +213,7 @@ def sthosvd_workspace_size(dims, dtype=torch.float32, **opt_kw) -> int:
 def sthosvd(x: torch.Tensor, rel_error: float = 1e-3, precision: str = "native", order=None, rtmss: float = 1.0,
             rule: str = "adaptive", fixed_ranks=None, max_sweeps: int = 0, eig_path: int = 0,
             workspace: Optional[torch.Tensor] = None, stream=None, profile: bool = False,
-            out: Optional[tuple] = None) -> Tucker:
+            out: Optional[tuple] = None, precision_guard: bool = True) -> Tucker:
     """ST-HOSVD of x (GPU tensor) to relative error rel_error; see atc_sthosvd in include/atc.h.
     The ranks and figures of the result are final on return; core and factors
     are written in the order of `stream` (torch's current stream by default)."""
@@ -218,7 +221,8 @@ def sthosvd(x: torch.Tensor, rel_error: float = 1e-3, precision: str = "native",
     _require_gpu(x, "x")
     dims = list(x.shape)
     s = _shape(dims, x.dtype)
-    o = make_opts(rel_error, precision, order, rtmss, rule, fixed_ranks, max_sweeps, eig_path, profile)
+    o = make_opts(rel_error, precision, order, rtmss, rule, fixed_ranks, max_sweeps, eig_path, profile,
+                  precision_guard)
     need = lib.atc_sthosvd_workspace_size(ctypes.byref(s), ctypes.byref(o))
     if need == 0:
         _check(-1)
@@ -248,7 +252,8 @@ def sthosvd(x: torch.Tensor, rel_error: float = 1e-3, precision: str = "native",
         budgets=[float(res.budget[k]) for k in range(d)], eig_path=[int(res.eig_path[k]) for k in range(d)],
         eig_sweeps=[int(res.eig_sweeps[k]) for k in range(d)], elapsed_ms=float(res.elapsed_ms),
         phase_ms={name: [float(getattr(res, name + "_ms")[k]) for k in range(d)]
-                  for name in ("gram", "reduce", "eig", "ttm")})
+                  for name in ("gram", "reduce", "eig", "ttm")},
+        gram_prec=[_PREC_NAMES[int(res.gram_prec[k])] for k in range(d)])
 
 
 # ----------------------------------------------------------------- reconstruction

@@ -124,6 +124,34 @@ int prec_of(const atc_shape* s, const atc_sthosvd_opts* o) {
 // Arithmetic of the mode products (projections): F64ACC projects in FP32
 int ttm_prec_of(int gram_prec) { return gram_prec == PREC_F64ACC ? PREC_F32 : gram_prec; }
 
+// Precision guard of the Gram matrix.  A Gram matrix accumulated from FP32
+// (or bf16x3) products carries rounding of a small multiple of
+// u32 = 2^-24 times the energy of the tensor it is formed from.  That rounding
+// has both signs, and in the trailing eigenvalues (true values far below it)
+// the negative part is clamped away, so the discarded-energy sums the rank
+// choice compares with the mode's budget come out biased upwards.  Measured on
+// smooth fields the bias stays near 0.2 u32 |Y|^2 for contractions of a few
+// thousand terms or more, and reaches several u32 |Y|^2 for short ones (the
+// last modes of strongly truncated tensors, small blocks).  So a mode's Gram
+// matrix is formed with FP64 accumulation instead (the 64-bit internal
+// arithmetic of Section 5) when
+//   * its budget share is below 2 u32 |Y|^2 (a tail error above a tenth of the
+//     share), or
+//   * its contraction is shorter than GUARD_MIN_TERMS terms (then n^2 K is
+//     small and the FP64 matrix cores cost little).
+// The projections keep the requested arithmetic.
+constexpr double GUARD_RATIO = 0x1p-23;
+constexpr int64_t GUARD_MIN_TERMS = 2048;
+
+bool guard_upgrades(int gprec, double budget, double energy, int64_t terms) {
+    if (gprec != PREC_F32 && gprec != PREC_BF16X3) return false;
+    return !(budget >= GUARD_RATIO * energy) || terms < GUARD_MIN_TERMS;
+}
+
+int32_t abi_prec(int p) {
+    return p == PREC_F64ACC ? ATC_PREC_F64ACC : p == PREC_BF16X3 ? ATC_PREC_BF16X3 : ATC_PREC_NATIVE;
+}
+
 size_t part_capacity(int nmax) {
     const size_t t = (size_t)ceil_div(nmax, TILE);
     const size_t one_split = t * t * TILE * TILE * sizeof(double);  // cross Gram: all tile pairs
@@ -338,28 +366,45 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
     int paths[ATC_MAX_DIMS] = {0};
     int lazy[ATC_MAX_DIMS], nlazy = 0;  // modes kept whole, rotated at the end
     bool wide_hint = false;             // the previous subspace mode needed m = 64
+    int32_t gram_used[ATC_MAX_DIMS] = {};
     for (int i = 0; i < d; ++i) {
         const int k = order[i];
         const int64_t L = prod(cur, 0, k), R = prod(cur, k + 1, d);
         const int n = (int)cur[k];
+        // this mode's budget share and the energy of the current tensor, both
+        // relative to |A|^2 (known from the previous mode's report; the first
+        // mode's share is S / d for either rule)
+        int gprec_i = gprec;
+        if (!opts->no_precision_guard && !opts->has_fixed_ranks) {
+            const double S = opts->rtmss * opts->rel_error * opts->rel_error;
+            double share = S / d, energy = 1.0;
+            if (i > 0 && rep_norm2 > 0.0) {
+                const double used = rep_used / rep_norm2;
+                share = opts->rank_rule == ATC_RANK_EQUAL ? S / d : (S - used) / (d - i);
+                energy = 1.0 - used;
+            }
+            if (guard_upgrades(gprec, share, energy, L * R)) gprec_i = PREC_F64ACC;
+        }
+        gram_used[k] = abi_prec(gprec_i);
         GramKcPlan kp{};
-        if (gram_kc_applicable(gprec, R)) kp = gram_kc_plan(gprec, L, n, R, w.part_cap, w.dpart_cap);
+        if (gram_kc_applicable(gprec_i, R)) kp = gram_kc_plan(gprec_i, L, n, R, w.part_cap, w.dpart_cap);
         if (kp.ok) {
             HIP_TRY(mark(i, 0));
-            HIP_TRY(launch_gram_kc(gprec, kp, (const float*)src, (float*)w.part, w.dpart, st));
+            HIP_TRY(launch_gram_kc(gprec_i, kp, (const float*)src, (float*)w.part, w.dpart, st));
             HIP_TRY(mark(i, 1));
             HIP_TRY(launch_gram_kc_reduce(kp, (const float*)w.part, w.dpart, w.G, st));
             HIP_TRY(mark(i, 2));
-        } else if (gram_tall_applicable(gprec, n, R) && reinterpret_cast<uintptr_t>(src) % 16 == 0) {
+        } else if (gram_tall_applicable(gprec_i, n, R) && reinterpret_cast<uintptr_t>(src) % 16 == 0) {
             // short last mode: FP64 MFMA over rows streamed through LDS (reduction included)
+            gram_used[k] = ATC_PREC_F64ACC;
             HIP_TRY(mark(i, 0));
             HIP_TRY(launch_gram_tall((const float*)src, n, L, w.part, w.part_cap, w.G, st));
             HIP_TRY(mark(i, 1));
             HIP_TRY(mark(i, 2));
         } else {
-            const GramPlan gp = gram_plan(gprec, L, n, n, R, true, w.part_cap);
+            const GramPlan gp = gram_plan(gprec_i, L, n, n, R, true, w.part_cap);
             HIP_TRY(mark(i, 0));
-            HIP_TRY(launch_gram(gprec, gp, src, src, w.part, st));
+            HIP_TRY(launch_gram(gprec_i, gp, src, src, w.part, st));
             HIP_TRY(mark(i, 1));
             HIP_TRY(launch_gram_reduce(gp, w.part, w.G, st));
             HIP_TRY(mark(i, 2));
@@ -545,6 +590,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
             result->budget[k] = rep_budget[k];
             result->eig_path[k] = paths[k];
             result->eig_sweeps[k] = rep_sweeps[k];
+            result->gram_prec[k] = gram_used[k];
             if (prof) {
                 hipEvent_t* e = g_phase.ev[i];
                 result->gram_ms[k] = event_ms(e[0], e[1]);
@@ -650,22 +696,30 @@ size_t atc_reconstruct_workspace_size(const atc_shape* shape, const int64_t* ran
     return carve_recon(shape, ranks, nullptr, nullptr, nullptr);
 }
 
-atc_status atc_reconstruct(const atc_shape* shape, const int64_t* ranks, const void* core, const void* const* factors,
-                           void* xhat, void* workspace, size_t workspace_bytes, void* stream) {
+namespace {
+
+// Argument checks of the reconstruction entry points.
+atc_status check_recon_call(const atc_shape* shape, const int64_t* ranks, const void* core, const void* const* factors,
+                            const void* xhat) {
     atc_status s;
     if ((s = check_shape(shape)) != ATC_OK) return s;
     if ((s = check_ranks(shape, ranks)) != ATC_OK) return s;
     if (!core || !factors || !xhat) return fail(ATC_ERR_INVALID_ARGUMENT, "core, factors and xhat must be non-NULL");
-    const int d = shape->ndim;
-    for (int k = 0; k < d; ++k)
+    for (int k = 0; k < shape->ndim; ++k)
         if (!factors[k]) return fail(ATC_ERR_INVALID_ARGUMENT, "factors[%d] is NULL", k);
-    const size_t need = carve_recon(shape, ranks, nullptr, nullptr, nullptr);
-    if (!workspace || workspace_bytes < need)
-        return fail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    return ATC_OK;
+}
+
+// The reconstruction proper: one mode product per mode in the cheapest
+// order, the intermediates in `workspace` (carve_recon's layout, checked by
+// the caller to be large enough).  Kernel launches only: no allocation, no
+// memset, no host wait.
+atc_status reconstruct_impl(const atc_shape* shape, const int64_t* ranks, const void* core, const void* const* factors,
+                            void* xhat, void* workspace, hipStream_t st) {
     void* buf[2];
     MatBufs mb;
     carve_recon(shape, ranks, (char*)workspace, buf, &mb);
-    hipStream_t st = (hipStream_t)stream;
+    const int d = shape->ndim;
     const bool f64 = shape->dtype == ATC_F64;
     const int prec = f64 ? PREC_F64 : PREC_F32;
     int order[ATC_MAX_DIMS];
@@ -687,6 +741,18 @@ atc_status atc_reconstruct(const atc_shape* shape, const int64_t* ranks, const v
         src = dst;
     }
     return ATC_OK;
+}
+
+}  // namespace
+
+atc_status atc_reconstruct(const atc_shape* shape, const int64_t* ranks, const void* core, const void* const* factors,
+                           void* xhat, void* workspace, size_t workspace_bytes, void* stream) {
+    atc_status s = check_recon_call(shape, ranks, core, factors, xhat);
+    if (s != ATC_OK) return s;
+    const size_t need = carve_recon(shape, ranks, nullptr, nullptr, nullptr);
+    if (!workspace || workspace_bytes < need)
+        return fail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    return reconstruct_impl(shape, ranks, core, factors, xhat, workspace, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------- reconstruction adjoint

@@ -5,8 +5,8 @@
 // pre-sorted longest first), then run the whole ST-HOSVD of that block
 // (Algorithm 1, Section 3.2; modes by increasing length, Section 4.1.1; error
 // budget split as in atc_sthosvd, Section 4.1.3):
-//   Gram matrix of the current unfolding  -> LDS, FP64 (MFMA, FP32 chunks of
-//                                            FLUSH_TERMS terms summed in FP64)
+//   Gram matrix of the current unfolding  -> LDS, FP64 (the staged floats
+//                                            widened, FP64 MFMA)
 //   FP64 cyclic Jacobi eigensolver         -> in LDS (round-robin pairs,
 //                                            exact annihilation)
 //   rank choice (FP64 tail sums) and sign rule
@@ -202,6 +202,23 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
                         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
                     }
             }
+        } else if (P == PREC_F64ACC) {
+            // the staged floats widened to FP64: exact products, FP64 sums
+#pragma unroll
+            for (int k4 = 0; k4 < BK; k4 += 4) {
+                const int kk = k4 + (lane >> 4);
+                double av[2], bv[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    av[a] = (double)sm.u.g.xf[wr + a * 16 + (lane & 15)][kk];
+                    bv[a] = (double)sm.u.g.xf[wc + a * 16 + (lane & 15)][kk];
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc64[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc64[a][b], 0, 0, 0);
+            }
         } else {
 #pragma unroll
             for (int k4 = 0; k4 < BK; k4 += 4) {
@@ -219,7 +236,7 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
                         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
             }
         }
-        if (++since == FLUSH_STEPS) {
+        if (P != PREC_F64ACC && ++since == FLUSH_STEPS) {
             since = 0;
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -238,7 +255,7 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = wr + a * 16 + mfma16_row<PREC_F32>(lane, v);
+                const int i = wr + a * 16 + mfma16_row<P>(lane, v);
                 const int j = wc + b * 16 + (lane & 15);
                 sm.u.e.A[i][j] = acc64[a][b][v] + (double)acc[a][b][v];
             }
@@ -624,9 +641,15 @@ __global__ __launch_bounds__(BT) void k_sthosvd_batched(const BlockDesc* __restr
             const int n = (int)cur[k];
             const int64_t L = (k > 0 ? cur[0] : 1) * (k > 1 ? cur[1] : 1);
             const int64_t R = (k < 2 ? cur[2] : 1) * (k < 1 ? cur[1] : 1);
-            if (R >= BK) blk_gram<P, LAYOUT_KC, BK>(src, n, L, R, sm);
-            else if (R == 1) blk_gram<P, LAYOUT_NC, BK>(src, n, L, R, sm);
-            else blk_gram<P, LAYOUT_SR, BK>(src, n, L, R, sm);
+            // Gram matrices FP64-accumulated in both precisions: the
+            // contractions of these blocks are short (at most 4096 terms), and
+            // the rounding of an FP32- or bf16x3-accumulated Gram matrix of a
+            // short contraction lands in the small trailing eigenvalues (its
+            // negative part is clamped away), which biases the discarded-energy
+            // sums by a sizeable part of a mode budget at eps = 1e-3
+            if (R >= BK) blk_gram<PREC_F64ACC, LAYOUT_KC, BK>(src, n, L, R, sm);
+            else if (R == 1) blk_gram<PREC_F64ACC, LAYOUT_NC, BK>(src, n, L, R, sm);
+            else blk_gram<PREC_F64ACC, LAYOUT_SR, BK>(src, n, L, R, sm);
             // trace (fixed order) and budget
             if (tid == 0) {
                 double tr = 0.0;

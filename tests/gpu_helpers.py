@@ -39,13 +39,17 @@ def gpu_rel_error(x, t_gpu):
 
 def boundary_ok(lam, budget, r_gpu, r_orc, band):
     """A rank other than the oracle's is accepted only next to it (|r_gpu - r_orc|
-    <= 1) and only when the oracle's own discarded energy at r_gpu lies within
-    band * budget of the budget: the budget then cuts the spectrum where an
-    FP32-grade Gram matrix cannot tell the two ranks apart."""
+    <= 1) and only when the budget cuts the spectrum where an FP32-grade Gram
+    matrix cannot tell the two ranks apart.  With r1 = min(r_gpu, r_orc), the
+    two runs disagree on one comparison only: whether the discarded energy at
+    r1 fits the budget.  The oracle's discarded energy at r1 must therefore lie
+    within band * budget of the budget (from below when the GPU kept one more
+    vector, from above when it kept one fewer)."""
     if abs(r_gpu - r_orc) > 1:
         return False
     tails = oracle.tail_sums(lam)
-    return abs(tails[r_gpu] - budget) <= band * budget
+    r1 = min(r_gpu, r_orc)
+    return abs(tails[r1] - budget) <= band * budget
 
 
 def rank_parity(x, t_gpu, t_orc, band, eps, **oracle_kw):
@@ -66,8 +70,9 @@ def rank_parity(x, t_gpu, t_orc, band, eps, **oracle_kw):
         if t_gpu.ranks[k] != t.ranks[k]:
             if not boundary_ok(t.eigvals[k], t.budgets[k], t_gpu.ranks[k], t.ranks[k], band):
                 tails = oracle.tail_sums(t.eigvals[k])
-                return False, "mode %d: gpu %d oracle %d (oracle tail at gpu rank / budget = %.4f)" % (
-                    k, t_gpu.ranks[k], t.ranks[k], tails[t_gpu.ranks[k]] / t.budgets[k]), t
+                r1 = min(t_gpu.ranks[k], t.ranks[k])
+                return False, "mode %d: gpu %d oracle %d (oracle tail at rank %d / budget = %.4f)" % (
+                    k, t_gpu.ranks[k], t.ranks[k], r1, tails[r1] / t.budgets[k]), t
             for j in t_orc.order[: i + 1]:
                 fixed[j] = t_gpu.ranks[j]
             t = oracle.sthosvd(x, eps, fixed_ranks=fixed, **oracle_kw)

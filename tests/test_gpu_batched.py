@@ -4,8 +4,8 @@ caller-placed input blocks.
 
 Bars per block, both precisions (bf16x3 and FP32 products with the exact FP64
 Gram diagonal, FP64 eigensolver): ranks equal or boundary-degenerate (next to
-the oracle's, oracle discarded energy at the GPU rank within 10% of the mode
-budget), achieved error <= 1.02 eps, |X~_gpu - X~_oracle| / |X| <= 0.2 eps
+the oracle's, oracle discarded energy at the smaller of the two ranks within
+10% of the mode budget), achieved error <= 1.02 eps, |X~_gpu - X~_oracle| / |X| <= 0.2 eps
 against the oracle run that kept the same ranks, and |A|^2 to 1e-6.
 """
 import os
@@ -31,7 +31,7 @@ def _arena(dims, seed0):
 def _check_block(plan, arena_np, core, fac, recs, b, eps):
     """One block against the oracle: |A|^2, error <= 1.02 eps, ranks equal or
     boundary-degenerate (rank_parity: next to the oracle's, oracle tail at the
-    GPU rank within 10% of the budget), reconstruction within 0.2 eps of the
+    smaller of the two ranks within 10% of the budget), reconstruction within 0.2 eps of the
     oracle run that kept the same ranks.  Returns True for equal ranks."""
     d = [int(v) for v in plan.dims[b]]
     x = arena_np[plan.input_off[b]: plan.input_off[b] + np.prod(d)].reshape(d)

@@ -5,7 +5,7 @@ Bars:
     subspaces (projectors) within 1e-9, reconstruction within 1e-11 of the
     oracle's (relative to |X|).
   * FP32 and BF16X3 paths: ranks identical or boundary-degenerate (the oracle's
-    discarded energy at the GPU rank within 10% of the mode budget), achieved
+    discarded energy at the smaller of the two ranks within 10% of the mode budget), achieved
     error <= 1.02 eps, and |X~_gpu - X~_oracle| / |X| reported and bounded.
 Shapes cover every loader layout of the Gram and mode-product kernels
 (contiguous-R, R == 1, 1 < R < tile depth), ragged tiles (n not a multiple
