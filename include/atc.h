@@ -262,6 +262,27 @@ atc_status atc_reconstruct(const atc_shape* shape, const int64_t* ranks, const v
                            const void* const* factors, void* xhat,
                            void* workspace, size_t workspace_bytes, void* stream);
 
+/* Size of the device scratch buffer the library holds for
+ * atc_reconstruct_noalloc (per device, for the life of the process). */
+#define ATC_NOALLOC_SCRATCH_MIB 64
+
+/*
+ * atc_reconstruct for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same reconstruction, its intermediates in a library-held device buffer of
+ * ATC_NOALLOC_SCRATCH_MIB MiB instead of a caller workspace.  The call
+ * allocates nothing (no hipMalloc, no allocating library routine); on its
+ * first use on a device it looks up that device's copy of the buffer.
+ *  Returns ATC_ERR_UNSUPPORTED when the reconstruction needs more scratch than
+ *  the buffer holds (atc_reconstruct_workspace_size tells the need).
+ *  Every call on one device shares that device's buffer: calls that overlap
+ *  on one device (different streams, or host threads, without ordering) race
+ *  and give undefined results.  Nothing in the buffer needs to start at zero
+ *  (every intermediate is written before it is read).
+ */
+atc_status atc_reconstruct_noalloc(const atc_shape* shape, const int64_t* ranks, const void* core,
+                                   const void* const* factors, void* xhat, void* stream);
+
 size_t atc_reconstruct_backward_workspace_size(const atc_shape* shape, const int64_t* ranks);
 
 /*

@@ -92,6 +92,7 @@ SIGNATURES = [
     ("atc_graph_destroy", None, [_VP]),
     ("atc_reconstruct_workspace_size", _SZ, [_P(Shape), _P(_I64)]),
     ("atc_reconstruct", _I32, [_P(Shape), _P(_I64), _VP, _P(_VP), _VP, _VP, _SZ, _VP]),
+    ("atc_reconstruct_noalloc", _I32, [_P(Shape), _P(_I64), _VP, _P(_VP), _VP, _VP]),
     ("atc_reconstruct_backward_workspace_size", _SZ, [_P(Shape), _P(_I64)]),
     ("atc_reconstruct_backward", _I32, [_P(Shape), _P(_I64), _VP, _P(_VP), _VP, _VP, _P(_VP), _VP, _SZ, _VP]),
     ("atc_status_string", ctypes.c_char_p, [_I32]),
@@ -287,6 +288,30 @@ def reconstruct(core: torch.Tensor, factors: Sequence[torch.Tensor], stream=None
     _check(lib.atc_reconstruct(ctypes.byref(s), ra, ctypes.c_void_p(core.data_ptr()), fptr,
                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), need,
                                ctypes.c_void_p(_stream(stream))))
+    return out
+
+
+def reconstruct_noalloc(core: torch.Tensor, factors: Sequence[torch.Tensor], out: torch.Tensor,
+                        stream=None) -> torch.Tensor:
+    """X~ = (U_0, ..., U_{d-1}) . G into the caller's `out`; see
+    atc_reconstruct_noalloc (intermediates in the library's device scratch)."""
+    lib = load()
+    _require_gpu(core, "core")
+    _require_gpu(out, "out")
+    for f in factors:
+        _require_gpu(f, "factor")
+        if f.dtype != core.dtype:
+            raise ValueError("factors must have the core's dtype")
+    dims = [int(f.shape[0]) for f in factors]
+    ranks = [int(f.shape[1]) for f in factors]
+    if list(core.shape) != ranks:
+        raise ValueError("core shape %s does not match factor ranks %s" % (list(core.shape), ranks))
+    if list(out.shape) != dims or out.dtype != core.dtype:
+        raise ValueError("out must be a %s tensor of shape %s" % (core.dtype, dims))
+    s = _shape(dims, core.dtype)
+    fptr = (ctypes.c_void_p * len(dims))(*[f.data_ptr() for f in factors])
+    _check(lib.atc_reconstruct_noalloc(ctypes.byref(s), _ranks_arr(ranks), ctypes.c_void_p(core.data_ptr()), fptr,
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream(stream))))
     return out
 
 

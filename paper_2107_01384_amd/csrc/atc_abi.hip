@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -743,6 +744,39 @@ atc_status reconstruct_impl(const atc_shape* shape, const int64_t* ranks, const 
     return ATC_OK;
 }
 
+// Library-held scratch of atc_reconstruct_noalloc: one copy per device,
+// alive until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host the name is a stand-in, not a device address); it uses
+// the address hipGetSymbolAddress returns for the current device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)ATC_NOALLOC_SCRATCH_MIB << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+atc_status noalloc_scratch(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(ATC_ERR_UNSUPPORTED, "device %d beyond the %d the scratch table holds", dev, NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(ATC_ERR_DEVICE, "hipGetSymbolAddress returned NULL for the scratch buffer");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ATC_OK;
+}
+
 }  // namespace
 
 atc_status atc_reconstruct(const atc_shape* shape, const int64_t* ranks, const void* core, const void* const* factors,
@@ -753,6 +787,19 @@ atc_status atc_reconstruct(const atc_shape* shape, const int64_t* ranks, const v
     if (!workspace || workspace_bytes < need)
         return fail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
     return reconstruct_impl(shape, ranks, core, factors, xhat, workspace, (hipStream_t)stream);
+}
+
+atc_status atc_reconstruct_noalloc(const atc_shape* shape, const int64_t* ranks, const void* core,
+                                   const void* const* factors, void* xhat, void* stream) {
+    atc_status s = check_recon_call(shape, ranks, core, factors, xhat);
+    if (s != ATC_OK) return s;
+    const size_t need = carve_recon(shape, ranks, nullptr, nullptr, nullptr);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(ATC_ERR_UNSUPPORTED, "reconstruction needs %zu bytes of scratch; the library's buffer holds %zu",
+                    need, NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    if ((s = noalloc_scratch(&ws)) != ATC_OK) return s;
+    return reconstruct_impl(shape, ranks, core, factors, xhat, ws, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------- reconstruction adjoint
