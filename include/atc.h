@@ -298,6 +298,88 @@ atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks
                                     void* const* dfactors, void* workspace, size_t workspace_bytes,
                                     void* stream);
 
+/* ------------------------------------------------------- core quantization */
+
+/* Stream record of one quantized core (device memory, written by the call). */
+typedef struct {
+    int32_t status;     /* ATC_OK; ATC_ERR_NONFINITE_INPUT (core not finite:
+                           nothing encoded); ATC_ERR_WORKSPACE_TOO_SMALL (the
+                           stream did not fit: cannot happen with enc_words >=
+                           atc_quantize_max_words) */
+    int32_t k;          /* scale exponent: 2^63 <= 2^k max|b| < 2^64;
+                           ATC_QUANT_KZERO for an all-zero core */
+    int32_t plane;      /* breakpoint plane P: planes 63 .. P+1 encoded for every
+                           coefficient, plane P for the first `count`; 64 =
+                           nothing encoded */
+    int32_t block_len;
+    int64_t n;
+    int64_t count;      /* coefficients encoded on plane P */
+    int64_t nblocks;
+    int64_t words;      /* stream length in 32-bit words */
+    double sse;         /* |B - B~|^2 at the breakpoint in the core's units: the
+                           exact integer error times 2^-2k, rounded */
+    int64_t pad;
+} atc_quant_info;
+
+#define ATC_QUANT_KZERO INT32_MIN
+#define ATC_QUANT_MAX_BLOCK 4096
+
+/* Capacity in 32-bit words a stream of n coefficients in blocks of block_len
+ * can need (0 on invalid arguments). */
+size_t atc_quantize_max_words(int64_t n, int32_t block_len);
+size_t atc_quantize_workspace_size(int64_t n, int32_t block_len);
+
+/*
+ * Bit-plane quantization and encoding of a core (Section 3.3, TTHRESH bit-plane
+ * truncation, Table 2; Section 4.2, blocks encoded independently with their
+ * sizes and a breakpoint each; Section 4.3, the dequantization correction
+ * inside the error tracking).
+ *  core        n coefficients (dtype ATC_F32 / ATC_F64), the core vectorised in
+ *              C order (lexicographic, last index fastest).
+ *  target_sse  quantization error allowed, |B - B~|^2 in the core's units
+ *              (e.g. the total SSE target minus the ST-HOSVD's, Section
+ *              4.1.3); below zero encodes every bit.
+ *  block_len   coefficients per block, 1 .. ATC_QUANT_MAX_BLOCK.
+ *  enc         output stream, at least atc_quantize_max_words words.
+ *  info        DEVICE pointer to one atc_quant_info, written by the call.
+ * Magnitudes q_i = rint(2^k |b_i|) (ties to even) are walked plane by plane
+ * from bit 63; the error of encoding every bit so far is tracked exactly
+ * (integers), each magnitude known down to plane p counting as its known bits
+ * plus 2^(p-1) (zero while none of its one-bits is known).  The breakpoint is
+ * the first position, on the first plane whose end reaches the target, at
+ * which the error is at most target_sse; blocks before it encode that plane
+ * in full, blocks after it not at all.
+ * Stream (32-bit words): magic 0x51435441, k, P, block_len, n (2 words), count
+ * (2), nblocks (2), nblocks block sizes in words (2 each), then the blocks.  A
+ * block: run bytes, sign bits, trailing bits (3 words), the zero-run lengths of
+ * its leading bits as LEB128 bytes (per plane from 63 down: the zeros before
+ * each one-bit of a coefficient not yet significant, then the zeros after the
+ * last; nothing for a plane without such coefficients), the signs of the
+ * coefficients as they become significant, and the bits of the coefficients
+ * already significant; bit fields packed least significant bit first, each
+ * field padded to whole words.  No entropy coder is applied.
+ * Nothing is allocated; no host wait; capturable in a HIP graph.
+ */
+atc_status atc_quantize_core(const void* core, int32_t dtype, int64_t n, double target_sse, int32_t block_len,
+                             uint32_t* enc, size_t enc_words, atc_quant_info* info, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
+size_t atc_dequantize_workspace_size(int64_t n, int32_t block_len);
+
+/*
+ * Decoding of an atc_quantize_core stream (n and block_len as recorded in its
+ * atc_quant_info): every coefficient becomes sign * (known bits + 2^(p-1)) *
+ * 2^-k, p its lowest encoded plane (nothing added when p = 0; zero when none of
+ * its one-bits is encoded), written as dtype to core_out (n values).
+ *  status  optional DEVICE int32: OR-ed with 2 when the stream's header does
+ *          not match n / block_len (every value is then written as zero), with
+ *          1 when a block's fields do not match its planes (a damaged stream;
+ *          that block's values are then undefined).  The caller guarantees
+ *          that `enc` holds the whole stream its header describes.
+ */
+atc_status atc_dequantize_core(const uint32_t* enc, int64_t n, int32_t block_len, int32_t dtype, void* core_out,
+                               int32_t* status, void* workspace, size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------------------------ misc */
 const char* atc_status_string(atc_status s);
 const char* atc_last_error(void);

@@ -74,6 +74,16 @@ class BlockResult(ctypes.Structure):
     ]
 
 
+class QuantInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("k", ctypes.c_int32), ("plane", ctypes.c_int32), ("block_len", ctypes.c_int32),
+        ("n", ctypes.c_int64), ("count", ctypes.c_int64), ("nblocks", ctypes.c_int64), ("words", ctypes.c_int64),
+        ("sse", ctypes.c_double), ("pad", ctypes.c_int64),
+    ]
+
+
+QUANT_KZERO = -(2 ** 31)
+
 # (name, restype, argtypes) of every symbol include/atc.h declares
 _VP, _SZ, _I64, _I32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int32
 _P = ctypes.POINTER
@@ -95,6 +105,11 @@ SIGNATURES = [
     ("atc_reconstruct_noalloc", _I32, [_P(Shape), _P(_I64), _VP, _P(_VP), _VP, _VP]),
     ("atc_reconstruct_backward_workspace_size", _SZ, [_P(Shape), _P(_I64)]),
     ("atc_reconstruct_backward", _I32, [_P(Shape), _P(_I64), _VP, _P(_VP), _VP, _VP, _P(_VP), _VP, _SZ, _VP]),
+    ("atc_quantize_max_words", _SZ, [_I64, _I32]),
+    ("atc_quantize_workspace_size", _SZ, [_I64, _I32]),
+    ("atc_quantize_core", _I32, [_VP, _I32, _I64, ctypes.c_double, _I32, _VP, _SZ, _VP, _VP, _SZ, _VP]),
+    ("atc_dequantize_workspace_size", _SZ, [_I64, _I32]),
+    ("atc_dequantize_core", _I32, [_VP, _I64, _I32, _I32, _VP, _VP, _VP, _SZ, _VP]),
     ("atc_status_string", ctypes.c_char_p, [_I32]),
     ("atc_last_error", ctypes.c_char_p, []),
     ("atc_version", ctypes.c_char_p, []),
@@ -372,3 +387,64 @@ def tucker_reconstruct(core, *factors):
 
 
 from .batched import BatchPlan, sthosvd_batched  # noqa: E402  (after the ctypes definitions)
+
+
+# ------------------------------------------------------------- core quantization
+@dataclass
+class QuantStream:
+    words: torch.Tensor          # int32 device tensor holding the 32-bit stream words
+    k: Optional[int]             # scale exponent (None for an all-zero core)
+    plane: int                   # breakpoint plane P (64: nothing encoded)
+    count: int                   # coefficients encoded on plane P
+    n: int
+    block_len: int
+    nblocks: int
+    sse: float                   # |B - B~|^2 at the breakpoint (core units)
+    status: int
+
+
+def quantize_core(core: torch.Tensor, target_sse: float, block_len: int = 1024, stream=None) -> QuantStream:
+    """Bit-plane quantization and encoding of `core` (vectorised in C order);
+    see atc_quantize_core.  Reads the device record back (one synchronisation
+    of `stream`)."""
+    lib = load()
+    _require_gpu(core, "core")
+    n = core.numel()
+    cap = lib.atc_quantize_max_words(n, int(block_len))
+    wsz = lib.atc_quantize_workspace_size(n, int(block_len))
+    if cap == 0 or wsz == 0:
+        _check(-1)
+    enc = torch.empty(cap, dtype=torch.int32, device=core.device)
+    ws = torch.empty(wsz, dtype=torch.uint8, device=core.device)
+    info_d = torch.empty(ctypes.sizeof(QuantInfo), dtype=torch.uint8, device=core.device)
+    dt = ATC_F64 if core.dtype == torch.float64 else ATC_F32
+    _check(lib.atc_quantize_core(ctypes.c_void_p(core.data_ptr()), dt, n, float(target_sse), int(block_len),
+                                 ctypes.c_void_p(enc.data_ptr()), cap, ctypes.c_void_p(info_d.data_ptr()),
+                                 ctypes.c_void_p(ws.data_ptr()), wsz, ctypes.c_void_p(_stream(stream))))
+    raw = bytes(info_d.cpu().numpy().tobytes())
+    info = QuantInfo.from_buffer_copy(raw)
+    if info.status not in (0,):
+        raise AtcError(info.status, "quantization of the core failed (device status)")
+    return QuantStream(words=enc[: info.words], k=None if info.k == QUANT_KZERO else int(info.k), plane=int(info.plane),
+                       count=int(info.count), n=int(info.n), block_len=int(info.block_len),
+                       nblocks=int(info.nblocks), sse=float(info.sse), status=int(info.status))
+
+
+def dequantize_core(words: torch.Tensor, n: int, block_len: int, dtype=torch.float32, stream=None) -> torch.Tensor:
+    """Decoded core (n values, vectorised) of a stream; see atc_dequantize_core."""
+    lib = load()
+    if not isinstance(words, torch.Tensor) or not words.is_cuda or words.dtype != torch.int32:
+        raise ValueError("words must be an int32 GPU tensor")
+    wsz = lib.atc_dequantize_workspace_size(int(n), int(block_len))
+    if wsz == 0:
+        _check(-1)
+    ws = torch.empty(wsz, dtype=torch.uint8, device=words.device)
+    out = torch.empty(int(n), dtype=dtype, device=words.device)
+    status = torch.zeros(1, dtype=torch.int32, device=words.device)
+    dt = ATC_F64 if dtype == torch.float64 else ATC_F32
+    _check(lib.atc_dequantize_core(ctypes.c_void_p(words.data_ptr()), int(n), int(block_len), dt,
+                                   ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+                                   ctypes.c_void_p(ws.data_ptr()), wsz, ctypes.c_void_p(_stream(stream))))
+    if int(status.item()) != 0:
+        raise AtcError(-7, "damaged stream: block fields do not match their planes")
+    return out

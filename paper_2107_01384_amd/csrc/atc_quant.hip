@@ -1,0 +1,895 @@
+// Core quantization and encoding on the GPU: TTHRESH bit-plane truncation
+// (Section 3.3), cut into blocks that are encoded independently with a
+// breakpoint per block (Section 4.2), with the dequantization correction inside
+// the error tracking (Section 4.3).
+//
+// The error tracking is exact.  Magnitudes q_i = rint(2^k |b_i|) are 64-bit
+// integers (2^63 <= 2^k max|b| < 2^64); the squared error of one magnitude
+// known down to plane p is a 128-bit integer; sums over the core are 192-bit.
+// The target T (in the core's units) is compared as S <= floor(T 2^(2k)),
+// which is the exact comparison for an integer S.
+//
+// Kernels, in launch order (n coefficients, B blocks of `len` coefficients):
+//   k_q_init       state words cleared
+//   k_q_max        max |b| (bit pattern of the double, atomicMax) + non-finite
+//   k_q_planes     per block: q_i (kept in the workspace), and for every plane
+//                  p in 0..64 the block's error with all its planes >= p known
+//   k_q_plane_pick one workgroup: the core's error at the end of every plane,
+//                  the breakpoint plane P (the first whose end reaches T), the
+//                  error at the start of every block on plane P
+//   k_q_cross      per block: walk of plane P with exact prefix sums, first
+//                  position where the running error reaches T (atomicMin)
+//   k_q_block_sse  per block: coefficients encoded on plane P, exact error
+//   k_q_segment<0> per (block, plane >= P) wavefront: run bytes, sign bits and
+//                  trailing bits of that plane's segment of the block
+//   k_q_layout     one workgroup: segment offsets, block sizes, stream header,
+//                  final error at the breakpoint, the caller's info record
+//   k_q_fill       the stream body cleared (its words are OR-ed into), then
+//                  k_q_block_headers
+//   k_q_segment<1> per (block, plane) wavefront: the segment's bits and bytes
+// Decoding: k_dq_offsets (block offsets from the sizes) and k_dq_decode (one
+// wavefront per block, planes in order, magnitudes in LDS).
+#include <cmath>
+
+#include "atc_internal.hpp"
+
+namespace atc {
+namespace {
+
+constexpr int QPLANES = 64;
+constexpr int32_t QKZERO = INT32_MIN;
+constexpr uint32_t QMAGIC = 0x51435441u;   // 'ATCQ'
+constexpr int QHEADER = 10;                // stream header words
+constexpr int QBLK_HDR = 3;                // block header words
+constexpr int QMAX_BLOCK = 4096;           // longest block (decoder keeps it in LDS)
+
+// ------------------------------------------------------------ 192-bit integers
+struct U192 {
+    uint64_t w0, w1, w2;
+};
+
+__device__ __forceinline__ U192 u192_zero() { return U192{0, 0, 0}; }
+
+__device__ __forceinline__ void u192_add(U192& a, const U192& b) {
+    const uint64_t s0 = a.w0 + b.w0;
+    const uint64_t c0 = s0 < b.w0;
+    const uint64_t s1 = a.w1 + b.w1;
+    uint64_t c1 = s1 < b.w1;
+    const uint64_t s1c = s1 + c0;
+    c1 += s1c < c0;
+    a.w0 = s0;
+    a.w1 = s1c;
+    a.w2 = a.w2 + b.w2 + c1;
+}
+
+// a - b modulo 2^192
+__device__ __forceinline__ void u192_sub(U192& a, const U192& b) {
+    const uint64_t d0 = a.w0 - b.w0;
+    const uint64_t br0 = a.w0 < b.w0;
+    const uint64_t d1 = a.w1 - b.w1;
+    uint64_t br1 = a.w1 < b.w1;
+    const uint64_t d1b = d1 - br0;
+    br1 += d1 < br0;
+    a.w0 = d0;
+    a.w1 = d1b;
+    a.w2 = a.w2 - b.w2 - br1;
+}
+
+__device__ __forceinline__ bool u192_le(const U192& a, const U192& b) {
+    if (a.w2 != b.w2) return a.w2 < b.w2;
+    if (a.w1 != b.w1) return a.w1 < b.w1;
+    return a.w0 <= b.w0;
+}
+
+__device__ __forceinline__ double u192_to_double(const U192& a) {
+    return ldexp((double)a.w2, 128) + ldexp((double)a.w1, 64) + (double)a.w0;
+}
+
+// ------------------------------------------------------------ bit-plane values
+// Magnitude decoded from the bits of planes >= p (Section 4.3): zero while no
+// one-bit is known, else the known bits plus 2^(p-1); nothing is added once
+// every bit is known (p = 0).
+__device__ __forceinline__ uint64_t dec_mag(uint64_t q, int p) {
+    if (p >= QPLANES) return 0;
+    const uint64_t hi = p == 0 ? q : (q >> p) << p;
+    if (hi == 0) return 0;
+    return p >= 1 ? hi + (1ull << (p - 1)) : hi;
+}
+
+// Squared error of one magnitude known down to plane p, as a 128-bit value
+__device__ __forceinline__ U192 err128(uint64_t q, int p) {
+    const uint64_t d = dec_mag(q, p);
+    const uint64_t a = q >= d ? q - d : d - q;
+    return U192{a * a, __umul64hi(a, a), 0};
+}
+
+__device__ __forceinline__ int varint_len(uint32_t v) {
+    return v < (1u << 7) ? 1 : v < (1u << 14) ? 2 : v < (1u << 21) ? 3 : v < (1u << 28) ? 4 : 5;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
+
+// ------------------------------------------------------------ shared state
+struct QState {
+    unsigned long long maxbits;   // bit pattern of max |b| (positive doubles order as integers)
+    unsigned long long first;     // first crossing position on plane P (atomicMin)
+    int32_t nonfinite;
+    int32_t k;
+    int32_t plane;
+    int32_t all_bits;             // the target is below zero: every bit is encoded
+    int64_t count;
+    U192 T;                       // floor(target 2^(2k)) (saturated)
+    U192 sse_bp;                  // exact error at the breakpoint
+    int64_t total_words;
+    int32_t pad[6];
+};
+
+struct QBlk {
+    int64_t word_off;             // block start in the stream
+    uint32_t nrb, nsb, ntb;       // run bytes, sign bits, trailing bits
+    uint32_t count;               // coefficients encoded on plane P
+};
+
+struct QWs {
+    QState* st;
+    uint64_t* q;
+    uint8_t* neg;
+    U192* part;        // [B][65]
+    U192* run_start;   // [B]
+    U192* sse_part;    // [B]
+    uint32_t* cnt;     // [B][64][3]
+    uint32_t* off;     // [B][64][3]
+    QBlk* blk;         // [B]
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t carve_quant(int64_t n, int64_t nb, char* base, QWs* w) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + o : nullptr;
+        o = align256(o + bytes);
+        return p;
+    };
+    QWs t{};
+    t.st = (QState*)take(sizeof(QState));
+    t.q = (uint64_t*)take((size_t)n * 8);
+    t.neg = (uint8_t*)take((size_t)n);
+    t.part = (U192*)take((size_t)nb * 65 * sizeof(U192));
+    t.run_start = (U192*)take((size_t)nb * sizeof(U192));
+    t.sse_part = (U192*)take((size_t)nb * sizeof(U192));
+    t.cnt = (uint32_t*)take((size_t)nb * QPLANES * 3 * 4);
+    t.off = (uint32_t*)take((size_t)nb * QPLANES * 3 * 4);
+    t.blk = (QBlk*)take((size_t)nb * sizeof(QBlk));
+    if (w) *w = t;
+    return o;
+}
+
+// worst case words of one block of m coefficients: header, runs (one per
+// coefficient plus a final one per plane, at most 2 bytes each for m <= 4096),
+// signs, trailing bits (63 planes at most after the first one-bit)
+size_t block_max_words(int64_t m) {
+    const size_t run_bytes = (size_t)2 * (m + QPLANES);
+    return QBLK_HDR + (run_bytes + 3) / 4 + ((size_t)m + 31) / 32 + ((size_t)QPLANES * m + 31) / 32;
+}
+
+// ------------------------------------------------------------ kernels
+__global__ void k_q_init(QState* st) {
+    if (threadIdx.x == 0) {
+        st->maxbits = 0;
+        st->first = ~0ull;
+        st->nonfinite = 0;
+        st->k = QKZERO;
+        st->plane = QPLANES;
+        st->all_bits = 0;
+        st->count = 0;
+        st->T = u192_zero();
+        st->sse_bp = u192_zero();
+        st->total_words = 0;
+    }
+}
+
+template <typename T>
+__global__ void k_q_max(const T* __restrict__ x, int64_t n, QState* st) {
+    unsigned long long m = 0;
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = fabs((double)x[i]);
+        if (!(v <= 1.7976931348623157e308)) bad = 1;
+        else m = max(m, (unsigned long long)__double_as_longlong(v));
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_xor(m, o);
+        m = max(m, t);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (m) atomicMax(&st->maxbits, m);
+    }
+    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(&st->nonfinite, 1);
+}
+
+// k with 2^63 <= 2^k m < 2^64 for the maximum m > 0 (Section 3.3)
+__device__ __forceinline__ int32_t scale_of(unsigned long long maxbits) {
+    if (maxbits == 0) return QKZERO;
+    int e = 0;
+    (void)frexp(__longlong_as_double((long long)maxbits), &e);  // m = f 2^e, 1/2 <= f < 1
+    return 64 - e;
+}
+
+constexpr int PLANES_THREADS = 320;   // 65 planes x 4 partial sums, 5 wavefronts
+
+template <typename T>
+__global__ void __launch_bounds__(PLANES_THREADS) k_q_planes(const T* __restrict__ x, int64_t n, int len,
+                                                              QWs w) {
+    __shared__ uint64_t sq[QMAX_BLOCK];
+    __shared__ U192 red[PLANES_THREADS];
+    const int b = blockIdx.x;
+    const int64_t lo = (int64_t)b * len;
+    const int m = (int)min<int64_t>(len, n - lo);
+    const int32_t k = scale_of(w.st->maxbits);
+    for (int i = threadIdx.x; i < m; i += PLANES_THREADS) {
+        const double v = (double)x[lo + i];
+        uint64_t q = 0;
+        if (k != QKZERO) {
+            const double s = rint(ldexp(fabs(v), k));
+            q = (uint64_t)s;
+        }
+        sq[i] = q;
+        w.q[lo + i] = q;
+        w.neg[lo + i] = v < 0.0 ? 1 : 0;
+    }
+    __syncthreads();
+    // thread (p, j): plane p = tid / 4, every fourth coefficient from j
+    const int tid = threadIdx.x;
+    U192 acc = u192_zero();
+    if (tid < 65 * 4) {
+        const int p = tid >> 2, j = tid & 3;
+        for (int i = j; i < m; i += 4) u192_add(acc, err128(sq[i], p));
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < 65) {
+        U192 s = red[4 * tid];
+        u192_add(s, red[4 * tid + 1]);
+        u192_add(s, red[4 * tid + 2]);
+        u192_add(s, red[4 * tid + 3]);
+        w.part[(size_t)b * 65 + tid] = s;
+    }
+}
+
+// floor(t 2^(2k)) as a saturated 192-bit integer (t >= 0, finite)
+__device__ U192 scaled_target(double t, int32_t k) {
+    U192 r = u192_zero();
+    if (!(t > 0.0)) return r;
+    int e = 0;
+    const double f = frexp(t, &e);                            // t = f 2^e
+    const uint64_t M = (uint64_t)ldexp(f, 53);                // t = M 2^(e - 53)
+    const int64_t s = (int64_t)e - 53 + 2 * (int64_t)(k == QKZERO ? 0 : k);
+    if (s >= 0) {
+        if (s > 192 - 53) return U192{~0ull, ~0ull, ~0ull};   // above every error there is
+        const int sh = (int)s;
+        if (sh < 64) {
+            r.w0 = M << sh;
+            r.w1 = sh ? (M >> (64 - sh)) : 0;
+        } else if (sh < 128) {
+            r.w1 = M << (sh - 64);
+            r.w2 = (sh - 64) ? (M >> (128 - sh)) : 0;
+        } else {
+            r.w2 = M << (sh - 128);
+        }
+    } else if (s > -64) {
+        r.w0 = M >> (int)(-s);
+    }
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_q_plane_pick(int64_t nb, double target, QWs w) {
+    __shared__ U192 S[65];
+    const int tid = threadIdx.x;
+    if (tid < 65) {
+        U192 s = u192_zero();
+        for (int64_t b = 0; b < nb; ++b) u192_add(s, w.part[(size_t)b * 65 + tid]);
+        S[tid] = s;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    QState* st = w.st;
+    const int32_t k = scale_of(st->maxbits);
+    st->k = k;
+    if (st->nonfinite || k == QKZERO) {   // nothing to encode
+        st->plane = QPLANES;
+        st->count = 0;
+        return;
+    }
+    if (target < 0.0) {                   // every bit
+        st->all_bits = 1;
+        st->plane = 0;
+        return;
+    }
+    const U192 T = scaled_target(target, k);
+    st->T = T;
+    if (u192_le(S[64], T)) {
+        st->plane = QPLANES;
+        st->count = 0;
+        return;
+    }
+    int P = 0;
+    bool found = false;
+    for (int p = QPLANES - 1; p >= 0; --p)
+        if (u192_le(S[p], T)) {
+            P = p;
+            found = true;
+            break;
+        }
+    if (!found) {  // cannot happen for T >= 0 (plane 0 ends with no error)
+        st->all_bits = 1;
+        st->plane = 0;
+        return;
+    }
+    st->plane = P;
+    U192 run = S[P + 1];
+    for (int64_t b = 0; b < nb; ++b) {
+        w.run_start[b] = run;
+        u192_add(run, w.part[(size_t)b * 65 + P]);
+        u192_sub(run, w.part[(size_t)b * 65 + P + 1]);
+    }
+}
+
+constexpr int CROSS_THREADS = 256;
+
+// First position of plane P where the running error reaches T: every thread
+// walks a contiguous piece of its block, the pieces' sums scanned in LDS.
+__global__ void __launch_bounds__(CROSS_THREADS) k_q_cross(int64_t n, int len, QWs w) {
+    __shared__ U192 sums[CROSS_THREADS];
+    const QState* st = w.st;
+    if (st->all_bits || st->plane >= QPLANES) return;
+    const int P = st->plane;
+    const U192 T = st->T;
+    const int b = blockIdx.x;
+    const int64_t lo = (int64_t)b * len;
+    const int m = (int)min<int64_t>(len, n - lo);
+    const int per = (m + CROSS_THREADS - 1) / CROSS_THREADS;
+    const int a0 = min(m, threadIdx.x * per), a1 = min(m, a0 + per);
+    U192 s = u192_zero();
+    for (int i = a0; i < a1; ++i) {
+        const uint64_t q = w.q[lo + i];
+        u192_add(s, err128(q, P));
+        u192_sub(s, err128(q, P + 1));
+    }
+    sums[threadIdx.x] = s;
+    __syncthreads();
+    // inclusive scan (Hillis-Steele), then exclusive by shifting
+    for (int o = 1; o < CROSS_THREADS; o <<= 1) {
+        U192 v = sums[threadIdx.x];
+        if (threadIdx.x >= o) u192_add(v, sums[threadIdx.x - o]);
+        __syncthreads();
+        sums[threadIdx.x] = v;
+        __syncthreads();
+    }
+    U192 run = w.run_start[b];
+    if (threadIdx.x > 0) u192_add(run, sums[threadIdx.x - 1]);
+    for (int i = a0; i < a1; ++i) {
+        const uint64_t q = w.q[lo + i];
+        u192_add(run, err128(q, P));
+        u192_sub(run, err128(q, P + 1));
+        if (u192_le(run, T)) {
+            atomicMin(&w.st->first, (unsigned long long)(lo + i));
+            break;
+        }
+    }
+}
+
+// Per block: coefficients encoded on plane P, and the exact error there.
+__global__ void __launch_bounds__(256) k_q_block_sse(int64_t n, int len, QWs w) {
+    __shared__ U192 red[256];
+    const QState* st = w.st;
+    const int b = blockIdx.x;
+    const int64_t lo = (int64_t)b * len;
+    const int m = (int)min<int64_t>(len, n - lo);
+    const int P = st->plane;
+    int64_t count;
+    if (st->all_bits) count = n;
+    else if (P >= QPLANES) count = 0;
+    else count = (int64_t)st->first + 1;
+    const int cb = (int)min<int64_t>(max<int64_t>(count - lo, 0), m);
+    U192 s = u192_zero();
+    for (int i = threadIdx.x; i < m; i += 256) u192_add(s, err128(w.q[lo + i], i < cb ? P : P + 1));
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) u192_add(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        w.sse_part[b] = red[0];
+        w.blk[b].count = (uint32_t)cb;
+    }
+}
+
+// One wavefront per (block, plane): the plane's segment of the block.
+// WRITE = false counts run bytes / sign bits / trailing bits; WRITE = true
+// ORs them into the stream at the offsets k_q_layout computed.
+template <bool WRITE>
+__global__ void __launch_bounds__(64) k_q_segment(int64_t n, int len, QWs w, uint32_t* __restrict__ out,
+                                                  size_t out_words) {
+    const QState* st = w.st;
+    if (WRITE && (size_t)st->total_words > out_words) return;
+    const int b = blockIdx.x;
+    const int p = QPLANES - 1 - (int)blockIdx.y;
+    const int P = st->plane;
+    const int lane = threadIdx.x;
+    uint32_t* c = w.cnt + ((size_t)b * QPLANES + p) * 3;
+    if (p < P || P >= QPLANES) {
+        if (!WRITE && lane == 0) c[0] = c[1] = c[2] = 0;
+        return;
+    }
+    const int64_t lo = (int64_t)b * len;
+    const int m = (int)min<int64_t>(len, n - lo);
+    const int upto = p == P ? (int)w.blk[b].count : m;
+    uint32_t run_pos = 0, sign_pos = 0, trail_pos = 0;   // within this segment
+    uint32_t* runs = nullptr;
+    uint32_t* signs = nullptr;
+    uint32_t* trail = nullptr;
+    uint32_t rbase = 0, sbase = 0, tbase = 0;
+    if (WRITE) {
+        const QBlk bk = w.blk[b];
+        const uint32_t* o = w.off + ((size_t)b * QPLANES + p) * 3;
+        uint32_t* blk = out + bk.word_off;
+        runs = blk + QBLK_HDR;
+        signs = runs + (bk.nrb + 3) / 4;
+        trail = signs + (bk.nsb + 31) / 32;
+        rbase = o[0];
+        sbase = o[1];
+        tbase = o[2];
+    }
+    uint32_t zeros = 0;
+    bool any_lead = false;
+    for (int c0 = 0; c0 < upto; c0 += 64) {
+        const int i = c0 + lane;
+        const bool valid = i < upto;
+        const uint64_t q = valid ? w.q[lo + i] : 0;
+        const bool sig = p < QPLANES - 1 && (q >> (p + 1)) != 0;
+        const bool bit = (q >> p) & 1;
+        const bool lead = valid && !sig;
+        const bool one = lead && bit;
+        const bool tr = valid && sig;
+        const uint64_t lmask = __ballot(lead), omask = __ballot(one), tmask = __ballot(tr);
+        const uint64_t lt = lanemask_lt(lane);
+        // run ending at this lane's one-bit: zeros since the previous one-bit
+        uint32_t run = 0;
+        if (one) {
+            const uint32_t my_rank = __popcll(lmask & lt);
+            const uint64_t prev = omask & lt;
+            if (prev) {
+                const int pl = 63 - __clzll(prev);
+                run = my_rank - (uint32_t)__popcll(lmask & lanemask_lt(pl)) - 1;
+            } else {
+                run = zeros + my_rank;
+            }
+        }
+        const int vl = one ? varint_len(run) : 0;
+        const uint64_t m2 = __ballot(vl >= 2), m3 = __ballot(vl >= 3), m4 = __ballot(vl >= 4), m5 = __ballot(vl >= 5);
+        const uint32_t chunk_bytes = __popcll(omask) + __popcll(m2) + __popcll(m3) + __popcll(m4) + __popcll(m5);
+        if (WRITE) {
+            if (one) {
+                uint32_t pos = rbase + run_pos + __popcll(omask & lt) + __popcll(m2 & lt) + __popcll(m3 & lt) +
+                               __popcll(m4 & lt) + __popcll(m5 & lt);
+                uint32_t v = run;
+                for (int j = 0; j < vl; ++j, ++pos) {
+                    const uint32_t byte = (v & 0x7Fu) | (j + 1 < vl ? 0x80u : 0u);
+                    v >>= 7;
+                    if (byte) atomicOr(&runs[pos >> 2], byte << (8 * (pos & 3)));
+                }
+                if (w.neg[lo + i]) {
+                    const uint32_t sp = sbase + sign_pos + __popcll(omask & lt);
+                    atomicOr(&signs[sp >> 5], 1u << (sp & 31));
+                }
+            }
+            if (tr && bit) {
+                const uint32_t tp = tbase + trail_pos + __popcll(tmask & lt);
+                atomicOr(&trail[tp >> 5], 1u << (tp & 31));
+            }
+        }
+        run_pos += chunk_bytes;
+        sign_pos += __popcll(omask);
+        trail_pos += __popcll(tmask);
+        if (lmask) any_lead = true;
+        if (omask) {
+            const int last = 63 - __clzll(omask);
+            zeros = __popcll(lmask) - __popcll(lmask & lanemask_lt(last)) - 1;
+        } else {
+            zeros += __popcll(lmask);
+        }
+    }
+    if (any_lead) {   // the zeros after the last one-bit of the plane
+        const int vl = varint_len(zeros);
+        if (WRITE && lane == 0) {
+            uint32_t pos = rbase + run_pos;
+            uint32_t v = zeros;
+            for (int j = 0; j < vl; ++j, ++pos) {
+                const uint32_t byte = (v & 0x7Fu) | (j + 1 < vl ? 0x80u : 0u);
+                v >>= 7;
+                if (byte) atomicOr(&runs[pos >> 2], byte << (8 * (pos & 3)));
+            }
+        }
+        run_pos += vl;
+    }
+    if (!WRITE && lane == 0) {
+        c[0] = run_pos;
+        c[1] = sign_pos;
+        c[2] = trail_pos;
+    }
+}
+
+// One workgroup: segment offsets (planes 63 .. P within each block), block
+// sizes and offsets, the stream header, the final error, the info record.
+__global__ void __launch_bounds__(256) k_q_layout(int64_t n, int len, int64_t nb, QWs w, uint32_t* __restrict__ out,
+                                                  size_t out_words, atc_quant_info* info) {
+    const QState* st = w.st;
+    const int P = st->plane;
+    // per block: prefix over planes (each thread a range of blocks)
+    for (int64_t b = threadIdx.x; b < nb; b += 256) {
+        uint32_t r = 0, s = 0, t = 0;
+        for (int p = QPLANES - 1; p >= 0; --p) {
+            uint32_t* o = w.off + ((size_t)b * QPLANES + p) * 3;
+            const uint32_t* c = w.cnt + ((size_t)b * QPLANES + p) * 3;
+            o[0] = r;
+            o[1] = s;
+            o[2] = t;
+            if (p >= P) {
+                r += c[0];
+                s += c[1];
+                t += c[2];
+            }
+        }
+        w.blk[b].nrb = r;
+        w.blk[b].nsb = s;
+        w.blk[b].ntb = t;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    int64_t pos = QHEADER + 2 * nb;
+    U192 sse = u192_zero();
+    for (int64_t b = 0; b < nb; ++b) {
+        QBlk& bk = w.blk[b];
+        const int64_t words = QBLK_HDR + (bk.nrb + 3) / 4 + (bk.nsb + 31) / 32 + (bk.ntb + 31) / 32;
+        bk.word_off = pos;
+        pos += words;
+        u192_add(sse, w.sse_part[b]);
+    }
+    QState* stw = w.st;
+    int64_t count;
+    if (st->all_bits) count = n;
+    else if (P >= QPLANES) count = 0;
+    else count = (int64_t)st->first + 1;
+    stw->count = count;
+    stw->sse_bp = sse;
+    stw->total_words = pos;
+    const int32_t k = st->k;
+    const bool fits = (size_t)pos <= out_words;
+    if (fits) {
+        out[0] = QMAGIC;
+        out[1] = (uint32_t)k;
+        out[2] = (uint32_t)P;
+        out[3] = (uint32_t)len;
+        out[4] = (uint32_t)(uint64_t)n;
+        out[5] = (uint32_t)((uint64_t)n >> 32);
+        out[6] = (uint32_t)(uint64_t)count;
+        out[7] = (uint32_t)((uint64_t)count >> 32);
+        out[8] = (uint32_t)(uint64_t)nb;
+        out[9] = (uint32_t)((uint64_t)nb >> 32);
+        for (int64_t b = 0; b < nb; ++b) {
+            const QBlk& bk = w.blk[b];
+            const int64_t words = QBLK_HDR + (bk.nrb + 3) / 4 + (bk.nsb + 31) / 32 + (bk.ntb + 31) / 32;
+            out[QHEADER + 2 * b] = (uint32_t)(uint64_t)words;
+            out[QHEADER + 2 * b + 1] = (uint32_t)((uint64_t)words >> 32);
+        }
+    }
+    if (info) {
+        info->status = st->nonfinite ? ATC_ERR_NONFINITE_INPUT : fits ? ATC_OK : ATC_ERR_WORKSPACE_TOO_SMALL;
+        info->k = k;
+        info->plane = P;
+        info->block_len = len;
+        info->n = n;
+        info->count = count;
+        info->nblocks = nb;
+        info->words = pos;
+        const double s_units = u192_to_double(sse);
+        info->sse = (k == QKZERO || st->nonfinite) ? 0.0 : ldexp(s_units, -2 * k);
+        info->pad = 0;
+    }
+}
+
+// Clears the block area of the stream; the block headers are written here.
+__global__ void k_q_fill(int64_t nb, QWs w, uint32_t* __restrict__ out, size_t out_words) {
+    const int64_t total = w.st->total_words;
+    if ((size_t)total > out_words) return;
+    const int64_t start = QHEADER + 2 * nb;
+    for (int64_t i = start + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = 0;
+}
+
+__global__ void k_q_block_headers(int64_t nb, QWs w, uint32_t* __restrict__ out, size_t out_words) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb || (size_t)w.st->total_words > out_words) return;
+    const QBlk bk = w.blk[b];
+    uint32_t* h = out + bk.word_off;
+    h[0] = bk.nrb;
+    h[1] = bk.nsb;
+    h[2] = bk.ntb;
+}
+
+// ------------------------------------------------------------ decoding
+// Block offsets from the recorded sizes, after checking the header against
+// the caller's n and block length (a mismatch marks every block unreadable).
+__global__ void __launch_bounds__(64) k_dq_offsets(const uint32_t* __restrict__ in, int64_t n, int len, int64_t nb,
+                                                   int64_t* boff, int32_t* status) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint64_t hn = (uint64_t)in[4] | ((uint64_t)in[5] << 32);
+    const uint64_t hnb = (uint64_t)in[8] | ((uint64_t)in[9] << 32);
+    const bool ok = in[0] == QMAGIC && in[3] == (uint32_t)len && hn == (uint64_t)n && hnb == (uint64_t)nb &&
+                    in[2] <= (uint32_t)QPLANES;
+    int64_t pos = QHEADER + 2 * nb;
+    for (int64_t b = 0; b < nb; ++b) {
+        boff[b] = ok ? pos : -1;
+        if (ok) pos += (int64_t)((uint64_t)in[QHEADER + 2 * b] | ((uint64_t)in[QHEADER + 2 * b + 1] << 32));
+    }
+    if (!ok && status) atomicOr(status, 2);
+}
+
+__device__ __forceinline__ uint32_t read_byte(const uint32_t* __restrict__ w, uint32_t i) {
+    return (w[i >> 2] >> (8 * (i & 3))) & 0xFFu;
+}
+__device__ __forceinline__ uint32_t read_bit(const uint32_t* __restrict__ w, uint32_t i) {
+    return (w[i >> 5] >> (i & 31)) & 1u;
+}
+
+// One wavefront per block: planes from 63 down to P, the known magnitude bits
+// in LDS; then the decoded values (Section 4.3) scaled by 2^-k.
+template <typename T>
+__global__ void __launch_bounds__(64) k_dq_decode(const uint32_t* __restrict__ in, int64_t n, int len,
+                                                  const int64_t* __restrict__ boff, T* __restrict__ out,
+                                                  int32_t* status) {
+    __shared__ uint64_t mag[QMAX_BLOCK];
+    __shared__ uint8_t negs[QMAX_BLOCK];
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x;
+    if (boff[b] < 0) {   // header did not match: zeros
+        for (int64_t i = (int64_t)b * len + lane; i < min<int64_t>(n, (int64_t)(b + 1) * len); i += 64) out[i] = (T)0;
+        return;
+    }
+    const int32_t k = (int32_t)in[1];
+    const int P = (int)in[2];
+    const int64_t count = (int64_t)((uint64_t)in[6] | ((uint64_t)in[7] << 32));
+    const int64_t lo = (int64_t)b * len;
+    const int m = (int)min<int64_t>(len, n - lo);
+    const int cb = (int)min<int64_t>(max<int64_t>(count - lo, 0), m);
+    for (int i = lane; i < m; i += 64) {
+        mag[i] = 0;
+        negs[i] = 0;
+    }
+    __syncthreads();
+    const uint32_t* blk = in + boff[b];
+    const uint32_t nrb = blk[0], nsb = blk[1], ntb = blk[2];
+    const uint32_t* runs = blk + QBLK_HDR;
+    const uint32_t* signs = runs + (nrb + 3) / 4;
+    const uint32_t* trail = signs + (nsb + 31) / 32;
+    uint32_t rpos = 0, spos = 0, tpos = 0;
+    bool bad = false;
+    for (int p = QPLANES - 1; p >= P && k != QKZERO; --p) {
+        const int upto = p == P ? cb : m;
+        // trailing bits of the coefficients significant before this plane
+        uint32_t nlead = 0;
+        for (int c0 = 0; c0 < upto; c0 += 64) {
+            const int i = c0 + lane;
+            const bool valid = i < upto;
+            const uint64_t v = valid ? mag[i] : 0;
+            const bool sig = p < QPLANES - 1 && (v >> (p + 1)) != 0;
+            const bool tr = valid && sig;
+            const uint64_t tmask = __ballot(tr);
+            if (tpos + (uint32_t)__popcll(tmask) > ntb) {
+                bad = true;
+                break;
+            }
+            if (tr && read_bit(trail, tpos + __popcll(tmask & lanemask_lt(lane)))) mag[i] = v | (1ull << p);
+            tpos += __popcll(tmask);
+            nlead += __popcll(__ballot(valid && !sig));
+        }
+        __syncthreads();
+        if (bad) break;
+        if (nlead == 0) continue;
+        // leading bits: zero runs, each but the last ended by a one-bit
+        uint32_t at = 0;      // rank among this plane's leading positions
+        int ci = 0;           // chunk holding rank `at`
+        uint32_t cum = 0;     // leading positions before chunk ci
+        uint64_t lmask = 0;
+        bool have = false;
+        for (;;) {
+            uint32_t r = 0;
+            for (int sh = 0;; sh += 7) {
+                if (rpos >= nrb || sh > 28) {
+                    bad = true;
+                    break;
+                }
+                const uint32_t byte = read_byte(runs, rpos++);
+                r |= (byte & 0x7Fu) << sh;
+                if (!(byte & 0x80u)) break;
+            }
+            if (bad) break;
+            at += r;
+            if (at == nlead) break;
+            if (at > nlead) {
+                bad = true;
+                break;
+            }
+            for (;;) {
+                if (!have) {
+                    const int i = ci * 64 + lane;
+                    const bool valid = i < upto;
+                    const uint64_t v = valid ? mag[i] : 0;
+                    const bool sig = p < QPLANES - 1 && (v >> (p + 1)) != 0;
+                    lmask = __ballot(valid && !sig);
+                    have = true;
+                }
+                const uint32_t c = __popcll(lmask);
+                if (at < cum + c) break;
+                cum += c;
+                ++ci;
+                have = false;
+            }
+            // lane of the (at - cum)-th leading position of chunk ci
+            uint64_t mm = lmask;
+            for (uint32_t j = 0; j < at - cum; ++j) mm &= mm - 1;
+            const int tl = __ffsll((long long)mm) - 1;
+            if (spos >= nsb) {
+                bad = true;
+                break;
+            }
+            if (lane == tl) {
+                const int i = ci * 64 + tl;
+                mag[i] |= 1ull << p;
+                negs[i] = (uint8_t)read_bit(signs, spos);
+            }
+            ++spos;
+            ++at;   // (a one-bit at the very end is followed by a final run of 0)
+        }
+        __syncthreads();
+        if (bad) break;
+    }
+    if (bad && lane == 0 && status) atomicOr(status, 1);
+    __syncthreads();
+    for (int i = lane; i < m; i += 64) {
+        double v = 0.0;
+        if (k != QKZERO) {
+            const int lowp = i < cb ? P : P + 1;
+            const uint64_t d = dec_mag(mag[i], lowp);
+            if (d) {
+                v = ldexp((double)d, -k);
+                if (negs[i]) v = -v;
+            }
+        }
+        out[lo + i] = (T)v;
+    }
+}
+
+// ------------------------------------------------------------ host side
+int64_t quant_nblocks(int64_t n, int len) { return (n + len - 1) / len; }
+
+size_t quant_workspace_bytes(int64_t n, int len) { return carve_quant(n, quant_nblocks(n, len), nullptr, nullptr); }
+
+size_t quant_max_words(int64_t n, int len) {
+    const int64_t nb = quant_nblocks(n, len);
+    return (size_t)QHEADER + 2 * (size_t)nb + (size_t)nb * block_max_words(len);
+}
+
+hipError_t launch_quantize(const void* core, int f64, int64_t n, double target, int len, uint32_t* out,
+                           size_t out_words, atc_quant_info* info, void* ws, hipStream_t st) {
+    const int64_t nb = quant_nblocks(n, len);
+    QWs w;
+    carve_quant(n, nb, (char*)ws, &w);
+    hipLaunchKernelGGL(k_q_init, dim3(1), dim3(64), 0, st, w.st);
+    const unsigned gmax = (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, ceil_div(n, 256)));
+    if (f64) hipLaunchKernelGGL(k_q_max<double>, dim3(gmax), dim3(256), 0, st, (const double*)core, n, w.st);
+    else hipLaunchKernelGGL(k_q_max<float>, dim3(gmax), dim3(256), 0, st, (const float*)core, n, w.st);
+    if (f64)
+        hipLaunchKernelGGL(k_q_planes<double>, dim3((unsigned)nb), dim3(PLANES_THREADS), 0, st, (const double*)core, n,
+                           len, w);
+    else
+        hipLaunchKernelGGL(k_q_planes<float>, dim3((unsigned)nb), dim3(PLANES_THREADS), 0, st, (const float*)core, n,
+                           len, w);
+    hipLaunchKernelGGL(k_q_plane_pick, dim3(1), dim3(256), 0, st, nb, target, w);
+    hipLaunchKernelGGL(k_q_cross, dim3((unsigned)nb), dim3(CROSS_THREADS), 0, st, n, len, w);
+    hipLaunchKernelGGL(k_q_block_sse, dim3((unsigned)nb), dim3(256), 0, st, n, len, w);
+    hipLaunchKernelGGL(k_q_segment<false>, dim3((unsigned)nb, QPLANES), dim3(64), 0, st, n, len, w, out, out_words);
+    hipLaunchKernelGGL(k_q_layout, dim3(1), dim3(256), 0, st, n, len, nb, w, out, out_words, info);
+    const unsigned gfill = (unsigned)std::min<size_t>(4096, std::max<size_t>(1, (out_words + 255) / 256));
+    hipLaunchKernelGGL(k_q_fill, dim3(gfill), dim3(256), 0, st, nb, w, out, out_words);
+    hipLaunchKernelGGL(k_q_block_headers, dim3((unsigned)ceil_div(nb, 256)), dim3(256), 0, st, nb, w, out, out_words);
+    hipLaunchKernelGGL(k_q_segment<true>, dim3((unsigned)nb, QPLANES), dim3(64), 0, st, n, len, w, out, out_words);
+    return hipGetLastError();
+}
+
+size_t dequant_workspace_bytes(int64_t n, int len) { return align256((size_t)quant_nblocks(n, len) * 8); }
+
+hipError_t launch_dequantize(const uint32_t* in, int64_t n, int len, int f64, void* out, int32_t* status, void* ws,
+                             hipStream_t st) {
+    const int64_t nb = quant_nblocks(n, len);
+    int64_t* boff = (int64_t*)ws;
+    hipLaunchKernelGGL(k_dq_offsets, dim3(1), dim3(64), 0, st, in, n, len, nb, boff, status);
+    if (f64) hipLaunchKernelGGL(k_dq_decode<double>, dim3((unsigned)nb), dim3(64), 0, st, in, n, len, boff,
+                                (double*)out, status);
+    else hipLaunchKernelGGL(k_dq_decode<float>, dim3((unsigned)nb), dim3(64), 0, st, in, n, len, boff, (float*)out,
+                            status);
+    return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace atc
+
+// ------------------------------------------------------------ C ABI
+using namespace atc;
+
+namespace {
+atc_status qfail(atc_status s, const char* msg) {
+    set_last_error(msg);
+    return s;
+}
+atc_status check_quant_args(int64_t n, int32_t block_len) {
+    if (n < 1) return qfail(ATC_ERR_INVALID_ARGUMENT, "n must be >= 1");
+    if (block_len < 1 || block_len > QMAX_BLOCK) return qfail(ATC_ERR_UNSUPPORTED, "block_len must lie in [1, 4096]");
+    if (quant_nblocks(n, block_len) > (int64_t)UINT32_MAX) return qfail(ATC_ERR_UNSUPPORTED, "too many blocks");
+    return ATC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t atc_quantize_max_words(int64_t n, int32_t block_len) {
+    if (n < 1 || block_len < 1 || block_len > QMAX_BLOCK) return 0;
+    return quant_max_words(n, block_len);
+}
+
+size_t atc_quantize_workspace_size(int64_t n, int32_t block_len) {
+    if (n < 1 || block_len < 1 || block_len > QMAX_BLOCK) return 0;
+    return quant_workspace_bytes(n, block_len);
+}
+
+atc_status atc_quantize_core(const void* core, int32_t dtype, int64_t n, double target_sse, int32_t block_len,
+                             uint32_t* enc, size_t enc_words, atc_quant_info* info, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+    atc_status s = check_quant_args(n, block_len);
+    if (s != ATC_OK) return s;
+    if (!core || !enc || !info || !workspace) return qfail(ATC_ERR_INVALID_ARGUMENT, "core, enc, info and workspace must be non-NULL");
+    if (dtype != ATC_F32 && dtype != ATC_F64) return qfail(ATC_ERR_INVALID_ARGUMENT, "unknown dtype");
+    if (std::isnan(target_sse) || std::isinf(target_sse)) return qfail(ATC_ERR_INVALID_ARGUMENT, "target_sse must be finite");
+    if (enc_words < quant_max_words(n, block_len))
+        return qfail(ATC_ERR_WORKSPACE_TOO_SMALL, "enc holds fewer words than atc_quantize_max_words");
+    if (workspace_bytes < quant_workspace_bytes(n, block_len))
+        return qfail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than atc_quantize_workspace_size");
+    const hipError_t e = launch_quantize(core, dtype == ATC_F64, n, target_sse, block_len, enc, enc_words, info,
+                                         workspace, (hipStream_t)stream);
+    if (e != hipSuccess) return qfail(ATC_ERR_DEVICE, hipGetErrorString(e));
+    return ATC_OK;
+}
+
+size_t atc_dequantize_workspace_size(int64_t n, int32_t block_len) {
+    if (n < 1 || block_len < 1 || block_len > QMAX_BLOCK) return 0;
+    return dequant_workspace_bytes(n, block_len);
+}
+
+atc_status atc_dequantize_core(const uint32_t* enc, int64_t n, int32_t block_len, int32_t dtype, void* core_out,
+                               int32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
+    atc_status s = check_quant_args(n, block_len);
+    if (s != ATC_OK) return s;
+    if (!enc || !core_out || !workspace) return qfail(ATC_ERR_INVALID_ARGUMENT, "enc, core_out and workspace must be non-NULL");
+    if (dtype != ATC_F32 && dtype != ATC_F64) return qfail(ATC_ERR_INVALID_ARGUMENT, "unknown dtype");
+    if (workspace_bytes < dequant_workspace_bytes(n, block_len))
+        return qfail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than atc_dequantize_workspace_size");
+    const hipError_t e = launch_dequantize(enc, n, block_len, dtype == ATC_F64, core_out, status, workspace,
+                                           (hipStream_t)stream);
+    if (e != hipSuccess) return qfail(ATC_ERR_DEVICE, hipGetErrorString(e));
+    return ATC_OK;
+}
+
+}  // extern "C"

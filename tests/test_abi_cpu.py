@@ -32,14 +32,15 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header(tmp_path):
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include "%s"\nint main(){printf("%%zu %%zu %%zu %%zu",'
-                   'sizeof(atc_sthosvd_opts),sizeof(atc_result),sizeof(atc_block_result),sizeof(atc_shape));}\n'
-                   % HEADER)
+    src.write_text('#include <stdio.h>\n#include "%s"\nint main(){printf("%%zu %%zu %%zu %%zu %%zu",'
+                   'sizeof(atc_sthosvd_opts),sizeof(atc_result),sizeof(atc_block_result),sizeof(atc_shape),'
+                   'sizeof(atc_quant_info));}\n' % HEADER)
     exe = tmp_path / "sz"
     subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     assert [int(v) for v in out] == [ctypes.sizeof(atc.Opts), ctypes.sizeof(atc.Result),
-                                     ctypes.sizeof(atc.BlockResult), ctypes.sizeof(atc.Shape)]
+                                     ctypes.sizeof(atc.BlockResult), ctypes.sizeof(atc.Shape),
+                                     ctypes.sizeof(atc.QuantInfo)]
 
 
 def _shape(dims, dtype=0):
@@ -97,3 +98,25 @@ def test_workspace_size_scales_with_tensor():
     small = lib.atc_sthosvd_workspace_size(ctypes.byref(_shape([64, 64, 64])), ctypes.byref(o))
     big = lib.atc_sthosvd_workspace_size(ctypes.byref(_shape([512, 512, 512])), ctypes.byref(o))
     assert big > 2 * 512 ** 3 * 4 > small
+
+
+def test_quant_argument_validation_without_device():
+    lib = atc.load()
+    assert lib.atc_quantize_max_words(0, 64) == 0
+    assert lib.atc_quantize_max_words(100, 5000) == 0
+    cap = lib.atc_quantize_max_words(100, 64)
+    wsz = lib.atc_quantize_workspace_size(100, 64)
+    assert cap > 10 + 2 * 2 and wsz > 100 * 8
+    one = ctypes.c_void_p(1)
+    null = ctypes.c_void_p(None)
+    assert lib.atc_quantize_core(one, 0, 0, 1.0, 64, one, cap, one, one, wsz, null) == -1
+    assert lib.atc_quantize_core(one, 0, 100, 1.0, 5000, one, cap, one, one, wsz, null) == -2
+    assert lib.atc_quantize_core(one, 0, 100, 1.0, 64, one, cap - 1, one, one, wsz, null) == -3
+    assert lib.atc_quantize_core(one, 0, 100, 1.0, 64, one, cap, one, one, wsz - 1, null) == -3
+    assert lib.atc_quantize_core(one, 0, 100, float("nan"), 64, one, cap, one, one, wsz, null) == -1
+    assert lib.atc_quantize_core(null, 0, 100, 1.0, 64, one, cap, one, one, wsz, null) == -1
+    assert lib.atc_quantize_core(one, 3, 100, 1.0, 64, one, cap, one, one, wsz, null) == -1
+    dsz = lib.atc_dequantize_workspace_size(100, 64)
+    assert dsz > 0
+    assert lib.atc_dequantize_core(one, 100, 64, 0, one, null, one, dsz - 1, null) == -3
+    assert lib.atc_dequantize_core(one, 100, 0, 0, one, null, one, dsz, null) == -2
