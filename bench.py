@@ -88,14 +88,69 @@ def mean_phase(results, name, k):
     return sum(r.phase_ms[name][k] for r in results) / len(results)
 
 
-def rel_error_gpu(atc, torch, x, t):
-    """|X - X~| / |X| with X~ rebuilt by the library; differences summed in FP64."""
+def rel_error_oracle(x_np, t):
+    """|X - X~| / |X| with X~ rebuilt in FP64 by the oracle from the GPU's core and factors."""
+    import numpy as np
+
+    import oracle
+
+    core = t.core.double().cpu().numpy()
+    facs = [f.double().cpu().numpy() for f in t.factors]
+    return oracle.rel_error(np.asarray(x_np, dtype=np.float64), core, facs)
+
+
+def rel_error_device(atc, torch, x, t):
+    """|X - X~| / |X| with X~ rebuilt by the library (FP32) and the differences
+    summed in FP64 on the device (for inputs too large to copy to the host)."""
     xh = atc.reconstruct(t.core.contiguous(), [f.contiguous() for f in t.factors])
     d = (x.double() - xh.double()).pow(2).sum()
     return float(torch.sqrt(d / x.double().pow(2).sum()))
 
 
+def error_deviation(errors, targets):
+    """Average relative error deviation exp(mean |ln(actual / target)|) (Section 6.3)."""
+    import math
+
+    logs = [abs(math.log(e / t)) for e, t in zip(errors, targets)]
+    return math.exp(sum(logs) / len(logs))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ORACLE_SAMPLE = """
+import sys, time, numpy as np
+sys.path.insert(0, %r)
+import oracle, synth
+x = synth.field((%d,) * 3, 0).astype(np.float64)
+t0 = time.perf_counter()
+t = oracle.sthosvd(x, %r)
+print(time.perf_counter() - t0, x.size * 4, *t.ranks)
+"""
+
+
+def _oracle_in_subprocess(n, eps, threads):
+    """The oracle on the n^3 field in a child process limited to `threads` OpenMP threads."""
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    code = _ORACLE_SAMPLE % (os.path.dirname(os.path.abspath(__file__)), n, eps)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+    vals = out.stdout.split()
+    return float(vals[0]), int(vals[1]), [int(v) for v in vals[2:]]
+
+
 def cpu_baseline(x_np, eps):
+    """The FP64 oracle on this host: the full workload with every OpenMP thread
+    (the value), and a 256^3 sample of the same generator on one thread."""
     import numpy as np
 
     import oracle
@@ -105,6 +160,13 @@ def cpu_baseline(x_np, eps):
     t = oracle.sthosvd(x64, eps)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    one = None
+    try:
+        dt1, nb1, r1 = _oracle_in_subprocess(256, eps, 1)
+        one = {"value": round(nb1 / dt1 / 1e9, 4), "unit": "GB/s", "cores": 1, "seconds": round(dt1, 3),
+               "sample": "256^3 field (seed 0) at eps %g, ranks %s" % (eps, r1)}
+    except Exception as e:  # the single-thread sample is context, not the baseline
+        one = {"error": str(e)[:200]}
     return {
         "value": round(x_np.nbytes / dt / 1e9, 4),
         "unit": "GB/s",
@@ -114,6 +176,8 @@ def cpu_baseline(x_np, eps):
                   % (dt, t.ranks),
         "ranks": t.ranks,
         "seconds": round(dt, 3),
+        "cpu_model": cpu_model(),
+        "single_thread": one,
     }
 
 
@@ -196,6 +260,88 @@ def bench_recon(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_quant(args):
+    """Core quantization and encoding (Sections 3.3, 4.2, 4.3): the 512^3 field's
+    ST-HOSVD core at RTMSS 0.5 quantized to the rest of the error target (the
+    hybrid truncation of Section 4.1.3), and a 128^3 hot-corner core (2.1M
+    coefficients, entries decaying away from the origin) at 1e-6 relative
+    error; blocks of 1024 coefficients.  value = core input GB/s of the large
+    core (encode only; decoding timed beside it)."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import paper_2107_01384_amd as atc
+    import synth
+
+    lib = atc.load()
+    eps = args.eps
+    x = torch.from_numpy(synth.field((512,) * 3, 0)).cuda()
+    t = atc.sthosvd(x, eps, "bf16x3", rtmss=0.5)
+    torch.cuda.synchronize()
+    del x
+    rng = np.random.default_rng(7)
+    g = np.meshgrid(*[np.arange(128)] * 3, indexing="ij")
+    big = (rng.standard_normal((128,) * 3) * np.exp(-(g[0] + g[1] + g[2]) / 16.0)).astype(np.float32)
+    cases = [("field512 core %s rtmss 0.5" % "x".join(map(str, t.ranks)), t.core.contiguous(),
+              eps * eps * t.norm2 - t.sse_pred),
+             ("hot-corner 128^3 core, 1e-6 relative", torch.from_numpy(big).cuda(), 1e-6 * float(np.sum(big.astype(np.float64) ** 2)))]
+    L = 1024
+    out = {}
+    st = torch.cuda.current_stream().cuda_stream
+    for name, core, target in cases:
+        n = core.numel()
+        cap = lib.atc_quantize_max_words(n, L)
+        wsz = lib.atc_quantize_workspace_size(n, L)
+        enc = torch.empty(cap, dtype=torch.int32, device="cuda")
+        ws = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+        info = torch.empty(ctypes.sizeof(atc.QuantInfo), dtype=torch.uint8, device="cuda")
+        dws = torch.empty(lib.atc_dequantize_workspace_size(n, L), dtype=torch.uint8, device="cuda")
+        dec = torch.empty(n, dtype=torch.float32, device="cuda")
+
+        def enc_call():
+            atc._check(lib.atc_quantize_core(ctypes.c_void_p(core.data_ptr()), 0, n, float(target), L,
+                                             ctypes.c_void_p(enc.data_ptr()), cap, ctypes.c_void_p(info.data_ptr()),
+                                             ctypes.c_void_p(ws.data_ptr()), wsz, ctypes.c_void_p(st)))
+
+        def dec_call():
+            atc._check(lib.atc_dequantize_core(ctypes.c_void_p(enc.data_ptr()), n, L, 0,
+                                               ctypes.c_void_p(dec.data_ptr()), None,
+                                               ctypes.c_void_p(dws.data_ptr()), dws.numel(), ctypes.c_void_p(st)))
+
+        for _ in range(args.warmup):
+            enc_call()
+            dec_call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            enc_call()
+        torch.cuda.synchronize()
+        ms_e = (time.perf_counter() - t0) * 1e3 / args.steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dec_call()
+        torch.cuda.synchronize()
+        ms_d = (time.perf_counter() - t0) * 1e3 / args.steps
+        qi = atc.QuantInfo.from_buffer_copy(bytes(info.cpu().numpy().tobytes()))
+        out[name] = {"coefficients": n, "encode_ms": round(ms_e, 4), "decode_ms": round(ms_d, 4),
+                     "plane": qi.plane, "count": qi.count, "words": qi.words,
+                     "bits_per_coefficient": round(32.0 * qi.words / n, 3),
+                     "sse_over_target": qi.sse / target if target > 0 else None}
+    big_name = cases[1][0]
+    ms = out[big_name]["encode_ms"]
+    line = {"metric": "core quantization + encoding input GB/s (bit planes, exact error tracking)",
+            "value": round(cases[1][1].numel() * 4 / (ms * 1e-3) / 1e9, 3), "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u64 magnitudes, exact integer errors",
+            "data": "synthetic",
+            "config": {"workload": "128^3 float32 hot-corner core at 1e-6 relative error, blocks of 1024; "
+                                   "also the 512^3 field's ST-HOSVD core at RTMSS 0.5"},
+            "cases": out}
+    print(json.dumps(line), flush=True)
+
+
 def bench_fourway(args):
     """200 x 500 x 500 x 13 float32 (13 independent fields stacked last), eps 1e-3, bf16x3."""
     import torch
@@ -216,7 +362,7 @@ def bench_fourway(args):
             "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3", "data": "synthetic",
             "config": {"workload": "200x500x500x13 float32, 13 independent fields stacked on the last mode, eps 1e-3"},
-            "ranks": t.ranks, "eig_path": t.eig_path, "rel_error_achieved": rel_error_gpu(atc, torch, x, t),
+            "ranks": t.ranks, "eig_path": t.eig_path, "rel_error_achieved": rel_error_device(atc, torch, x, t),
             "phase_ms": {k: [round(v, 4) for v in vals] for k, vals in t.phase_ms.items()},
             "fp32_ms_per_step": round(res["native"][0], 4), "fp32_ranks": res["native"][1].ranks}
     print(json.dumps(line), flush=True)
@@ -229,7 +375,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic field")
     ap.add_argument("--eps", type=float, default=1e-3)
-    ap.add_argument("--workload", default="field", choices=["field", "batched", "recon", "fourway"],
+    ap.add_argument("--workload", default="field", choices=["field", "batched", "recon", "fourway", "quant"],
                     help="field: the 512^3 headline (default); the others print their own line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison path")
@@ -242,7 +388,8 @@ def main():
               "(multi-GPU sharding is a design note, not built); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload != "field":
-        {"batched": bench_batched, "recon": bench_recon, "fourway": bench_fourway}[args.workload](args)
+        {"batched": bench_batched, "recon": bench_recon, "fourway": bench_fourway,
+         "quant": bench_quant}[args.workload](args)
         return
 
     import numpy as np
@@ -273,7 +420,7 @@ def main():
 
     ms_bf, res_bf = time_path(atc, torch, x, args.eps, "bf16x3", args.steps, args.warmup, ws, out)
     t_bf = res_bf[-1]
-    err_bf = rel_error_gpu(atc, torch, x, t_bf)
+    err_bf = rel_error_oracle(x_np, t_bf)
     print("bench: bf16x3 %.3f ms/step ranks %s err %.4e" % (ms_bf, t_bf.ranks, err_bf), file=sys.stderr, flush=True)
 
     gram, ttm = algorithmic_flops(dims, t_bf.ranks, t_bf.order)
@@ -298,13 +445,14 @@ def main():
     if not args.no_fp32:
         ms_32, res_32 = time_path(atc, torch, x, args.eps, "native", args.steps, args.warmup, ws, out)
         t_32 = res_32[-1]
-        err_32 = rel_error_gpu(atc, torch, x, t_32)
+        err_32 = rel_error_oracle(x_np, t_32)
         g32 = {k: mean_phase(res_32, "gram", k) for k in t_32.order}
         fp32 = {"value": round(nbytes / (ms_32 * 1e-3) / 1e9, 3), "ms_per_step": round(ms_32, 4),
                 "ranks": t_32.ranks, "rel_error": err_32,
                 "gram_mode0_tflops": round(gram[k0] / (g32[k0] * 1e-3) / 1e12, 2),
                 "gram_mode0_frac_fp32_peak": round(gram[k0] / (g32[k0] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
-                "speedup_bf16x3_vs_fp32": round(ms_32 / ms_bf, 3)}
+                "speedup_bf16x3_vs_fp32": round(ms_32 / ms_bf, 3),
+                "error_deviation": round(error_deviation([err_32], [args.eps]), 4)}
         print("bench: fp32 %.3f ms/step ranks %s err %.4e" % (ms_32, t_32.ranks, err_32), file=sys.stderr,
               flush=True)
 
@@ -328,6 +476,9 @@ def main():
                    "shape": list(dims), "rel_error": args.eps, "parallelism": "single GPU"},
         "ranks": t_bf.ranks,
         "rel_error_achieved": err_bf,
+        "rel_error_how": "FP64 oracle reconstruction of the GPU core and factors",
+        "error_deviation": round(error_deviation([err_bf], [args.eps]), 4),
+        "gram_prec": t_bf.gram_prec,
         "mfma_frac": {"gram": round(frac_gram, 4), "gram_ttm": round(frac_gt, 4), "e2e": round(frac_e2e, 4),
                       "peak_tflops_fp32_equiv": round(peak_eq, 1)},
         "phase_ms": {"gram": {str(k): round(v, 4) for k, v in gram_ms.items()},
