@@ -342,6 +342,53 @@ def bench_quant(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_hybrid(args):
+    """The hybrid truncation of Section 4.1.3 end to end (atc.compress): the
+    512^3 field at eps, RTMSS 0.5, bf16x3 and FP64-accumulated Gram matrices;
+    value = input GB/s of the bf16x3 pipeline (ST-HOSVD, core and factor
+    quantization, error model; its host reads of the stream records included).
+    Reports the error prediction of eq. (total_error_approximation) against
+    the measured error and the error deviation of Section 6.3."""
+    import torch
+
+    import paper_2107_01384_amd as atc
+    import synth
+
+    x_np = synth.field((512,) * 3, 0)
+    x = torch.from_numpy(x_np).cuda()
+    res = {}
+    for prec in ("bf16x3", "f64acc"):
+        for _ in range(args.warmup):
+            atc.compress(x, args.eps, rtmss=0.5, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            c = atc.compress(x, args.eps, rtmss=0.5, precision=prec)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        xh = atc.decompress(c)
+        actual = float(((x.double() - xh.double()) ** 2).sum())
+        words = c.core_stream.words.numel() + sum(0 if f is None else f.words.numel() for f in c.factor_streams)
+        err = (actual / c.tucker.norm2) ** 0.5
+        res[prec] = {"ms": round(ms, 4), "ranks": c.tucker.ranks,
+                     "rel_error": err, "error_deviation": round(error_deviation([err], [args.eps]), 5),
+                     "predicted_over_actual": c.predicted_sse / actual,
+                     "terms_over_target": {"sthosvd": c.terms["sthosvd"] / c.target_sse,
+                                           "core": c.terms["core"] / c.target_sse,
+                                           "factors": [v / c.target_sse for v in c.terms["factors"]]},
+                     "stream_bytes": 4 * words, "compression_factor": round(x_np.nbytes / (4.0 * words), 1)}
+    ms = res["bf16x3"]["ms"]
+    line = {"metric": "hybrid compressor (ST-HOSVD + core and factor quantization) input GB/s at rel err 1e-3",
+            "value": round(x_np.nbytes / (ms * 1e-3) / 1e9, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "bf16x3 Gram/TTM, FP64 eig, exact-integer quantization",
+            "data": "synthetic",
+            "config": {"workload": "512^3 float32 field, eps %g, RTMSS 0.5, blocks of 1024, factors at 1%% of "
+                                   "the target" % args.eps},
+            "paths": res}
+    print(json.dumps(line), flush=True)
+
+
 def bench_fourway(args):
     """200 x 500 x 500 x 13 float32 (13 independent fields stacked last), eps 1e-3, bf16x3."""
     import torch
@@ -375,7 +422,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic field")
     ap.add_argument("--eps", type=float, default=1e-3)
-    ap.add_argument("--workload", default="field", choices=["field", "batched", "recon", "fourway", "quant"],
+    ap.add_argument("--workload", default="field", choices=["field", "batched", "recon", "fourway", "quant",
+                                                                 "hybrid"],
                     help="field: the 512^3 headline (default); the others print their own line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the plain FP32 comparison path")
@@ -389,7 +437,7 @@ def main():
         sys.exit(2)
     if args.workload != "field":
         {"batched": bench_batched, "recon": bench_recon, "fourway": bench_fourway,
-         "quant": bench_quant}[args.workload](args)
+         "quant": bench_quant, "hybrid": bench_hybrid}[args.workload](args)
         return
 
     import numpy as np

@@ -380,6 +380,59 @@ size_t atc_dequantize_workspace_size(int64_t n, int32_t block_len);
 atc_status atc_dequantize_core(const uint32_t* enc, int64_t n, int32_t block_len, int32_t dtype, void* core_out,
                                int32_t* status, void* workspace, size_t workspace_bytes, void* stream);
 
+/* ------------------------------------ factor representation, error model */
+
+/* Device workspace of atc_factor_householder / atc_factor_from_householder
+ * (0 unless 1 <= r <= n <= 4096, r <= 256). */
+size_t atc_householder_workspace_size(int64_t n, int64_t r);
+
+/*
+ * Householder representation of a factor (supplement S.2): U (n x r,
+ * row-major, dtype, orthonormal columns) = H_1 ... H_r [I_r; 0] diag(signs)
+ * with H_j = I - 2 v_j v_j^T, v_j of unit norm, zero above row j, v_jj > 0.
+ *  sigma2   optional DEVICE array of r squared slice norms of the quantized
+ *           core in this factor's mode: each stored entry of v_j is then
+ *           scaled by sqrt(2 alpha_j) (alpha_j as in supplement S.2, n_j =
+ *           n - j + 1, 1-based j); NULL stores the entries unscaled.
+ *  coef     DEVICE output, n r - r (r + 1) / 2 doubles: the entries of v_j
+ *           below its diagonal, column by column (v_jj follows from |v_j| = 1).
+ *  signs    DEVICE output, r int32: +1 / -1, the sign of R_jj in the
+ *           Householder QR of U; U' = U diag(signs) is what the reflectors
+ *           rebuild (apply the same signs to the core's slices,
+ *           atc_core_apply_signs, to keep the decomposition).
+ *  Uprime   optional DEVICE output (n x r, dtype): U diag(signs).
+ * One workgroup, FP64.  No allocation, no host wait.
+ */
+atc_status atc_factor_householder(const void* U, int32_t dtype, int64_t n, int64_t r, const double* sigma2,
+                                  double* coef, int32_t* signs, void* Uprime, void* workspace, size_t workspace_bytes,
+                                  void* stream);
+
+/* The factor U' = H_1 ... H_r [I_r; 0] from the stored entries (weighted as
+ * given to atc_factor_householder when sigma2 is non-NULL; a column whose
+ * weight is zero, which happens only when it and every later slice norm are
+ * zero, decodes with v_j = e_j).  U_out: DEVICE, n x r, dtype. */
+atc_status atc_factor_from_householder(const double* coef, const double* sigma2, int64_t n, int64_t r, int32_t dtype,
+                                       void* U_out, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Number of slice norms of a core: dims[0] + ... + dims[d-1]. */
+size_t atc_core_slice_norms_count(const atc_shape* shape);
+
+/* Squared slice norms of a core in every mode (eq. total_error_approximation,
+ * Section 4.1.3): out (DEVICE, atc_core_slice_norms_count doubles) holds, mode
+ * after mode, sum over the other indices of B[..., i_k, ...]^2.  shape->dims
+ * are the core's sizes; dtype F32 or F64. */
+atc_status atc_core_slice_norms(const void* core, const atc_shape* shape, double* out, void* stream);
+
+/* Flips the core's slices: B[i_0, .., i_{d-1}] *= prod_k signs_k[i_k], signs
+ * (DEVICE int32) laid out mode after mode as the slice norms. */
+atc_status atc_core_apply_signs(void* core, const atc_shape* shape, const int32_t* signs, void* stream);
+
+/* |dU Sigma|_F^2 = sum_j sigma2[j] sum_i (Uq[i][j] - U[i][j])^2 for one factor
+ * (the factor term of eq. total_error_approximation); U, Uq DEVICE n x r
+ * (dtype), sigma2 DEVICE r doubles, out DEVICE one double. */
+atc_status atc_factor_error_term(const void* U, const void* Uq, int32_t dtype, int64_t n, int64_t r,
+                                 const double* sigma2, double* out, void* stream);
+
 /* ------------------------------------------------------------------ misc */
 const char* atc_status_string(atc_status s);
 const char* atc_last_error(void);

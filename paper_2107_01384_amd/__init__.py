@@ -110,6 +110,13 @@ SIGNATURES = [
     ("atc_quantize_core", _I32, [_VP, _I32, _I64, ctypes.c_double, _I32, _VP, _SZ, _VP, _VP, _SZ, _VP]),
     ("atc_dequantize_workspace_size", _SZ, [_I64, _I32]),
     ("atc_dequantize_core", _I32, [_VP, _I64, _I32, _I32, _VP, _VP, _VP, _SZ, _VP]),
+    ("atc_householder_workspace_size", _SZ, [_I64, _I64]),
+    ("atc_factor_householder", _I32, [_VP, _I32, _I64, _I64, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    ("atc_factor_from_householder", _I32, [_VP, _VP, _I64, _I64, _I32, _VP, _VP, _SZ, _VP]),
+    ("atc_core_slice_norms_count", _SZ, [_P(Shape)]),
+    ("atc_core_slice_norms", _I32, [_VP, _P(Shape), _VP, _VP]),
+    ("atc_core_apply_signs", _I32, [_VP, _P(Shape), _VP, _VP]),
+    ("atc_factor_error_term", _I32, [_VP, _VP, _I32, _I64, _I64, _VP, _VP, _VP]),
     ("atc_status_string", ctypes.c_char_p, [_I32]),
     ("atc_last_error", ctypes.c_char_p, []),
     ("atc_version", ctypes.c_char_p, []),
@@ -448,3 +455,158 @@ def dequantize_core(words: torch.Tensor, n: int, block_len: int, dtype=torch.flo
     if int(status.item()) != 0:
         raise AtcError(-7, "damaged stream: block fields do not match their planes")
     return out
+
+
+# ------------------------------------------- factor representation, error model
+def _ptr_or_null(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(None)
+
+
+def factor_householder(U: torch.Tensor, sigma2: Optional[torch.Tensor] = None, stream=None):
+    """(coef float64, signs int32, U' = U diag(signs)) of a factor with
+    orthonormal columns; see atc_factor_householder."""
+    lib = load()
+    _require_gpu(U, "U")
+    n, r = int(U.shape[0]), int(U.shape[1])
+    wsz = lib.atc_householder_workspace_size(n, r)
+    if wsz == 0:
+        _check(-1)
+    if sigma2 is not None and (sigma2.dtype != torch.float64 or sigma2.numel() != r or not sigma2.is_cuda):
+        raise ValueError("sigma2 must be a float64 GPU tensor of r entries")
+    ws = torch.empty(wsz, dtype=torch.uint8, device=U.device)
+    ncoef = n * r - r * (r + 1) // 2
+    coef = torch.empty(max(1, ncoef), dtype=torch.float64, device=U.device)
+    signs = torch.empty(r, dtype=torch.int32, device=U.device)
+    up = torch.empty_like(U)
+    dt = ATC_F64 if U.dtype == torch.float64 else ATC_F32
+    _check(lib.atc_factor_householder(ctypes.c_void_p(U.data_ptr()), dt, n, r,
+                                      _ptr_or_null(sigma2.contiguous() if sigma2 is not None else None),
+                                      _ptr_or_null(coef), _ptr_or_null(signs), _ptr_or_null(up),
+                                      ctypes.c_void_p(ws.data_ptr()), wsz, ctypes.c_void_p(_stream(stream))))
+    return coef[:ncoef], signs, up
+
+
+def factor_from_householder(coef: torch.Tensor, sigma2: Optional[torch.Tensor], n: int, r: int,
+                            dtype=torch.float32, stream=None) -> torch.Tensor:
+    """U' (n x r) from stored reflector entries; see atc_factor_from_householder."""
+    lib = load()
+    if coef.dtype != torch.float64 or not coef.is_cuda:
+        raise ValueError("coef must be a float64 GPU tensor")
+    wsz = lib.atc_householder_workspace_size(int(n), int(r))
+    if wsz == 0:
+        _check(-1)
+    ws = torch.empty(wsz, dtype=torch.uint8, device=coef.device)
+    out = torch.empty((int(n), int(r)), dtype=dtype, device=coef.device)
+    if coef.numel() == 0:  # nothing stored (r = n = 1): any non-NULL pointer
+        coef = torch.zeros(1, dtype=torch.float64, device=out.device)
+    dt = ATC_F64 if dtype == torch.float64 else ATC_F32
+    _check(lib.atc_factor_from_householder(ctypes.c_void_p(coef.data_ptr()),
+                                           _ptr_or_null(sigma2.contiguous() if sigma2 is not None else None),
+                                           int(n), int(r), dt, ctypes.c_void_p(out.data_ptr()),
+                                           ctypes.c_void_p(ws.data_ptr()), wsz, ctypes.c_void_p(_stream(stream))))
+    return out
+
+
+def core_slice_norms(core: torch.Tensor, stream=None) -> List[torch.Tensor]:
+    """Squared slice norms of the core per mode (float64 GPU tensors); see atc_core_slice_norms."""
+    lib = load()
+    _require_gpu(core, "core")
+    s = _shape(list(core.shape), core.dtype)
+    cnt = lib.atc_core_slice_norms_count(ctypes.byref(s))
+    out = torch.empty(cnt, dtype=torch.float64, device=core.device)
+    _check(lib.atc_core_slice_norms(ctypes.c_void_p(core.data_ptr()), ctypes.byref(s),
+                                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream(stream))))
+    return list(torch.split(out, [int(n) for n in core.shape]))
+
+
+def core_apply_signs(core: torch.Tensor, signs: Sequence[torch.Tensor], stream=None) -> torch.Tensor:
+    """Flips the core's slices in place by the per-mode signs; see atc_core_apply_signs."""
+    lib = load()
+    _require_gpu(core, "core")
+    s = _shape(list(core.shape), core.dtype)
+    allsg = torch.cat([g.to(torch.int32) for g in signs]).contiguous()
+    if allsg.numel() != sum(int(n) for n in core.shape):
+        raise ValueError("one sign per slice of every mode")
+    _check(lib.atc_core_apply_signs(ctypes.c_void_p(core.data_ptr()), ctypes.byref(s),
+                                    ctypes.c_void_p(allsg.data_ptr()), ctypes.c_void_p(_stream(stream))))
+    return core
+
+
+def factor_error_term(U: torch.Tensor, Uq: torch.Tensor, sigma2: torch.Tensor, stream=None) -> float:
+    """|dU Sigma|_F^2 of one factor (reads the device result back); see atc_factor_error_term."""
+    lib = load()
+    _require_gpu(U, "U")
+    _require_gpu(Uq, "Uq")
+    if U.shape != Uq.shape or U.dtype != Uq.dtype:
+        raise ValueError("U and Uq must match")
+    out = torch.empty(1, dtype=torch.float64, device=U.device)
+    dt = ATC_F64 if U.dtype == torch.float64 else ATC_F32
+    _check(lib.atc_factor_error_term(ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(Uq.data_ptr()), dt,
+                                     int(U.shape[0]), int(U.shape[1]), ctypes.c_void_p(sigma2.contiguous().data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream(stream))))
+    return float(out.item())
+
+
+# ------------------------------------------------------------- hybrid compressor
+@dataclass
+class Compressed:
+    tucker: Tucker                     # the ST-HOSVD (core and factors before quantization)
+    core_stream: QuantStream           # the quantized core (slices flipped by the factor signs)
+    factor_coef: List[torch.Tensor]    # weighted reflector entries per mode (before quantization)
+    factor_streams: List[Optional[QuantStream]]  # their quantized streams (None: nothing to store)
+    signs: List[torch.Tensor]
+    sigma2: List[torch.Tensor]         # squared slice norms of the quantized core, per mode
+    core_q: torch.Tensor               # dequantized core
+    factors_q: List[torch.Tensor]      # factors rebuilt from the quantized reflectors
+    factors_signed: List[torch.Tensor] # U diag(signs): the factors the quantized ones approximate
+    predicted_sse: float               # eq. (total_error_approximation)
+    terms: dict
+    target_sse: float
+
+
+def compress(x: torch.Tensor, rel_error: float = 1e-3, rtmss: float = 0.5, precision: str = "bf16x3",
+             block_len: int = 1024, factor_share: float = 0.01, stream=None) -> Compressed:
+    """The hybrid truncation of Section 4.1.3 end to end on the GPU: ST-HOSVD to
+    rtmss * (rel_error |x|)^2; the core quantized (Sections 3.3, 4.2, 4.3) to
+    the rest of the target; each factor in its Householder form with the
+    weights of supplement S.2, quantized to factor_share of the target split
+    over the modes; the error predicted by eq. (total_error_approximation).
+    Every step runs in the library's kernels; this function sequences them and
+    forms the targets."""
+    t = sthosvd(x, rel_error, precision, rtmss=rtmss, stream=stream)
+    d = len(t.ranks)
+    target = rel_error * rel_error * t.norm2
+    core = t.core.contiguous().clone()
+    # column signs of the Householder form; the core's slices follow them
+    signs, signed = [], []
+    for k in range(d):
+        _, sg, up = factor_householder(t.factors[k].contiguous(), None, stream=stream)
+        signs.append(sg)
+        signed.append(up)
+    core_apply_signs(core, signs, stream=stream)
+    cs = quantize_core(core, target - t.sse_pred, block_len, stream=stream)
+    core_q = dequantize_core(cs.words, cs.n, block_len, core.dtype, stream=stream).view(*t.ranks)
+    s2 = core_slice_norms(core_q, stream=stream)
+    coefs, fstreams, facs_q, fterms = [], [], [], []
+    for k in range(d):
+        n, r = int(signed[k].shape[0]), int(signed[k].shape[1])
+        coef, _, _ = factor_householder(signed[k], s2[k], stream=stream)
+        coefs.append(coef)
+        if coef.numel() > 0:
+            fs = quantize_core(coef, factor_share * target / d, block_len, stream=stream)
+            cq = dequantize_core(fs.words, fs.n, block_len, torch.float64, stream=stream)
+        else:
+            fs, cq = None, coef
+        fstreams.append(fs)
+        uq = factor_from_householder(cq, s2[k], n, r, signed[k].dtype, stream=stream)
+        facs_q.append(uq)
+        fterms.append(factor_error_term(signed[k], uq, s2[k], stream=stream))
+    pred = t.sse_pred + cs.sse + sum(fterms)
+    return Compressed(tucker=t, core_stream=cs, factor_coef=coefs, factor_streams=fstreams, signs=signs, sigma2=s2,
+                      core_q=core_q, factors_q=facs_q, factors_signed=signed, predicted_sse=pred,
+                      terms={"sthosvd": t.sse_pred, "core": cs.sse, "factors": fterms}, target_sse=target)
+
+
+def decompress(c: Compressed, stream=None) -> torch.Tensor:
+    """A~ = (U~_0, ..., U~_{d-1}) . B~ from the quantized core and factors."""
+    return reconstruct(c.core_q.contiguous(), [f.contiguous() for f in c.factors_q], stream=stream)
