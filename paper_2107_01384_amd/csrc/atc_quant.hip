@@ -14,16 +14,18 @@
 //   k_q_max        max |b| (bit pattern of the double, atomicMax) + non-finite
 //   k_q_planes     per block: q_i (kept in the workspace), and for every plane
 //                  p in 0..64 the block's error with all its planes >= p known
-//   k_q_plane_pick one workgroup: the core's error at the end of every plane,
-//                  the breakpoint plane P (the first whose end reaches T), the
-//                  error at the start of every block on plane P
+//   k_q_plane_sums one workgroup per plane: the core's error at its end
+//   k_q_plane_pick the breakpoint plane P (the first whose end reaches T)
+//   k_q_run_start  one workgroup: the error at the start of every block on
+//                  plane P (a scan over blocks)
 //   k_q_cross      per block: walk of plane P with exact prefix sums, first
 //                  position where the running error reaches T (atomicMin)
 //   k_q_block_sse  per block: coefficients encoded on plane P, exact error
 //   k_q_segment<0> per (block, plane >= P) wavefront: run bytes, sign bits and
 //                  trailing bits of that plane's segment of the block
-//   k_q_layout     one workgroup: segment offsets, block sizes, stream header,
-//                  final error at the breakpoint, the caller's info record
+//   k_q_seg_offsets one wavefront per block: segment offsets (scan over planes)
+//   k_q_layout     one workgroup: block offsets (scan over blocks), stream
+//                  header, final error at the breakpoint, the info record
 //   k_q_fill       the stream body cleared (its words are OR-ed into), then
 //                  k_q_block_headers
 //   k_q_segment<1> per (block, plane) wavefront: the segment's bits and bytes
@@ -42,6 +44,9 @@ constexpr uint32_t QMAGIC = 0x51435441u;   // 'ATCQ'
 constexpr int QHEADER = 10;                // stream header words
 constexpr int QBLK_HDR = 3;                // block header words
 constexpr int QMAX_BLOCK = 4096;           // longest block (decoder keeps it in LDS)
+// run bytes of a block of QMAX_BLOCK coefficients: one run per coefficient plus
+// a final one per plane, at most 2 bytes each
+constexpr int QMAX_RUN_WORDS = (2 * (QMAX_BLOCK + 64) + 3) / 4;
 
 // ------------------------------------------------------------ 192-bit integers
 struct U192 {
@@ -122,6 +127,7 @@ struct QState {
     U192 sse_bp;                  // exact error at the breakpoint
     int64_t total_words;
     int32_t pad[6];
+    U192 S[65];                   // the core's error with every plane >= p known, p = 0..64
 };
 
 struct QBlk {
@@ -283,16 +289,33 @@ __device__ U192 scaled_target(double t, int32_t k) {
     return r;
 }
 
-__global__ void __launch_bounds__(256) k_q_plane_pick(int64_t nb, double target, QWs w) {
-    __shared__ U192 S[65];
-    const int tid = threadIdx.x;
-    if (tid < 65) {
-        U192 s = u192_zero();
-        for (int64_t b = 0; b < nb; ++b) u192_add(s, w.part[(size_t)b * 65 + tid]);
-        S[tid] = s;
-    }
+// Block-wide sum of one U192 per thread in a fixed order (LDS tree).
+__device__ U192 block_sum_u192(U192 v, U192* red) {
+    red[threadIdx.x] = v;
     __syncthreads();
-    if (tid != 0) return;
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) u192_add(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    const U192 t = red[0];
+    __syncthreads();
+    return t;
+}
+
+// Workgroup p: the core's error with every plane >= p known, summed over the
+// blocks' partials.
+__global__ void __launch_bounds__(256) k_q_plane_sums(int64_t nb, QWs w) {
+    __shared__ U192 red[256];
+    const int p = blockIdx.x;
+    U192 s = u192_zero();
+    for (int64_t b = threadIdx.x; b < nb; b += 256) u192_add(s, w.part[(size_t)b * 65 + p]);
+    const U192 t = block_sum_u192(s, red);
+    if (threadIdx.x == 0) w.st->S[p] = t;
+}
+
+// One thread: scale, target, breakpoint plane.
+__global__ void k_q_plane_pick(double target, QWs w) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
     QState* st = w.st;
     const int32_t k = scale_of(st->maxbits);
     st->k = k;
@@ -308,27 +331,47 @@ __global__ void __launch_bounds__(256) k_q_plane_pick(int64_t nb, double target,
     }
     const U192 T = scaled_target(target, k);
     st->T = T;
-    if (u192_le(S[64], T)) {
+    if (u192_le(st->S[64], T)) {
         st->plane = QPLANES;
         st->count = 0;
         return;
     }
-    int P = 0;
-    bool found = false;
     for (int p = QPLANES - 1; p >= 0; --p)
-        if (u192_le(S[p], T)) {
-            P = p;
-            found = true;
-            break;
+        if (u192_le(st->S[p], T)) {
+            st->plane = p;
+            return;
         }
-    if (!found) {  // cannot happen for T >= 0 (plane 0 ends with no error)
-        st->all_bits = 1;
-        st->plane = 0;
-        return;
+    st->all_bits = 1;  // cannot happen for T >= 0 (plane 0 ends with no error)
+    st->plane = 0;
+}
+
+// The error at the start of every block on plane P: S[P + 1] plus the
+// exclusive prefix over blocks of (block error at P - block error at P + 1).
+// Each thread scans a contiguous run of blocks; the runs' sums are scanned in LDS.
+__global__ void __launch_bounds__(256) k_q_run_start(int64_t nb, QWs w) {
+    __shared__ U192 sums[256];
+    const QState* st = w.st;
+    if (st->all_bits || st->plane >= QPLANES) return;
+    const int P = st->plane;
+    const int64_t per = (nb + 255) / 256;
+    const int64_t b0 = min(nb, (int64_t)threadIdx.x * per), b1 = min(nb, b0 + per);
+    U192 s = u192_zero();
+    for (int64_t b = b0; b < b1; ++b) {
+        u192_add(s, w.part[(size_t)b * 65 + P]);
+        u192_sub(s, w.part[(size_t)b * 65 + P + 1]);
     }
-    st->plane = P;
-    U192 run = S[P + 1];
-    for (int64_t b = 0; b < nb; ++b) {
+    sums[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        U192 v = sums[threadIdx.x];
+        if ((int)threadIdx.x >= o) u192_add(v, sums[threadIdx.x - o]);
+        __syncthreads();
+        sums[threadIdx.x] = v;
+        __syncthreads();
+    }
+    U192 run = st->S[P + 1];
+    if (threadIdx.x > 0) u192_add(run, sums[threadIdx.x - 1]);
+    for (int64_t b = b0; b < b1; ++b) {
         w.run_start[b] = run;
         u192_add(run, w.part[(size_t)b * 65 + P]);
         u192_sub(run, w.part[(size_t)b * 65 + P + 1]);
@@ -521,52 +564,93 @@ __global__ void __launch_bounds__(64) k_q_segment(int64_t n, int len, QWs w, uin
     }
 }
 
-// One workgroup: segment offsets (planes 63 .. P within each block), block
-// sizes and offsets, the stream header, the final error, the info record.
+// One wavefront per block: segment offsets within the block's three fields,
+// planes 63 .. P in that order (lane l holds plane 63 - l), and the block's
+// field sizes.
+__global__ void __launch_bounds__(64) k_q_seg_offsets(QWs w) {
+    const int P = w.st->plane;
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int p = QPLANES - 1 - lane;
+    const uint32_t* c = w.cnt + ((size_t)b * QPLANES + p) * 3;
+    uint32_t v[3] = {0, 0, 0};
+    if (p >= P) {
+        v[0] = c[0];
+        v[1] = c[1];
+        v[2] = c[2];
+    }
+    uint32_t* o = w.off + ((size_t)b * QPLANES + p) * 3;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        // inclusive scan over lanes (planes from the top)
+        uint32_t x = v[f];
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d);
+            if (lane >= d) x += y;
+        }
+        o[f] = x - v[f];
+        const uint32_t tot = __shfl(x, 63);
+        if (lane == 0) {
+            if (f == 0) w.blk[b].nrb = tot;
+            if (f == 1) w.blk[b].nsb = tot;
+            if (f == 2) w.blk[b].ntb = tot;
+        }
+    }
+}
+
+__device__ __forceinline__ int64_t block_words(const QBlk& bk) {
+    return QBLK_HDR + (bk.nrb + 3) / 4 + (bk.nsb + 31) / 32 + (bk.ntb + 31) / 32;
+}
+
+// One workgroup: block word offsets (scan over blocks), the exact error at
+// the breakpoint (sum over blocks), the stream header and block sizes, the
+// caller's info record.
 __global__ void __launch_bounds__(256) k_q_layout(int64_t n, int len, int64_t nb, QWs w, uint32_t* __restrict__ out,
                                                   size_t out_words, atc_quant_info* info) {
+    __shared__ int64_t wsum[256];
+    __shared__ U192 red[256];
     const QState* st = w.st;
     const int P = st->plane;
-    // per block: prefix over planes (each thread a range of blocks)
-    for (int64_t b = threadIdx.x; b < nb; b += 256) {
-        uint32_t r = 0, s = 0, t = 0;
-        for (int p = QPLANES - 1; p >= 0; --p) {
-            uint32_t* o = w.off + ((size_t)b * QPLANES + p) * 3;
-            const uint32_t* c = w.cnt + ((size_t)b * QPLANES + p) * 3;
-            o[0] = r;
-            o[1] = s;
-            o[2] = t;
-            if (p >= P) {
-                r += c[0];
-                s += c[1];
-                t += c[2];
-            }
-        }
-        w.blk[b].nrb = r;
-        w.blk[b].nsb = s;
-        w.blk[b].ntb = t;
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    int64_t pos = QHEADER + 2 * nb;
+    const int64_t per = (nb + 255) / 256;
+    const int64_t b0 = min(nb, (int64_t)threadIdx.x * per), b1 = min(nb, b0 + per);
+    int64_t mine = 0;
     U192 sse = u192_zero();
-    for (int64_t b = 0; b < nb; ++b) {
-        QBlk& bk = w.blk[b];
-        const int64_t words = QBLK_HDR + (bk.nrb + 3) / 4 + (bk.nsb + 31) / 32 + (bk.ntb + 31) / 32;
-        bk.word_off = pos;
-        pos += words;
+    for (int64_t b = b0; b < b1; ++b) {
+        mine += block_words(w.blk[b]);
         u192_add(sse, w.sse_part[b]);
     }
+    wsum[threadIdx.x] = mine;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int64_t v = wsum[threadIdx.x] + ((int)threadIdx.x >= o ? wsum[threadIdx.x - o] : 0);
+        __syncthreads();
+        wsum[threadIdx.x] = v;
+        __syncthreads();
+    }
+    const int64_t total = QHEADER + 2 * nb + wsum[255];
+    int64_t pos = QHEADER + 2 * nb + (threadIdx.x > 0 ? wsum[threadIdx.x - 1] : 0);
+    const bool fits = (size_t)total <= out_words;
+    for (int64_t b = b0; b < b1; ++b) {
+        QBlk& bk = w.blk[b];
+        const int64_t words = block_words(bk);
+        bk.word_off = pos;
+        pos += words;
+        if (fits) {
+            out[QHEADER + 2 * b] = (uint32_t)(uint64_t)words;
+            out[QHEADER + 2 * b + 1] = (uint32_t)((uint64_t)words >> 32);
+        }
+    }
+    const U192 sse_all = block_sum_u192(sse, red);
+    if (threadIdx.x != 0) return;
     QState* stw = w.st;
     int64_t count;
     if (st->all_bits) count = n;
     else if (P >= QPLANES) count = 0;
     else count = (int64_t)st->first + 1;
     stw->count = count;
-    stw->sse_bp = sse;
-    stw->total_words = pos;
+    stw->sse_bp = sse_all;
+    stw->total_words = total;
     const int32_t k = st->k;
-    const bool fits = (size_t)pos <= out_words;
     if (fits) {
         out[0] = QMAGIC;
         out[1] = (uint32_t)k;
@@ -578,12 +662,6 @@ __global__ void __launch_bounds__(256) k_q_layout(int64_t n, int len, int64_t nb
         out[7] = (uint32_t)((uint64_t)count >> 32);
         out[8] = (uint32_t)(uint64_t)nb;
         out[9] = (uint32_t)((uint64_t)nb >> 32);
-        for (int64_t b = 0; b < nb; ++b) {
-            const QBlk& bk = w.blk[b];
-            const int64_t words = QBLK_HDR + (bk.nrb + 3) / 4 + (bk.nsb + 31) / 32 + (bk.ntb + 31) / 32;
-            out[QHEADER + 2 * b] = (uint32_t)(uint64_t)words;
-            out[QHEADER + 2 * b + 1] = (uint32_t)((uint64_t)words >> 32);
-        }
     }
     if (info) {
         info->status = st->nonfinite ? ATC_ERR_NONFINITE_INPUT : fits ? ATC_OK : ATC_ERR_WORKSPACE_TOO_SMALL;
@@ -593,8 +671,8 @@ __global__ void __launch_bounds__(256) k_q_layout(int64_t n, int len, int64_t nb
         info->n = n;
         info->count = count;
         info->nblocks = nb;
-        info->words = pos;
-        const double s_units = u192_to_double(sse);
+        info->words = total;
+        const double s_units = u192_to_double(sse_all);
         info->sse = (k == QKZERO || st->nonfinite) ? 0.0 : ldexp(s_units, -2 * k);
         info->pad = 0;
     }
@@ -621,21 +699,36 @@ __global__ void k_q_block_headers(int64_t nb, QWs w, uint32_t* __restrict__ out,
 }
 
 // ------------------------------------------------------------ decoding
-// Block offsets from the recorded sizes, after checking the header against
-// the caller's n and block length (a mismatch marks every block unreadable).
-__global__ void __launch_bounds__(64) k_dq_offsets(const uint32_t* __restrict__ in, int64_t n, int len, int64_t nb,
-                                                   int64_t* boff, int32_t* status) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Block offsets from the recorded sizes (scan over blocks in one workgroup),
+// after checking the header against the caller's n and block length (a
+// mismatch marks every block unreadable).
+__global__ void __launch_bounds__(256) k_dq_offsets(const uint32_t* __restrict__ in, int64_t n, int len, int64_t nb,
+                                                    int64_t* boff, int32_t* status) {
+    __shared__ int64_t wsum[256];
     const uint64_t hn = (uint64_t)in[4] | ((uint64_t)in[5] << 32);
     const uint64_t hnb = (uint64_t)in[8] | ((uint64_t)in[9] << 32);
     const bool ok = in[0] == QMAGIC && in[3] == (uint32_t)len && hn == (uint64_t)n && hnb == (uint64_t)nb &&
                     in[2] <= (uint32_t)QPLANES;
-    int64_t pos = QHEADER + 2 * nb;
-    for (int64_t b = 0; b < nb; ++b) {
+    const int64_t per = (nb + 255) / 256;
+    const int64_t b0 = min(nb, (int64_t)threadIdx.x * per), b1 = min(nb, b0 + per);
+    int64_t mine = 0;
+    if (ok)
+        for (int64_t b = b0; b < b1; ++b)
+            mine += (int64_t)((uint64_t)in[QHEADER + 2 * b] | ((uint64_t)in[QHEADER + 2 * b + 1] << 32));
+    wsum[threadIdx.x] = mine;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+        const int64_t v = wsum[threadIdx.x] + ((int)threadIdx.x >= o ? wsum[threadIdx.x - o] : 0);
+        __syncthreads();
+        wsum[threadIdx.x] = v;
+        __syncthreads();
+    }
+    int64_t pos = QHEADER + 2 * nb + (threadIdx.x > 0 ? wsum[threadIdx.x - 1] : 0);
+    for (int64_t b = b0; b < b1; ++b) {
         boff[b] = ok ? pos : -1;
         if (ok) pos += (int64_t)((uint64_t)in[QHEADER + 2 * b] | ((uint64_t)in[QHEADER + 2 * b + 1] << 32));
     }
-    if (!ok && status) atomicOr(status, 2);
+    if (!ok && threadIdx.x == 0 && status) atomicOr(status, 2);
 }
 
 __device__ __forceinline__ uint32_t read_byte(const uint32_t* __restrict__ w, uint32_t i) {
@@ -653,6 +746,7 @@ __global__ void __launch_bounds__(64) k_dq_decode(const uint32_t* __restrict__ i
                                                   int32_t* status) {
     __shared__ uint64_t mag[QMAX_BLOCK];
     __shared__ uint8_t negs[QMAX_BLOCK];
+    __shared__ uint32_t runs_lds[QMAX_RUN_WORDS];   // the block's run bytes (parsed serially)
     const int lane = threadIdx.x;
     const int b = blockIdx.x;
     if (boff[b] < 0) {   // header did not match: zeros
@@ -672,12 +766,16 @@ __global__ void __launch_bounds__(64) k_dq_decode(const uint32_t* __restrict__ i
     __syncthreads();
     const uint32_t* blk = in + boff[b];
     const uint32_t nrb = blk[0], nsb = blk[1], ntb = blk[2];
-    const uint32_t* runs = blk + QBLK_HDR;
-    const uint32_t* signs = runs + (nrb + 3) / 4;
+    const uint32_t* runs_g = blk + QBLK_HDR;
+    const uint32_t* signs = runs_g + (nrb + 3) / 4;
     const uint32_t* trail = signs + (nsb + 31) / 32;
     uint32_t rpos = 0, spos = 0, tpos = 0;
-    bool bad = false;
-    for (int p = QPLANES - 1; p >= P && k != QKZERO; --p) {
+    bool bad = (nrb + 3) / 4 > (uint32_t)QMAX_RUN_WORDS;
+    if (!bad)
+        for (uint32_t i = lane; i < (nrb + 3) / 4; i += 64) runs_lds[i] = runs_g[i];
+    __syncthreads();
+    const uint32_t* runs = runs_lds;
+    for (int p = QPLANES - 1; p >= P && k != QKZERO && !bad; --p) {
         const int upto = p == P ? cb : m;
         // trailing bits of the coefficients significant before this plane
         uint32_t nlead = 0;
@@ -798,10 +896,13 @@ hipError_t launch_quantize(const void* core, int f64, int64_t n, double target, 
     else
         hipLaunchKernelGGL(k_q_planes<float>, dim3((unsigned)nb), dim3(PLANES_THREADS), 0, st, (const float*)core, n,
                            len, w);
-    hipLaunchKernelGGL(k_q_plane_pick, dim3(1), dim3(256), 0, st, nb, target, w);
+    hipLaunchKernelGGL(k_q_plane_sums, dim3(65), dim3(256), 0, st, nb, w);
+    hipLaunchKernelGGL(k_q_plane_pick, dim3(1), dim3(64), 0, st, target, w);
+    hipLaunchKernelGGL(k_q_run_start, dim3(1), dim3(256), 0, st, nb, w);
     hipLaunchKernelGGL(k_q_cross, dim3((unsigned)nb), dim3(CROSS_THREADS), 0, st, n, len, w);
     hipLaunchKernelGGL(k_q_block_sse, dim3((unsigned)nb), dim3(256), 0, st, n, len, w);
     hipLaunchKernelGGL(k_q_segment<false>, dim3((unsigned)nb, QPLANES), dim3(64), 0, st, n, len, w, out, out_words);
+    hipLaunchKernelGGL(k_q_seg_offsets, dim3((unsigned)nb), dim3(64), 0, st, w);
     hipLaunchKernelGGL(k_q_layout, dim3(1), dim3(256), 0, st, n, len, nb, w, out, out_words, info);
     const unsigned gfill = (unsigned)std::min<size_t>(4096, std::max<size_t>(1, (out_words + 255) / 256));
     hipLaunchKernelGGL(k_q_fill, dim3(gfill), dim3(256), 0, st, nb, w, out, out_words);
@@ -816,7 +917,7 @@ hipError_t launch_dequantize(const uint32_t* in, int64_t n, int len, int f64, vo
                              hipStream_t st) {
     const int64_t nb = quant_nblocks(n, len);
     int64_t* boff = (int64_t*)ws;
-    hipLaunchKernelGGL(k_dq_offsets, dim3(1), dim3(64), 0, st, in, n, len, nb, boff, status);
+    hipLaunchKernelGGL(k_dq_offsets, dim3(1), dim3(256), 0, st, in, n, len, nb, boff, status);
     if (f64) hipLaunchKernelGGL(k_dq_decode<double>, dim3((unsigned)nb), dim3(64), 0, st, in, n, len, boff,
                                 (double*)out, status);
     else hipLaunchKernelGGL(k_dq_decode<float>, dim3((unsigned)nb), dim3(64), 0, st, in, n, len, boff, (float*)out,
