@@ -747,6 +747,7 @@ __global__ void __launch_bounds__(64) k_dq_decode(const uint32_t* __restrict__ i
     __shared__ uint64_t mag[QMAX_BLOCK];
     __shared__ uint8_t negs[QMAX_BLOCK];
     __shared__ uint32_t runs_lds[QMAX_RUN_WORDS];   // the block's run bytes (parsed serially)
+    __shared__ uint32_t signs_lds[QMAX_BLOCK / 32];  // its sign bits (one per coefficient at most)
     const int lane = threadIdx.x;
     const int b = blockIdx.x;
     if (boff[b] < 0) {   // header did not match: zeros
@@ -770,9 +771,11 @@ __global__ void __launch_bounds__(64) k_dq_decode(const uint32_t* __restrict__ i
     const uint32_t* signs = runs_g + (nrb + 3) / 4;
     const uint32_t* trail = signs + (nsb + 31) / 32;
     uint32_t rpos = 0, spos = 0, tpos = 0;
-    bool bad = (nrb + 3) / 4 > (uint32_t)QMAX_RUN_WORDS;
-    if (!bad)
+    bool bad = (nrb + 3) / 4 > (uint32_t)QMAX_RUN_WORDS || (nsb + 31) / 32 > (uint32_t)(QMAX_BLOCK / 32);
+    if (!bad) {
         for (uint32_t i = lane; i < (nrb + 3) / 4; i += 64) runs_lds[i] = runs_g[i];
+        for (uint32_t i = lane; i < (nsb + 31) / 32; i += 64) signs_lds[i] = signs[i];
+    }
     __syncthreads();
     const uint32_t* runs = runs_lds;
     for (int p = QPLANES - 1; p >= P && k != QKZERO && !bad; --p) {
@@ -836,10 +839,9 @@ __global__ void __launch_bounds__(64) k_dq_decode(const uint32_t* __restrict__ i
                 ++ci;
                 have = false;
             }
-            // lane of the (at - cum)-th leading position of chunk ci
-            uint64_t mm = lmask;
-            for (uint32_t j = 0; j < at - cum; ++j) mm &= mm - 1;
-            const int tl = __ffsll((long long)mm) - 1;
+            // the lane holding the (at - cum)-th leading position of chunk ci
+            const bool mine = ((lmask >> lane) & 1) && (uint32_t)__popcll(lmask & lanemask_lt(lane)) == at - cum;
+            const int tl = __ffsll((long long)__ballot(mine)) - 1;
             if (spos >= nsb) {
                 bad = true;
                 break;
@@ -847,7 +849,7 @@ __global__ void __launch_bounds__(64) k_dq_decode(const uint32_t* __restrict__ i
             if (lane == tl) {
                 const int i = ci * 64 + tl;
                 mag[i] |= 1ull << p;
-                negs[i] = (uint8_t)read_bit(signs, spos);
+                negs[i] = (uint8_t)read_bit(signs_lds, spos);
             }
             ++spos;
             ++at;   // (a one-bit at the very end is followed by a final run of 0)
