@@ -407,6 +407,16 @@ atc_status atc_factor_householder(const void* U, int32_t dtype, int64_t n, int64
                                   double* coef, int32_t* signs, void* Uprime, void* workspace, size_t workspace_bytes,
                                   void* stream);
 
+/* Scales stored reflector entries in place by the weights of supplement S.2:
+ * the entries of column j (coef as written by atc_factor_householder with
+ * sigma2 NULL, n r - r (r + 1) / 2 DEVICE doubles) are multiplied by
+ * sqrt(2 alpha_j), alpha_j from the r squared slice norms sigma2 (DEVICE) and
+ * n_j = n - j + 1 (1-based j); the result equals atc_factor_householder's
+ * output with the same sigma2.  The reflectors of U diag(s) for any signs s
+ * are those of U, so entries computed before the core is quantized serve
+ * after it.  Grid of (rows, columns) workgroups; no allocation, no host wait. */
+atc_status atc_factor_weight_coefficients(double* coef, const double* sigma2, int64_t n, int64_t r, void* stream);
+
 /* The factor U' = H_1 ... H_r [I_r; 0] from the stored entries (weighted as
  * given to atc_factor_householder when sigma2 is non-NULL; a column whose
  * weight is zero, which happens only when it and every later slice norm are

@@ -112,6 +112,7 @@ SIGNATURES = [
     ("atc_dequantize_core", _I32, [_VP, _I64, _I32, _I32, _VP, _VP, _VP, _SZ, _VP]),
     ("atc_householder_workspace_size", _SZ, [_I64, _I64]),
     ("atc_factor_householder", _I32, [_VP, _I32, _I64, _I64, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    ("atc_factor_weight_coefficients", _I32, [_VP, _VP, _I64, _I64, _VP]),
     ("atc_factor_from_householder", _I32, [_VP, _VP, _I64, _I64, _I32, _VP, _VP, _SZ, _VP]),
     ("atc_core_slice_norms_count", _SZ, [_P(Shape)]),
     ("atc_core_slice_norms", _I32, [_VP, _P(Shape), _VP, _VP]),
@@ -410,10 +411,8 @@ class QuantStream:
     status: int
 
 
-def quantize_core(core: torch.Tensor, target_sse: float, block_len: int = 1024, stream=None) -> QuantStream:
-    """Bit-plane quantization and encoding of `core` (vectorised in C order);
-    see atc_quantize_core.  Reads the device record back (one synchronisation
-    of `stream`)."""
+def _quantize_launch(core: torch.Tensor, target_sse: float, block_len: int, stream=None):
+    """Queues atc_quantize_core; returns (stream buffer of the maximal size, device info record)."""
     lib = load()
     _require_gpu(core, "core")
     n = core.numel()
@@ -428,6 +427,11 @@ def quantize_core(core: torch.Tensor, target_sse: float, block_len: int = 1024, 
     _check(lib.atc_quantize_core(ctypes.c_void_p(core.data_ptr()), dt, n, float(target_sse), int(block_len),
                                  ctypes.c_void_p(enc.data_ptr()), cap, ctypes.c_void_p(info_d.data_ptr()),
                                  ctypes.c_void_p(ws.data_ptr()), wsz, ctypes.c_void_p(_stream(stream))))
+    return enc, info_d
+
+
+def _quantize_finish(enc: torch.Tensor, info_d: torch.Tensor) -> QuantStream:
+    """Reads the device record back (waits for the stream that wrote it)."""
     raw = bytes(info_d.cpu().numpy().tobytes())
     info = QuantInfo.from_buffer_copy(raw)
     if info.status not in (0,):
@@ -437,8 +441,17 @@ def quantize_core(core: torch.Tensor, target_sse: float, block_len: int = 1024, 
                        nblocks=int(info.nblocks), sse=float(info.sse), status=int(info.status))
 
 
-def dequantize_core(words: torch.Tensor, n: int, block_len: int, dtype=torch.float32, stream=None) -> torch.Tensor:
-    """Decoded core (n values, vectorised) of a stream; see atc_dequantize_core."""
+def quantize_core(core: torch.Tensor, target_sse: float, block_len: int = 1024, stream=None) -> QuantStream:
+    """Bit-plane quantization and encoding of `core` (vectorised in C order);
+    see atc_quantize_core.  Reads the device record back (one synchronisation
+    of `stream`)."""
+    return _quantize_finish(*_quantize_launch(core, target_sse, block_len, stream))
+
+
+def _dequantize_launch(words: torch.Tensor, n: int, block_len: int, dtype, status: torch.Tensor,
+                       stream=None) -> torch.Tensor:
+    """Queues atc_dequantize_core; the decoder's flags are OR-ed into `status`
+    (a device int32), read by the caller."""
     lib = load()
     if not isinstance(words, torch.Tensor) or not words.is_cuda or words.dtype != torch.int32:
         raise ValueError("words must be an int32 GPU tensor")
@@ -447,11 +460,17 @@ def dequantize_core(words: torch.Tensor, n: int, block_len: int, dtype=torch.flo
         _check(-1)
     ws = torch.empty(wsz, dtype=torch.uint8, device=words.device)
     out = torch.empty(int(n), dtype=dtype, device=words.device)
-    status = torch.zeros(1, dtype=torch.int32, device=words.device)
     dt = ATC_F64 if dtype == torch.float64 else ATC_F32
     _check(lib.atc_dequantize_core(ctypes.c_void_p(words.data_ptr()), int(n), int(block_len), dt,
                                    ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(status.data_ptr()),
                                    ctypes.c_void_p(ws.data_ptr()), wsz, ctypes.c_void_p(_stream(stream))))
+    return out
+
+
+def dequantize_core(words: torch.Tensor, n: int, block_len: int, dtype=torch.float32, stream=None) -> torch.Tensor:
+    """Decoded core (n values, vectorised) of a stream; see atc_dequantize_core."""
+    status = torch.zeros(1, dtype=torch.int32, device=words.device)
+    out = _dequantize_launch(words, n, block_len, dtype, status, stream)
     if int(status.item()) != 0:
         raise AtcError(-7, "damaged stream: block fields do not match their planes")
     return out
@@ -484,6 +503,24 @@ def factor_householder(U: torch.Tensor, sigma2: Optional[torch.Tensor] = None, s
                                       _ptr_or_null(coef), _ptr_or_null(signs), _ptr_or_null(up),
                                       ctypes.c_void_p(ws.data_ptr()), wsz, ctypes.c_void_p(_stream(stream))))
     return coef[:ncoef], signs, up
+
+
+def factor_weight_coefficients(coef: torch.Tensor, sigma2: torch.Tensor, n: int, r: int, stream=None) -> torch.Tensor:
+    """Scales unweighted reflector entries in place by sqrt(2 alpha_j); see
+    atc_factor_weight_coefficients."""
+    lib = load()
+    if coef.dtype != torch.float64 or not coef.is_cuda or not coef.is_contiguous():
+        raise ValueError("coef must be a contiguous float64 GPU tensor")
+    if sigma2.dtype != torch.float64 or sigma2.numel() != int(r) or not sigma2.is_cuda:
+        raise ValueError("sigma2 must be a float64 GPU tensor of r entries")
+    if coef.numel() != int(n) * int(r) - int(r) * (int(r) + 1) // 2:
+        raise ValueError("coef must hold n r - r (r + 1) / 2 entries")
+    if coef.numel() == 0:
+        return coef
+    _check(lib.atc_factor_weight_coefficients(ctypes.c_void_p(coef.data_ptr()),
+                                              ctypes.c_void_p(sigma2.contiguous().data_ptr()), int(n), int(r),
+                                              ctypes.c_void_p(_stream(stream))))
+    return coef
 
 
 def factor_from_householder(coef: torch.Tensor, sigma2: Optional[torch.Tensor], n: int, r: int,
@@ -532,18 +569,23 @@ def core_apply_signs(core: torch.Tensor, signs: Sequence[torch.Tensor], stream=N
     return core
 
 
-def factor_error_term(U: torch.Tensor, Uq: torch.Tensor, sigma2: torch.Tensor, stream=None) -> float:
-    """|dU Sigma|_F^2 of one factor (reads the device result back); see atc_factor_error_term."""
+def _factor_error_launch(U: torch.Tensor, Uq: torch.Tensor, sigma2: torch.Tensor, out: torch.Tensor, stream=None):
+    """Queues atc_factor_error_term into out (one float64 on the device)."""
     lib = load()
     _require_gpu(U, "U")
     _require_gpu(Uq, "Uq")
     if U.shape != Uq.shape or U.dtype != Uq.dtype:
         raise ValueError("U and Uq must match")
-    out = torch.empty(1, dtype=torch.float64, device=U.device)
     dt = ATC_F64 if U.dtype == torch.float64 else ATC_F32
     _check(lib.atc_factor_error_term(ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(Uq.data_ptr()), dt,
                                      int(U.shape[0]), int(U.shape[1]), ctypes.c_void_p(sigma2.contiguous().data_ptr()),
                                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream(stream))))
+
+
+def factor_error_term(U: torch.Tensor, Uq: torch.Tensor, sigma2: torch.Tensor, stream=None) -> float:
+    """|dU Sigma|_F^2 of one factor (reads the device result back); see atc_factor_error_term."""
+    out = torch.empty(1, dtype=torch.float64, device=U.device)
+    _factor_error_launch(U, Uq, sigma2, out, stream)
     return float(out.item())
 
 
@@ -564,6 +606,18 @@ class Compressed:
     target_sse: float
 
 
+_SIDE_STREAMS = {}
+
+
+def _side_streams(device, count: int) -> List[torch.cuda.Stream]:
+    """Streams of the default priority for the per-factor steps, kept per device."""
+    key = torch.device(device).index
+    lst = _SIDE_STREAMS.setdefault(key, [])
+    while len(lst) < count:
+        lst.append(torch.cuda.Stream(device=device))
+    return lst[:count]
+
+
 def compress(x: torch.Tensor, rel_error: float = 1e-3, rtmss: float = 0.5, precision: str = "bf16x3",
              block_len: int = 1024, factor_share: float = 0.01, stream=None) -> Compressed:
     """The hybrid truncation of Section 4.1.3 end to end on the GPU: ST-HOSVD to
@@ -572,35 +626,72 @@ def compress(x: torch.Tensor, rel_error: float = 1e-3, rtmss: float = 0.5, preci
     weights of supplement S.2, quantized to factor_share of the target split
     over the modes; the error predicted by eq. (total_error_approximation).
     Every step runs in the library's kernels; this function sequences them and
-    forms the targets."""
-    t = sthosvd(x, rel_error, precision, rtmss=rtmss, stream=stream)
+    forms the targets.  The factors' steps run on side streams of their own
+    (forked from `stream` and joined back to it), and the device records are
+    read once, at the end."""
+    main = stream if stream is not None else torch.cuda.current_stream(x.device)
+    with torch.cuda.stream(main):
+        t = sthosvd(x, rel_error, precision, rtmss=rtmss)
     d = len(t.ranks)
     target = rel_error * rel_error * t.norm2
-    core = t.core.contiguous().clone()
-    # column signs of the Householder form; the core's slices follow them
-    signs, signed = [], []
-    for k in range(d):
-        _, sg, up = factor_householder(t.factors[k].contiguous(), None, stream=stream)
-        signs.append(sg)
-        signed.append(up)
-    core_apply_signs(core, signs, stream=stream)
-    cs = quantize_core(core, target - t.sse_pred, block_len, stream=stream)
-    core_q = dequantize_core(cs.words, cs.n, block_len, core.dtype, stream=stream).view(*t.ranks)
-    s2 = core_slice_norms(core_q, stream=stream)
-    coefs, fstreams, facs_q, fterms = [], [], [], []
-    for k in range(d):
+    side = _side_streams(x.device, d)
+
+    def fork_join(work):
+        """work(k) on side stream k for every mode, after what `main` has queued;
+        `main` then waits for all of them."""
+        start = torch.cuda.Event()
+        start.record(main)
+        ends = []
+        for k in range(d):
+            side[k].wait_event(start)
+            with torch.cuda.stream(side[k]):
+                work(k)
+            ev = torch.cuda.Event()
+            ev.record(side[k])
+            ends.append(ev)
+        for ev in ends:
+            main.wait_event(ev)
+
+    # reflectors and column signs of every factor (supplement S.2); the
+    # reflectors of U diag(signs) are those of U, so the unweighted entries
+    # are weighted once the quantized core's slice norms are known
+    hh = [None] * d
+
+    def reflectors(k):
+        hh[k] = factor_householder(t.factors[k].contiguous(), None)
+
+    fork_join(reflectors)
+    signs = [h[1] for h in hh]
+    signed = [h[2] for h in hh]
+    with torch.cuda.stream(main):
+        core = t.core.contiguous().clone()
+        core_apply_signs(core, signs)
+        enc, info = _quantize_launch(core, target - t.sse_pred, block_len)
+        status = torch.zeros(1 + d, dtype=torch.int32, device=x.device)
+        core_q = _dequantize_launch(enc, core.numel(), block_len, core.dtype, status[0:1]).view(*t.ranks)
+        s2 = core_slice_norms(core_q)
+        fterm = torch.zeros(d, dtype=torch.float64, device=x.device)
+    coefs, fq, facs_q = [None] * d, [None] * d, [None] * d
+
+    def factor(k):
         n, r = int(signed[k].shape[0]), int(signed[k].shape[1])
-        coef, _, _ = factor_householder(signed[k], s2[k], stream=stream)
-        coefs.append(coef)
+        coef = factor_weight_coefficients(hh[k][0], s2[k], n, r)
+        coefs[k] = coef
         if coef.numel() > 0:
-            fs = quantize_core(coef, factor_share * target / d, block_len, stream=stream)
-            cq = dequantize_core(fs.words, fs.n, block_len, torch.float64, stream=stream)
+            fq[k] = _quantize_launch(coef, factor_share * target / d, block_len)
+            cq = _dequantize_launch(fq[k][0], coef.numel(), block_len, torch.float64, status[1 + k:2 + k])
         else:
-            fs, cq = None, coef
-        fstreams.append(fs)
-        uq = factor_from_householder(cq, s2[k], n, r, signed[k].dtype, stream=stream)
-        facs_q.append(uq)
-        fterms.append(factor_error_term(signed[k], uq, s2[k], stream=stream))
+            cq = coef
+        facs_q[k] = factor_from_householder(cq, s2[k], n, r, signed[k].dtype)
+        _factor_error_launch(signed[k], facs_q[k], s2[k], fterm[k:k + 1])
+
+    fork_join(factor)
+    main.synchronize()
+    cs = _quantize_finish(enc, info)
+    fstreams = [_quantize_finish(*fq[k]) if fq[k] is not None else None for k in range(d)]
+    if int(status.max().item()) != 0:
+        raise AtcError(-7, "damaged stream: block fields do not match their planes")
+    fterms = [float(v) for v in fterm.cpu().tolist()]
     pred = t.sse_pred + cs.sse + sum(fterms)
     return Compressed(tucker=t, core_stream=cs, factor_coef=coefs, factor_streams=fstreams, signs=signs, sigma2=s2,
                       core_q=core_q, factors_q=facs_q, factors_signed=signed, predicted_sse=pred,

@@ -12,9 +12,9 @@
 // quantized core per mode and |dU Sigma|_F^2 per factor.
 //
 // One workgroup per factor (n <= 4096 rows, r <= 256 columns); the working
-// matrix R sits in the caller's workspace (FP64, L2-resident at these sizes).
-// Reductions run in a fixed order (per-thread strided sums, then wavefront
-// shuffles, then wavefronts in order).
+// matrix sits in the caller's workspace (FP64, column-major, L2-resident at
+// these sizes).  Reductions run in a fixed order (per-thread sums, then
+// wavefront shuffles, then wavefronts in order).
 #include <algorithm>
 #include <cmath>
 
@@ -23,7 +23,7 @@
 namespace atc {
 namespace {
 
-constexpr int HT = 256;          // threads of the Householder workgroup
+constexpr int HT = 256;          // threads of the slice-norm and factor-error workgroups
 constexpr int HW = HT / 64;
 constexpr int64_t HH_MAX_N = 4096;
 constexpr int64_t HH_MAX_R = 256;
@@ -72,123 +72,217 @@ __device__ void column_weights(int64_t n, int r, const double* __restrict__ s2, 
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(HT) k_hh_encode(const T* __restrict__ U, int64_t n, int r,
-                                                  const double* __restrict__ s2, double* __restrict__ coef,
-                                                  int32_t* __restrict__ signs, T* __restrict__ Uprime,
-                                                  double* __restrict__ R) {
-    __shared__ double red[HW];
-    __shared__ double wcol[HH_MAX_R];   // v^T R[:, c], then the column weights
-    __shared__ int32_t sg[HH_MAX_R];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int64_t e = tid; e < n * r; e += HT) R[e] = ld(U, e);
-    __syncthreads();
-    double* vcol = R;  // v_j is kept in column j of R below the diagonal once the column is done
-    for (int j = 0; j < r; ++j) {
-        // x = R[j:, j]; |x|^2
-        double p = 0.0;
-        for (int64_t i = j + tid; i < n; i += HT) {
-            const double x = R[i * r + j];
-            p += x * x;
-        }
-        const double nx = sqrt(block_sum(p, red));
-        const double x0 = R[(int64_t)j * r + j];
-        const double v0 = x0 + (x0 >= 0.0 ? nx : -nx);
-        // |v|^2 = v0^2 + |x[1:]|^2
-        double q = 0.0;
-        for (int64_t i = j + 1 + tid; i < n; i += HT) {
-            const double x = R[i * r + j];
-            q += x * x;
-        }
-        const double nv = sqrt(v0 * v0 + block_sum(q, red));
-        const bool zero = !(nv > 0.0);
-        const double inv = zero ? 0.0 : 1.0 / nv;
-        // w_c = v^T R[j:, c] for c > j, one wavefront per column (strided)
-        for (int c = j + 1 + wave; c < r; c += HW) {
-            double s = 0.0;
-            for (int64_t i = j + lane; i < n; i += 64) {
-                const double v = zero ? (i == j ? 1.0 : 0.0) : (i == j ? v0 : R[i * r + j]) * inv;
-                s += v * R[i * r + c];
-            }
-            s = wave_sum(s);
-            if (lane == 0) wcol[c] = s;
-        }
-        __syncthreads();
-        // R[j:, c] -= 2 v w_c (c > j); column j becomes (R_jj, 0, ..., 0)
-        for (int64_t e = tid; e < (n - j) * (int64_t)(r - j - 1); e += HT) {
-            const int64_t i = j + e / (r - j - 1);
-            const int c = j + 1 + (int)(e % (r - j - 1));
-            const double v = zero ? (i == j ? 1.0 : 0.0) : (i == j ? v0 : R[i * r + j]) * inv;
-            R[i * r + c] -= 2.0 * v * wcol[c];
-        }
-        __syncthreads();
-        // H_j x = -sgn(x0) |x| e_1 for the column itself: R_jj = -sgn(x0) nx
-        if (tid == 0) sg[j] = zero ? 1 : (x0 >= 0.0 ? -1 : 1);
-        // v_j into column j (v_jj > 0: H_j does not change with the sign of v)
-        const double flip = (zero || v0 >= 0.0) ? 1.0 : -1.0;
-        for (int64_t i = j + 1 + tid; i < n; i += HT) vcol[i * r + j] = zero ? 0.0 : flip * R[i * r + j] * inv;
-        __syncthreads();
-    }
-    // weights, coefficients (column by column, rows below the diagonal)
-    column_weights(n, r, s2, wcol);
-    __syncthreads();
-    int64_t base = 0;
-    for (int j = 0; j < r; ++j) {
-        const int64_t m = n - j - 1;
-        for (int64_t i = tid; i < m; i += HT) coef[base + i] = vcol[(j + 1 + i) * r + j] * wcol[j];
-        base += m;
-    }
-    for (int j = tid; j < r; j += HT) signs[j] = sg[j];
-    if (Uprime)
-        for (int64_t e = tid; e < n * r; e += HT) Uprime[e] = (T)(ld(U, e) * (double)sg[e % r]);
+// Work split of the Householder kernels: HHT threads, thread t < S r takes
+// column c = t % r and row slice s = t / r (S = HHT / r slices of
+// consecutive rows), so every dot product of a step is a thread-local sum
+// over its slice, and the S slice partials of a column are summed in order
+// from LDS: two barriers per reflector, no cross-lane shuffles.  The working
+// matrix (row-major, odd row stride) lives in LDS when it fits, else in the
+// workspace.
+constexpr int HHT = 512;
+constexpr size_t HH_LDS_CAP = 128 * 1024;  // bytes of LDS for the working matrix
+
+__host__ __device__ inline int hh_ld(int r) { return r | 1; }
+__host__ __device__ inline int64_t hh_coef_base(int64_t n, int j) { return (int64_t)j * (n - 1) - (int64_t)j * (j - 1) / 2; }
+// whether the working matrix (plus `extra` doubles) fits the LDS budget
+inline bool hh_in_lds(int64_t n, int r, int64_t extra) {
+    return ((size_t)n * hh_ld(r) + (size_t)extra) * sizeof(double) <= HH_LDS_CAP;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(HT) k_hh_decode(const double* __restrict__ coef, const double* __restrict__ s2,
-                                                  int64_t n, int r, T* __restrict__ Uout,
-                                                  double* __restrict__ V, double* __restrict__ X) {
-    __shared__ double red[HW];
+struct HhSlice {
+    int c, s, S, i0, i1;  // column, slice, slices, rows [i0, i1)
+    bool on;
+};
+__device__ __forceinline__ HhSlice hh_slice(int64_t n, int r) {
+    HhSlice h;
+    const int t = threadIdx.x;
+    h.S = HHT / r;
+    h.on = t < h.S * r;
+    h.c = t % r;
+    h.s = t / r;
+    const int L = (int)((n + h.S - 1) / h.S);
+    h.i0 = h.on ? min((int64_t)h.s * L, n) : 0;
+    h.i1 = h.on ? min((int64_t)(h.s + 1) * L, n) : 0;
+    return h;
+}
+
+// Two sums over the S slice partials, sum_s a[s * sa] and sum_s b[s * sb],
+// each in slice order, with eight LDS loads of each in flight (the missing
+// entries of the last batch count as zeros).
+__device__ __forceinline__ void slice_sums(const double* a, int sa, const double* b, int sb, int S, double& ta,
+                                           double& tb) {
+    ta = 0.0;
+    tb = 0.0;
+    for (int s = 0; s < S; s += 8) {
+        double va[8], vb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const bool in = s + u < S;
+            va[u] = in ? a[(s + u) * sa] : 0.0;
+            vb[u] = in ? b[(s + u) * sb] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            ta += va[u];
+            tb += vb[u];
+        }
+    }
+}
+
+// Householder QR of U (n x r), column by column (supplement S.2).  Step j
+// takes x = R[j:, j], |v|^2 = 2 |x| (|x| + |x_0|) for v = x + sgn(x_0) |x| e_1,
+// and w_c = v^T R[j:, c] = x^T R[j:, c] + sgn(x_0) |x| R[j][c] for the later
+// columns, then R[j:, c] -= 2 v w_c / |v|^2.  Column j itself is not
+// rewritten: v_j / |v| (sign so that v_jj > 0), weighted, goes straight to the
+// coefficients.  R[j][c] and x_0 are read before the first barrier, since
+// the thread of row j updates them after it.
+template <typename T, bool LDS>
+__global__ void __launch_bounds__(HHT) k_hh_encode(const T* __restrict__ U, int64_t n, int r,
+                                                   const double* __restrict__ s2, double* __restrict__ coef,
+                                                   int32_t* __restrict__ signs, T* __restrict__ Uprime,
+                                                   double* __restrict__ Rg) {
+    extern __shared__ double hh_lds[];
+    __shared__ double part[HHT];
     __shared__ double wcol[HH_MAX_R];
-    __shared__ double ycol[HH_MAX_R];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ int32_t sg[HH_MAX_R];
+    const int ld = hh_ld(r);
+    double* R = LDS ? hh_lds : Rg;
+    const HhSlice h = hh_slice(n, r);
+    const int nr = (int)n * r;  // at most 4096 x 256
+    for (int e = threadIdx.x; e < nr; e += HHT) {
+        const int i = e / r;
+        R[(int64_t)i * ld + (e - i * r)] = (double)U[e];
+    }
     column_weights(n, r, s2, wcol);
     __syncthreads();
-    // V: unweighted coefficients, v_jj from the unit norm
-    int64_t base = 0;
     for (int j = 0; j < r; ++j) {
-        const int64_t m = n - j - 1;
-        double p = 0.0;
-        for (int64_t i = tid; i < m; i += HT) {
-            // a zero weight only ends the factor: every later slice norm is zero
-            // too, so those columns multiply nothing and their reflectors are e_j
-            const double v = wcol[j] > 0.0 ? coef[base + i] / wcol[j] : 0.0;
-            V[(j + 1 + i) * r + j] = v;
-            p += v * v;
+        // phase A: slice partials of |x|^2 (column j) or x^T R[:, c] (c > j)
+        const bool act = h.on && h.c >= j;
+        double p = 0.0, rjc = 0.0, x0 = 0.0;
+        if (act) {
+            rjc = R[(int64_t)j * ld + h.c];
+            x0 = R[(int64_t)j * ld + j];
+#pragma unroll 4
+            for (int i = max(h.i0, j); i < h.i1; ++i) p += R[(int64_t)i * ld + j] * R[(int64_t)i * ld + h.c];
+            part[h.s * r + h.c] = p;
         }
-        const double t = block_sum(p, red);
-        if (tid == 0) V[(int64_t)j * r + j] = sqrt(fmax(0.0, 1.0 - t));
-        for (int64_t i = tid; i < j; i += HT) V[i * r + j] = 0.0;
-        base += m;
+        __syncthreads();
+        // phase B: the reflector, then the owned slice of column c
+        if (act) {
+            double xx, wsum;
+            slice_sums(part + j, r, part + h.c, r, h.S, xx, wsum);
+            const double nx = sqrt(xx);
+            const double sgn = x0 >= 0.0 ? 1.0 : -1.0;
+            const double v0 = x0 + sgn * nx;
+            const double nv2 = 2.0 * nx * (nx + fabs(x0));
+            const bool zero = !(nv2 > 0.0);
+            if (h.c == j) {
+                // v_j / |v| below the diagonal, weighted
+                const double sc = zero ? 0.0 : (v0 >= 0.0 ? 1.0 : -1.0) / sqrt(nv2) * wcol[j];
+                const int64_t base = hh_coef_base(n, j) - j - 1;
+                for (int i = max(h.i0, j + 1); i < h.i1; ++i) coef[base + i] = sc * R[(int64_t)i * ld + j];
+                if (h.s == 0) sg[j] = zero ? 1 : (x0 >= 0.0 ? -1 : 1);
+            } else {
+                const double w = zero ? rjc : wsum + sgn * nx * rjc;
+                const double gw = (zero ? 2.0 : 2.0 / nv2) * w;
+                const double vj = zero ? 1.0 : v0;
+                if (h.i0 <= j && j < h.i1) R[(int64_t)j * ld + h.c] -= gw * vj;
+                if (!zero)
+#pragma unroll 4
+                    for (int i = max(h.i0, j + 1); i < h.i1; ++i)
+                        R[(int64_t)i * ld + h.c] -= gw * R[(int64_t)i * ld + j];
+            }
+        }
+        __syncthreads();
     }
-    // X = first r columns of the identity, then H_r .. H_1 applied in turn
-    for (int64_t e = tid; e < n * r; e += HT) X[e] = (e / r == e % r) ? 1.0 : 0.0;
+    if (Uprime)
+        for (int e = threadIdx.x; e < nr; e += HHT) Uprime[e] = (T)((double)U[e] * (double)sg[e % r]);
+    for (int j = threadIdx.x; j < r; j += HHT) signs[j] = sg[j];
+}
+
+// U' = H_1 ... H_r [I_r; 0] from the weighted coefficients, the reflectors
+// applied from H_r down to H_1.  Before H_j is applied, row j and the columns
+// before j are still those of the identity, so step j only touches columns
+// j .. r - 1 and y_c = v_j^T X[:, c] = (sum over rows below j) + v_jj [c == j];
+// v_jj = sqrt(max(0, 1 - sum of the stored entries' squares)) comes from the
+// slice partials of column j's threads.  v_j (unweighted) is staged in LDS,
+// the next reflector's while the current one is applied.
+template <typename T, bool LDS>
+__global__ void __launch_bounds__(HHT) k_hh_decode(const double* __restrict__ coef, const double* __restrict__ s2,
+                                                   int64_t n, int r, T* __restrict__ Uout, double* __restrict__ Xg) {
+    extern __shared__ double hh_lds[];
+    __shared__ double part[HHT];
+    __shared__ double partv[HHT];
+    __shared__ double wcol[HH_MAX_R];
+    const int ld = hh_ld(r);
+    double* vbuf = hh_lds;                     // 2 x n
+    double* X = LDS ? hh_lds + 2 * n : Xg;    // n x ld
+    const HhSlice h = hh_slice(n, r);
+    column_weights(n, r, s2, wcol);
+    const int nr = (int)n * r;  // at most 4096 x 256
+    for (int e = threadIdx.x; e < nr; e += HHT) {
+        const int i = e / r, c = e - i * r;
+        X[(int64_t)i * ld + c] = (i == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // a zero weight only ends the factor: every later slice norm is zero too,
+    // so those columns multiply nothing and their reflectors are e_j
+    auto stage = [&](int j, double* vb) {
+        const double wj = wcol[j];
+        const int64_t base = hh_coef_base(n, j) - j - 1;
+        for (int64_t i = threadIdx.x; i < n; i += HHT) vb[i] = (i > j && wj > 0.0) ? coef[base + i] / wj : 0.0;
+    };
+    stage(r - 1, vbuf + ((r - 1) & 1) * n);
     __syncthreads();
     for (int j = r - 1; j >= 0; --j) {
-        for (int c = wave; c < r; c += HW) {
-            double s = 0.0;
-            for (int64_t i = j + lane; i < n; i += 64) s += V[i * r + j] * X[i * r + c];
-            s = wave_sum(s);
-            if (lane == 0) ycol[c] = s;
+        const double* v = vbuf + (j & 1) * n;
+        const bool act = h.on && h.c >= j;
+        if (act) {
+            double p = 0.0, q = 0.0;
+#pragma unroll 4
+            for (int i = max(h.i0, j + 1); i < h.i1; ++i) {
+                const double vi = v[i];
+                p += vi * X[(int64_t)i * ld + h.c];
+                q += vi * vi;
+            }
+            part[h.s * r + h.c] = p;
+            if (h.c == j) partv[h.s] = q;
         }
         __syncthreads();
-        for (int64_t e = tid; e < (n - j) * (int64_t)r; e += HT) {
-            const int64_t i = j + e / r;
-            const int c = (int)(e % r);
-            X[i * r + c] -= 2.0 * V[i * r + j] * ycol[c];
+        if (j > 0) stage(j - 1, vbuf + ((j - 1) & 1) * n);
+        if (act) {
+            double vv, y;
+            slice_sums(partv, 1, part + h.c, r, h.S, vv, y);
+            const double vjj = sqrt(fmax(0.0, 1.0 - vv));
+            if (h.c == j) y += vjj;
+            const double y2 = 2.0 * y;
+            if (h.i0 <= j && j < h.i1) X[(int64_t)j * ld + h.c] -= y2 * vjj;
+#pragma unroll 4
+            for (int i = max(h.i0, j + 1); i < h.i1; ++i) X[(int64_t)i * ld + h.c] -= y2 * v[i];
         }
         __syncthreads();
     }
-    for (int64_t e = tid; e < n * r; e += HT) Uout[e] = (T)X[e];
+    for (int e = threadIdx.x; e < nr; e += HHT) {
+        const int i = e / r;
+        Uout[e] = (T)X[(int64_t)i * ld + (e - i * r)];
+    }
+}
+
+// coef of column j (blockIdx.y) times sqrt(2 alpha_j); each workgroup forms
+// its column's weight from the slice norms after it.
+__global__ void __launch_bounds__(256) k_hh_weight(double* __restrict__ coef, const double* __restrict__ s2, int64_t n,
+                                                   int r) {
+    __shared__ double wj;
+    const int j = blockIdx.y;
+    if (threadIdx.x == 0) {
+        double rest = 0.0;
+        for (int k = r - 1; k > j; --k) rest += s2[k];
+        wj = sqrt(2.0 * alpha_of(n, j, r, s2[j], rest));
+    }
+    __syncthreads();
+    const int64_t m = n - j - 1;
+    const int64_t base = hh_coef_base(n, j);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) coef[base + i] *= wj;
 }
 
 // Squared slice norms of the core in every mode: one workgroup per (mode,
@@ -256,6 +350,26 @@ __global__ void __launch_bounds__(HT) k_factor_error(const T* __restrict__ U, co
     if (threadIdx.x == 0) *out = t;
 }
 
+// Dynamic LDS beyond the default limit for the eight kernel instances, once.
+bool hh_lds_ready() {
+    static int state = 0;
+    if (state == 0) {
+        const int cap = (int)HH_LDS_CAP;  // also covers the decoder's 2 n staged entries (n <= 4096)
+        const void* ks[] = {reinterpret_cast<const void*>(&k_hh_encode<float, true>),
+                            reinterpret_cast<const void*>(&k_hh_encode<float, false>),
+                            reinterpret_cast<const void*>(&k_hh_encode<double, true>),
+                            reinterpret_cast<const void*>(&k_hh_encode<double, false>),
+                            reinterpret_cast<const void*>(&k_hh_decode<float, true>),
+                            reinterpret_cast<const void*>(&k_hh_decode<float, false>),
+                            reinterpret_cast<const void*>(&k_hh_decode<double, true>),
+                            reinterpret_cast<const void*>(&k_hh_decode<double, false>)};
+        bool ok = true;
+        for (const void* k : ks) ok = ok && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, cap) == hipSuccess;
+        state = ok ? 1 : -1;
+    }
+    return state == 1;
+}
+
 atc_status hfail(atc_status s, const char* msg) {
     set_last_error(msg);
     return s;
@@ -289,12 +403,18 @@ atc_status atc_factor_householder(const void* U, int32_t dtype, int64_t n, int64
     if (workspace_bytes < atc_householder_workspace_size(n, r)) return hfail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
     hipStream_t st = (hipStream_t)stream;
     double* R = (double*)workspace;
-    if (dtype == ATC_F64)
-        hipLaunchKernelGGL(k_hh_encode<double>, dim3(1), dim3(HT), 0, st, (const double*)U, n, (int)r, sigma2, coef,
-                           signs, (double*)Uprime, R);
-    else
-        hipLaunchKernelGGL(k_hh_encode<float>, dim3(1), dim3(HT), 0, st, (const float*)U, n, (int)r, sigma2, coef,
-                           signs, (float*)Uprime, R);
+    const bool lds = hh_in_lds(n, (int)r, 0);
+    const size_t shm = lds ? (size_t)n * hh_ld((int)r) * sizeof(double) : 0;
+    if (!hh_lds_ready()) return hfail(ATC_ERR_DEVICE, "could not raise the LDS limit of the Householder kernels");
+    if (dtype == ATC_F64) {
+        auto k = lds ? k_hh_encode<double, true> : k_hh_encode<double, false>;
+        hipLaunchKernelGGL(k, dim3(1), dim3(HHT), shm, st, (const double*)U, n, (int)r, sigma2, coef, signs,
+                           (double*)Uprime, R);
+    } else {
+        auto k = lds ? k_hh_encode<float, true> : k_hh_encode<float, false>;
+        hipLaunchKernelGGL(k, dim3(1), dim3(HHT), shm, st, (const float*)U, n, (int)r, sigma2, coef, signs,
+                           (float*)Uprime, R);
+    }
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? ATC_OK : hfail(ATC_ERR_DEVICE, hipGetErrorString(e));
 }
@@ -307,12 +427,28 @@ atc_status atc_factor_from_householder(const double* coef, const double* sigma2,
     if (dtype != ATC_F32 && dtype != ATC_F64) return hfail(ATC_ERR_INVALID_ARGUMENT, "unknown dtype");
     if (workspace_bytes < atc_householder_workspace_size(n, r)) return hfail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
     hipStream_t st = (hipStream_t)stream;
-    double* V = (double*)workspace;
-    double* X = V + n * r;
-    if (dtype == ATC_F64)
-        hipLaunchKernelGGL(k_hh_decode<double>, dim3(1), dim3(HT), 0, st, coef, sigma2, n, (int)r, (double*)U_out, V, X);
-    else
-        hipLaunchKernelGGL(k_hh_decode<float>, dim3(1), dim3(HT), 0, st, coef, sigma2, n, (int)r, (float*)U_out, V, X);
+    double* X = (double*)workspace;
+    const bool lds = hh_in_lds(n, (int)r, 2 * n);
+    const size_t shm = ((size_t)2 * n + (lds ? (size_t)n * hh_ld((int)r) : 0)) * sizeof(double);
+    if (!hh_lds_ready()) return hfail(ATC_ERR_DEVICE, "could not raise the LDS limit of the Householder kernels");
+    if (dtype == ATC_F64) {
+        auto k = lds ? k_hh_decode<double, true> : k_hh_decode<double, false>;
+        hipLaunchKernelGGL(k, dim3(1), dim3(HHT), shm, st, coef, sigma2, n, (int)r, (double*)U_out, X);
+    } else {
+        auto k = lds ? k_hh_decode<float, true> : k_hh_decode<float, false>;
+        hipLaunchKernelGGL(k, dim3(1), dim3(HHT), shm, st, coef, sigma2, n, (int)r, (float*)U_out, X);
+    }
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ATC_OK : hfail(ATC_ERR_DEVICE, hipGetErrorString(e));
+}
+
+atc_status atc_factor_weight_coefficients(double* coef, const double* sigma2, int64_t n, int64_t r, void* stream) {
+    atc_status s = check_nr(n, r);
+    if (s != ATC_OK) return s;
+    if (!coef || !sigma2) return hfail(ATC_ERR_INVALID_ARGUMENT, "coef and sigma2 must be non-NULL");
+    if (n == 1) return ATC_OK;  // r = 1: nothing stored
+    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(16, ceil_div(n - 1, 256)));
+    hipLaunchKernelGGL(k_hh_weight, dim3(gx, (unsigned)r), dim3(256), 0, (hipStream_t)stream, coef, sigma2, n, (int)r);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? ATC_OK : hfail(ATC_ERR_DEVICE, hipGetErrorString(e));
 }

@@ -30,7 +30,8 @@
 //                  k_q_block_headers
 //   k_q_segment<1> per (block, plane) wavefront: the segment's bits and bytes
 // Decoding: k_dq_offsets (block offsets from the sizes) and k_dq_decode (one
-// wavefront per block, planes in order, magnitudes in LDS).
+// wavefront per block: the runs parsed in parallel, then planes in order with
+// every coefficient of the block on its own lane, magnitudes in LDS).
 #include <cmath>
 
 #include "atc_internal.hpp"
@@ -738,16 +739,48 @@ __device__ __forceinline__ uint32_t read_bit(const uint32_t* __restrict__ w, uin
     return (w[i >> 5] >> (i & 31)) & 1u;
 }
 
-// One wavefront per block: planes from 63 down to P, the known magnitude bits
-// in LDS; then the decoded values (Section 4.3) scaled by 2^-k.
+// Inclusive sum over lanes 0 .. lane of a wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+constexpr int QMAX_WORDS = QMAX_BLOCK / 64;        // significance words of the longest block
+constexpr int QMAX_RUNS = QMAX_BLOCK + QPLANES;    // a run per one-bit of a leading position, a final one per plane
+
+// One wavefront per block, every step parallel over the block:
+//  * the run bytes are parsed at once: lane j looks at byte j of a 64-byte
+//    window, a byte with its top bit clear ends a run, whose value is read
+//    back from the bytes after the previous end; the prefix sums B_k of
+//    (run_k + 1) go to LDS, so the k-th run of a plane ends at leading rank
+//    B_k - B_(start - 1) - 1, a one-bit when below the plane's count of
+//    leading positions and the plane's last run when equal to it;
+//  * per plane, lane w takes significance word w (coefficients 64 w ..
+//    64 w + 63) for the counts and their prefix over words; the plane's
+//    one-bits, as ranks among its leading positions, become a bit mask;
+//    then lane l takes coefficient 64 w + l of every word w: a significant
+//    one reads its trailing bit at (bits so far) + (its rank among the
+//    significant), a leading one looks its rank up in the mask, and a
+//    one-bit there also takes the next sign bits in rank order.
+// The magnitudes stay in LDS; the values (Section 4.3) are scaled by 2^-k at
+// the end.
 template <typename T>
 __global__ void __launch_bounds__(64) k_dq_decode(const uint32_t* __restrict__ in, int64_t n, int len,
                                                   const int64_t* __restrict__ boff, T* __restrict__ out,
                                                   int32_t* status) {
     __shared__ uint64_t mag[QMAX_BLOCK];
-    __shared__ uint8_t negs[QMAX_BLOCK];
-    __shared__ uint32_t runs_lds[QMAX_RUN_WORDS];   // the block's run bytes (parsed serially)
+    __shared__ uint32_t runs_lds[QMAX_RUN_WORDS];   // the block's run bytes
     __shared__ uint32_t signs_lds[QMAX_BLOCK / 32];  // its sign bits (one per coefficient at most)
+    __shared__ uint32_t bsum[QMAX_RUNS];             // B_k = sum over runs i <= k of (run_i + 1)
+    __shared__ uint64_t sigw[QMAX_WORDS];            // coefficients with a decoded one-bit
+    __shared__ uint64_t negw[QMAX_WORDS];            // their signs
+    __shared__ uint64_t onew[QMAX_WORDS];            // this plane's one-bits by leading rank
+    __shared__ uint32_t onepre[QMAX_WORDS], sigpre[QMAX_WORDS], leadpre[QMAX_WORDS];
+    __shared__ uint32_t tplane[QMAX_BLOCK / 32 + 2];  // this plane's trailing bits, from bit tpos & ~31
     const int lane = threadIdx.x;
     const int b = blockIdx.x;
     if (boff[b] < 0) {   // header did not match: zeros
@@ -760,103 +793,162 @@ __global__ void __launch_bounds__(64) k_dq_decode(const uint32_t* __restrict__ i
     const int64_t lo = (int64_t)b * len;
     const int m = (int)min<int64_t>(len, n - lo);
     const int cb = (int)min<int64_t>(max<int64_t>(count - lo, 0), m);
-    for (int i = lane; i < m; i += 64) {
-        mag[i] = 0;
-        negs[i] = 0;
+    const int nw = (m + 63) / 64;
+    for (int i = lane; i < m; i += 64) mag[i] = 0;
+    if (lane < nw) {
+        sigw[lane] = 0;
+        negw[lane] = 0;
     }
-    __syncthreads();
+    const uint64_t bwords = (uint64_t)in[QHEADER + 2 * b] | ((uint64_t)in[QHEADER + 2 * b + 1] << 32);
     const uint32_t* blk = in + boff[b];
     const uint32_t nrb = blk[0], nsb = blk[1], ntb = blk[2];
     const uint32_t* runs_g = blk + QBLK_HDR;
     const uint32_t* signs = runs_g + (nrb + 3) / 4;
     const uint32_t* trail = signs + (nsb + 31) / 32;
-    uint32_t rpos = 0, spos = 0, tpos = 0;
-    bool bad = (nrb + 3) / 4 > (uint32_t)QMAX_RUN_WORDS || (nsb + 31) / 32 > (uint32_t)(QMAX_BLOCK / 32);
+    bool bad = (nrb + 3) / 4 > (uint32_t)QMAX_RUN_WORDS || (nsb + 31) / 32 > (uint32_t)(QMAX_BLOCK / 32) ||
+               (uint64_t)QBLK_HDR + (nrb + 3) / 4 + (nsb + 31) / 32 + ((uint64_t)ntb + 31) / 32 > bwords;
     if (!bad) {
         for (uint32_t i = lane; i < (nrb + 3) / 4; i += 64) runs_lds[i] = runs_g[i];
         for (uint32_t i = lane; i < (nsb + 31) / 32; i += 64) signs_lds[i] = signs[i];
     }
     __syncthreads();
-    const uint32_t* runs = runs_lds;
+    // the runs: B_k for k < nruns
+    uint32_t nruns = 0, carry = 0;
+    int prev_end = -1;
+    for (uint32_t c0 = 0; c0 < nrb && !bad; c0 += 64) {
+        const uint32_t j = c0 + lane;
+        const bool inb = j < nrb;
+        const uint32_t byte = inb ? read_byte(runs_lds, j) : 0u;
+        const bool end = inb && !(byte & 0x80u);
+        const uint64_t em = __ballot(end);
+        const uint64_t below = em & lanemask_lt(lane);
+        const int start = below ? (int)(c0 + 63 - __clzll(below)) + 1 : prev_end + 1;
+        uint32_t v = 0;
+        bool over = false;
+        if (end) {
+            const int L = (int)j - start + 1;
+            if (L > 5) over = true;
+            else
+                for (int t = 0; t < L; ++t) v |= (read_byte(runs_lds, (uint32_t)(start + t)) & 0x7Fu) << (7 * t);
+        }
+        const uint32_t kk = nruns + (uint32_t)__popcll(below);
+        if (end && kk >= (uint32_t)QMAX_RUNS) over = true;
+        if (__ballot(over)) {
+            bad = true;
+            break;
+        }
+        const uint32_t x = wave_incl_scan(end ? v + 1 : 0u, lane);
+        if (end) bsum[kk] = carry + x;
+        carry += __shfl(x, 63);
+        nruns += (uint32_t)__popcll(em);
+        if (em) prev_end = (int)(c0 + 63 - __clzll(em));
+    }
+    if (nrb > 0 && prev_end != (int)nrb - 1) bad = true;   // an unterminated last run
+    __syncthreads();
+    uint32_t rk = 0, spos = 0, tpos = 0;
     for (int p = QPLANES - 1; p >= P && k != QKZERO && !bad; --p) {
         const int upto = p == P ? cb : m;
-        // trailing bits of the coefficients significant before this plane
-        uint32_t nlead = 0;
-        for (int c0 = 0; c0 < upto; c0 += 64) {
-            const int i = c0 + lane;
-            const bool valid = i < upto;
-            const uint64_t v = valid ? mag[i] : 0;
-            const bool sig = p < QPLANES - 1 && (v >> (p + 1)) != 0;
-            const bool tr = valid && sig;
-            const uint64_t tmask = __ballot(tr);
-            if (tpos + (uint32_t)__popcll(tmask) > ntb) {
-                bad = true;
-                break;
-            }
-            if (tr && read_bit(trail, tpos + __popcll(tmask & lanemask_lt(lane)))) mag[i] = v | (1ull << p);
-            tpos += __popcll(tmask);
-            nlead += __popcll(__ballot(valid && !sig));
+        uint64_t sw = 0, lw = 0;
+        if (lane < nw) {
+            const int c = min(64, max(0, upto - 64 * lane));
+            const uint64_t vm = c >= 64 ? ~0ull : ((1ull << c) - 1);
+            sw = sigw[lane] & vm;
+            lw = ~sigw[lane] & vm;
+        }
+        const uint32_t cs = (uint32_t)__popcll(sw), cl = (uint32_t)__popcll(lw);
+        const uint32_t isig = wave_incl_scan(cs, lane), ilead = wave_incl_scan(cl, lane);
+        const uint32_t nsig = __shfl(isig, 63), nlead = __shfl(ilead, 63);
+        if (lane < nw) {
+            sigpre[lane] = isig - cs;
+            leadpre[lane] = ilead - cl;
+            onew[lane] = 0;
+        }
+        if (tpos + nsig > ntb) {
+            bad = true;
+            break;
+        }
+        {
+            const uint32_t tw = ((tpos & 31u) + nsig + 31u) >> 5;   // at most QMAX_BLOCK / 32 + 1
+            for (uint32_t i = lane; i < tw; i += 64) tplane[i] = trail[(tpos >> 5) + i];
         }
         __syncthreads();
-        if (bad) break;
-        if (nlead == 0) continue;
-        // leading bits: zero runs, each but the last ended by a one-bit
-        uint32_t at = 0;      // rank among this plane's leading positions
-        int ci = 0;           // chunk holding rank `at`
-        uint32_t cum = 0;     // leading positions before chunk ci
-        uint64_t lmask = 0;
-        bool have = false;
-        for (;;) {
-            uint32_t r = 0;
-            for (int sh = 0;; sh += 7) {
-                if (rpos >= nrb || sh > 28) {
+        // this plane's runs: one-bits at the leading ranks below nlead, then the final run
+        uint32_t nones = 0;
+        if (nlead > 0) {
+            const uint32_t base = rk > 0 ? bsum[rk - 1] : 0u;
+            bool found = false;
+            for (uint32_t c0 = rk; !found; c0 += 64) {
+                if (c0 >= nruns) {
                     bad = true;
                     break;
                 }
-                const uint32_t byte = read_byte(runs, rpos++);
-                r |= (byte & 0x7Fu) << sh;
-                if (!(byte & 0x80u)) break;
+                const uint32_t kk = c0 + lane;
+                const bool inr = kk < nruns;
+                const uint32_t val = inr ? bsum[kk] - base - 1u : 0u;
+                const uint64_t endm = __ballot(inr && val == nlead);
+                const uint64_t overm = __ballot(inr && val > nlead);
+                const int le = endm ? __ffsll((long long)endm) - 1 : 64;
+                const int lov = overm ? __ffsll((long long)overm) - 1 : 64;
+                if (lov < le) {
+                    bad = true;
+                    break;
+                }
+                const bool one = inr && lane < le && val < nlead;
+                if (one) atomicOr((unsigned long long*)&onew[val >> 6], 1ull << (val & 63));
+                nones += (uint32_t)__popcll(__ballot(one));
+                if (endm) {
+                    found = true;
+                    rk = c0 + (uint32_t)le + 1;
+                }
             }
             if (bad) break;
-            at += r;
-            if (at == nlead) break;
-            if (at > nlead) {
+            if (spos + nones > nsb) {
                 bad = true;
                 break;
             }
-            for (;;) {
-                if (!have) {
-                    const int i = ci * 64 + lane;
-                    const bool valid = i < upto;
-                    const uint64_t v = valid ? mag[i] : 0;
-                    const bool sig = p < QPLANES - 1 && (v >> (p + 1)) != 0;
-                    lmask = __ballot(valid && !sig);
-                    have = true;
-                }
-                const uint32_t c = __popcll(lmask);
-                if (at < cum + c) break;
-                cum += c;
-                ++ci;
-                have = false;
-            }
-            // the lane holding the (at - cum)-th leading position of chunk ci
-            const bool mine = ((lmask >> lane) & 1) && (uint32_t)__popcll(lmask & lanemask_lt(lane)) == at - cum;
-            const int tl = __ffsll((long long)__ballot(mine)) - 1;
-            if (spos >= nsb) {
-                bad = true;
-                break;
-            }
-            if (lane == tl) {
-                const int i = ci * 64 + tl;
-                mag[i] |= 1ull << p;
-                negs[i] = (uint8_t)read_bit(signs_lds, spos);
-            }
-            ++spos;
-            ++at;   // (a one-bit at the very end is followed by a final run of 0)
         }
         __syncthreads();
-        if (bad) break;
+        {
+            const uint32_t co = lane < nw ? (uint32_t)__popcll(onew[lane]) : 0u;
+            const uint32_t io = wave_incl_scan(co, lane);
+            if (lane < nw) onepre[lane] = io - co;
+        }
+        __syncthreads();
+        const uint64_t me = 1ull << lane, lt = me - 1;
+        const uint32_t tb0 = tpos & 31u;
+#pragma unroll 4
+        for (int w = 0; w < nw; ++w) {
+            const int c = min(64, max(0, upto - 64 * w));
+            const uint64_t vm = c >= 64 ? ~0ull : ((1ull << c) - 1);
+            const uint64_t sg = sigw[w];
+            bool becomes = false, negative = false;
+            if (vm & me) {
+                const int i = 64 * w + lane;
+                if (sg & me) {
+                    const uint32_t rho = sigpre[w] + (uint32_t)__popcll(sg & vm & lt);
+                    if (read_bit(tplane, tb0 + rho)) atomicOr((unsigned long long*)&mag[i], 1ull << p);
+                } else {
+                    const uint32_t a = leadpre[w] + (uint32_t)__popcll(~sg & vm & lt);
+                    const uint64_t ow = onew[a >> 6];
+                    if ((ow >> (a & 63)) & 1ull) {
+                        atomicOr((unsigned long long*)&mag[i], 1ull << p);
+                        const uint32_t si = spos + onepre[a >> 6] + (uint32_t)__popcll(ow & ((1ull << (a & 63)) - 1));
+                        negative = read_bit(signs_lds, si) != 0;
+                        becomes = true;
+                    }
+                }
+            }
+            const uint64_t nbm = __ballot(becomes), ngm = __ballot(negative);
+            if (lane == 0 && nbm) {
+                sigw[w] = sg | nbm;
+                negw[w] |= ngm;
+            }
+        }
+        tpos += nsig;
+        spos += nones;
+        __syncthreads();
     }
+    if (!bad && k != QKZERO && P < QPLANES && (rk != nruns || spos != nsb || tpos != ntb)) bad = true;
     if (bad && lane == 0 && status) atomicOr(status, 1);
     __syncthreads();
     for (int i = lane; i < m; i += 64) {
@@ -866,7 +958,7 @@ __global__ void __launch_bounds__(64) k_dq_decode(const uint32_t* __restrict__ i
             const uint64_t d = dec_mag(mag[i], lowp);
             if (d) {
                 v = ldexp((double)d, -k);
-                if (negs[i]) v = -v;
+                if ((negw[i >> 6] >> (i & 63)) & 1ull) v = -v;
             }
         }
         out[lo + i] = (T)v;

@@ -59,6 +59,29 @@ def test_householder_parity(n, r, dtype):
         assert np.abs(Ur - U64 * s_o).max() <= 1e-12 * max(1, r) + 4.0 * defect
 
 
+@pytest.mark.parametrize("n,r", [(1, 1), (6, 6), (200, 20), (512, 18), (1000, 3)])
+def test_weighting_stored_entries(n, r):
+    """Unweighted entries scaled in place (atc_factor_weight_coefficients)
+    against the oracle's weighted encoding, and the entries of U diag(s) for
+    random signs s against those of U (supplement S.2: the same reflectors)."""
+    U = _orth(n, r, 5 * n + r)
+    rng = np.random.default_rng(3 * n + r)
+    s2 = np.sort(rng.uniform(0.01, 100.0, r))[::-1].copy()
+    Ud = torch.from_numpy(U).cuda()
+    sd = torch.from_numpy(s2).cuda()
+    log("weighting n %d r %d" % (n, r))
+    coef, signs, _ = atc.factor_householder(Ud, None)
+    flip = torch.from_numpy(np.where(rng.random(r) < 0.5, -1.0, 1.0)).cuda()
+    coef_f, _, _ = atc.factor_householder((Ud * flip).contiguous(), None)
+    assert torch.equal(coef, coef_f)
+    atc.factor_weight_coefficients(coef, sd, n, r)
+    c_o, _, _ = hh.encode(U, s2)
+    cg = coef.cpu().numpy()
+    scale = max(1.0, np.abs(c_o).max(initial=0.0))
+    assert cg.size == c_o.size
+    assert np.abs(cg - c_o).max(initial=0.0) <= 1e-12 * scale
+
+
 def test_slice_norms_signs_and_factor_term_field512():
     """The 512^3 field's ST-HOSVD (eps 1e-3, RTMSS 0.5): slice norms of its core
     per mode, the core's slices flipped by the Householder signs of every
