@@ -651,7 +651,9 @@ struct MatBufs {
     float* m32;
 };
 
-size_t carve_recon(const atc_shape* s, const int64_t* ranks, char* base, void** buf, MatBufs* mb) {
+// The two intermediates of the reconstruction, in the cheapest order; the
+// factors serve as the mode-product matrices as they are.
+size_t carve_recon(const atc_shape* s, const int64_t* ranks, char* base, void** buf) {
     const int d = s->ndim;
     const size_t esz = s->dtype == ATC_F64 ? 8 : 4;
     int order[ATC_MAX_DIMS];
@@ -663,21 +665,13 @@ size_t carve_recon(const atc_shape* s, const int64_t* ranks, char* base, void** 
         cur[order[i]] = s->dims[order[i]];
         big = std::max<int64_t>(big, prod(cur, 0, d));
     }
-    size_t nr = 1;
-    for (int k = 0; k < d; ++k) nr = std::max<size_t>(nr, (size_t)s->dims[k] * ranks[k]);
     Carver c;
     c.base = base;
     void* b0 = c.take((size_t)big * esz);
     void* b1 = c.take((size_t)big * esz);
-    double* m64 = (double*)c.take(s->dtype == ATC_F64 ? nr * 8 : 0);
-    float* m32 = (float*)c.take(s->dtype == ATC_F32 ? nr * 4 : 0);
     if (buf) {
         buf[0] = b0;
         buf[1] = b1;
-    }
-    if (mb) {
-        mb->m64 = m64;
-        mb->m32 = m32;
     }
     return c.off;
 }
@@ -694,7 +688,7 @@ void recon_order(const atc_shape* s, const int64_t* ranks, int* order) { best_or
 
 size_t atc_reconstruct_workspace_size(const atc_shape* shape, const int64_t* ranks) {
     if (check_shape(shape) != ATC_OK || check_ranks(shape, ranks) != ATC_OK) return 0;
-    return carve_recon(shape, ranks, nullptr, nullptr, nullptr);
+    return carve_recon(shape, ranks, nullptr, nullptr);
 }
 
 namespace {
@@ -718,8 +712,7 @@ atc_status check_recon_call(const atc_shape* shape, const int64_t* ranks, const 
 atc_status reconstruct_impl(const atc_shape* shape, const int64_t* ranks, const void* core, const void* const* factors,
                             void* xhat, void* workspace, hipStream_t st) {
     void* buf[2];
-    MatBufs mb;
-    carve_recon(shape, ranks, (char*)workspace, buf, &mb);
+    carve_recon(shape, ranks, (char*)workspace, buf);
     const int d = shape->ndim;
     const bool f64 = shape->dtype == ATC_F64;
     const int prec = f64 ? PREC_F64 : PREC_F32;
@@ -732,12 +725,10 @@ atc_status reconstruct_impl(const atc_shape* shape, const int64_t* ranks, const 
         const int k = order[i];
         const int64_t L = prod(cur, 0, k), R = prod(cur, k + 1, d);
         const int rk = (int)ranks[k], nk = (int)shape->dims[k];
-        // M = U_k (n_k x r_k): expands mode k from r_k to n_k
-        HIP_TRY(launch_prepare_matrix(prec, factors[k], f64, nk, rk, 0, f64 ? mb.m64 : nullptr, f64 ? nullptr : mb.m32,
-                                      nullptr, nullptr, st));
+        // M = U_k (n_k x r_k, row-major, the factor as given): expands mode k from r_k to n_k
         void* dst = (i == d - 1) ? xhat : buf[i % 2];
         const TtmPlan tp = ttm_plan(prec, L, rk, R, nk);
-        HIP_TRY(launch_ttm(prec, tp, src, f64 ? (const void*)mb.m64 : (const void*)mb.m32, nullptr, nullptr, dst, st));
+        HIP_TRY(launch_ttm(prec, tp, src, factors[k], nullptr, nullptr, dst, st));
         cur[k] = nk;
         src = dst;
     }
@@ -783,7 +774,7 @@ atc_status atc_reconstruct(const atc_shape* shape, const int64_t* ranks, const v
                            void* xhat, void* workspace, size_t workspace_bytes, void* stream) {
     atc_status s = check_recon_call(shape, ranks, core, factors, xhat);
     if (s != ATC_OK) return s;
-    const size_t need = carve_recon(shape, ranks, nullptr, nullptr, nullptr);
+    const size_t need = carve_recon(shape, ranks, nullptr, nullptr);
     if (!workspace || workspace_bytes < need)
         return fail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
     return reconstruct_impl(shape, ranks, core, factors, xhat, workspace, (hipStream_t)stream);
@@ -793,7 +784,7 @@ atc_status atc_reconstruct_noalloc(const atc_shape* shape, const int64_t* ranks,
                                    const void* const* factors, void* xhat, void* stream) {
     atc_status s = check_recon_call(shape, ranks, core, factors, xhat);
     if (s != ATC_OK) return s;
-    const size_t need = carve_recon(shape, ranks, nullptr, nullptr, nullptr);
+    const size_t need = carve_recon(shape, ranks, nullptr, nullptr);
     if (need > NOALLOC_SCRATCH_BYTES)
         return fail(ATC_ERR_UNSUPPORTED, "reconstruction needs %zu bytes of scratch; the library's buffer holds %zu",
                     need, NOALLOC_SCRATCH_BYTES);

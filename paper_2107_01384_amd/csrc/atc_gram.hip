@@ -291,19 +291,43 @@ __global__ __launch_bounds__(NTHREADS) void k_gram(const typename ElemOf<P>::T* 
             }
 }
 
-__global__ void k_gram_reduce(const double* __restrict__ part, int nsplit, int npairs, int tiles_x,
-                              int tiles_y, int nx, int ny, int sym, double* __restrict__ C) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)nx * ny) return;
-    const int a = (int)(idx / ny), b = (int)(idx % ny);
-    if (sym && a > b) return;
-    const int ti = a / TILE, tj = b / TILE;
-    const int pair = sym ? upper_pair_index(ti, tj, tiles_x) : ti * tiles_y + tj;
-    const int i = a % TILE, j = b % TILE;
+// Sum of the split partials: a workgroup takes 64 consecutive outputs
+// (row-major over nx x ny) and four groups of splits (group q: splits q, q +
+// 4, ..., four loads in flight each), whose sums are added in group order.
+constexpr int RED_OUT = 64;
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int nsplit, int npairs,
+                                                     int tiles_x, int tiles_y, int nx, int ny, int sym,
+                                                     double* __restrict__ C) {
+    __shared__ double red[4][RED_OUT];
+    const int o = threadIdx.x & (RED_OUT - 1), q = threadIdx.x / RED_OUT;
+    const int64_t idx = (int64_t)blockIdx.x * RED_OUT + o;
+    const bool ok = idx < (int64_t)nx * ny;
+    const int a = ok ? (int)(idx / ny) : 0, b = ok ? (int)(idx % ny) : 0;
+    const bool want = ok && !(sym && a > b);
     double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += part[((int64_t)sp * npairs + pair) * (TILE * TILE) + i * TILE + j];
-    C[(int64_t)a * ny + b] = s;
-    if (sym) C[(int64_t)b * ny + a] = s;
+    if (want) {
+        const int ti = a / TILE, tj = b / TILE;
+        const int pair = sym ? upper_pair_index(ti, tj, tiles_x) : ti * tiles_y + tj;
+        const double* p = part + (int64_t)pair * (TILE * TILE) + (a % TILE) * TILE + (b % TILE);
+        const int64_t stride = (int64_t)npairs * TILE * TILE;
+        int sp = q;
+        for (; sp + 12 < nsplit; sp += 16) {
+            const double v0 = p[sp * stride], v1 = p[(sp + 4) * stride], v2 = p[(sp + 8) * stride],
+                         v3 = p[(sp + 12) * stride];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; sp < nsplit; sp += 4) s += p[sp * stride];
+    }
+    red[q][o] = s;
+    __syncthreads();
+    if (q == 0 && want) {
+        const double t = ((red[0][o] + red[1][o]) + red[2][o]) + red[3][o];
+        C[(int64_t)a * ny + b] = t;
+        if (sym) C[(int64_t)b * ny + a] = t;
+    }
 }
 
 template <int P, int LAYOUT, bool SYM>
@@ -355,9 +379,10 @@ GramPlan gram_plan(int prec, int64_t L, int nx, int ny, int64_t R, bool sym, siz
     g.tiles_y = (int)ceil_div(ny, TILE);
     g.npairs = sym ? g.tiles_x * (g.tiles_x + 1) / 2 : g.tiles_x * g.tiles_y;
     // enough workgroups to cover 256 CUs several times, at least 8 steps each
-    // (2 for short products, whose time is one memory latency per step)
+    // (2 for short products, whose time is one memory latency per step, and
+    // for products of a few tile pairs, which need the splits to fill the chip)
     int64_t want = ceil_div(2048, g.npairs);
-    const int64_t min_steps = g.steps < 64 ? 2 : 8;
+    const int64_t min_steps = (g.steps < 64 || g.npairs <= 4) ? 2 : 8;
     int64_t max_by_steps = g.steps / min_steps > 0 ? g.steps / min_steps : 1;
     int64_t max_by_mem = (int64_t)(part_capacity_bytes / ((size_t)g.npairs * TILE * TILE * sizeof(double)));
     int64_t ns = want;
@@ -383,9 +408,8 @@ hipError_t launch_gram(int prec, const GramPlan& g, const void* X, const void* Y
 
 hipError_t launch_gram_reduce(const GramPlan& g, const double* part, double* C, hipStream_t st) {
     const int64_t total = (int64_t)g.nx * g.ny;
-    const int threads = 256;
-    const int64_t blocks = ceil_div(total, threads);
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)blocks), dim3(threads), 0, st, part, g.nsplit, g.npairs,
+    const int64_t blocks = ceil_div(total, (int64_t)RED_OUT);
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)blocks), dim3(256), 0, st, part, g.nsplit, g.npairs,
                        g.tiles_x, g.tiles_y, g.nx, g.ny, g.sym, C);
     return hipGetLastError();
 }

@@ -13,6 +13,7 @@
 // (BK x 64) slab of Y in LDS (Y stored column-major so each lane reads its
 // MFMA operand contiguously).  The kernel reads the tensor exactly once and
 // is bound by HBM bandwidth for small m_out.
+#include <algorithm>
 #include <type_traits>
 
 #include "atc_internal.hpp"
@@ -206,15 +207,16 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm(const typename ElemOf<P>::T* _
     }
 }
 
-// Wide variant for the contiguous-R layout (R >= 256, R % 4 == 0) and small
-// m_out (<= 16 MT): a workgroup owns 256 consecutive columns of one slice and
-// every output row, so the tensor is read once, in coalesced float4 rows.  The
+// Wide variant for the contiguous-R layout (R % 4 == 0) and small m_out (<=
+// 16 MT): a workgroup owns 256 consecutive columns of one slice (R >= 256,
+// pl = 1) or pl = 256 / R whole slices of R columns each (R < 256), and every
+// output row, so the tensor is read once, in coalesced float4 rows.  The
 // next 32-row slab of Y (and of M, split into bf16 hi/lo on the fly for the
 // bf16x3 form) is loaded into registers while the current one is multiplied;
 // Y is staged in LDS column-major, eight rows of a column per 16-byte store.
 template <int P, int MT>
-__global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__ Y, int n, int64_t R, int m_out,
-                                                       int64_t tpl, const float* __restrict__ M32,
+__global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__ Y, int64_t L, int n, int64_t R,
+                                                       int m_out, int64_t tpl, int pl, const float* __restrict__ M32,
                                                        float* __restrict__ Z, const int32_t* __restrict__ m_dev) {
     constexpr int W = 256, BK = 32, MR = 16 * MT;
     if (m_dev) m_out = min(m_out, *m_dev);  // the rank chosen on the device
@@ -234,18 +236,21 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
     (void)YP;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t ct = blockIdx.x;
-    const int64_t l = ct / tpl;
-    const int64_t c0 = (ct - l * tpl) * W;
-    const float* ybase = Y + l * (int64_t)n * R + c0;
-    const int cg = tid & 63, rg = tid >> 6;  // columns c0 + 4 cg .. + 3, slab rows 8 rg .. + 7
-    const bool colok = c0 + 4 * cg < R;
+    // column c of the tile: slice l0 + c / R, position c0 + c % R (pl > 1: c0 = 0)
+    const int64_t l0 = pl > 1 ? ct * pl : ct / tpl;
+    const int64_t c0 = pl > 1 ? 0 : (ct - l0 * tpl) * W;
+    const int cg = tid & 63, rg = tid >> 6;  // columns 4 cg .. + 3, slab rows 8 rg .. + 7
+    const int pc = pl > 1 ? (4 * cg) / (int)R : 0;
+    const int64_t rc = pl > 1 ? 4 * cg - (int64_t)pc * R : c0 + 4 * cg;
+    const bool colok = pc < pl && l0 + pc < L && rc < R;
+    const float* ybase = Y + (l0 + pc) * (int64_t)n * R + rc;
     float4 yv[8];
     float mv[MT][8];
     auto load = [&](int i0) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int i = i0 + 8 * rg + e;
-            yv[e] = (colok && i < n) ? *reinterpret_cast<const float4*>(ybase + (int64_t)i * R + 4 * cg)
+            yv[e] = (colok && i < n) ? *reinterpret_cast<const float4*>(ybase + (int64_t)i * R)
                                      : float4{0.f, 0.f, 0.f, 0.f};
         }
         // M: MR rows x 32 k, eight consecutive k per (thread, row block)
@@ -354,17 +359,19 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
             }
         }
     }
-    float* zbase = Z + l * (int64_t)m_out * R + c0;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-        const int64_t c = wc + 16 * b + (lane & 15);
-        if (c0 + c >= R) continue;
+        const int c = wc + 16 * b + (lane & 15);
+        const int p = pl > 1 ? c / (int)R : 0;
+        const int64_t r = pl > 1 ? c - (int64_t)p * R : c0 + c;
+        if (p >= pl || l0 + p >= L || r >= R) continue;
+        float* zbase = Z + (l0 + p) * (int64_t)m_out * R + r;
 #pragma unroll
         for (int a = 0; a < MT; ++a)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int j = 16 * a + mfma16_row<PREC_F32>(lane, v);
-                if (j < m_out) zbase[(int64_t)j * R + c] = acc[a][b][v];
+                if (j < m_out) zbase[(int64_t)j * R] = acc[a][b][v];
             }
     }
 }
@@ -424,6 +431,97 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_rows(const float* __restrict__
     }
 }
 
+// Expansion of a last, contiguous mode (R == 1) in FP32: Z[l][j] = sum_i
+// Y[l][i] M[j][i] with n <= 4 KC contracted entries and m_out <= 16 JT
+// outputs per row (m_out % 4 == 0), the reconstruction's final step.  A
+// workgroup takes tiles of EXP_ROWS consecutive rows of Y (one contiguous
+// block, coalesced loads) into LDS rows padded to an odd stride; each
+// wavefront then forms 16 rows at a time as Z^T tiles on
+// v_mfma_f32_16x16x4f32 (FP32 products and sums): A = M (16 outputs j x 4
+// entries i, held in registers for the whole kernel), B = the rows' entries
+// from LDS, so lane (c, q) ends with Z[l0 + c][16 t + 4 q .. 16 t + 4 q + 3]
+// and writes it with one 16-byte store.
+constexpr int EXP_ROWS = 256;
+
+template <int KC, int JT>
+__global__ __launch_bounds__(NTHREADS) void k_ttm_expand_last(const float* __restrict__ Y, int64_t L, int n,
+                                                              int m_out, const float* __restrict__ M32,
+                                                              float* __restrict__ Z) {
+    constexpr int NS = 4 * KC + 1;
+    __shared__ float ys[EXP_ROWS * NS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 15, q = lane >> 4;
+    float a[JT][KC];
+#pragma unroll
+    for (int t = 0; t < JT; ++t)
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const int j = 16 * t + c, i = 4 * k + q;
+            a[t][k] = (j < m_out && i < n) ? M32[(int64_t)j * n + i] : 0.f;
+        }
+    const bool vec = (n & 3) == 0;
+    for (int64_t tile = blockIdx.x; tile * EXP_ROWS < L; tile += gridDim.x) {
+        const int64_t l0 = tile * EXP_ROWS;
+        const int rows = (int)min<int64_t>(EXP_ROWS, L - l0);
+        // rows' entries in groups of four (zeros past n), all loads issued first
+        float v[KC][4];
+#pragma unroll
+        for (int x = 0; x < KC; ++x) {
+            const int e = tid + x * NTHREADS;
+            const int rr = e / KC, k4 = 4 * (e % KC);
+            const float* src = Y + (l0 + min(rr, rows - 1)) * n + k4;
+            if (vec && k4 < n) {
+                const float4 w = rr < rows ? *reinterpret_cast<const float4*>(src) : float4{0.f, 0.f, 0.f, 0.f};
+                v[x][0] = w.x;
+                v[x][1] = w.y;
+                v[x][2] = w.z;
+                v[x][3] = w.w;
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[x][u] = (rr < rows && k4 + u < n) ? src[u] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int x = 0; x < KC; ++x) {
+            const int e = tid + x * NTHREADS;
+            const int rr = e / KC, k4 = 4 * (e % KC);
+            if (rr < rows)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) ys[rr * NS + k4 + u] = v[x][u];
+        }
+        __syncthreads();
+        for (int rb = 16 * wave; rb < rows; rb += 16 * (NTHREADS / 64)) {
+            const int r = min(rb + c, rows - 1);
+            f32x4 acc[JT];
+#pragma unroll
+            for (int t = 0; t < JT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const float b = ys[r * NS + 4 * k + q];
+#pragma unroll
+                for (int t = 0; t < JT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][k], b, acc[t], 0, 0, 0);
+            }
+            if (rb + c < rows) {
+                float* zr = Z + (l0 + rb + c) * m_out;
+#pragma unroll
+                for (int t = 0; t < JT; ++t) {
+                    const int j = 16 * t + 4 * q;
+                    if (j < m_out) *reinterpret_cast<float4*>(zr + j) = float4{acc[t][0], acc[t][1], acc[t][2], acc[t][3]};
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int KC>
+void launch_expand_last_k(int jt, unsigned grid, hipStream_t st, const float* Y, int64_t L, int n, int m_out,
+                          const float* M, float* Z) {
+    if (jt <= 2) hipLaunchKernelGGL((k_ttm_expand_last<KC, 2>), dim3(grid), dim3(NTHREADS), 0, st, Y, L, n, m_out, M, Z);
+    else if (jt <= 4) hipLaunchKernelGGL((k_ttm_expand_last<KC, 4>), dim3(grid), dim3(NTHREADS), 0, st, Y, L, n, m_out, M, Z);
+    else hipLaunchKernelGGL((k_ttm_expand_last<KC, 8>), dim3(grid), dim3(NTHREADS), 0, st, Y, L, n, m_out, M, Z);
+}
+
 template <int P, int LAYOUT>
 hipError_t launch_ttm_t(const TtmPlan& t, const void* Y, const void* M, const void* Mh, const void* Ml, void* Z,
                         const int32_t* m_dev, hipStream_t st) {
@@ -474,19 +572,36 @@ TtmPlan ttm_plan(int prec, int64_t L, int n, int64_t R, int m_out) {
 
 hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, const void* Mh, const void* Ml,
                       void* Z, hipStream_t st, const int32_t* m_dev) {
-    if (prec != PREC_F64 && t.layout == LAYOUT_KC && t.R >= 256 && t.R % 4 == 0 && t.m_out <= 64) {
-        const int64_t tpl = ceil_div(t.R, (int64_t)256);
-        const dim3 grid((unsigned)(t.L * tpl));
+    if (prec != PREC_F64 && t.layout == LAYOUT_KC && t.R >= 32 && t.R % 4 == 0 && t.m_out <= 64 &&
+        reinterpret_cast<uintptr_t>(Y) % 16 == 0) {
+        // R >= 256: 256-column chunks of one slice; R < 256: 256 / R whole slices per workgroup
+        const int pl = t.R >= 256 ? 1 : (int)(256 / t.R);
+        const int64_t tpl = t.R >= 256 ? ceil_div(t.R, (int64_t)256) : 1;
+        const dim3 grid((unsigned)(pl > 1 ? ceil_div(t.L, (int64_t)pl) : t.L * tpl));
         const float* y = (const float*)Y;
         const float* m = (const float*)M;
         float* z = (float*)Z;
         if (prec == PREC_BF16X3) {
-            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 2>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z, m_dev);
-            else hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 4>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z, m_dev);
+            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 2>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
+            else hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 4>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
         } else {
-            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 2>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z, m_dev);
-            else hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 4>), grid, dim3(NTHREADS), 0, st, y, t.n, t.R, t.m_out, tpl, m, z, m_dev);
+            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 2>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
+            else hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 4>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
         }
+        return hipGetLastError();
+    }
+    // expansion of a last, contiguous mode in FP32 (the reconstruction's last step)
+    if (prec == PREC_F32 && t.layout == LAYOUT_NC && t.R == 1 && !m_dev && t.n <= 32 && t.m_out > t.n &&
+        t.m_out % 4 == 0 && t.m_out <= 128 && reinterpret_cast<uintptr_t>(Y) % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(Z) % 16 == 0) {
+        const unsigned grid = (unsigned)std::min<int64_t>(std::max<int64_t>(1, ceil_div(t.L, (int64_t)EXP_ROWS)), 4096);
+        const int jt = (int)ceil_div(t.m_out, 16);
+        const float* y = (const float*)Y;
+        const float* m = (const float*)M;
+        float* z = (float*)Z;
+        if (t.n <= 8) launch_expand_last_k<2>(jt, grid, st, y, t.L, t.n, t.m_out, m, z);
+        else if (t.n <= 16) launch_expand_last_k<4>(jt, grid, st, y, t.L, t.n, t.m_out, m, z);
+        else launch_expand_last_k<8>(jt, grid, st, y, t.L, t.n, t.m_out, m, z);
         return hipGetLastError();
     }
     // short slabs (few 64-row tiles for the tile kernel, latency-bound): rows kernel
