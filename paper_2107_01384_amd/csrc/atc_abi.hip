@@ -715,7 +715,8 @@ atc_status reconstruct_impl(const atc_shape* shape, const int64_t* ranks, const 
     carve_recon(shape, ranks, (char*)workspace, buf);
     const int d = shape->ndim;
     const bool f64 = shape->dtype == ATC_F64;
-    const int prec = f64 ? PREC_F64 : PREC_F32;
+    // float32 mode products at FP32-equivalent accuracy (bf16 three-way splits where MFMA-bound)
+    const int prec = f64 ? PREC_F64 : PREC_BF16X6;
     int order[ATC_MAX_DIMS];
     best_order(shape->dims, ranks, d, order);
     int64_t cur[ATC_MAX_DIMS];
@@ -806,8 +807,10 @@ atc_status atc_reconstruct_noalloc(const atc_shape* shape, const int64_t* ranks,
 namespace {
 
 struct BwdPlan {
-    int a;                 // mode shrunk first
-    int64_t big;           // largest intermediate (elements)
+    int a;                                // mode shrunk first: P = R x_a U_a^T
+    std::vector<int> chain[ATC_MAX_DIMS];  // n != a: modes shrinking P into T_n, in order;
+                                          // n == a: modes shrinking R into T_a
+    int64_t big;                          // largest intermediate (elements)
 };
 
 // elements of the tensor after shrinking the modes in `mask`
@@ -817,17 +820,65 @@ int64_t shrunk_size(const atc_shape* s, const int64_t* ranks, unsigned mask) {
     return t;
 }
 
+// Work of shrinking, from the modes in `mask` already shrunk, the modes in
+// `modes` in that order: the products' flops plus eight per byte moved (the
+// FP32 mode products run at about eight flops per byte of HBM traffic).
+double chain_cost(const atc_shape* s, const int64_t* ranks, unsigned mask, const std::vector<int>& modes) {
+    const double esz = s->dtype == ATC_F64 ? 8.0 : 4.0;
+    double c = 0.0;
+    for (int k : modes) {
+        const double in = (double)shrunk_size(s, ranks, mask);
+        const double out = in / (double)s->dims[k] * (double)ranks[k];
+        c += 2.0 * in * (double)ranks[k] + 8.0 * esz * (in + out);
+        mask |= 1u << k;
+    }
+    return c;
+}
+
+// The cheapest order of `modes` (first in lexicographic order on ties).
+std::vector<int> best_chain(const atc_shape* s, const int64_t* ranks, unsigned mask, std::vector<int> modes,
+                            double* cost) {
+    std::sort(modes.begin(), modes.end());
+    std::vector<int> best = modes;
+    double bc = chain_cost(s, ranks, mask, modes);
+    while (std::next_permutation(modes.begin(), modes.end())) {
+        const double c = chain_cost(s, ranks, mask, modes);
+        if (c < bc) {
+            bc = c;
+            best = modes;
+        }
+    }
+    if (cost) *cost = bc;
+    return best;
+}
+
+// The first mode a and every chain order, by exhaustive search over a.
 BwdPlan bwd_plan(const atc_shape* s, const int64_t* ranks) {
     const int d = s->ndim;
     BwdPlan p{};
-    // shrink first the mode with the largest reduction of the tensor
-    p.a = 0;
-    double best = 0;
-    for (int k = 0; k < d; ++k) {
-        const double red = (double)s->dims[k] / (double)ranks[k];
-        if (red > best) {
-            best = red;
-            p.a = k;
+    double best = -1.0;
+    for (int a = 0; a < d; ++a) {
+        BwdPlan q{};
+        q.a = a;
+        double c = chain_cost(s, ranks, 0u, std::vector<int>{a});
+        for (int n = 0; n < d; ++n) {
+            std::vector<int> modes;
+            for (int k = 0; k < d; ++k)
+                if (k != a && k != n) modes.push_back(k);
+            double cc = 0.0;
+            if (n == a) {
+                modes.clear();
+                for (int k = 0; k < d; ++k)
+                    if (k != a) modes.push_back(k);
+                q.chain[n] = best_chain(s, ranks, 0u, modes, &cc);
+            } else {
+                q.chain[n] = best_chain(s, ranks, 1u << a, modes, &cc);
+            }
+            c += cc;
+        }
+        if (best < 0.0 || c < best) {
+            best = c;
+            p = q;
         }
     }
     p.big = 1;
@@ -907,6 +958,8 @@ atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = shape->dtype == ATC_F64;
     const int prec = f64 ? PREC_F64 : PREC_F32;
+    // float32 mode products at FP32-equivalent accuracy (bf16 three-way splits where MFMA-bound)
+    const int tprec = f64 ? PREC_F64 : PREC_BF16X6;
     const size_t esz = f64 ? 8 : 4;
     size_t nr = 1;
     for (int k = 0; k < d; ++k) nr = std::max<size_t>(nr, (size_t)shape->dims[k] * ranks[k]);
@@ -932,8 +985,8 @@ atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks
             const int64_t L = prod(cur, 0, k), R = prod(cur, k + 1, d);
             void* dst = (i + 1 == modes.size() && final_dst) ? final_dst : bufs[1 + flip];
             flip ^= 1;
-            const TtmPlan tp = ttm_plan(prec, L, (int)cur[k], R, (int)ranks[k]);
-            HIP_TRY(launch_ttm(prec, tp, s_, Mt[k], nullptr, nullptr, dst, st));
+            const TtmPlan tp = ttm_plan(tprec, L, (int)cur[k], R, (int)ranks[k]);
+            HIP_TRY(launch_ttm(tprec, tp, s_, Mt[k], nullptr, nullptr, dst, st));
             cur[k] = ranks[k];
             s_ = dst;
         }
@@ -962,16 +1015,14 @@ atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks
     for (int k = 0; k < d; ++k) curP[k] = shape->dims[k];
     {
         const int64_t L = prod(curP, 0, a), R = prod(curP, a + 1, d);
-        const TtmPlan tp = ttm_plan(prec, L, (int)curP[a], R, (int)ranks[a]);
-        HIP_TRY(launch_ttm(prec, tp, dxhat, Mt[a], nullptr, nullptr, bufs[0], st));
+        const TtmPlan tp = ttm_plan(tprec, L, (int)curP[a], R, (int)ranks[a]);
+        HIP_TRY(launch_ttm(tprec, tp, dxhat, Mt[a], nullptr, nullptr, bufs[0], st));
         curP[a] = ranks[a];
     }
     // T_n for n != a from P (P itself stays intact in bufs[0])
     for (int n = 0; n < d; ++n) {
         if (n == a) continue;
-        std::vector<int> modes;
-        for (int k = 0; k < d; ++k)
-            if (k != a && k != n) modes.push_back(k);
+        const std::vector<int>& modes = bp.chain[n];
         int64_t cur[ATC_MAX_DIMS];
         for (int k = 0; k < d; ++k) cur[k] = curP[k];
         const void* Tn = bufs[0];
@@ -992,9 +1043,7 @@ atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks
     }
     // T_a: one more pass over R, shrinking every other mode
     if (dfactors && dfactors[a]) {
-        std::vector<int> modes;
-        for (int k = 0; k < d; ++k)
-            if (k != a) modes.push_back(k);
+        const std::vector<int>& modes = bp.chain[a];
         int64_t cur[ATC_MAX_DIMS];
         for (int k = 0; k < d; ++k) cur[k] = shape->dims[k];
         const void* Ta = dxhat;

@@ -19,7 +19,13 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 //  PREC_F64ACC: float32 operands widened to FP64 on their way to LDS, FP64
 //  MFMA products and accumulation (the Gram matrix of float32 data to FP64
 //  accuracy); the mode products of that path run as PREC_F32.
-enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2, PREC_F64ACC = 3 };
+//  PREC_BF16X6: float32 operands split into three bf16 pieces (8 + 8 + 8
+//              significant bits, exact), the six products of order <= 2 on
+//              bf16 MFMA with FP32 accumulation: FP32-equivalent products (the
+//              dropped terms are below 2^-23 of |a b|).  Mode products of the
+//              reconstruction and its adjoint only; everything else treats it
+//              as PREC_F32.
+enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2, PREC_F64ACC = 3, PREC_BF16X6 = 4 };
 
 // How the contracted index of an (L, n, R) view is walked:
 //  KC: R large, the R index is contiguous -> tiles step along R inside one l.

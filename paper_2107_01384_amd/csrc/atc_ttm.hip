@@ -231,7 +231,11 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
     struct SmF {
         float yf[W][BK + 4], mf[MR][BK + 4];
     };
-    typedef typename std::conditional<P == PREC_BF16X3, SmB, SmF>::type Sm;
+    struct SmB6 {
+        __bf16 yh[W][BK], ym[W][BK], yl[W][BK], mh[MR][BK + 8], mm[MR][BK + 8], ml[MR][BK + 8];
+    };
+    typedef typename std::conditional<
+        P == PREC_BF16X3, SmB, typename std::conditional<P == PREC_BF16X6, SmB6, SmF>::type>::type Sm;
     __shared__ Sm sm;
     (void)YP;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -283,6 +287,22 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
                 const int ch = rg ^ (((row >> 1) ^ (row >> 3)) & 3);
                 *reinterpret_cast<bf16x8*>(&sm.yh[row][8 * ch]) = hv;
                 *reinterpret_cast<bf16x8*>(&sm.yl[row][8 * ch]) = lv;
+            } else if constexpr (P == PREC_BF16X6) {
+                bf16x8 hv, mv_, lv;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const __bf16 h = (__bf16)f[e];
+                    const float r1 = f[e] - (float)h;
+                    const __bf16 m = (__bf16)r1;
+                    hv[e] = h;
+                    mv_[e] = m;
+                    lv[e] = (__bf16)(r1 - (float)m);
+                }
+                const int row = 4 * cg + q;
+                const int ch = rg ^ (((row >> 1) ^ (row >> 3)) & 3);
+                *reinterpret_cast<bf16x8*>(&sm.yh[row][8 * ch]) = hv;
+                *reinterpret_cast<bf16x8*>(&sm.ym[row][8 * ch]) = mv_;
+                *reinterpret_cast<bf16x8*>(&sm.yl[row][8 * ch]) = lv;
             } else {
                 *reinterpret_cast<float4*>(&sm.yf[4 * cg + q][8 * rg]) = float4{f[0], f[1], f[2], f[3]};
                 *reinterpret_cast<float4*>(&sm.yf[4 * cg + q][8 * rg + 4]) = float4{f[4], f[5], f[6], f[7]};
@@ -302,6 +322,20 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
                     lv[e] = (__bf16)(mv[q][e] - (float)h);
                 }
                 *reinterpret_cast<bf16x8*>(&sm.mh[mr][kq]) = hv;
+                *reinterpret_cast<bf16x8*>(&sm.ml[mr][kq]) = lv;
+            } else if constexpr (P == PREC_BF16X6) {
+                bf16x8 hv, mv_, lv;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const __bf16 h = (__bf16)mv[q][e];
+                    const float r1 = mv[q][e] - (float)h;
+                    const __bf16 m = (__bf16)r1;
+                    hv[e] = h;
+                    mv_[e] = m;
+                    lv[e] = (__bf16)(r1 - (float)m);
+                }
+                *reinterpret_cast<bf16x8*>(&sm.mh[mr][kq]) = hv;
+                *reinterpret_cast<bf16x8*>(&sm.mm[mr][kq]) = mv_;
                 *reinterpret_cast<bf16x8*>(&sm.ml[mr][kq]) = lv;
             } else {
                 *reinterpret_cast<float4*>(&sm.mf[mr][kq]) = float4{mv[q][0], mv[q][1], mv[q][2], mv[q][3]};
@@ -340,6 +374,34 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
                     acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[b], acc[a][b], 0, 0, 0);
+                }
+            }
+        } else if constexpr (P == PREC_BF16X6) {
+            const int kq = 8 * (lane >> 4);
+            bf16x8 bh[4], bm[4], bl[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int row = wc + 16 * b + (lane & 15);
+                const int yq = 8 * ((lane >> 4) ^ (((row >> 1) ^ (row >> 3)) & 3));
+                bh[b] = *reinterpret_cast<const bf16x8*>(&sm.yh[row][yq]);
+                bm[b] = *reinterpret_cast<const bf16x8*>(&sm.ym[row][yq]);
+                bl[b] = *reinterpret_cast<const bf16x8*>(&sm.yl[row][yq]);
+            }
+#pragma unroll
+            for (int a = 0; a < MT; ++a) {
+                const int mrow = 16 * a + (lane & 15);
+                const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&sm.mh[mrow][kq]);
+                const bf16x8 am = *reinterpret_cast<const bf16x8*>(&sm.mm[mrow][kq]);
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(&sm.ml[mrow][kq]);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    // the terms of order 2, then 1, then 0 (smallest first)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[b], acc[a][b], 0, 0, 0);
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[b], acc[a][b], 0, 0, 0);
                 }
             }
         } else {
@@ -522,6 +584,97 @@ void launch_expand_last_k(int jt, unsigned grid, hipStream_t st, const float* Y,
     else hipLaunchKernelGGL((k_ttm_expand_last<KC, 8>), dim3(grid), dim3(NTHREADS), 0, st, Y, L, n, m_out, M, Z);
 }
 
+// Shrinking of a last, contiguous mode (R == 1) in FP32: Z[l][j] = sum_i
+// Y[l][i] M[j][i] with n <= 4 KC entries per row and m_out <= 16 JT outputs
+// (the reconstruction adjoint's projections of the last mode).  Tiles of
+// SHR_ROWS consecutive rows of Y (one contiguous block, coalesced loads) are
+// staged in LDS rows of odd stride; each wavefront then forms 16 rows at a
+// time on v_mfma_f32_16x16x4f32 with A = the rows' entries (16 rows x 4
+// entries, from LDS) and B = M^T (4 entries x 16 outputs, in registers for
+// the whole kernel): lane (c, q) ends with Z[l0 + 4 q + v][16 t + c], v < 4.
+constexpr int SHR_ROWS = 128;
+
+template <int KC, int JT>
+__global__ __launch_bounds__(NTHREADS) void k_ttm_shrink_last(const float* __restrict__ Y, int64_t L, int n,
+                                                              int m_out, const float* __restrict__ M32,
+                                                              float* __restrict__ Z) {
+    constexpr int NS = 4 * KC + 1;
+    __shared__ float ys[SHR_ROWS * NS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 15, q = lane >> 4;
+    float bm[JT][KC];
+#pragma unroll
+    for (int t = 0; t < JT; ++t)
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+            const int j = 16 * t + c, i = 4 * k + q;
+            bm[t][k] = (j < m_out && i < n) ? M32[(int64_t)j * n + i] : 0.f;
+        }
+    const bool vec = (n & 3) == 0;
+    for (int64_t tile = blockIdx.x; tile * SHR_ROWS < L; tile += gridDim.x) {
+        const int64_t l0 = tile * SHR_ROWS;
+        const int rows = (int)min<int64_t>(SHR_ROWS, L - l0);
+        // the tile's entries in groups of four (zeros past n), loads first
+        constexpr int PER = SHR_ROWS * KC / NTHREADS;
+        static_assert(PER * NTHREADS == SHR_ROWS * KC, "tile split");
+        float v[PER][4];
+#pragma unroll
+        for (int x = 0; x < PER; ++x) {
+            const int e = tid + x * NTHREADS;
+            const int rr = e / KC, k4 = 4 * (e % KC);
+            const float* src = Y + (l0 + min(rr, rows - 1)) * n + k4;
+            if (vec && k4 < n) {
+                const float4 w = rr < rows ? *reinterpret_cast<const float4*>(src) : float4{0.f, 0.f, 0.f, 0.f};
+                v[x][0] = w.x;
+                v[x][1] = w.y;
+                v[x][2] = w.z;
+                v[x][3] = w.w;
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[x][u] = (rr < rows && k4 + u < n) ? src[u] : 0.f;
+            }
+        }
+#pragma unroll
+        for (int x = 0; x < PER; ++x) {
+            const int e = tid + x * NTHREADS;
+            const int rr = e / KC, k4 = 4 * (e % KC);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ys[rr * NS + k4 + u] = v[x][u];
+        }
+        __syncthreads();
+        for (int rb = 16 * wave; rb < rows; rb += 16 * (NTHREADS / 64)) {
+            const int r = min(rb + c, rows - 1);
+            f32x4 acc[JT];
+#pragma unroll
+            for (int t = 0; t < JT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+                const float av = ys[r * NS + 4 * k + q];
+#pragma unroll
+                for (int t = 0; t < JT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bm[t][k], acc[t], 0, 0, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < JT; ++t) {
+                const int j = 16 * t + c;
+                if (j >= m_out) continue;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int row = rb + mfma16_row<PREC_F32>(lane, u);
+                    if (row < rows) Z[(l0 + row) * m_out + j] = acc[t][u];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int KC>
+void launch_shrink_last_k(int jt, unsigned grid, hipStream_t st, const float* Y, int64_t L, int n, int m_out,
+                          const float* M, float* Z) {
+    if (jt <= 1) hipLaunchKernelGGL((k_ttm_shrink_last<KC, 1>), dim3(grid), dim3(NTHREADS), 0, st, Y, L, n, m_out, M, Z);
+    else hipLaunchKernelGGL((k_ttm_shrink_last<KC, 2>), dim3(grid), dim3(NTHREADS), 0, st, Y, L, n, m_out, M, Z);
+}
+
 template <int P, int LAYOUT>
 hipError_t launch_ttm_t(const TtmPlan& t, const void* Y, const void* M, const void* Mh, const void* Ml, void* Z,
                         const int32_t* m_dev, hipStream_t st) {
@@ -584,6 +737,9 @@ hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, 
         if (prec == PREC_BF16X3) {
             if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 2>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
             else hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 4>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
+        } else if (prec == PREC_BF16X6) {
+            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X6, 2>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
+            else hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X6, 4>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
         } else {
             if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 2>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
             else hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 4>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
@@ -591,7 +747,8 @@ hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, 
         return hipGetLastError();
     }
     // expansion of a last, contiguous mode in FP32 (the reconstruction's last step)
-    if (prec == PREC_F32 && t.layout == LAYOUT_NC && t.R == 1 && !m_dev && t.n <= 32 && t.m_out > t.n &&
+    const bool f32ish = prec == PREC_F32 || prec == PREC_BF16X6;
+    if (f32ish && t.layout == LAYOUT_NC && t.R == 1 && !m_dev && t.n <= 32 && t.m_out > t.n &&
         t.m_out % 4 == 0 && t.m_out <= 128 && reinterpret_cast<uintptr_t>(Y) % 16 == 0 &&
         reinterpret_cast<uintptr_t>(Z) % 16 == 0) {
         const unsigned grid = (unsigned)std::min<int64_t>(std::max<int64_t>(1, ceil_div(t.L, (int64_t)EXP_ROWS)), 4096);
@@ -604,6 +761,20 @@ hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, 
         else launch_expand_last_k<8>(jt, grid, st, y, t.L, t.n, t.m_out, m, z);
         return hipGetLastError();
     }
+    // shrinking of a last, contiguous mode in FP32 over many rows
+    if (f32ish && t.layout == LAYOUT_NC && t.R == 1 && !m_dev && t.n <= 128 && t.m_out < t.n &&
+        t.m_out <= 32 && t.L >= 8192 && reinterpret_cast<uintptr_t>(Y) % 16 == 0) {
+        const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(t.L, (int64_t)SHR_ROWS), 4096);
+        const int jt = (int)ceil_div(t.m_out, 16);
+        const float* y = (const float*)Y;
+        const float* m = (const float*)M;
+        float* z = (float*)Z;
+        if (t.n <= 16) launch_shrink_last_k<4>(jt, grid, st, y, t.L, t.n, t.m_out, m, z);
+        else if (t.n <= 32) launch_shrink_last_k<8>(jt, grid, st, y, t.L, t.n, t.m_out, m, z);
+        else if (t.n <= 64) launch_shrink_last_k<16>(jt, grid, st, y, t.L, t.n, t.m_out, m, z);
+        else launch_shrink_last_k<32>(jt, grid, st, y, t.L, t.n, t.m_out, m, z);
+        return hipGetLastError();
+    }
     // short slabs (few 64-row tiles for the tile kernel, latency-bound): rows kernel
     if (prec != PREC_F64 && t.layout == LAYOUT_NC && t.R == 1 && t.m_out <= 32 && t.L < 8192) {
         hipLaunchKernelGGL(k_ttm_rows, dim3((unsigned)ceil_div(t.L, 16)), dim3(NTHREADS), 0, st, (const float*)Y, t.L,
@@ -612,7 +783,8 @@ hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, 
     }
     switch (prec) {
         case PREC_F64: return launch_ttm_p<PREC_F64>(t, Y, M, Mh, Ml, Z, m_dev, st);
-        case PREC_F32: return launch_ttm_p<PREC_F32>(t, Y, M, Mh, Ml, Z, m_dev, st);
+        case PREC_F32:
+        case PREC_BF16X6: return launch_ttm_p<PREC_F32>(t, Y, M, Mh, Ml, Z, m_dev, st);
         default: return launch_ttm_p<PREC_BF16X3>(t, Y, M, Mh, Ml, Z, m_dev, st);
     }
 }

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 CASES = [((6, 5, 4, 3), (3, 2, 3, 2)), ((70, 33, 9), (10, 33, 4)), ((130, 20), (7, 20)), ((17,), (5,)),
          ((40, 50, 3, 20), (8, 12, 3, 5)), ((20, 17, 64), (9, 7, 4)), ((10, 9, 96), (8, 8, 6)),
-         ((12, 11, 40), (6, 5, 3))]
+         ((12, 11, 40), (6, 5, 3)), ((30, 21, 17, 36), (5, 4, 3, 9)), ((30, 21, 17, 35), (5, 4, 3, 9))]
 
 
 def _model(dims, ranks, seed):
