@@ -289,7 +289,7 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
 template <int M>
 __device__ __attribute__((noinline)) bool blk_jacobi_slots(int n, int max_sweeps, double (*A)[APAD],
                                                            double (*V)[APAD], J64Shared* sh, int* sweeps) {
-    return jacobi_slots<M>(n, max_sweeps, 0x1p-53, A, V, *sh, V, *sweeps);
+    return jacobi_slots<M>(n, max_sweeps, JACOBI_FLOOR_F32, A, V, *sh, V, *sweeps);
 }
 
 template <int BK>
@@ -324,12 +324,12 @@ __device__ bool blk_jacobi(int n, int max_sweeps, BatchSmem<BK>& sm) {
     }
     __syncthreads();
     const double tol = (double)n * 0x1p-53;
-    // entries at or below u |trace| are left alone: the Gram matrix of FP32
-    // data carries errors of that size already, and rotating them away costs
-    // sweeps without changing the result at that accuracy
+    // couplings at or below JACOBI_FLOOR_F32 |trace| are left alone: below
+    // what the float32 input resolves, and rotating them away costs sweeps
+    // without changing the result at that accuracy
     double trace = 0.0;
     for (int i = 0; i < n; ++i) trace += A[i][i];
-    const double floor = 0x1p-53 * fabs(trace);
+    const double floor = JACOBI_FLOOR_F32 * fabs(trace);
     // this thread's share of the round's work, fixed for the whole solve: up
     // to 3 of the h (h + 1) / 2 blocks (k, l), k <= l, and up to 8 of the m h
     // (row, pair) entries of the eigenvector update (codes k | l << 8 and

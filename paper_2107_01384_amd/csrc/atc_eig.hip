@@ -1201,10 +1201,10 @@ __global__ __launch_bounds__(OT) void k_orth32(double* __restrict__ Y, int n, in
 // rotations each block needs and store it.  A round with no rotation is
 // skipped.  Wavefronts 1, 2, 3 and 5 (off wavefront 0's SIMD) meanwhile
 // apply the previous sweep's log to 8 rows of W each; one workgroup barrier
-// per sweep.  Besides the relative test, an off-diagonal entry below u
-// trace(A) (u = 2^-53) is left alone: it is under the rounding error the
-// entries of A = Q^T G Q carry already, and rotating it away costs a sweep
-// without changing the result at that accuracy.  log: 2 x 31 x 16 double2
+// per sweep.  Besides the relative test, an off-diagonal entry at or below
+// JACOBI_FLOOR_F32 trace(A) is left alone: it is under what the float32 data
+// behind A = Q^T G Q resolves, and rotating it away costs sweeps without
+// changing the result at that accuracy.  log: 2 x 31 x 16 double2
 // (c, s); ptab: 31 x 16 ints; btab:
 // 31 x 128 uint4 (62 KB); flag: 1 int; all LDS.  Unused block slots point at
 // the padding column of A, which nothing reads.
@@ -1221,7 +1221,7 @@ __device__ __forceinline__ void jacobi32(double (*A)[S32 + 1], double (*W)[S32 +
     const double tol2 = tol * tol;
     double trace = 0.0;
     for (int i = 0; i < S32; ++i) trace += A[i][i];
-    const double floor = 0x1p-53 * fabs(trace);
+    const double floor = JACOBI_FLOOR_F32 * fabs(trace);
     const double floor2 = floor * floor;
     char* const abase = reinterpret_cast<char*>(&A[0][0]);
     for (int e = tid; e < LOGR; e += blockDim.x) {
@@ -2425,8 +2425,9 @@ hipError_t run_subspace64_select(const double* G, int n, int max_sweeps, double*
                            (const double*)Za, (const double*)Zb, n, (const int32_t*)ok, sa.book, B);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    // the Ritz problem of FP32-grade data: entries under u trace(B) left alone, as in jacobi32
-    if ((e = launch_eig_jacobi_lds(B, 64, 64, max_sweeps, lam, W, 64, sweeps_dev, ok_dev, st, 0x1p-53)) != hipSuccess)
+    // the Ritz problem of float32 data: couplings under JACOBI_FLOOR_F32 trace(B) left alone, as in jacobi32
+    if ((e = launch_eig_jacobi_lds(B, 64, 64, max_sweeps, lam, W, 64, sweeps_dev, ok_dev, st, JACOBI_FLOOR_F32)) !=
+        hipSuccess)
         return e;
     hipLaunchKernelGGL(k_combine64, dim3((unsigned)ceil_div((int64_t)n * 64, 256)), dim3(256), 0, st,
                        (const double*)Pa, (const double*)Pb, (const double*)W, V, n);

@@ -27,6 +27,16 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 //              as PREC_F32.
 enum Prec : int { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2, PREC_F64ACC = 3, PREC_BF16X6 = 4 };
 
+// Jacobi couplings left alone in the eigenproblems of float32 data (the
+// Rayleigh-Ritz problems of the subspace paths and the batched blocks'
+// Gram matrices): entries at or below JACOBI_FLOOR_F32 times the trace.  The
+// input's own float32 rounding already moves every Gram entry of the data it
+// stands for by about 2^-24 of the trace; couplings 64 times smaller resolve
+// nothing of the data, and leaving them changes a discarded-energy sum only at
+// second order, or not at all when both indices lie in the discarded block
+// (rotations inside it keep its trace).  FP64 input keeps 2^-53.
+constexpr double JACOBI_FLOOR_F32 = 0x1p-30;
+
 // How the contracted index of an (L, n, R) view is walked:
 //  KC: R large, the R index is contiguous -> tiles step along R inside one l.
 //  NC: R == 1, the n index is contiguous -> tiles step along l.
