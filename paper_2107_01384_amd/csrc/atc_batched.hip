@@ -284,10 +284,12 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
 }
 
 // ---- cyclic Jacobi on sm.u.e.A (n <= 64) --------------------------------
-// The slot-order Jacobi as a call of its own: its eigenvector registers are
-// then not allocated next to the rest of the persistent kernel's state.
+// The slot-order Jacobi inlined into the persistent kernel: a call would
+// keep the kernel off the accumulation registers, whose 256 extra registers
+// per lane then take what the Gram and mode-product loops would otherwise
+// spill to scratch memory (133 -> 16 spilled registers).
 template <int M>
-__device__ __attribute__((noinline)) bool blk_jacobi_slots(int n, int max_sweeps, double (*A)[APAD],
+__device__ __attribute__((always_inline)) inline bool blk_jacobi_slots(int n, int max_sweeps, double (*A)[APAD],
                                                            double (*V)[APAD], J64Shared* sh, int* sweeps) {
     return jacobi_slots<M>(n, max_sweeps, JACOBI_FLOOR_F32, A, V, *sh, V, *sweeps);
 }
