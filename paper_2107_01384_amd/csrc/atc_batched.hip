@@ -146,12 +146,12 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
     for (int e = 0; e < E; ++e) dsq[e] = 0.0;
     constexpr int FLUSH_STEPS = FLUSH_TERMS / BK;
     int since = 0;
-    for (int64_t s = 0; s < steps; ++s) {
-        __syncthreads();
+    // the slab of step s into registers (zeros outside the tensor)
+    float vreg[E];
+    auto load = [&](int64_t s) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int row = srow[e];
-            float v = 0.f;
             bool in = sok[e] && row < n;
             int64_t off = 0;
             if (LAYOUT == LAYOUT_KC) {
@@ -168,7 +168,16 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
                 in = in && l < L;
                 off = (l * n + row) * R + sr[e];
             }
-            if (in) v = Y[off];
+            vreg[e] = in ? Y[off] : 0.f;
+        }
+    };
+    if (steps > 0) load(0);
+    for (int64_t s = 0; s < steps; ++s) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int row = srow[e];
+            const float v = vreg[e];
             dsq[e] = fma((double)v, (double)v, dsq[e]);
             if (sok[e]) {
                 if (P == PREC_BF16X3) {
@@ -181,6 +190,7 @@ __device__ void blk_gram(const float* __restrict__ Y, int n, int64_t L, int64_t 
             }
         }
         __syncthreads();
+        if (s + 1 < steps) load(s + 1);  // in flight while this slab is multiplied
         if (P == PREC_BF16X3) {
 #pragma unroll
             for (int k0 = 0; k0 < BK; k0 += 32) {
@@ -504,27 +514,50 @@ __device__ void blk_ttm(const float* __restrict__ Y, int n, int64_t L, int64_t R
             return p < planes && l < L;
         }
     };
-    for (int64_t ct = 0; ct < ctiles; ++ct) {
-        f32x4 acc[2][2];
+    // (column tile, slab) steps in one sequence, the next step's loads in
+    // flight while the current slab is multiplied
+    const int nks = (n + BK - 1) / BK;
+    const int64_t total = ctiles * nks;
+    auto slot = [&](int e, int& cc, int& kk) {
+        if (LAYOUT == LAYOUT_NC) {
+            kk = tid % BK;
+            cc = tid / BK + (BT / BK) * e;
+        } else {
+            cc = tid % CT;
+            kk = tid / CT + (BT / CT) * e;
+        }
+    };
+    float vreg[E];
+    auto load = [&](int64_t step) {
+        const int64_t ct = step / nks;
+        const int i0 = (int)(step - ct * nks) * BK;
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int e = 0; e < E; ++e) {
+            int cc, kk;
+            slot(e, cc, kk);
+            int64_t l, rr;
+            const bool ok = colmap(ct, cc, l, rr) && i0 + kk < n;
+            vreg[e] = ok ? Y[(l * n + i0 + kk) * R + rr] : 0.f;
+        }
+    };
+    if (total > 0) load(0);
+    f32x4 acc[2][2];
+    for (int64_t step = 0; step < total; ++step) {
+        const int64_t ct = step / nks;
+        const int i0 = (int)(step - ct * nks) * BK;
+        if (i0 == 0) {
 #pragma unroll
-            for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
-        for (int i0 = 0; i0 < n; i0 += BK) {
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
+        }
+        {
             __syncthreads();
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 int cc, kk;
-                if (LAYOUT == LAYOUT_NC) {
-                    kk = tid % BK;
-                    cc = tid / BK + (BT / BK) * e;
-                } else {
-                    cc = tid % CT;
-                    kk = tid / CT + (BT / CT) * e;
-                }
-                int64_t l, rr;
-                const bool ok = colmap(ct, cc, l, rr) && i0 + kk < n;
-                const float v = ok ? Y[(l * n + i0 + kk) * R + rr] : 0.f;
+                slot(e, cc, kk);
+                const float v = vreg[e];
                 if (P == PREC_BF16X3) {
                     const __bf16 hh = (__bf16)v;
                     sm.u.t.b.yh[cc][kk] = hh;
@@ -534,6 +567,7 @@ __device__ void blk_ttm(const float* __restrict__ Y, int n, int64_t L, int64_t R
                 }
             }
             __syncthreads();
+            if (step + 1 < total) load(step + 1);
             if (P == PREC_BF16X3) {
 #pragma unroll
                 for (int k0 = 0; k0 < BK; k0 += 32) {
@@ -586,18 +620,20 @@ __device__ void blk_ttm(const float* __restrict__ Y, int n, int64_t L, int64_t R
                 }
             }
         }
+        if (i0 + BK >= n) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int cc = wc + b * 16 + (lane & 15);
-            int64_t l, rr;
-            if (!colmap(ct, cc, l, rr)) continue;
+            for (int b = 0; b < 2; ++b) {
+                const int cc = wc + b * 16 + (lane & 15);
+                int64_t l, rr;
+                if (!colmap(ct, cc, l, rr)) continue;
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < 2; ++a)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int j = wr + a * 16 + mfma16_row<PREC_F32>(lane, v);
-                    if (j < r) Z[(l * r + j) * R + rr] = acc[a][b][v];
-                }
+                    for (int v = 0; v < 4; ++v) {
+                        const int j = wr + a * 16 + mfma16_row<PREC_F32>(lane, v);
+                        if (j < r) Z[(l * r + j) * R + rr] = acc[a][b][v];
+                    }
+            }
         }
     }
     __syncthreads();
