@@ -443,6 +443,55 @@ atc_status atc_core_apply_signs(void* core, const atc_shape* shape, const int32_
 atc_status atc_factor_error_term(const void* U, const void* Uq, int32_t dtype, int64_t n, int64_t r,
                                  const double* sigma2, double* out, void* stream);
 
+/* ------------------------------------------------------- hybrid compressor */
+
+/* Outputs of atc_hybrid_quantize: DEVICE buffers the caller owns (d = the
+ * core's order, r_k its sizes, n_k the factors' rows, e_k = n_k r_k - r_k
+ * (r_k + 1) / 2 the stored reflector entries of factor k). */
+typedef struct {
+    uint32_t* core_enc;                 /* atc_quantize_max_words(prod r_k, block_len) words */
+    atc_quant_info* core_info;          /* one record */
+    void* core_q;                       /* the dequantized core (core dtype, prod r_k values) */
+    double* sigma2;                     /* squared slice norms of core_q, mode after mode (sum r_k) */
+    int32_t* signs;                     /* the factors' column signs, mode after mode (sum r_k) */
+    void* factor_signed[ATC_MAX_DIMS];  /* U_k diag(signs_k), n_k x r_k (core dtype) */
+    double* factor_coef[ATC_MAX_DIMS];  /* weighted reflector entries, max(1, e_k) doubles */
+    uint32_t* factor_enc[ATC_MAX_DIMS]; /* atc_quantize_max_words(e_k, block_len) words (unused when e_k = 0) */
+    atc_quant_info* factor_info[ATC_MAX_DIMS];  /* one record each (not written when e_k = 0) */
+    void* factor_q[ATC_MAX_DIMS];       /* factors rebuilt from the quantized entries, n_k x r_k */
+    double* factor_term;                /* d doubles: |dU_k Sigma_k|_F^2 */
+    int32_t* status;                    /* one int32: the decoders' damage flags OR-ed (0 expected) */
+} atc_hybrid_out;
+
+/* Workspace of atc_hybrid_quantize (0 on invalid arguments).  core_shape:
+ * the core (r_k, dtype); n: the factors' rows n_k. */
+size_t atc_hybrid_workspace_size(const atc_shape* core_shape, const int64_t* n, int32_t block_len);
+
+/*
+ * The quantization half of the hybrid truncation (Section 4.1.3) after an
+ * ST-HOSVD, in one call: the Householder form of every factor and its column
+ * signs (supplement S.2), the core's slices flipped by them, the core
+ * quantized to core_target_sse and decoded (Sections 3.3, 4.2, 4.3), its
+ * slice norms, then per factor the stored entries weighted by sqrt(2 alpha_j),
+ * quantized to factor_target_sse, decoded, the factor rebuilt from them and
+ * its error term |dU Sigma|_F^2 (eq. total_error_approximation).  The error
+ * predicted by that equation is the ST-HOSVD's discarded energy plus
+ * core_info->sse plus the sum of factor_term.
+ *  core      DEVICE, the ST-HOSVD core (row-major r_0 x ... x r_{d-1}).
+ *  factors   host array of d DEVICE pointers, U_k (n_k x r_k, row-major,
+ *            orthonormal columns, the core's dtype).
+ *  n         host array of the d row counts n_k (<= 4096; r_k <= 256).
+ * Every step runs on `stream`, the d factors sharing each launch; no
+ * allocation of device memory, no host wait.  Targets must be finite (a
+ * negative target keeps every bit).  Errors: ATC_ERR_INVALID_ARGUMENT (NULL
+ * buffer, bad shape, r_k > n_k), ATC_ERR_UNSUPPORTED (n_k > 4096 or r_k > 256),
+ * ATC_ERR_WORKSPACE_TOO_SMALL, ATC_ERR_DEVICE (a launch failed).
+ */
+atc_status atc_hybrid_quantize(const void* core, const atc_shape* core_shape, const void* const* factors,
+                               const int64_t* n, double core_target_sse, double factor_target_sse,
+                               int32_t block_len, const atc_hybrid_out* out, void* workspace,
+                               size_t workspace_bytes, void* stream);
+
 /* ------------------------------------------------------------------ misc */
 const char* atc_status_string(atc_status s);
 const char* atc_last_error(void);

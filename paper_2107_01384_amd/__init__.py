@@ -20,6 +20,7 @@ import os
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -84,6 +85,16 @@ class QuantInfo(ctypes.Structure):
 
 QUANT_KZERO = -(2 ** 31)
 
+
+class HybridOut(ctypes.Structure):
+    _fields_ = [
+        ("core_enc", ctypes.c_void_p), ("core_info", ctypes.c_void_p), ("core_q", ctypes.c_void_p),
+        ("sigma2", ctypes.c_void_p), ("signs", ctypes.c_void_p),
+        ("factor_signed", ctypes.c_void_p * MAX_DIMS), ("factor_coef", ctypes.c_void_p * MAX_DIMS),
+        ("factor_enc", ctypes.c_void_p * MAX_DIMS), ("factor_info", ctypes.c_void_p * MAX_DIMS),
+        ("factor_q", ctypes.c_void_p * MAX_DIMS), ("factor_term", ctypes.c_void_p), ("status", ctypes.c_void_p),
+    ]
+
 # (name, restype, argtypes) of every symbol include/atc.h declares
 _VP, _SZ, _I64, _I32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int32
 _P = ctypes.POINTER
@@ -118,6 +129,9 @@ SIGNATURES = [
     ("atc_core_slice_norms", _I32, [_VP, _P(Shape), _VP, _VP]),
     ("atc_core_apply_signs", _I32, [_VP, _P(Shape), _VP, _VP]),
     ("atc_factor_error_term", _I32, [_VP, _VP, _I32, _I64, _I64, _VP, _VP, _VP]),
+    ("atc_hybrid_workspace_size", _SZ, [_P(Shape), _P(_I64), _I32]),
+    ("atc_hybrid_quantize", _I32, [_VP, _P(Shape), _P(_VP), _P(_I64), ctypes.c_double, ctypes.c_double, _I32,
+                                   _P(HybridOut), _VP, _SZ, _VP]),
     ("atc_status_string", ctypes.c_char_p, [_I32]),
     ("atc_last_error", ctypes.c_char_p, []),
     ("atc_version", ctypes.c_char_p, []),
@@ -433,7 +447,11 @@ def _quantize_launch(core: torch.Tensor, target_sse: float, block_len: int, stre
 def _quantize_finish(enc: torch.Tensor, info_d: torch.Tensor) -> QuantStream:
     """Reads the device record back (waits for the stream that wrote it)."""
     raw = bytes(info_d.cpu().numpy().tobytes())
-    info = QuantInfo.from_buffer_copy(raw)
+    return _quantize_stream(enc, QuantInfo.from_buffer_copy(raw))
+
+
+def _quantize_stream(enc: torch.Tensor, info: QuantInfo) -> QuantStream:
+    """The stream of a quantization from its host copy of the record."""
     if info.status not in (0,):
         raise AtcError(info.status, "quantization of the core failed (device status)")
     return QuantStream(words=enc[: info.words], k=None if info.k == QUANT_KZERO else int(info.k), plane=int(info.plane),
@@ -606,96 +624,90 @@ class Compressed:
     target_sse: float
 
 
-_SIDE_STREAMS = {}
-
-
-def _side_streams(device, count: int) -> List[torch.cuda.Stream]:
-    """Streams of the default priority for the per-factor steps, kept per device."""
-    key = torch.device(device).index
-    lst = _SIDE_STREAMS.setdefault(key, [])
-    while len(lst) < count:
-        lst.append(torch.cuda.Stream(device=device))
-    return lst[:count]
-
-
 def compress(x: torch.Tensor, rel_error: float = 1e-3, rtmss: float = 0.5, precision: str = "bf16x3",
              block_len: int = 1024, factor_share: float = 0.01, stream=None) -> Compressed:
     """The hybrid truncation of Section 4.1.3 end to end on the GPU: ST-HOSVD to
-    rtmss * (rel_error |x|)^2; the core quantized (Sections 3.3, 4.2, 4.3) to
-    the rest of the target; each factor in its Householder form with the
-    weights of supplement S.2, quantized to factor_share of the target split
-    over the modes; the error predicted by eq. (total_error_approximation).
-    Every step runs in the library's kernels; this function sequences them and
-    forms the targets.  The factors' steps run on side streams of their own
-    (forked from `stream` and joined back to it), and the device records are
-    read once, at the end."""
-    main = stream if stream is not None else torch.cuda.current_stream(x.device)
-    with torch.cuda.stream(main):
-        t = sthosvd(x, rel_error, precision, rtmss=rtmss)
+    rtmss * (rel_error |x|)^2, then one atc_hybrid_quantize call: the core
+    quantized (Sections 3.3, 4.2, 4.3) to the rest of the target, each factor
+    in its Householder form with the weights of supplement S.2 quantized to
+    factor_share of the target split over the modes, and the terms of eq.
+    (total_error_approximation).  This function allocates the outputs, forms
+    the targets and reads the device records back once, at the end."""
+    lib = load()
+    t = sthosvd(x, rel_error, precision, rtmss=rtmss, stream=stream)
     d = len(t.ranks)
     target = rel_error * rel_error * t.norm2
-    side = _side_streams(x.device, d)
+    core = t.core.contiguous()
+    facs = [f.contiguous() for f in t.factors]
+    dev = x.device
+    ranks = [int(r) for r in t.ranks]
+    ns = [int(f.shape[0]) for f in facs]
+    cs = _shape(ranks, core.dtype)
+    n_arr = (ctypes.c_int64 * d)(*ns)
+    wsz = lib.atc_hybrid_workspace_size(ctypes.byref(cs), n_arr, int(block_len))
+    if wsz == 0:
+        _check(-1)
+    total = core.numel()
+    out = HybridOut()
+    keep = []  # every tensor the call writes, alive until the readback
 
-    def fork_join(work):
-        """work(k) on side stream k for every mode, after what `main` has queued;
-        `main` then waits for all of them."""
-        start = torch.cuda.Event()
-        start.record(main)
-        ends = []
-        for k in range(d):
-            side[k].wait_event(start)
-            with torch.cuda.stream(side[k]):
-                work(k)
-            ev = torch.cuda.Event()
-            ev.record(side[k])
-            ends.append(ev)
-        for ev in ends:
-            main.wait_event(ev)
+    def buf(count, dtype):
+        tt = torch.empty(max(1, int(count)), dtype=dtype, device=dev)
+        keep.append(tt)
+        return tt
 
-    # reflectors and column signs of every factor (supplement S.2); the
-    # reflectors of U diag(signs) are those of U, so the unweighted entries
-    # are weighted once the quantized core's slice norms are known
-    hh = [None] * d
-
-    def reflectors(k):
-        hh[k] = factor_householder(t.factors[k].contiguous(), None)
-
-    fork_join(reflectors)
-    signs = [h[1] for h in hh]
-    signed = [h[2] for h in hh]
-    with torch.cuda.stream(main):
-        core = t.core.contiguous().clone()
-        core_apply_signs(core, signs)
-        enc, info = _quantize_launch(core, target - t.sse_pred, block_len)
-        status = torch.zeros(1 + d, dtype=torch.int32, device=x.device)
-        core_q = _dequantize_launch(enc, core.numel(), block_len, core.dtype, status[0:1]).view(*t.ranks)
-        s2 = core_slice_norms(core_q)
-        fterm = torch.zeros(d, dtype=torch.float64, device=x.device)
-    coefs, fq, facs_q = [None] * d, [None] * d, [None] * d
-
-    def factor(k):
-        n, r = int(signed[k].shape[0]), int(signed[k].shape[1])
-        coef = factor_weight_coefficients(hh[k][0], s2[k], n, r)
-        coefs[k] = coef
-        if coef.numel() > 0:
-            fq[k] = _quantize_launch(coef, factor_share * target / d, block_len)
-            cq = _dequantize_launch(fq[k][0], coef.numel(), block_len, torch.float64, status[1 + k:2 + k])
+    # the device records in one buffer, read back with one copy: d + 1 stream
+    # records, d error terms, the decoders' status
+    qsz = ctypes.sizeof(QuantInfo)
+    rec = buf((d + 1) * qsz + 8 * d + 8, torch.uint8)
+    core_info = rec[0:qsz]
+    fterm = rec[(d + 1) * qsz:(d + 1) * qsz + 8 * d].view(torch.float64)
+    status = rec[(d + 1) * qsz + 8 * d:(d + 1) * qsz + 8 * d + 4].view(torch.int32)
+    core_enc = buf(lib.atc_quantize_max_words(total, int(block_len)), torch.int32)
+    core_q = buf(total, core.dtype)
+    sigma2 = buf(sum(ranks), torch.float64)
+    signs_all = buf(sum(ranks), torch.int32)
+    out.core_enc, out.core_info, out.core_q = core_enc.data_ptr(), core_info.data_ptr(), core_q.data_ptr()
+    out.sigma2, out.signs = sigma2.data_ptr(), signs_all.data_ptr()
+    out.factor_term, out.status = fterm.data_ptr(), status.data_ptr()
+    signed, coefs, fencs, finfos, facs_q, ncoef = [], [], [], [], [], []
+    for k in range(d):
+        n, r = ns[k], ranks[k]
+        e = n * r - r * (r + 1) // 2
+        ncoef.append(e)
+        signed.append(buf(n * r, core.dtype).view(n, r))
+        coefs.append(buf(e, torch.float64))
+        facs_q.append(buf(n * r, core.dtype).view(n, r))
+        if e > 0:
+            fencs.append(buf(lib.atc_quantize_max_words(e, int(block_len)), torch.int32))
+            finfos.append(rec[(k + 1) * qsz:(k + 2) * qsz])
+            out.factor_enc[k], out.factor_info[k] = fencs[-1].data_ptr(), finfos[-1].data_ptr()
         else:
-            cq = coef
-        facs_q[k] = factor_from_householder(cq, s2[k], n, r, signed[k].dtype)
-        _factor_error_launch(signed[k], facs_q[k], s2[k], fterm[k:k + 1])
-
-    fork_join(factor)
-    main.synchronize()
-    cs = _quantize_finish(enc, info)
-    fstreams = [_quantize_finish(*fq[k]) if fq[k] is not None else None for k in range(d)]
-    if int(status.max().item()) != 0:
+            fencs.append(None)
+            finfos.append(None)
+        out.factor_signed[k], out.factor_coef[k] = signed[k].data_ptr(), coefs[k].data_ptr()
+        out.factor_q[k] = facs_q[k].data_ptr()
+    ws = buf(wsz, torch.uint8)
+    fptrs = (ctypes.c_void_p * d)(*[f.data_ptr() for f in facs])
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(lib.atc_hybrid_quantize(ctypes.c_void_p(core.data_ptr()), ctypes.byref(cs), fptrs, n_arr,
+                                   float(target - t.sse_pred), float(factor_share * target / d), int(block_len),
+                                   ctypes.byref(out), ctypes.c_void_p(ws.data_ptr()), wsz,
+                                   ctypes.c_void_p(_stream(st))))
+    raw = rec.cpu().numpy().tobytes()  # waits for the stream
+    infos = [QuantInfo.from_buffer_copy(raw[i * qsz:(i + 1) * qsz]) for i in range(d + 1)]
+    cs_q = _quantize_stream(core_enc, infos[0])
+    fstreams = [_quantize_stream(fencs[k], infos[k + 1]) if ncoef[k] > 0 else None for k in range(d)]
+    if int(np.frombuffer(raw, dtype=np.int32, count=1, offset=(d + 1) * qsz + 8 * d)[0]) != 0:
         raise AtcError(-7, "damaged stream: block fields do not match their planes")
-    fterms = [float(v) for v in fterm.cpu().tolist()]
-    pred = t.sse_pred + cs.sse + sum(fterms)
-    return Compressed(tucker=t, core_stream=cs, factor_coef=coefs, factor_streams=fstreams, signs=signs, sigma2=s2,
-                      core_q=core_q, factors_q=facs_q, factors_signed=signed, predicted_sse=pred,
-                      terms={"sthosvd": t.sse_pred, "core": cs.sse, "factors": fterms}, target_sse=target)
+    fterms = [float(v) for v in np.frombuffer(raw, dtype=np.float64, count=d, offset=(d + 1) * qsz)]
+    signs = list(torch.split(signs_all, ranks))
+    s2 = list(torch.split(sigma2, ranks))
+    pred = t.sse_pred + cs_q.sse + sum(fterms)
+    return Compressed(tucker=t, core_stream=cs_q, factor_coef=[coefs[k][:ncoef[k]] for k in range(d)],
+                      factor_streams=fstreams, signs=signs, sigma2=s2, core_q=core_q.view(*ranks),
+                      factors_q=facs_q, factors_signed=signed, predicted_sse=pred,
+                      terms={"sthosvd": t.sse_pred, "core": cs_q.sse, "factors": fterms}, target_sse=target)
 
 
 def decompress(c: Compressed, stream=None) -> torch.Tensor:

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libatc.so")
 SOURCES = ["atc_gram.hip", "atc_gram_kc.hip", "atc_ttm.hip", "atc_eig.hip", "atc_batched.hip", "atc_quant.hip",
-           "atc_hh.hip", "atc_abi.hip"]
+           "atc_hh.hip", "atc_hybrid.hip", "atc_abi.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -89,6 +89,11 @@ inline bool hh_in_lds(int64_t n, int r, int64_t extra) {
     return ((size_t)n * hh_ld(r) + (size_t)extra) * sizeof(double) <= HH_LDS_CAP;
 }
 
+// The factors of one launch, indexed by the workgroup's factor slot.
+struct FJobs {
+    FactorTask j[ATC_MAX_DIMS];
+};
+
 struct HhSlice {
     int c, s, S, i0, i1;  // column, slice, slices, rows [i0, i1)
     bool on;
@@ -137,14 +142,20 @@ __device__ __forceinline__ void slice_sums(const double* a, int sa, const double
 // coefficients.  R[j][c] and x_0 are read before the first barrier, since
 // the thread of row j updates them after it.
 template <typename T, bool LDS>
-__global__ void __launch_bounds__(HHT) k_hh_encode(const T* __restrict__ U, int64_t n, int r,
-                                                   const double* __restrict__ s2, double* __restrict__ coef,
-                                                   int32_t* __restrict__ signs, T* __restrict__ Uprime,
-                                                   double* __restrict__ Rg) {
+__global__ void __launch_bounds__(HHT) k_hh_encode(const FJobs B) {
     extern __shared__ double hh_lds[];
     __shared__ double part[HHT];
     __shared__ double wcol[HH_MAX_R];
     __shared__ int32_t sg[HH_MAX_R];
+    const FactorTask& J = B.j[blockIdx.x];
+    const T* __restrict__ U = (const T*)J.U;
+    const int64_t n = J.n;
+    const int r = J.r;
+    const double* __restrict__ s2 = J.s2;
+    double* __restrict__ coef = J.coef;
+    int32_t* __restrict__ signs = J.signs;
+    T* __restrict__ Uprime = (T*)J.Uprime;
+    double* __restrict__ Rg = J.ws;
     const int ld = hh_ld(r);
     double* R = LDS ? hh_lds : Rg;
     const HhSlice h = hh_slice(n, r);
@@ -208,12 +219,18 @@ __global__ void __launch_bounds__(HHT) k_hh_encode(const T* __restrict__ U, int6
 // slice partials of column j's threads.  v_j (unweighted) is staged in LDS,
 // the next reflector's while the current one is applied.
 template <typename T, bool LDS>
-__global__ void __launch_bounds__(HHT) k_hh_decode(const double* __restrict__ coef, const double* __restrict__ s2,
-                                                   int64_t n, int r, T* __restrict__ Uout, double* __restrict__ Xg) {
+__global__ void __launch_bounds__(HHT) k_hh_decode(const FJobs B) {
     extern __shared__ double hh_lds[];
     __shared__ double part[HHT];
     __shared__ double partv[HHT];
     __shared__ double wcol[HH_MAX_R];
+    const FactorTask& J = B.j[blockIdx.x];
+    const double* __restrict__ coef = J.entries;
+    const double* __restrict__ s2 = J.s2;
+    const int64_t n = J.n;
+    const int r = J.r;
+    T* __restrict__ Uout = (T*)J.Uq;
+    double* __restrict__ Xg = J.ws;
     const int ld = hh_ld(r);
     double* vbuf = hh_lds;                     // 2 x n
     double* X = LDS ? hh_lds + 2 * n : Xg;    // n x ld
@@ -268,12 +285,17 @@ __global__ void __launch_bounds__(HHT) k_hh_decode(const double* __restrict__ co
     }
 }
 
-// coef of column j (blockIdx.y) times sqrt(2 alpha_j); each workgroup forms
-// its column's weight from the slice norms after it.
-__global__ void __launch_bounds__(256) k_hh_weight(double* __restrict__ coef, const double* __restrict__ s2, int64_t n,
-                                                   int r) {
+// coef of column j (blockIdx.y) of factor blockIdx.z times sqrt(2 alpha_j);
+// each workgroup forms its column's weight from the slice norms after it.
+__global__ void __launch_bounds__(256) k_hh_weight(const FJobs B) {
     __shared__ double wj;
+    const FactorTask& J = B.j[blockIdx.z];
+    double* __restrict__ coef = J.coef;
+    const double* __restrict__ s2 = J.s2;
+    const int64_t n = J.n;
+    const int r = J.r;
     const int j = blockIdx.y;
+    if (j >= r) return;
     if (threadIdx.x == 0) {
         double rest = 0.0;
         for (int k = r - 1; k > j; --k) rest += s2[k];
@@ -338,9 +360,15 @@ __global__ void k_apply_signs(T* __restrict__ core, int d, Dims8 dm, int64_t tot
 }
 
 template <typename T>
-__global__ void __launch_bounds__(HT) k_factor_error(const T* __restrict__ U, const T* __restrict__ Uq, int64_t n, int r,
-                                                     const double* __restrict__ s2, double* __restrict__ out) {
+__global__ void __launch_bounds__(HT) k_factor_error(const FJobs B) {
     __shared__ double red[HW];
+    const FactorTask& J = B.j[blockIdx.x];
+    const T* __restrict__ U = (const T*)J.U;
+    const T* __restrict__ Uq = (const T*)J.Uq;
+    const int64_t n = J.n;
+    const int r = J.r;
+    const double* __restrict__ s2 = J.s2;
+    double* __restrict__ out = J.err;
     double p = 0.0;
     for (int64_t e = threadIdx.x; e < n * r; e += HT) {
         const double dlt = (double)Uq[e] - (double)U[e];
@@ -370,6 +398,30 @@ bool hh_lds_ready() {
     return state == 1;
 }
 
+// Factors whose working matrix fits the LDS budget go in one launch, the
+// others in a second one (the kernel variant is per launch).
+template <typename Kt, typename Kg>
+hipError_t launch_hh_groups(const FactorTask* t, int count, int64_t extra_per_n, Kt k_lds, Kg k_ws, hipStream_t st) {
+    FJobs in{}, out{};
+    int ni = 0, no = 0;
+    size_t shm_in = 0, shm_out = 0;
+    for (int z = 0; z < count; ++z) {
+        const int64_t n = t[z].n;
+        const int r = t[z].r;
+        const int64_t extra = extra_per_n * n;
+        if (hh_in_lds(n, r, extra)) {
+            in.j[ni++] = t[z];
+            shm_in = std::max(shm_in, ((size_t)n * hh_ld(r) + (size_t)extra) * sizeof(double));
+        } else {
+            out.j[no++] = t[z];
+            shm_out = std::max(shm_out, (size_t)extra * sizeof(double));
+        }
+    }
+    if (ni) hipLaunchKernelGGL(k_lds, dim3((unsigned)ni), dim3(HHT), shm_in, st, in);
+    if (no) hipLaunchKernelGGL(k_ws, dim3((unsigned)no), dim3(HHT), shm_out, st, out);
+    return hipGetLastError();
+}
+
 atc_status hfail(atc_status s, const char* msg) {
     set_last_error(msg);
     return s;
@@ -382,6 +434,43 @@ atc_status check_nr(int64_t n, int64_t r) {
 }
 
 }  // namespace
+
+hipError_t householder_encode_batch(const FactorTask* t, int count, int f64, hipStream_t st) {
+    if (count < 1 || count > ATC_MAX_DIMS || !hh_lds_ready()) return hipErrorInvalidValue;
+    return f64 ? launch_hh_groups(t, count, 0, k_hh_encode<double, true>, k_hh_encode<double, false>, st)
+               : launch_hh_groups(t, count, 0, k_hh_encode<float, true>, k_hh_encode<float, false>, st);
+}
+
+hipError_t householder_decode_batch(const FactorTask* t, int count, int f64, hipStream_t st) {
+    if (count < 1 || count > ATC_MAX_DIMS || !hh_lds_ready()) return hipErrorInvalidValue;
+    return f64 ? launch_hh_groups(t, count, 2, k_hh_decode<double, true>, k_hh_decode<double, false>, st)
+               : launch_hh_groups(t, count, 2, k_hh_decode<float, true>, k_hh_decode<float, false>, st);
+}
+
+hipError_t householder_weight_batch(const FactorTask* t, int count, hipStream_t st) {
+    if (count < 1 || count > ATC_MAX_DIMS) return hipErrorInvalidValue;
+    FJobs B{};
+    int64_t maxn = 1;
+    int maxr = 1;
+    for (int z = 0; z < count; ++z) {
+        B.j[z] = t[z];
+        maxn = std::max(maxn, t[z].n);
+        maxr = std::max(maxr, t[z].r);
+    }
+    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(16, ceil_div(maxn - 1, 256)));
+    hipLaunchKernelGGL(k_hh_weight, dim3(gx, (unsigned)maxr, (unsigned)count), dim3(256), 0, st, B);
+    return hipGetLastError();
+}
+
+hipError_t factor_error_batch(const FactorTask* t, int count, int f64, hipStream_t st) {
+    if (count < 1 || count > ATC_MAX_DIMS) return hipErrorInvalidValue;
+    FJobs B{};
+    for (int z = 0; z < count; ++z) B.j[z] = t[z];
+    if (f64) hipLaunchKernelGGL(k_factor_error<double>, dim3((unsigned)count), dim3(HT), 0, st, B);
+    else hipLaunchKernelGGL(k_factor_error<float>, dim3((unsigned)count), dim3(HT), 0, st, B);
+    return hipGetLastError();
+}
+
 }  // namespace atc
 
 using namespace atc;
@@ -401,21 +490,17 @@ atc_status atc_factor_householder(const void* U, int32_t dtype, int64_t n, int64
     if (!U || !coef || !signs || !workspace) return hfail(ATC_ERR_INVALID_ARGUMENT, "U, coef, signs and workspace must be non-NULL");
     if (dtype != ATC_F32 && dtype != ATC_F64) return hfail(ATC_ERR_INVALID_ARGUMENT, "unknown dtype");
     if (workspace_bytes < atc_householder_workspace_size(n, r)) return hfail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
-    hipStream_t st = (hipStream_t)stream;
-    double* R = (double*)workspace;
-    const bool lds = hh_in_lds(n, (int)r, 0);
-    const size_t shm = lds ? (size_t)n * hh_ld((int)r) * sizeof(double) : 0;
     if (!hh_lds_ready()) return hfail(ATC_ERR_DEVICE, "could not raise the LDS limit of the Householder kernels");
-    if (dtype == ATC_F64) {
-        auto k = lds ? k_hh_encode<double, true> : k_hh_encode<double, false>;
-        hipLaunchKernelGGL(k, dim3(1), dim3(HHT), shm, st, (const double*)U, n, (int)r, sigma2, coef, signs,
-                           (double*)Uprime, R);
-    } else {
-        auto k = lds ? k_hh_encode<float, true> : k_hh_encode<float, false>;
-        hipLaunchKernelGGL(k, dim3(1), dim3(HHT), shm, st, (const float*)U, n, (int)r, sigma2, coef, signs,
-                           (float*)Uprime, R);
-    }
-    const hipError_t e = hipGetLastError();
+    FactorTask t{};
+    t.n = n;
+    t.r = (int)r;
+    t.U = U;
+    t.s2 = sigma2;
+    t.coef = coef;
+    t.signs = signs;
+    t.Uprime = Uprime;
+    t.ws = (double*)workspace;
+    const hipError_t e = householder_encode_batch(&t, 1, dtype == ATC_F64, (hipStream_t)stream);
     return e == hipSuccess ? ATC_OK : hfail(ATC_ERR_DEVICE, hipGetErrorString(e));
 }
 
@@ -426,19 +511,15 @@ atc_status atc_factor_from_householder(const double* coef, const double* sigma2,
     if (!coef || !U_out || !workspace) return hfail(ATC_ERR_INVALID_ARGUMENT, "coef, U_out and workspace must be non-NULL");
     if (dtype != ATC_F32 && dtype != ATC_F64) return hfail(ATC_ERR_INVALID_ARGUMENT, "unknown dtype");
     if (workspace_bytes < atc_householder_workspace_size(n, r)) return hfail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace too small");
-    hipStream_t st = (hipStream_t)stream;
-    double* X = (double*)workspace;
-    const bool lds = hh_in_lds(n, (int)r, 2 * n);
-    const size_t shm = ((size_t)2 * n + (lds ? (size_t)n * hh_ld((int)r) : 0)) * sizeof(double);
     if (!hh_lds_ready()) return hfail(ATC_ERR_DEVICE, "could not raise the LDS limit of the Householder kernels");
-    if (dtype == ATC_F64) {
-        auto k = lds ? k_hh_decode<double, true> : k_hh_decode<double, false>;
-        hipLaunchKernelGGL(k, dim3(1), dim3(HHT), shm, st, coef, sigma2, n, (int)r, (double*)U_out, X);
-    } else {
-        auto k = lds ? k_hh_decode<float, true> : k_hh_decode<float, false>;
-        hipLaunchKernelGGL(k, dim3(1), dim3(HHT), shm, st, coef, sigma2, n, (int)r, (float*)U_out, X);
-    }
-    const hipError_t e = hipGetLastError();
+    FactorTask t{};
+    t.n = n;
+    t.r = (int)r;
+    t.s2 = sigma2;
+    t.entries = coef;
+    t.Uq = U_out;
+    t.ws = (double*)workspace;
+    const hipError_t e = householder_decode_batch(&t, 1, dtype == ATC_F64, (hipStream_t)stream);
     return e == hipSuccess ? ATC_OK : hfail(ATC_ERR_DEVICE, hipGetErrorString(e));
 }
 
@@ -447,9 +528,12 @@ atc_status atc_factor_weight_coefficients(double* coef, const double* sigma2, in
     if (s != ATC_OK) return s;
     if (!coef || !sigma2) return hfail(ATC_ERR_INVALID_ARGUMENT, "coef and sigma2 must be non-NULL");
     if (n == 1) return ATC_OK;  // r = 1: nothing stored
-    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(16, ceil_div(n - 1, 256)));
-    hipLaunchKernelGGL(k_hh_weight, dim3(gx, (unsigned)r), dim3(256), 0, (hipStream_t)stream, coef, sigma2, n, (int)r);
-    const hipError_t e = hipGetLastError();
+    FactorTask t{};
+    t.n = n;
+    t.r = (int)r;
+    t.s2 = sigma2;
+    t.coef = coef;
+    const hipError_t e = householder_weight_batch(&t, 1, (hipStream_t)stream);
     return e == hipSuccess ? ATC_OK : hfail(ATC_ERR_DEVICE, hipGetErrorString(e));
 }
 
@@ -510,14 +594,14 @@ atc_status atc_factor_error_term(const void* U, const void* Uq, int32_t dtype, i
     if (!U || !Uq || !sigma2 || !out) return hfail(ATC_ERR_INVALID_ARGUMENT, "U, Uq, sigma2 and out must be non-NULL");
     if (n < 1 || r < 1) return hfail(ATC_ERR_INVALID_ARGUMENT, "n and r must be >= 1");
     if (dtype != ATC_F32 && dtype != ATC_F64) return hfail(ATC_ERR_INVALID_ARGUMENT, "unknown dtype");
-    hipStream_t st = (hipStream_t)stream;
-    if (dtype == ATC_F64)
-        hipLaunchKernelGGL(k_factor_error<double>, dim3(1), dim3(HT), 0, st, (const double*)U, (const double*)Uq, n,
-                           (int)r, sigma2, out);
-    else
-        hipLaunchKernelGGL(k_factor_error<float>, dim3(1), dim3(HT), 0, st, (const float*)U, (const float*)Uq, n,
-                           (int)r, sigma2, out);
-    const hipError_t e = hipGetLastError();
+    FactorTask t{};
+    t.n = n;
+    t.r = (int)r;
+    t.U = U;
+    t.Uq = const_cast<void*>(Uq);  // read only by the error-term kernel
+    t.s2 = sigma2;
+    t.err = out;
+    const hipError_t e = factor_error_batch(&t, 1, dtype == ATC_F64, (hipStream_t)stream);
     return e == hipSuccess ? ATC_OK : hfail(ATC_ERR_DEVICE, hipGetErrorString(e));
 }
 

@@ -283,4 +283,51 @@ void recon_order(const atc_shape* s, const int64_t* ranks, int* order);
 // Zeroes n bytes with a kernel (capturable in a graph, unlike memset nodes).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 
+// Batched forms of atc_quantize_core and atc_dequantize_core: `count` arrays
+// (1 .. ATC_MAX_DIMS) of one dtype and block length share every launch, grid
+// slice z working on task z.  Fields as in the C entry points, checked by the
+// caller; ws sized by atc_quantize_workspace_size / atc_dequantize_workspace_size
+// for the task's n.
+struct QuantTask {
+    const void* x;
+    int64_t n;
+    double target;
+    uint32_t* enc;
+    size_t enc_words;
+    atc_quant_info* info;
+    void* ws;
+};
+hipError_t quantize_batch(const QuantTask* tasks, int count, int f64, int len, hipStream_t st);
+struct DequantTask {
+    const uint32_t* enc;
+    int64_t n;
+    void* out;
+    int32_t* status;
+    void* ws;
+};
+hipError_t dequantize_batch(const DequantTask* tasks, int count, int f64, int len, hipStream_t st);
+
+// Batched forms of the factor steps of the hybrid compressor (supplement S.2,
+// eq. (total_error_approximation)): one workgroup (or grid slice) per factor,
+// `count` factors (1 .. ATC_MAX_DIMS) of one dtype per launch, each n x r
+// with 1 <= r <= n <= 4096, r <= 256 (checked by the caller).  A step reads
+// and writes the fields that its C entry point takes.
+struct FactorTask {
+    int64_t n;
+    int r;
+    const void* U;          // the factor (encode, error term)
+    const double* s2;       // squared slice norms of the quantized core (NULL: unweighted encode)
+    double* coef;           // reflector entries (written by encode, weighted in place)
+    int32_t* signs;         // column signs (encode)
+    void* Uprime;           // the signed factor (encode; may be NULL)
+    const double* entries;  // the entries a factor is rebuilt from (decode)
+    void* Uq;               // the rebuilt factor (decode, error term)
+    double* err;            // |dU Sigma|_F^2 (error term)
+    double* ws;             // atc_householder_workspace_size(n, r) bytes (encode, decode)
+};
+hipError_t householder_encode_batch(const FactorTask* t, int count, int f64, hipStream_t st);
+hipError_t householder_weight_batch(const FactorTask* t, int count, hipStream_t st);
+hipError_t householder_decode_batch(const FactorTask* t, int count, int f64, hipStream_t st);
+hipError_t factor_error_batch(const FactorTask* t, int count, int f64, hipStream_t st);
+
 }  // namespace atc

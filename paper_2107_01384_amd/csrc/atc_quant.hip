@@ -180,8 +180,25 @@ size_t block_max_words(int64_t m) {
     return QBLK_HDR + (run_bytes + 3) / 4 + ((size_t)m + 31) / 32 + ((size_t)QPLANES * m + 31) / 32;
 }
 
+// One array of a batch quantized by the same launches: grid slice z of every
+// kernel works on job z (arrays of one dtype and block length).
+constexpr int QMAX_JOBS = ATC_MAX_DIMS;
+struct QJob {
+    const void* x;
+    int64_t n, nb;
+    double target;
+    uint32_t* out;
+    size_t out_words;
+    atc_quant_info* info;
+    QWs w;
+};
+struct QJobs {
+    QJob j[QMAX_JOBS];
+};
+
 // ------------------------------------------------------------ kernels
-__global__ void k_q_init(QState* st) {
+__global__ void k_q_init(const QJobs B) {
+    QState* st = B.j[blockIdx.z].w.st;
     if (threadIdx.x == 0) {
         st->maxbits = 0;
         st->first = ~0ull;
@@ -197,7 +214,11 @@ __global__ void k_q_init(QState* st) {
 }
 
 template <typename T>
-__global__ void k_q_max(const T* __restrict__ x, int64_t n, QState* st) {
+__global__ void k_q_max(const QJobs B) {
+    const QJob& J = B.j[blockIdx.z];
+    const T* __restrict__ x = (const T*)J.x;
+    const int64_t n = J.n;
+    QState* st = J.w.st;
     unsigned long long m = 0;
     int bad = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -226,11 +247,15 @@ __device__ __forceinline__ int32_t scale_of(unsigned long long maxbits) {
 constexpr int PLANES_THREADS = 320;   // 65 planes x 4 partial sums, 5 wavefronts
 
 template <typename T>
-__global__ void __launch_bounds__(PLANES_THREADS) k_q_planes(const T* __restrict__ x, int64_t n, int len,
-                                                              QWs w) {
+__global__ void __launch_bounds__(PLANES_THREADS) k_q_planes(const QJobs B, int len) {
     __shared__ uint64_t sq[QMAX_BLOCK];
     __shared__ U192 red[PLANES_THREADS];
+    const QJob& J = B.j[blockIdx.z];
+    const T* __restrict__ x = (const T*)J.x;
+    const int64_t n = J.n;
+    const QWs w = J.w;
     const int b = blockIdx.x;
+    if (b >= J.nb) return;
     const int64_t lo = (int64_t)b * len;
     const int m = (int)min<int64_t>(len, n - lo);
     const int32_t k = scale_of(w.st->maxbits);
@@ -305,8 +330,10 @@ __device__ U192 block_sum_u192(U192 v, U192* red) {
 
 // Workgroup p: the core's error with every plane >= p known, summed over the
 // blocks' partials.
-__global__ void __launch_bounds__(256) k_q_plane_sums(int64_t nb, QWs w) {
+__global__ void __launch_bounds__(256) k_q_plane_sums(const QJobs B) {
     __shared__ U192 red[256];
+    const int64_t nb = B.j[blockIdx.z].nb;
+    const QWs w = B.j[blockIdx.z].w;
     const int p = blockIdx.x;
     U192 s = u192_zero();
     for (int64_t b = threadIdx.x; b < nb; b += 256) u192_add(s, w.part[(size_t)b * 65 + p]);
@@ -315,9 +342,10 @@ __global__ void __launch_bounds__(256) k_q_plane_sums(int64_t nb, QWs w) {
 }
 
 // One thread: scale, target, breakpoint plane.
-__global__ void k_q_plane_pick(double target, QWs w) {
+__global__ void k_q_plane_pick(const QJobs B) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    QState* st = w.st;
+    const double target = B.j[blockIdx.z].target;
+    QState* st = B.j[blockIdx.z].w.st;
     const int32_t k = scale_of(st->maxbits);
     st->k = k;
     if (st->nonfinite || k == QKZERO) {   // nothing to encode
@@ -349,8 +377,10 @@ __global__ void k_q_plane_pick(double target, QWs w) {
 // The error at the start of every block on plane P: S[P + 1] plus the
 // exclusive prefix over blocks of (block error at P - block error at P + 1).
 // Each thread scans a contiguous run of blocks; the runs' sums are scanned in LDS.
-__global__ void __launch_bounds__(256) k_q_run_start(int64_t nb, QWs w) {
+__global__ void __launch_bounds__(256) k_q_run_start(const QJobs B) {
     __shared__ U192 sums[256];
+    const int64_t nb = B.j[blockIdx.z].nb;
+    const QWs w = B.j[blockIdx.z].w;
     const QState* st = w.st;
     if (st->all_bits || st->plane >= QPLANES) return;
     const int P = st->plane;
@@ -383,13 +413,17 @@ constexpr int CROSS_THREADS = 256;
 
 // First position of plane P where the running error reaches T: every thread
 // walks a contiguous piece of its block, the pieces' sums scanned in LDS.
-__global__ void __launch_bounds__(CROSS_THREADS) k_q_cross(int64_t n, int len, QWs w) {
+__global__ void __launch_bounds__(CROSS_THREADS) k_q_cross(const QJobs B, int len) {
     __shared__ U192 sums[CROSS_THREADS];
+    const QJob& J = B.j[blockIdx.z];
+    const int64_t n = J.n;
+    const QWs w = J.w;
+    const int b = blockIdx.x;
+    if (b >= J.nb) return;
     const QState* st = w.st;
     if (st->all_bits || st->plane >= QPLANES) return;
     const int P = st->plane;
     const U192 T = st->T;
-    const int b = blockIdx.x;
     const int64_t lo = (int64_t)b * len;
     const int m = (int)min<int64_t>(len, n - lo);
     const int per = (m + CROSS_THREADS - 1) / CROSS_THREADS;
@@ -424,10 +458,14 @@ __global__ void __launch_bounds__(CROSS_THREADS) k_q_cross(int64_t n, int len, Q
 }
 
 // Per block: coefficients encoded on plane P, and the exact error there.
-__global__ void __launch_bounds__(256) k_q_block_sse(int64_t n, int len, QWs w) {
+__global__ void __launch_bounds__(256) k_q_block_sse(const QJobs B, int len) {
     __shared__ U192 red[256];
+    const QJob& J = B.j[blockIdx.z];
+    const int64_t n = J.n;
+    const QWs w = J.w;
     const QState* st = w.st;
     const int b = blockIdx.x;
+    if (b >= J.nb) return;
     const int64_t lo = (int64_t)b * len;
     const int m = (int)min<int64_t>(len, n - lo);
     const int P = st->plane;
@@ -454,11 +492,15 @@ __global__ void __launch_bounds__(256) k_q_block_sse(int64_t n, int len, QWs w) 
 // WRITE = false counts run bytes / sign bits / trailing bits; WRITE = true
 // ORs them into the stream at the offsets k_q_layout computed.
 template <bool WRITE>
-__global__ void __launch_bounds__(64) k_q_segment(int64_t n, int len, QWs w, uint32_t* __restrict__ out,
-                                                  size_t out_words) {
+__global__ void __launch_bounds__(64) k_q_segment(const QJobs B, int len) {
+    const QJob& J = B.j[blockIdx.z];
+    const int64_t n = J.n;
+    const QWs w = J.w;
+    uint32_t* __restrict__ out = J.out;
     const QState* st = w.st;
-    if (WRITE && (size_t)st->total_words > out_words) return;
     const int b = blockIdx.x;
+    if (b >= J.nb) return;
+    if (WRITE && (size_t)st->total_words > J.out_words) return;
     const int p = QPLANES - 1 - (int)blockIdx.y;
     const int P = st->plane;
     const int lane = threadIdx.x;
@@ -568,9 +610,11 @@ __global__ void __launch_bounds__(64) k_q_segment(int64_t n, int len, QWs w, uin
 // One wavefront per block: segment offsets within the block's three fields,
 // planes 63 .. P in that order (lane l holds plane 63 - l), and the block's
 // field sizes.
-__global__ void __launch_bounds__(64) k_q_seg_offsets(QWs w) {
+__global__ void __launch_bounds__(64) k_q_seg_offsets(const QJobs B) {
+    const QWs w = B.j[blockIdx.z].w;
     const int P = w.st->plane;
     const int b = blockIdx.x;
+    if (b >= B.j[blockIdx.z].nb) return;
     const int lane = threadIdx.x;
     const int p = QPLANES - 1 - lane;
     const uint32_t* c = w.cnt + ((size_t)b * QPLANES + p) * 3;
@@ -606,10 +650,15 @@ __device__ __forceinline__ int64_t block_words(const QBlk& bk) {
 // One workgroup: block word offsets (scan over blocks), the exact error at
 // the breakpoint (sum over blocks), the stream header and block sizes, the
 // caller's info record.
-__global__ void __launch_bounds__(256) k_q_layout(int64_t n, int len, int64_t nb, QWs w, uint32_t* __restrict__ out,
-                                                  size_t out_words, atc_quant_info* info) {
+__global__ void __launch_bounds__(256) k_q_layout(const QJobs B, int len) {
     __shared__ int64_t wsum[256];
     __shared__ U192 red[256];
+    const QJob& J = B.j[blockIdx.z];
+    const int64_t n = J.n, nb = J.nb;
+    const QWs w = J.w;
+    uint32_t* __restrict__ out = J.out;
+    const size_t out_words = J.out_words;
+    atc_quant_info* info = J.info;
     const QState* st = w.st;
     const int P = st->plane;
     const int64_t per = (nb + 255) / 256;
@@ -680,32 +729,51 @@ __global__ void __launch_bounds__(256) k_q_layout(int64_t n, int len, int64_t nb
 }
 
 // Clears the block area of the stream; the block headers are written here.
-__global__ void k_q_fill(int64_t nb, QWs w, uint32_t* __restrict__ out, size_t out_words) {
-    const int64_t total = w.st->total_words;
-    if ((size_t)total > out_words) return;
-    const int64_t start = QHEADER + 2 * nb;
+__global__ void k_q_fill(const QJobs B) {
+    const QJob& J = B.j[blockIdx.z];
+    uint32_t* __restrict__ out = J.out;
+    const int64_t total = J.w.st->total_words;
+    if ((size_t)total > J.out_words) return;
+    const int64_t start = QHEADER + 2 * J.nb;
     for (int64_t i = start + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x)
         out[i] = 0;
 }
 
-__global__ void k_q_block_headers(int64_t nb, QWs w, uint32_t* __restrict__ out, size_t out_words) {
+__global__ void k_q_block_headers(const QJobs B) {
+    const QJob& J = B.j[blockIdx.z];
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb || (size_t)w.st->total_words > out_words) return;
-    const QBlk bk = w.blk[b];
-    uint32_t* h = out + bk.word_off;
+    if (b >= J.nb || (size_t)J.w.st->total_words > J.out_words) return;
+    const QBlk bk = J.w.blk[b];
+    uint32_t* h = J.out + bk.word_off;
     h[0] = bk.nrb;
     h[1] = bk.nsb;
     h[2] = bk.ntb;
 }
 
 // ------------------------------------------------------------ decoding
+// One stream of a batch decoded by the same launches (grid slice z = job z).
+struct DJob {
+    const uint32_t* in;
+    int64_t n, nb;
+    int64_t* boff;
+    void* out;
+    int32_t* status;
+};
+struct DJobs {
+    DJob j[QMAX_JOBS];
+};
+
 // Block offsets from the recorded sizes (scan over blocks in one workgroup),
 // after checking the header against the caller's n and block length (a
 // mismatch marks every block unreadable).
-__global__ void __launch_bounds__(256) k_dq_offsets(const uint32_t* __restrict__ in, int64_t n, int len, int64_t nb,
-                                                    int64_t* boff, int32_t* status) {
+__global__ void __launch_bounds__(256) k_dq_offsets(const DJobs B, int len) {
     __shared__ int64_t wsum[256];
+    const DJob& J = B.j[blockIdx.z];
+    const uint32_t* __restrict__ in = J.in;
+    const int64_t n = J.n, nb = J.nb;
+    int64_t* boff = J.boff;
+    int32_t* status = J.status;
     const uint64_t hn = (uint64_t)in[4] | ((uint64_t)in[5] << 32);
     const uint64_t hnb = (uint64_t)in[8] | ((uint64_t)in[9] << 32);
     const bool ok = in[0] == QMAGIC && in[3] == (uint32_t)len && hn == (uint64_t)n && hnb == (uint64_t)nb &&
@@ -769,9 +837,7 @@ constexpr int QMAX_RUNS = QMAX_BLOCK + QPLANES;    // a run per one-bit of a lea
 // The magnitudes stay in LDS; the values (Section 4.3) are scaled by 2^-k at
 // the end.
 template <typename T>
-__global__ void __launch_bounds__(64) k_dq_decode(const uint32_t* __restrict__ in, int64_t n, int len,
-                                                  const int64_t* __restrict__ boff, T* __restrict__ out,
-                                                  int32_t* status) {
+__global__ void __launch_bounds__(64) k_dq_decode(const DJobs B, int len) {
     __shared__ uint64_t mag[QMAX_BLOCK];
     __shared__ uint32_t runs_lds[QMAX_RUN_WORDS];   // the block's run bytes
     __shared__ uint32_t signs_lds[QMAX_BLOCK / 32];  // its sign bits (one per coefficient at most)
@@ -781,8 +847,15 @@ __global__ void __launch_bounds__(64) k_dq_decode(const uint32_t* __restrict__ i
     __shared__ uint64_t onew[QMAX_WORDS];            // this plane's one-bits by leading rank
     __shared__ uint32_t onepre[QMAX_WORDS], sigpre[QMAX_WORDS], leadpre[QMAX_WORDS];
     __shared__ uint32_t tplane[QMAX_BLOCK / 32 + 2];  // this plane's trailing bits, from bit tpos & ~31
+    const DJob& J = B.j[blockIdx.z];
+    const uint32_t* __restrict__ in = J.in;
+    const int64_t n = J.n;
+    const int64_t* __restrict__ boff = J.boff;
+    T* __restrict__ out = (T*)J.out;
+    int32_t* status = J.status;
     const int lane = threadIdx.x;
     const int b = blockIdx.x;
+    if (b >= J.nb) return;
     if (boff[b] < 0) {   // header did not match: zeros
         for (int64_t i = (int64_t)b * len + lane; i < min<int64_t>(n, (int64_t)(b + 1) * len); i += 64) out[i] = (T)0;
         return;
@@ -975,51 +1048,84 @@ size_t quant_max_words(int64_t n, int len) {
     return (size_t)QHEADER + 2 * (size_t)nb + (size_t)nb * block_max_words(len);
 }
 
-hipError_t launch_quantize(const void* core, int f64, int64_t n, double target, int len, uint32_t* out,
-                           size_t out_words, atc_quant_info* info, void* ws, hipStream_t st) {
-    const int64_t nb = quant_nblocks(n, len);
-    QWs w;
-    carve_quant(n, nb, (char*)ws, &w);
-    hipLaunchKernelGGL(k_q_init, dim3(1), dim3(64), 0, st, w.st);
-    const unsigned gmax = (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, ceil_div(n, 256)));
-    if (f64) hipLaunchKernelGGL(k_q_max<double>, dim3(gmax), dim3(256), 0, st, (const double*)core, n, w.st);
-    else hipLaunchKernelGGL(k_q_max<float>, dim3(gmax), dim3(256), 0, st, (const float*)core, n, w.st);
-    if (f64)
-        hipLaunchKernelGGL(k_q_planes<double>, dim3((unsigned)nb), dim3(PLANES_THREADS), 0, st, (const double*)core, n,
-                           len, w);
-    else
-        hipLaunchKernelGGL(k_q_planes<float>, dim3((unsigned)nb), dim3(PLANES_THREADS), 0, st, (const float*)core, n,
-                           len, w);
-    hipLaunchKernelGGL(k_q_plane_sums, dim3(65), dim3(256), 0, st, nb, w);
-    hipLaunchKernelGGL(k_q_plane_pick, dim3(1), dim3(64), 0, st, target, w);
-    hipLaunchKernelGGL(k_q_run_start, dim3(1), dim3(256), 0, st, nb, w);
-    hipLaunchKernelGGL(k_q_cross, dim3((unsigned)nb), dim3(CROSS_THREADS), 0, st, n, len, w);
-    hipLaunchKernelGGL(k_q_block_sse, dim3((unsigned)nb), dim3(256), 0, st, n, len, w);
-    hipLaunchKernelGGL(k_q_segment<false>, dim3((unsigned)nb, QPLANES), dim3(64), 0, st, n, len, w, out, out_words);
-    hipLaunchKernelGGL(k_q_seg_offsets, dim3((unsigned)nb), dim3(64), 0, st, w);
-    hipLaunchKernelGGL(k_q_layout, dim3(1), dim3(256), 0, st, n, len, nb, w, out, out_words, info);
-    const unsigned gfill = (unsigned)std::min<size_t>(4096, std::max<size_t>(1, (out_words + 255) / 256));
-    hipLaunchKernelGGL(k_q_fill, dim3(gfill), dim3(256), 0, st, nb, w, out, out_words);
-    hipLaunchKernelGGL(k_q_block_headers, dim3((unsigned)ceil_div(nb, 256)), dim3(256), 0, st, nb, w, out, out_words);
-    hipLaunchKernelGGL(k_q_segment<true>, dim3((unsigned)nb, QPLANES), dim3(64), 0, st, n, len, w, out, out_words);
+// The kernels over jobs 0 .. count - 1 (one dtype, one block length); the
+// x extent of every grid is the largest job's, the surplus workgroups of the
+// smaller jobs return at once.
+hipError_t launch_quantize_jobs(const QJobs& B, int count, int f64, int len, hipStream_t st) {
+    int64_t maxn = 1, maxnb = 1;
+    size_t maxout = 1;
+    for (int z = 0; z < count; ++z) {
+        maxn = std::max(maxn, B.j[z].n);
+        maxnb = std::max(maxnb, B.j[z].nb);
+        maxout = std::max(maxout, B.j[z].out_words);
+    }
+    const unsigned Z = (unsigned)count, nb = (unsigned)maxnb;
+    hipLaunchKernelGGL(k_q_init, dim3(1, 1, Z), dim3(64), 0, st, B);
+    const unsigned gmax = (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, ceil_div(maxn, 256)));
+    if (f64) hipLaunchKernelGGL(k_q_max<double>, dim3(gmax, 1, Z), dim3(256), 0, st, B);
+    else hipLaunchKernelGGL(k_q_max<float>, dim3(gmax, 1, Z), dim3(256), 0, st, B);
+    if (f64) hipLaunchKernelGGL(k_q_planes<double>, dim3(nb, 1, Z), dim3(PLANES_THREADS), 0, st, B, len);
+    else hipLaunchKernelGGL(k_q_planes<float>, dim3(nb, 1, Z), dim3(PLANES_THREADS), 0, st, B, len);
+    hipLaunchKernelGGL(k_q_plane_sums, dim3(65, 1, Z), dim3(256), 0, st, B);
+    hipLaunchKernelGGL(k_q_plane_pick, dim3(1, 1, Z), dim3(64), 0, st, B);
+    hipLaunchKernelGGL(k_q_run_start, dim3(1, 1, Z), dim3(256), 0, st, B);
+    hipLaunchKernelGGL(k_q_cross, dim3(nb, 1, Z), dim3(CROSS_THREADS), 0, st, B, len);
+    hipLaunchKernelGGL(k_q_block_sse, dim3(nb, 1, Z), dim3(256), 0, st, B, len);
+    hipLaunchKernelGGL(k_q_segment<false>, dim3(nb, QPLANES, Z), dim3(64), 0, st, B, len);
+    hipLaunchKernelGGL(k_q_seg_offsets, dim3(nb, 1, Z), dim3(64), 0, st, B);
+    hipLaunchKernelGGL(k_q_layout, dim3(1, 1, Z), dim3(256), 0, st, B, len);
+    const unsigned gfill = (unsigned)std::min<size_t>(4096, std::max<size_t>(1, (maxout + 255) / 256));
+    hipLaunchKernelGGL(k_q_fill, dim3(gfill, 1, Z), dim3(256), 0, st, B);
+    hipLaunchKernelGGL(k_q_block_headers, dim3((unsigned)ceil_div(maxnb, 256), 1, Z), dim3(256), 0, st, B);
+    hipLaunchKernelGGL(k_q_segment<true>, dim3(nb, QPLANES, Z), dim3(64), 0, st, B, len);
     return hipGetLastError();
 }
 
 size_t dequant_workspace_bytes(int64_t n, int len) { return align256((size_t)quant_nblocks(n, len) * 8); }
 
-hipError_t launch_dequantize(const uint32_t* in, int64_t n, int len, int f64, void* out, int32_t* status, void* ws,
-                             hipStream_t st) {
-    const int64_t nb = quant_nblocks(n, len);
-    int64_t* boff = (int64_t*)ws;
-    hipLaunchKernelGGL(k_dq_offsets, dim3(1), dim3(256), 0, st, in, n, len, nb, boff, status);
-    if (f64) hipLaunchKernelGGL(k_dq_decode<double>, dim3((unsigned)nb), dim3(64), 0, st, in, n, len, boff,
-                                (double*)out, status);
-    else hipLaunchKernelGGL(k_dq_decode<float>, dim3((unsigned)nb), dim3(64), 0, st, in, n, len, boff, (float*)out,
-                            status);
+hipError_t launch_dequantize_jobs(const DJobs& B, int count, int f64, int len, hipStream_t st) {
+    int64_t maxnb = 1;
+    for (int z = 0; z < count; ++z) maxnb = std::max(maxnb, B.j[z].nb);
+    const unsigned Z = (unsigned)count;
+    hipLaunchKernelGGL(k_dq_offsets, dim3(1, 1, Z), dim3(256), 0, st, B, len);
+    if (f64) hipLaunchKernelGGL(k_dq_decode<double>, dim3((unsigned)maxnb, 1, Z), dim3(64), 0, st, B, len);
+    else hipLaunchKernelGGL(k_dq_decode<float>, dim3((unsigned)maxnb, 1, Z), dim3(64), 0, st, B, len);
     return hipGetLastError();
 }
 
+QJob quant_job(const QuantTask& t, int len) {
+    QJob j{};
+    j.x = t.x;
+    j.n = t.n;
+    j.nb = quant_nblocks(t.n, len);
+    j.target = t.target;
+    j.out = t.enc;
+    j.out_words = t.enc_words;
+    j.info = t.info;
+    carve_quant(t.n, j.nb, (char*)t.ws, &j.w);
+    return j;
+}
+
+DJob dequant_job(const DequantTask& t, int len) {
+    return DJob{t.enc, t.n, quant_nblocks(t.n, len), (int64_t*)t.ws, t.out, t.status};
+}
+
 }  // namespace
+
+hipError_t quantize_batch(const QuantTask* tasks, int count, int f64, int len, hipStream_t st) {
+    if (count < 1 || count > QMAX_JOBS) return hipErrorInvalidValue;
+    QJobs B{};
+    for (int z = 0; z < count; ++z) B.j[z] = quant_job(tasks[z], len);
+    return launch_quantize_jobs(B, count, f64, len, st);
+}
+
+hipError_t dequantize_batch(const DequantTask* tasks, int count, int f64, int len, hipStream_t st) {
+    if (count < 1 || count > QMAX_JOBS) return hipErrorInvalidValue;
+    DJobs B{};
+    for (int z = 0; z < count; ++z) B.j[z] = dequant_job(tasks[z], len);
+    return launch_dequantize_jobs(B, count, f64, len, st);
+}
+
 }  // namespace atc
 
 // ------------------------------------------------------------ C ABI
@@ -1062,8 +1168,8 @@ atc_status atc_quantize_core(const void* core, int32_t dtype, int64_t n, double 
         return qfail(ATC_ERR_WORKSPACE_TOO_SMALL, "enc holds fewer words than atc_quantize_max_words");
     if (workspace_bytes < quant_workspace_bytes(n, block_len))
         return qfail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than atc_quantize_workspace_size");
-    const hipError_t e = launch_quantize(core, dtype == ATC_F64, n, target_sse, block_len, enc, enc_words, info,
-                                         workspace, (hipStream_t)stream);
+    const QuantTask t{core, n, target_sse, enc, enc_words, info, workspace};
+    const hipError_t e = quantize_batch(&t, 1, dtype == ATC_F64, block_len, (hipStream_t)stream);
     if (e != hipSuccess) return qfail(ATC_ERR_DEVICE, hipGetErrorString(e));
     return ATC_OK;
 }
@@ -1081,8 +1187,8 @@ atc_status atc_dequantize_core(const uint32_t* enc, int64_t n, int32_t block_len
     if (dtype != ATC_F32 && dtype != ATC_F64) return qfail(ATC_ERR_INVALID_ARGUMENT, "unknown dtype");
     if (workspace_bytes < dequant_workspace_bytes(n, block_len))
         return qfail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace smaller than atc_dequantize_workspace_size");
-    const hipError_t e = launch_dequantize(enc, n, block_len, dtype == ATC_F64, core_out, status, workspace,
-                                           (hipStream_t)stream);
+    const DequantTask t{enc, n, core_out, status, workspace};
+    const hipError_t e = dequantize_batch(&t, 1, dtype == ATC_F64, block_len, (hipStream_t)stream);
     if (e != hipSuccess) return qfail(ATC_ERR_DEVICE, hipGetErrorString(e));
     return ATC_OK;
 }

@@ -7,6 +7,7 @@ import re
 import subprocess
 
 import pytest
+import torch
 
 import paper_2107_01384_amd as atc
 
@@ -32,15 +33,15 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header(tmp_path):
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include "%s"\nint main(){printf("%%zu %%zu %%zu %%zu %%zu",'
+    src.write_text('#include <stdio.h>\n#include "%s"\nint main(){printf("%%zu %%zu %%zu %%zu %%zu %%zu",'
                    'sizeof(atc_sthosvd_opts),sizeof(atc_result),sizeof(atc_block_result),sizeof(atc_shape),'
-                   'sizeof(atc_quant_info));}\n' % HEADER)
+                   'sizeof(atc_quant_info),sizeof(atc_hybrid_out));}\n' % HEADER)
     exe = tmp_path / "sz"
     subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     assert [int(v) for v in out] == [ctypes.sizeof(atc.Opts), ctypes.sizeof(atc.Result),
                                      ctypes.sizeof(atc.BlockResult), ctypes.sizeof(atc.Shape),
-                                     ctypes.sizeof(atc.QuantInfo)]
+                                     ctypes.sizeof(atc.QuantInfo), ctypes.sizeof(atc.HybridOut)]
 
 
 def _shape(dims, dtype=0):
@@ -120,3 +121,25 @@ def test_quant_argument_validation_without_device():
     assert dsz > 0
     assert lib.atc_dequantize_core(one, 100, 64, 0, one, null, one, dsz - 1, null) == -3
     assert lib.atc_dequantize_core(one, 100, 0, 0, one, null, one, dsz, null) == -2
+
+
+def test_hybrid_argument_validation_without_device():
+    """atc_hybrid_workspace_size / atc_hybrid_quantize reject bad shapes,
+    block lengths and NULL buffers before touching a device."""
+    lib = atc.load()
+    cs = atc._shape([5, 4, 3], torch.float32)
+    n = (ctypes.c_int64 * 3)(20, 16, 12)
+    assert lib.atc_hybrid_workspace_size(ctypes.byref(cs), n, 64) > 0
+    assert lib.atc_hybrid_workspace_size(ctypes.byref(cs), n, 0) == 0
+    assert lib.atc_hybrid_workspace_size(ctypes.byref(cs), n, 5000) == 0
+    bad = (ctypes.c_int64 * 3)(20, 3, 12)  # r_1 = 4 > n_1 = 3
+    assert lib.atc_hybrid_workspace_size(ctypes.byref(cs), bad, 64) == 0
+    big = atc._shape([300, 4, 3], torch.float32)  # r_0 > 256
+    assert lib.atc_hybrid_workspace_size(ctypes.byref(big), (ctypes.c_int64 * 3)(400, 16, 12), 64) == 0
+    out = atc.HybridOut()
+    one = ctypes.c_void_p(1)
+    facs = (ctypes.c_void_p * 3)(1, 1, 1)
+    # NULL outputs are refused before any launch
+    st = lib.atc_hybrid_quantize(one, ctypes.byref(cs), facs, n, 1.0, 1.0, 64, ctypes.byref(out), one, 1 << 30,
+                                 ctypes.c_void_p(None))
+    assert st == -1

@@ -33,18 +33,16 @@ def _sq_err(x, core, facs):
     return float(((x.double() - xh.double()) ** 2).sum())
 
 
-@pytest.mark.parametrize("n,eps,precision", [(256, 1e-2, "f64acc"), (512, 1e-3, "f64acc"), (512, 1e-3, "bf16x3")])
-def test_hybrid_pipeline_and_error_model(n, eps, precision):
-    x = torch.from_numpy(synth.field((n,) * 3, 0)).cuda()
-    c = atc.compress(x, eps, rtmss=0.5, precision=precision)
-    torch.cuda.synchronize()
+def _check_stages(c):
+    """Every stage of atc.compress against the oracle on the same inputs."""
     t = c.tucker
     S = c.target_sse
     L = c.core_stream.block_len
+    d = len(t.ranks)
     # the core's stream: the oracle encodes the same (sign-flipped) core
     flipped = t.core.double().cpu().numpy()
-    for k in range(3):
-        sh = [1, 1, 1]
+    for k in range(d):
+        sh = [1] * d
         sh[k] = -1
         flipped = flipped * c.signs[k].cpu().numpy().astype(np.float64).reshape(sh)
     flipped = flipped.astype(np.float32).astype(np.float64)
@@ -54,11 +52,11 @@ def test_hybrid_pipeline_and_error_model(n, eps, precision):
     assert np.array_equal(cq.ravel(), quant.dequantize(w_o).astype(np.float32).astype(np.float64))
     # slice norms of the quantized core
     s2_o = hh.slice_norms2(cq)
-    for k in range(3):
+    for k in range(d):
         assert np.abs(c.sigma2[k].cpu().numpy() - s2_o[k]).max() <= 1e-12 * s2_o[k].max()
     # factors: weighted coefficients against the oracle's encoding of the same
     # factor, their streams bit for bit, the rebuilt factors
-    for k in range(3):
+    for k in range(d):
         Up = c.factors_signed[k].double().cpu().numpy()
         s2 = c.sigma2[k].cpu().numpy()
         c_o, sg_o, _ = hh.encode(t.factors[k].double().cpu().numpy(), s2)
@@ -67,7 +65,7 @@ def test_hybrid_pipeline_and_error_model(n, eps, precision):
         assert np.abs(cg - c_o).max(initial=0.0) <= 1e-12 * max(1.0, np.abs(c_o).max(initial=0.0))
         fs = c.factor_streams[k]
         if fs is not None:
-            fw_o = quant.encode(cg, 0.01 * S / 3, L)
+            fw_o = quant.encode(cg, 0.01 * S / d, L)
             assert np.array_equal(fs.words.cpu().numpy().view(np.uint32), fw_o)
             cdq = quant.dequantize(fw_o)
         else:
@@ -76,6 +74,16 @@ def test_hybrid_pipeline_and_error_model(n, eps, precision):
         assert np.abs(c.factors_q[k].double().cpu().numpy() - uq_o).max() <= 1e-6  # float32 factor output
         assert abs(c.terms["factors"][k] - hh.factor_error_term(Up, c.factors_q[k].double().cpu().numpy(), s2)) \
             <= 1e-9 * max(c.terms["factors"][k], 1e-300)
+
+
+@pytest.mark.parametrize("n,eps,precision", [(256, 1e-2, "f64acc"), (512, 1e-3, "f64acc"), (512, 1e-3, "bf16x3")])
+def test_hybrid_pipeline_and_error_model(n, eps, precision):
+    x = torch.from_numpy(synth.field((n,) * 3, 0)).cuda()
+    c = atc.compress(x, eps, rtmss=0.5, precision=precision)
+    torch.cuda.synchronize()
+    t = c.tucker
+    S = c.target_sse
+    _check_stages(c)
     # the model
     actual = _sq_err(x, c.core_q, c.factors_q)
     e_trunc = _sq_err(x, t.core, t.factors)
@@ -93,3 +101,22 @@ def test_hybrid_pipeline_and_error_model(n, eps, precision):
         assert abs(dev_p) <= 1.5e-3
     # the factors' share is small: the whole error stays near the target
     assert actual <= 1.02 ** 2 * S
+
+
+@pytest.mark.parametrize("shape,eps", [((200, 120, 48), 1e-3), ((48, 40, 32, 3), 1e-4)])
+def test_hybrid_modes_of_different_sizes(shape, eps):
+    """The factors share every launch of the quantization half; modes of
+    different sizes and ranks (a 4-way input whose last mode keeps all three
+    slices) put factors of different n, r and stream lengths in one launch."""
+    if len(shape) == 3:
+        xn = synth.field(shape, 4)
+    else:
+        xn = synth.field4(shape[:3], shape[3], seed0=7)
+    x = torch.from_numpy(xn).cuda()
+    c = atc.compress(x, eps, rtmss=0.5, precision="f64acc")
+    torch.cuda.synchronize()
+    log("hybrid %s eps %g: ranks %s, factor stream words %s" % (
+        shape, eps, c.tucker.ranks, [0 if f is None else f.words.numel() for f in c.factor_streams]))
+    _check_stages(c)
+    actual = _sq_err(x, c.core_q, c.factors_q)
+    assert actual <= 1.02 ** 2 * c.target_sse
