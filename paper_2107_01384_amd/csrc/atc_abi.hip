@@ -174,6 +174,8 @@ struct SthosvdWs {
     float* Mt32;
     __bf16* Mth;
     __bf16* Mtl;
+    QtOut qt;        // Q^T of the m = 32 basis (32 x n), mode-product operand
+    SelectArgs wt;   // only its Wt* fields: the Ritz rotation operand (32 x 32)
     DevBook* book;
 };
 
@@ -206,6 +208,30 @@ size_t carve_sthosvd(const atc_shape* s, char* base, SthosvdWs* w) {
     t.Mt32 = (float*)c.take(s->dtype == ATC_F32 ? n2 * 4 : 0);
     t.Mth = (__bf16*)c.take(s->dtype == ATC_F32 ? n2 * 2 : 0);
     t.Mtl = (__bf16*)c.take(s->dtype == ATC_F32 ? n2 * 2 : 0);
+    // the split m = 32 path (modes of 65 .. 512 rows): Q^T and the rotation
+    const size_t qn = nmax > 64 ? (size_t)S32_RANKS * std::min(nmax, 512) : 0;
+    const size_t wn = nmax > 64 ? (size_t)S32_RANKS * S32_RANKS : 0;
+    const bool d64 = s->dtype == ATC_F64;
+    t.qt.t64 = (double*)c.take(d64 ? qn * 8 : 0);
+    t.qt.t32 = (float*)c.take(d64 ? 0 : qn * 4);
+    t.qt.th = (__bf16*)c.take(d64 ? 0 : qn * 2);
+    t.qt.tl = (__bf16*)c.take(d64 ? 0 : qn * 2);
+    t.wt.Wt64 = (double*)c.take(d64 ? wn * 8 : 0);
+    t.wt.Wt32 = (float*)c.take(d64 ? 0 : wn * 4);
+    t.wt.Wth = (__bf16*)c.take(d64 ? 0 : wn * 2);
+    t.wt.Wtl = (__bf16*)c.take(d64 ? 0 : wn * 2);
+    // a region of size 0 still has an address: the unused dtype's pointers
+    // are cleared, since the kernels write every non-null one
+    if (qn == 0 || !d64) {
+        t.qt.t64 = nullptr;
+        t.wt.Wt64 = nullptr;
+    }
+    if (qn == 0 || d64) {
+        t.qt.t32 = nullptr;
+        t.qt.th = t.qt.tl = nullptr;
+        t.wt.Wt32 = nullptr;
+        t.wt.Wth = t.wt.Wtl = nullptr;
+    }
     t.book = (DevBook*)c.take(sizeof(DevBook));
     if (w) *w = t;
     return c.off;
@@ -285,6 +311,59 @@ struct PinnedFlags {
     }
 };
 thread_local PinnedFlags g_flags;
+
+// A second stream per device and two events, for the split m = 32 solver:
+// the mode product by the basis runs there beside the Rayleigh-Ritz step on
+// the caller's stream.  Made on first use (default priority), kept until
+// atc_finalize.  (Giving the Rayleigh-Ritz step a stream of its own, on CUs
+// that the product's stream masks off, was slower: it did not shorten that
+// step, and each extra queue with a pending event wait delayed the next
+// dispatches by tens of microseconds.)
+struct SideQueue {
+    static constexpr int MAXDEV = 16;
+    struct Dev {
+        hipStream_t ttm = nullptr;
+        hipEvent_t basis = nullptr, proj = nullptr;
+        bool tried = false, ok = false;
+    };
+    Dev dv[MAXDEV];
+    Dev* get() {
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAXDEV) return nullptr;
+        Dev& q = dv[dev];
+        if (!q.tried) {
+            q.tried = true;
+            q.ok = hipStreamCreateWithPriority(&q.ttm, hipStreamNonBlocking, 0) == hipSuccess &&
+                   hipEventCreateWithFlags(&q.basis, hipEventDisableTiming) == hipSuccess &&
+                   hipEventCreateWithFlags(&q.proj, hipEventDisableTiming) == hipSuccess;
+        }
+        return q.ok ? &q : nullptr;
+    }
+    void release() {
+        for (int i = 0; i < MAXDEV; ++i) {
+            Dev& q = dv[i];
+            if (q.basis) (void)hipEventDestroy(q.basis);
+            if (q.proj) (void)hipEventDestroy(q.proj);
+            if (q.ttm) (void)hipStreamDestroy(q.ttm);
+            q = Dev{};
+        }
+    }
+};
+thread_local SideQueue g_side;
+
+// Smallest tensor (bytes) whose mode product takes the split m = 32 solver;
+// ATC_SPLIT_MIN_BYTES in the environment (read at every call) overrides it.
+size_t split_min_bytes() {
+    const char* e = getenv("ATC_SPLIT_MIN_BYTES");
+    return e ? (size_t)strtoull(e, nullptr, 10) : ((size_t)64 << 20);
+}
+
+// ATC_NO_OVERLAP=1 in the environment (read at every call) keeps the m = 32
+// solver in one launch (no side stream).
+bool overlap_enabled() {
+    const char* e = getenv("ATC_NO_OVERLAP");
+    return !(e && e[0] == '1');
+}
 
 // Spins until the selection kernel reports sequence number `expect`; gives up
 // with an error when the stream has drained without the report.
@@ -450,10 +529,57 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         const void* M = f64 ? (const void*)w.Mt64 : (const void*)w.Mt32;
         void* const dst = (i == d - 1) ? core : (src == w.buf[0] ? w.buf[1] : w.buf[0]);
         bool queued = false;  // mode product queued with the device-side rank
+        // split form: the rotation, queued once the host knows the rank fits;
+        // the side stream's product must end before anything else writes dst
+        SideQueue::Dev* split_q = nullptr;
+        void* split_yq = nullptr;
+        SelectArgs split_sr{};
         for (;; ++attempt) {
             bool selected = false;
             sa.seq = ++g_flags.seq;
-            if (attempt == 0 && subspace32_available(n)) {
+            // the split form: basis, then the mode product by Q^T on the side
+            // stream beside the Rayleigh-Ritz step, then the rotation by W_r^T
+            // into dst (the projection by Q^T sits after dst's rows in the same
+            // buffer; a later mode of a wider rank than 24 never takes this path)
+            const size_t esz_ = f64 ? 8 : 4;
+            const size_t qoff = ((size_t)L * (S32_RANKS - SUBSPACE_GUARD) * R * esz_ + 255) & ~(size_t)255;
+            // worth it when the mode product by the basis is long enough to hide
+            // the Rayleigh-Ritz step behind it (splitting costs ~20 us: a second
+            // launch, and the Rayleigh-Ritz products formed by one workgroup)
+            const bool split_pays = (size_t)L * n * R * esz_ >= split_min_bytes();
+            const bool split_fits = i + 1 < d && split_pays && (w.qt.t64 || w.qt.t32) && overlap_enabled() &&
+                                    dst != core &&
+                                    qoff + (size_t)L * S32_RANKS * R * esz_ <= (size_t)prod(shape->dims, 0, d) * esz_;
+            SideQueue::Dev* sq = nullptr;
+            if (attempt == 0 && split_fits && subspace32_split_available(n) && (sq = g_side.get()) != nullptr) {
+                sa.ldv = 32;
+                sa.ncand = 32;
+                sa.subspace = 1;
+                paths[k] = 2;
+                HIP_TRY(run_subspace32_basis(w.G, n, SUBSPACE_ITERS, w.sub, sa, w.qt, st));
+                void* yq = (char*)dst + qoff;
+                const TtmPlan tq = ttm_plan(prec, L, n, R, S32_RANKS);
+                HIP_TRY(hipEventRecord(sq->basis, st));
+                HIP_TRY(hipStreamWaitEvent(sq->ttm, sq->basis, 0));
+                HIP_TRY(launch_ttm(prec, tq, src, f64 ? (const void*)w.qt.t64 : (const void*)w.qt.t32, w.qt.th,
+                                   w.qt.tl, yq, sq->ttm, split_rows_dev(w.sub, n)));
+                HIP_TRY(hipEventRecord(sq->proj, sq->ttm));
+                SelectArgs sr = sa;
+                sr.Wt64 = w.wt.Wt64;
+                sr.Wt32 = w.wt.Wt32;
+                sr.Wth = prec == PREC_BF16X3 ? w.wt.Wth : nullptr;
+                sr.Wtl = prec == PREC_BF16X3 ? w.wt.Wtl : nullptr;
+                // U^T is not a mode-product operand on this path
+                sr.Mt64 = nullptr;
+                sr.Mt32 = nullptr;
+                sr.Mth = sr.Mtl = nullptr;
+                HIP_TRY(run_rr32_select(n, SUBSPACE_ITERS, max_sweeps, w.sub, sr, st));
+                selected = true;
+                HIP_TRY(mark(i, 3));
+                split_q = sq;
+                split_yq = yq;
+                split_sr = sr;
+            } else if (attempt == 0 && subspace32_available(n)) {
                 sa.ldv = 32;
                 sa.ncand = 32;
                 sa.subspace = 1;
@@ -519,6 +645,11 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
                                                        : "mode eigensolver: a grid barrier wait gave up");
             if (!hf.need_dense) break;
             queued = false;
+            if (split_q && split_yq) {
+                // handed on: the product by the basis is dropped, but it still
+                // writes dst's tail until it ends
+                split_yq = nullptr;
+            }
             if (attempt >= 2) return fail(ATC_ERR_INTERNAL, "mode %d: dense eigensolver asked for more", k);
             if (attempt == 1 && opts->eig_path == 2)
                 return fail(ATC_ERR_UNSUPPORTED, "mode %d: rank needs more than %d Ritz pairs", k,
@@ -535,6 +666,19 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         const int r = hf.rank;
         if (r < 1 || r > n) return fail(ATC_ERR_INTERNAL, "mode %d: rank %d outside [1, %d]", k, r, n);
         cur[k] = r;
+        if (split_q) {
+            // the side stream's product by the basis ends before dst is written
+            // again; when the split selection stood, the rotation by W_r^T
+            // takes it into dst (rows from the device-side rank, as above)
+            HIP_TRY(hipStreamWaitEvent(st, split_q->proj, 0));
+            if (split_yq) {
+                const TtmPlan tw = ttm_plan(prec, L, S32_RANKS, R, S32_RANKS - SUBSPACE_GUARD);
+                HIP_TRY(launch_ttm(prec, tw, split_yq, f64 ? (const void*)w.wt.Wt64 : (const void*)w.wt.Wt32,
+                                   split_sr.Wth, split_sr.Wtl, dst, st, &w.book->rank[k]));
+                HIP_TRY(mark(i, 4));
+                queued = true;
+            }
+        }
         if (queued) {
             if (r >= n) return fail(ATC_ERR_INTERNAL, "mode %d: rank %d of the subspace path", k, r);
             src = dst;
@@ -1081,6 +1225,7 @@ const char* atc_last_error(void) { return g_last_error.c_str(); }
 
 void atc_finalize(void) {
     g_flags.release();
+    g_side.release();
     g_phase.release();
     g_timer.release();
 }

@@ -1479,7 +1479,8 @@ __device__ __forceinline__ void rr_factor_out(const SelectArgs& a, const double*
 // orthonormalisation failed the mode is handed to the next eigensolver.
 __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q, const double* __restrict__ Z,
                                                     int n, int max_sweeps,
-                                                    const int32_t* __restrict__ orth_ok, SelectArgs a) {
+                                                    const int32_t* __restrict__ orth_ok, int quiet,
+                                                    const double* __restrict__ bsym, SelectArgs a) {
     extern __shared__ double lds[];
     double* part_lds = lds;
     double(*Bm)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + RW * S32 * S32);
@@ -1496,25 +1497,38 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
     const int tid = threadIdx.x;
     DevBook* bk = a.book;
     if (!*orth_ok) {
-        if (tid == 0) {
+        // quiet: the basis launch has reported the hand-over already
+        if (tid == 0 && !quiet) {
             bk->need_dense = 1;
             publish_selection(a, 0);
         }
         return;
     }
-    const double tr = gram_trace(a, red);
-    cross32<RW, 1, 1>(Q, Z, n, part_lds, Bm);
-    for (int e = tid; e < S32 * S32; e += RT) {
-        const int i = e >> 5, j = e & 31;
-        Wm[i][j] = 0.5 * (Bm[i][j] + Bm[j][i]);
+    double tr;
+    if (bsym) {
+        // B (symmetrised) and trace(G) from the basis launch
+        for (int e = tid; e < S32 * S32; e += RT) {
+            const int i = e >> 5, j = e & 31;
+            Bm[i][j] = bsym[e];
+            Wm[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+        tr = bsym[S32 * S32];
+        __syncthreads();
+    } else {
+        tr = gram_trace(a, red);
+        cross32<RW, 1, 1>(Q, Z, n, part_lds, Bm);
+        for (int e = tid; e < S32 * S32; e += RT) {
+            const int i = e >> 5, j = e & 31;
+            Wm[i][j] = 0.5 * (Bm[i][j] + Bm[j][i]);
+        }
+        __syncthreads();
+        for (int e = tid; e < S32 * S32; e += RT) {
+            const int i = e >> 5, j = e & 31;
+            Bm[i][j] = Wm[i][j];
+            Wm[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = tid; e < S32 * S32; e += RT) {
-        const int i = e >> 5, j = e & 31;
-        Bm[i][j] = Wm[i][j];
-        Wm[i][j] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
     {
         int sw;
         bool cv;
@@ -1551,10 +1565,36 @@ __global__ __launch_bounds__(RT) void k_rr32_select(const double* __restrict__ Q
     al.lam = lam_s;  // the Ritz values from LDS
     if (tid == 0) choose_rank(al, tr, r_s, dense_s);
     __syncthreads();
-    if (dense_s) return;
+    if (dense_s) {
+        // split form: the mode product by the basis, running beside this
+        // launch, is of no use now; its workgroups that start from here on
+        // read 0 rows and return
+        if (tid == 0 && quiet)
+            __hip_atomic_store(const_cast<int32_t*>(orth_ok) + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
     // V = Q W[:, col_of], sign rule and factor output (the partials' space is free again)
     static_assert(RW * S32 * S32 * sizeof(double) >= RW * S32 * sizeof(SignCand), "sign candidates");
     rr_factor_out(al, Q, n, Wm, col_of, r_s, reinterpret_cast<SignCand*>(part_lds), sign_s);
+    // the rotation operand (W_r diag(signs))^T, r x 32 (sign_s is final after
+    // the barriers inside rr_factor_out)
+    if (a.Wt64 || a.Wt32) {
+        const int r = r_s;
+        for (int e = tid; e < r * S32; e += RT) {
+            const int j = e >> 5, c = e & 31;
+            const double u = sign_s[j] * Wm[c][col_of[j]];
+            if (a.Wt64) a.Wt64[e] = u;
+            if (a.Wt32) {
+                const float f = (float)u;
+                a.Wt32[e] = f;
+                if (a.Wth) {
+                    const __bf16 hh = (__bf16)f;
+                    a.Wth[e] = hh;
+                    a.Wtl[e] = (__bf16)(f - (float)hh);
+                }
+            }
+        }
+    }
 }
 
 // ------------------------------- subspace path, m = 32, one cooperative launch
@@ -1580,6 +1620,8 @@ struct Sub32Grid {
     double* cand;     // GRID_MAXB x 32 x 3: sign candidates (|v|, v, row)
     unsigned* sync;   // DevBook::grid: [0] arrivals, [1] rank, [2] need_dense, [3] a wait gave up, [4] exits
     unsigned spin_limit;  // polls before a wait gives up
+    int32_t* basis_ok;    // basis-only launch: 1 when Q was formed (null otherwise)
+    double* bsym;         // basis-only launch: B = Q^T G Q symmetrised (32 x 32), then trace(G)
 };
 
 // Grid barrier: every wavefront drains its stores, thread 0 makes the
@@ -1801,7 +1843,7 @@ __device__ __forceinline__ bool orth_grid(GridCtx& x, double* Y, bool full, doub
 }
 
 __device__ __forceinline__ void sub32_grid_body(const double* __restrict__ G, int n, int steps, int max_sweeps,
-                                                const Sub32Grid& g, const SelectArgs& a) {
+                                                const Sub32Grid& g, const SelectArgs& a, const QtOut& qt) {
     extern __shared__ double lds[];
     double* part_lds = lds;
     double(*Bm)[S32 + 1] = reinterpret_cast<double(*)[S32 + 1]>(lds + RW * S32 * S32);
@@ -1848,10 +1890,49 @@ __device__ __forceinline__ void sub32_grid_body(const double* __restrict__ G, in
     if (!good) {
         // the same outcome in every workgroup: hand the mode to the next eigensolver
         if (x.b == 0 && tid == 0) {
+            if (g.basis_ok) {
+                g.basis_ok[0] = 0;
+                g.basis_ok[1] = 0;
+            }
             bk->need_dense = 1;
             if (__hip_atomic_load(&g.sync[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
                 bk->status = ATC_ERR_INTERNAL;  // not a failed basis: a wait gave up
             publish_selection(a, 0);
+        }
+        return;
+    }
+    if (qt.t64 || qt.t32) {
+        // basis only: Q^T for the mode product by the basis; the Rayleigh-Ritz
+        // step follows in its own launch
+        for (int e = tid; e < x.nr * S32; e += RT) {
+            const int i = e >> 5, j = e & 31;
+            const int row = x.row0 + i;
+            const double q = P2[(int64_t)row * S32 + j];
+            const int64_t t = (int64_t)j * n + row;
+            if (qt.t64) qt.t64[t] = q;
+            if (qt.t32) {
+                const float f = (float)q;
+                qt.t32[t] = f;
+                if (qt.th) {
+                    const __bf16 hh = (__bf16)f;
+                    qt.th[t] = hh;
+                    qt.tl[t] = (__bf16)(f - (float)hh);
+                }
+            }
+        }
+        // B = Q^T Z from the slabs (every workgroup), stored symmetrised with
+        // trace(G) by workgroup 0 for the Rayleigh-Ritz launch
+        cross_grid(x, P2 + (int64_t)x.row0 * S32, P1 + (int64_t)x.row0 * S32, part_lds, Bm);
+        if (x.b == 0) {
+            for (int e = tid; e < S32 * S32; e += RT) {
+                const int i = e >> 5, j = e & 31;
+                g.bsym[e] = 0.5 * (Bm[i][j] + Bm[j][i]);
+            }
+            if (tid == 0) {
+                g.bsym[S32 * S32] = tr;
+                *g.basis_ok = 1;
+                g.basis_ok[1] = S32;  // rows of the product by the basis (0 once handed on)
+            }
         }
         return;
     }
@@ -1994,8 +2075,8 @@ __device__ __forceinline__ void sub32_grid_body(const double* __restrict__ G, in
 // The body above, then the last workgroup to finish clears the barrier words
 // for the next launch (every workgroup has passed its last wait by then).
 __global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G, int n, int steps, int max_sweeps,
-                                                   Sub32Grid g, SelectArgs a) {
-    sub32_grid_body(G, n, steps, max_sweeps, g, a);
+                                                   Sub32Grid g, SelectArgs a, QtOut qt) {
+    sub32_grid_body(G, n, steps, max_sweeps, g, a, qt);
     grid_exit(g.sync);
 }
 
@@ -2297,11 +2378,31 @@ bool sub64_grid_ready() {
 
 bool subspace32_available(int n) { return n >= 2 * S32 && n <= 512 && sub32_ready(); }
 
+bool subspace32_split_available(int n) { return subspace32_available(n) && sub32_grid_ready(); }
+
 // P1, P2 (n x 32 each), 8 doubles of flags, then the cooperative path's
-// partial products and sign candidates.
+// partial products and sign candidates, then B and trace(G) of the split form.
 size_t subspace32_ws_doubles(int n) {
-    return (size_t)2 * n * S32 + 8 + (size_t)2 * GRID_MAXB * S32 * S32 + (size_t)GRID_MAXB * S32 * 3;
+    return (size_t)2 * n * S32 + 8 + (size_t)2 * GRID_MAXB * S32 * S32 + (size_t)GRID_MAXB * S32 * 3 + S32 * S32 + 8;
 }
+
+namespace {
+Sub32Grid sub32_grid_args(double* ws, int n, const SelectArgs& sa) {
+    Sub32Grid g;
+    g.P1 = ws;
+    g.P2 = ws + (size_t)n * S32;
+    g.part = g.P2 + (size_t)n * S32 + 8;
+    g.cand = g.part + (size_t)2 * GRID_MAXB * S32 * S32;
+    g.sync = &sa.book->grid[0];
+    // ATC_GRID_SPIN_LIMIT (tests): a small limit makes the waits give up,
+    // which the mode must report as an error without hanging
+    const char* lim = getenv("ATC_GRID_SPIN_LIMIT");
+    g.spin_limit = lim ? (unsigned)strtoul(lim, nullptr, 10) : GRID_SPIN_LIMIT;
+    g.basis_ok = nullptr;
+    g.bsym = nullptr;
+    return g;
+}
+}  // namespace
 
 hipError_t run_subspace32_select(const double* G, int n, int iters, int max_sweeps, double* ws, const SelectArgs& sa,
                                  hipStream_t st) {
@@ -2313,20 +2414,12 @@ hipError_t run_subspace32_select(const double* G, int n, int iters, int max_swee
     const int steps = iters < 1 ? 1 : iters;
     hipError_t e;
     if (sub32_grid_ready()) {
-        Sub32Grid g;
-        g.P1 = P1;
-        g.P2 = P2;
-        g.part = P2 + (size_t)n * S32 + 8;
-        g.cand = g.part + (size_t)2 * GRID_MAXB * S32 * S32;
-        g.sync = &sa.book->grid[0];
-        // ATC_GRID_SPIN_LIMIT (tests): a small limit makes the waits give up,
-        // which the mode must report as an error without hanging
-        const char* lim = getenv("ATC_GRID_SPIN_LIMIT");
-        g.spin_limit = lim ? (unsigned)strtoul(lim, nullptr, 10) : GRID_SPIN_LIMIT;
+        Sub32Grid g = sub32_grid_args(ws, n, sa);
         const int nb = (int)ceil_div(n, GRID_ROWS);
         int n_ = n, steps_ = steps, sweeps_ = max_sweeps;
         SelectArgs sa_ = sa;
-        void* args[] = {(void*)&G, (void*)&n_, (void*)&steps_, (void*)&sweeps_, (void*)&g, (void*)&sa_};
+        QtOut qt{};
+        void* args[] = {(void*)&G, (void*)&n_, (void*)&steps_, (void*)&sweeps_, (void*)&g, (void*)&sa_, (void*)&qt};
         e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sub32_grid), dim3(nb), dim3(RT), args,
                                        (unsigned)RR_LDS, st);
         if (e == hipSuccess) return hipSuccess;
@@ -2348,7 +2441,41 @@ hipError_t run_subspace32_select(const double* G, int n, int iters, int max_swee
     }
     // P2 holds the basis, P1 = G times it
     hipLaunchKernelGGL(k_rr32_select, dim3(1), dim3(RT), RR_LDS, st, (const double*)P2, (const double*)P1, n,
-                       max_sweeps, (const int32_t*)ok, sa);
+                       max_sweeps, (const int32_t*)ok, 0, (const double*)nullptr, sa);
+    return hipGetLastError();
+}
+
+hipError_t run_subspace32_basis(const double* G, int n, int iters, double* ws, const SelectArgs& sa, const QtOut& qt,
+                                hipStream_t st) {
+    if (!subspace32_available(n) || !sub32_grid_ready()) return hipErrorInvalidValue;
+    if (sa.ncand != S32 || sa.ldv != S32 || !sa.subspace || (!qt.t64 && !qt.t32)) return hipErrorInvalidValue;
+    Sub32Grid g = sub32_grid_args(ws, n, sa);
+    g.basis_ok = reinterpret_cast<int32_t*>(g.P2 + (size_t)n * S32);
+    g.bsym = g.cand + (size_t)GRID_MAXB * S32 * 3;
+    const int nb = (int)ceil_div(n, GRID_ROWS);
+    const double* G_ = G;
+    int n_ = n, steps_ = iters < 1 ? 1 : iters, sweeps_ = 0;
+    SelectArgs sa_ = sa;
+    QtOut qt_ = qt;
+    void* args[] = {(void*)&G_, (void*)&n_, (void*)&steps_, (void*)&sweeps_, (void*)&g, (void*)&sa_, (void*)&qt_};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_sub32_grid), dim3(nb), dim3(RT), args,
+                                      (unsigned)RR_LDS, st);
+}
+
+const int32_t* split_rows_dev(const double* ws, int n) {
+    return reinterpret_cast<const int32_t*>(ws + (size_t)2 * n * S32) + 1;
+}
+
+hipError_t run_rr32_select(int n, int iters, int max_sweeps, double* ws, const SelectArgs& sa, hipStream_t st) {
+    if (!subspace32_available(n)) return hipErrorInvalidValue;
+    // the power steps swap the two n x 32 blocks once each: after an odd
+    // number of steps the basis is in the first block
+    const int steps = iters < 1 ? 1 : iters;
+    const double* Q = ws + ((steps & 1) ? 0 : (size_t)n * S32);
+    const double* Z = ws + ((steps & 1) ? (size_t)n * S32 : 0);  // G Q
+    const int32_t* ok = reinterpret_cast<const int32_t*>(ws + (size_t)2 * n * S32);
+    const double* bsym = ws + (size_t)2 * n * S32 + 8 + (size_t)2 * GRID_MAXB * S32 * S32 + (size_t)GRID_MAXB * S32 * 3;
+    hipLaunchKernelGGL(k_rr32_select, dim3(1), dim3(RT), RR_LDS, st, Q, Z, n, max_sweeps, ok, 1, bsym, sa);
     return hipGetLastError();
 }
 
@@ -2380,6 +2507,8 @@ hipError_t run_subspace64_select(const double* G, int n, int max_sweeps, double*
         g.part = W + 64 * 64 + 8;
         g.cand = nullptr;
         g.sync = &sa.book->grid[0];
+        g.basis_ok = nullptr;
+        g.bsym = nullptr;
         const char* lim = getenv("ATC_GRID_SPIN_LIMIT");
         g.spin_limit = lim ? (unsigned)strtoul(lim, nullptr, 10) : GRID_SPIN_LIMIT;
         const int nb = (int)ceil_div(n, GRID_ROWS);

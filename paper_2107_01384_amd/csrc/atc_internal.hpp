@@ -245,6 +245,13 @@ struct SelectArgs {
     int32_t publish_late; // one-launch m = 32 path: report after the last grid barrier
                           // (the last processed mode: nothing waits on it, and a
                           // barrier wait that gave up is then still reported)
+    // optional (null: not written): (W_r diag(signs))^T, r x 32, the Ritz
+    // rotation that takes the projection onto the basis Q to the projection
+    // onto U = Q W_r diag(signs) (split path of the m = 32 solver)
+    double* Wt64;
+    float* Wt32;
+    __bf16* Wth;
+    __bf16* Wtl;
 };
 hipError_t launch_select_factor(const SelectArgs& a, hipStream_t st);
 
@@ -255,6 +262,30 @@ hipError_t launch_select_factor(const SelectArgs& a, hipStream_t st);
 // written.  ws holds subspace32_ws_doubles(n) doubles.
 bool subspace32_available(int n);
 size_t subspace32_ws_doubles(int n);
+// The m = 32 solver in two launches, so that the mode product by the basis can
+// run beside the Rayleigh-Ritz step: run_subspace32_basis leaves the
+// orthonormal basis Q (n x 32) and G Q in ws and writes Q^T (32 x n) into the
+// mode-product operand buffers of qt (FP64, or FP32 with its bf16 hi / lo
+// split; null pointers are skipped); run_rr32_select then takes the
+// Rayleigh-Ritz step, rank choice and factor output (sa as for
+// run_subspace32_select, with sa.Wt* set for the rotation operand; iters as
+// given to the basis launch).  When the
+// basis fails, the first launch reports the hand-over and the second does
+// nothing.  split_rows_dev(ws, n): a device int, 32 once the basis stands and
+// 0 when the mode is handed on (set by either launch); the product by the
+// basis takes it as its device-side row count, so that its workgroups stop
+// early when the result will not be used.
+struct QtOut {
+    double* t64;
+    float* t32;
+    __bf16* th;
+    __bf16* tl;
+};
+bool subspace32_split_available(int n);  // the basis launch is cooperative
+hipError_t run_subspace32_basis(const double* G, int n, int iters, double* ws, const SelectArgs& sa, const QtOut& qt,
+                                hipStream_t st);
+hipError_t run_rr32_select(int n, int iters, int max_sweeps, double* ws, const SelectArgs& sa, hipStream_t st);
+const int32_t* split_rows_dev(const double* ws, int n);
 hipError_t run_subspace32_select(const double* G, int n, int iters, int max_sweeps, double* ws, const SelectArgs& sa,
                                  hipStream_t st);
 // m = 64 for 64 <= n <= 512 from the m = 32 kernels: the block as two
