@@ -834,18 +834,17 @@ constexpr int QMAX_RUNS = QMAX_BLOCK + QPLANES;    // a run per one-bit of a lea
 //    one reads its trailing bit at (bits so far) + (its rank among the
 //    significant), a leading one looks its rank up in the mask, and a
 //    one-bit there also takes the next sign bits in rank order.
-// The magnitudes stay in LDS; the values (Section 4.3) are scaled by 2^-k at
-// the end.
-template <typename T>
+// The magnitudes stay in registers (MAXW 64-bit words per lane: coefficient
+// 64 w + lane in word w, MAXW >= len / 64), and so do the per-word state
+// (lane w holds word w's significance and sign masks, read by every lane with
+// readlane), so the words of a plane carry no LDS dependence on each other;
+// the values (Section 4.3) are scaled by 2^-k at the end.
+template <typename T, int MAXW>
 __global__ void __launch_bounds__(64) k_dq_decode(const DJobs B, int len) {
-    __shared__ uint64_t mag[QMAX_BLOCK];
     __shared__ uint32_t runs_lds[QMAX_RUN_WORDS];   // the block's run bytes
     __shared__ uint32_t signs_lds[QMAX_BLOCK / 32];  // its sign bits (one per coefficient at most)
     __shared__ uint32_t bsum[QMAX_RUNS];             // B_k = sum over runs i <= k of (run_i + 1)
-    __shared__ uint64_t sigw[QMAX_WORDS];            // coefficients with a decoded one-bit
-    __shared__ uint64_t negw[QMAX_WORDS];            // their signs
     __shared__ uint64_t onew[QMAX_WORDS];            // this plane's one-bits by leading rank
-    __shared__ uint32_t onepre[QMAX_WORDS], sigpre[QMAX_WORDS], leadpre[QMAX_WORDS];
     __shared__ uint32_t tplane[QMAX_BLOCK / 32 + 2];  // this plane's trailing bits, from bit tpos & ~31
     const DJob& J = B.j[blockIdx.z];
     const uint32_t* __restrict__ in = J.in;
@@ -866,12 +865,13 @@ __global__ void __launch_bounds__(64) k_dq_decode(const DJobs B, int len) {
     const int64_t lo = (int64_t)b * len;
     const int m = (int)min<int64_t>(len, n - lo);
     const int cb = (int)min<int64_t>(max<int64_t>(count - lo, 0), m);
-    const int nw = (m + 63) / 64;
-    for (int i = lane; i < m; i += 64) mag[i] = 0;
-    if (lane < nw) {
-        sigw[lane] = 0;
-        negw[lane] = 0;
-    }
+    const int nw = (m + 63) / 64;   // <= MAXW (the launch picks MAXW from len)
+    // registers: mag[w] = magnitude of coefficient 64 w + lane; lane w holds
+    // the significance and sign words of word w (sw_l, ng_l)
+    uint64_t mag[MAXW];
+#pragma unroll
+    for (int w = 0; w < MAXW; ++w) mag[w] = 0;
+    uint64_t sw_l = 0, ng_l = 0;
     const uint64_t bwords = (uint64_t)in[QHEADER + 2 * b] | ((uint64_t)in[QHEADER + 2 * b + 1] << 32);
     const uint32_t* blk = in + boff[b];
     const uint32_t nrb = blk[0], nsb = blk[1], ntb = blk[2];
@@ -919,23 +919,23 @@ __global__ void __launch_bounds__(64) k_dq_decode(const DJobs B, int len) {
     if (nrb > 0 && prev_end != (int)nrb - 1) bad = true;   // an unterminated last run
     __syncthreads();
     uint32_t rk = 0, spos = 0, tpos = 0;
+    const uint64_t me = 1ull << lane, lt = me - 1;
     for (int p = QPLANES - 1; p >= P && k != QKZERO && !bad; --p) {
         const int upto = p == P ? cb : m;
+        // word `lane`: significant and leading positions below upto, their
+        // prefix counts over the words before it
         uint64_t sw = 0, lw = 0;
         if (lane < nw) {
             const int c = min(64, max(0, upto - 64 * lane));
             const uint64_t vm = c >= 64 ? ~0ull : ((1ull << c) - 1);
-            sw = sigw[lane] & vm;
-            lw = ~sigw[lane] & vm;
+            sw = sw_l & vm;
+            lw = ~sw_l & vm;
         }
         const uint32_t cs = (uint32_t)__popcll(sw), cl = (uint32_t)__popcll(lw);
         const uint32_t isig = wave_incl_scan(cs, lane), ilead = wave_incl_scan(cl, lane);
         const uint32_t nsig = __shfl(isig, 63), nlead = __shfl(ilead, 63);
-        if (lane < nw) {
-            sigpre[lane] = isig - cs;
-            leadpre[lane] = ilead - cl;
-            onew[lane] = 0;
-        }
+        const uint32_t sigpre_l = isig - cs, leadpre_l = ilead - cl;
+        if (lane < nw) onew[lane] = 0;
         if (tpos + nsig > ntb) {
             bad = true;
             break;
@@ -981,40 +981,49 @@ __global__ void __launch_bounds__(64) k_dq_decode(const DJobs B, int len) {
             }
         }
         __syncthreads();
-        {
-            const uint32_t co = lane < nw ? (uint32_t)__popcll(onew[lane]) : 0u;
-            const uint32_t io = wave_incl_scan(co, lane);
-            if (lane < nw) onepre[lane] = io - co;
-        }
-        __syncthreads();
-        const uint64_t me = 1ull << lane, lt = me - 1;
+        // one-bits of the words before each word of onew (lane w: word w)
+        const uint64_t onew_l = lane < nw ? onew[lane] : 0ull;
+        const uint32_t co = (uint32_t)__popcll(onew_l);
+        const uint32_t onepre_l = wave_incl_scan(co, lane) - co;
         const uint32_t tb0 = tpos & 31u;
-#pragma unroll 4
-        for (int w = 0; w < nw; ++w) {
-            const int c = min(64, max(0, upto - 64 * w));
-            const uint64_t vm = c >= 64 ? ~0ull : ((1ull << c) - 1);
-            const uint64_t sg = sigw[w];
-            bool becomes = false, negative = false;
-            if (vm & me) {
-                const int i = 64 * w + lane;
-                if (sg & me) {
-                    const uint32_t rho = sigpre[w] + (uint32_t)__popcll(sg & vm & lt);
-                    if (read_bit(tplane, tb0 + rho)) atomicOr((unsigned long long*)&mag[i], 1ull << p);
-                } else {
-                    const uint32_t a = leadpre[w] + (uint32_t)__popcll(~sg & vm & lt);
-                    const uint64_t ow = onew[a >> 6];
+        // lane l, word w: coefficient 64 w + l.  A significant one reads its
+        // trailing bit at (bits so far) + (its rank among the significant); a
+        // leading one looks its rank a up in onew, and a one-bit there takes
+        // the next sign bit in rank order.  Every word's loads are independent
+        // of the others' (the word state sits in registers), so they overlap.
+#pragma unroll
+        for (int w = 0; w < MAXW; ++w) {
+            if (w < nw) {
+                const int c = min(64, max(0, upto - 64 * w));
+                const uint64_t vm = c >= 64 ? ~0ull : ((1ull << c) - 1);
+                const uint64_t sg = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(sw_l >> 32), w) << 32) |
+                                    (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)sw_l, w);
+                const uint32_t sp = (uint32_t)__builtin_amdgcn_readlane((int)sigpre_l, w);
+                const uint32_t lp = (uint32_t)__builtin_amdgcn_readlane((int)leadpre_l, w);
+                const bool valid = (vm & me) != 0;
+                const bool is_sig = (sg & me) != 0;
+                const uint32_t a = lp + (uint32_t)__popcll(~sg & vm & lt);
+                const uint32_t ai = min(a >> 6, (uint32_t)(QMAX_WORDS - 1));
+                const uint32_t op = (uint32_t)__shfl((int)onepre_l, (int)ai);   // every lane takes part
+                bool setbit = false, becomes = false, negative = false;
+                if (valid && is_sig) {
+                    const uint32_t rho = sp + (uint32_t)__popcll(sg & vm & lt);
+                    setbit = read_bit(tplane, tb0 + rho) != 0;
+                } else if (valid) {
+                    const uint64_t ow = onew[ai];
                     if ((ow >> (a & 63)) & 1ull) {
-                        atomicOr((unsigned long long*)&mag[i], 1ull << p);
-                        const uint32_t si = spos + onepre[a >> 6] + (uint32_t)__popcll(ow & ((1ull << (a & 63)) - 1));
-                        negative = read_bit(signs_lds, si) != 0;
+                        setbit = true;
                         becomes = true;
+                        const uint32_t si = spos + op + (uint32_t)__popcll(ow & ((1ull << (a & 63)) - 1));
+                        negative = read_bit(signs_lds, si) != 0;
                     }
                 }
-            }
-            const uint64_t nbm = __ballot(becomes), ngm = __ballot(negative);
-            if (lane == 0 && nbm) {
-                sigw[w] = sg | nbm;
-                negw[w] |= ngm;
+                if (setbit) mag[w] |= 1ull << p;
+                const uint64_t nbm = __ballot(becomes), ngm = __ballot(negative);
+                if (lane == w) {
+                    sw_l |= nbm;
+                    ng_l |= ngm;
+                }
             }
         }
         tpos += nsig;
@@ -1023,18 +1032,23 @@ __global__ void __launch_bounds__(64) k_dq_decode(const DJobs B, int len) {
     }
     if (!bad && k != QKZERO && P < QPLANES && (rk != nruns || spos != nsb || tpos != ntb)) bad = true;
     if (bad && lane == 0 && status) atomicOr(status, 1);
-    __syncthreads();
-    for (int i = lane; i < m; i += 64) {
-        double v = 0.0;
-        if (k != QKZERO) {
-            const int lowp = i < cb ? P : P + 1;
-            const uint64_t d = dec_mag(mag[i], lowp);
-            if (d) {
-                v = ldexp((double)d, -k);
-                if ((negw[i >> 6] >> (i & 63)) & 1ull) v = -v;
+#pragma unroll
+    for (int w = 0; w < MAXW; ++w) {
+        const int i = 64 * w + lane;
+        const uint64_t ngw = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(ng_l >> 32), w) << 32) |
+                             (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)ng_l, w);
+        if (w < nw && i < m) {
+            double v = 0.0;
+            if (k != QKZERO) {
+                const int lowp = i < cb ? P : P + 1;
+                const uint64_t d = dec_mag(mag[w], lowp);
+                if (d) {
+                    v = ldexp((double)d, -k);
+                    if ((ngw >> lane) & 1ull) v = -v;
+                }
             }
+            out[lo + i] = (T)v;
         }
-        out[lo + i] = (T)v;
     }
 }
 
@@ -1088,8 +1102,14 @@ hipError_t launch_dequantize_jobs(const DJobs& B, int count, int f64, int len, h
     for (int z = 0; z < count; ++z) maxnb = std::max(maxnb, B.j[z].nb);
     const unsigned Z = (unsigned)count;
     hipLaunchKernelGGL(k_dq_offsets, dim3(1, 1, Z), dim3(256), 0, st, B, len);
-    if (f64) hipLaunchKernelGGL(k_dq_decode<double>, dim3((unsigned)maxnb, 1, Z), dim3(64), 0, st, B, len);
-    else hipLaunchKernelGGL(k_dq_decode<float>, dim3((unsigned)maxnb, 1, Z), dim3(64), 0, st, B, len);
+    const dim3 grid((unsigned)maxnb, 1, Z);
+    if (len <= 1024) {
+        if (f64) hipLaunchKernelGGL((k_dq_decode<double, 16>), grid, dim3(64), 0, st, B, len);
+        else hipLaunchKernelGGL((k_dq_decode<float, 16>), grid, dim3(64), 0, st, B, len);
+    } else {
+        if (f64) hipLaunchKernelGGL((k_dq_decode<double, QMAX_WORDS>), grid, dim3(64), 0, st, B, len);
+        else hipLaunchKernelGGL((k_dq_decode<float, QMAX_WORDS>), grid, dim3(64), 0, st, B, len);
+    }
     return hipGetLastError();
 }
 
