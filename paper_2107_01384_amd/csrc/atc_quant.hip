@@ -839,24 +839,32 @@ constexpr int QMAX_RUNS = QMAX_BLOCK + QPLANES;    // a run per one-bit of a lea
 // (lane w holds word w's significance and sign masks, read by every lane with
 // readlane), so the words of a plane carry no LDS dependence on each other;
 // the values (Section 4.3) are scaled by 2^-k at the end.
+constexpr int DQ_WAVES = 4;   // wavefronts per decoded block
+
 template <typename T, int MAXW>
-__global__ void __launch_bounds__(64) k_dq_decode(const DJobs B, int len) {
+__global__ void __launch_bounds__(64 * DQ_WAVES) k_dq_decode(const DJobs B, int len) {
+    constexpr int MW = MAXW / DQ_WAVES;             // words per wavefront (word w = DQ_WAVES j + wave)
     __shared__ uint32_t runs_lds[QMAX_RUN_WORDS];   // the block's run bytes
     __shared__ uint32_t signs_lds[QMAX_BLOCK / 32];  // its sign bits (one per coefficient at most)
     __shared__ uint32_t bsum[QMAX_RUNS];             // B_k = sum over runs i <= k of (run_i + 1)
     __shared__ uint64_t onew[QMAX_WORDS];            // this plane's one-bits by leading rank
+    __shared__ uint64_t sigw[QMAX_WORDS];            // coefficients with a decoded one-bit, by word
     __shared__ uint32_t tplane[QMAX_BLOCK / 32 + 2];  // this plane's trailing bits, from bit tpos & ~31
+    __shared__ uint32_t sh_nruns, sh_rk, sh_nones;
+    __shared__ int sh_bad;
     const DJob& J = B.j[blockIdx.z];
     const uint32_t* __restrict__ in = J.in;
     const int64_t n = J.n;
     const int64_t* __restrict__ boff = J.boff;
     T* __restrict__ out = (T*)J.out;
     int32_t* status = J.status;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int b = blockIdx.x;
     if (b >= J.nb) return;
     if (boff[b] < 0) {   // header did not match: zeros
-        for (int64_t i = (int64_t)b * len + lane; i < min<int64_t>(n, (int64_t)(b + 1) * len); i += 64) out[i] = (T)0;
+        for (int64_t i = (int64_t)b * len + tid; i < min<int64_t>(n, (int64_t)(b + 1) * len); i += 64 * DQ_WAVES)
+            out[i] = (T)0;
         return;
     }
     const int32_t k = (int32_t)in[1];
@@ -866,12 +874,12 @@ __global__ void __launch_bounds__(64) k_dq_decode(const DJobs B, int len) {
     const int m = (int)min<int64_t>(len, n - lo);
     const int cb = (int)min<int64_t>(max<int64_t>(count - lo, 0), m);
     const int nw = (m + 63) / 64;   // <= MAXW (the launch picks MAXW from len)
-    // registers: mag[w] = magnitude of coefficient 64 w + lane; lane w holds
-    // the significance and sign words of word w (sw_l, ng_l)
-    uint64_t mag[MAXW];
+    // registers: mag[j] = magnitude of coefficient 64 w + lane of word
+    // w = DQ_WAVES j + wave; ng_l (lane w of w's wavefront) its sign mask
+    uint64_t mag[MW];
 #pragma unroll
-    for (int w = 0; w < MAXW; ++w) mag[w] = 0;
-    uint64_t sw_l = 0, ng_l = 0;
+    for (int j = 0; j < MW; ++j) mag[j] = 0;
+    uint64_t ng_l = 0;
     const uint64_t bwords = (uint64_t)in[QHEADER + 2 * b] | ((uint64_t)in[QHEADER + 2 * b + 1] << 32);
     const uint32_t* blk = in + boff[b];
     const uint32_t nrb = blk[0], nsb = blk[1], ntb = blk[2];
@@ -881,49 +889,59 @@ __global__ void __launch_bounds__(64) k_dq_decode(const DJobs B, int len) {
     bool bad = (nrb + 3) / 4 > (uint32_t)QMAX_RUN_WORDS || (nsb + 31) / 32 > (uint32_t)(QMAX_BLOCK / 32) ||
                (uint64_t)QBLK_HDR + (nrb + 3) / 4 + (nsb + 31) / 32 + ((uint64_t)ntb + 31) / 32 > bwords;
     if (!bad) {
-        for (uint32_t i = lane; i < (nrb + 3) / 4; i += 64) runs_lds[i] = runs_g[i];
-        for (uint32_t i = lane; i < (nsb + 31) / 32; i += 64) signs_lds[i] = signs[i];
+        for (uint32_t i = tid; i < (nrb + 3) / 4; i += 64 * DQ_WAVES) runs_lds[i] = runs_g[i];
+        for (uint32_t i = tid; i < (nsb + 31) / 32; i += 64 * DQ_WAVES) signs_lds[i] = signs[i];
+    }
+    if (tid < QMAX_WORDS) sigw[tid] = 0;
+    __syncthreads();
+    // the runs (wavefront 0): B_k for k < nruns
+    if (wave == 0) {
+        uint32_t nruns = 0, carry = 0;
+        int prev_end = -1;
+        for (uint32_t c0 = 0; c0 < nrb && !bad; c0 += 64) {
+            const uint32_t j = c0 + lane;
+            const bool inb = j < nrb;
+            const uint32_t byte = inb ? read_byte(runs_lds, j) : 0u;
+            const bool end = inb && !(byte & 0x80u);
+            const uint64_t em = __ballot(end);
+            const uint64_t below = em & lanemask_lt(lane);
+            const int start = below ? (int)(c0 + 63 - __clzll(below)) + 1 : prev_end + 1;
+            uint32_t v = 0;
+            bool over = false;
+            if (end) {
+                const int L = (int)j - start + 1;
+                if (L > 5) over = true;
+                else
+                    for (int t = 0; t < L; ++t) v |= (read_byte(runs_lds, (uint32_t)(start + t)) & 0x7Fu) << (7 * t);
+            }
+            const uint32_t kk = nruns + (uint32_t)__popcll(below);
+            if (end && kk >= (uint32_t)QMAX_RUNS) over = true;
+            if (__ballot(over)) {
+                bad = true;
+                break;
+            }
+            const uint32_t x = wave_incl_scan(end ? v + 1 : 0u, lane);
+            if (end) bsum[kk] = carry + x;
+            carry += __shfl(x, 63);
+            nruns += (uint32_t)__popcll(em);
+            if (em) prev_end = (int)(c0 + 63 - __clzll(em));
+        }
+        if (nrb > 0 && prev_end != (int)nrb - 1) bad = true;   // an unterminated last run
+        if (lane == 0) {
+            sh_nruns = nruns;
+            sh_bad = bad ? 1 : 0;
+        }
     }
     __syncthreads();
-    // the runs: B_k for k < nruns
-    uint32_t nruns = 0, carry = 0;
-    int prev_end = -1;
-    for (uint32_t c0 = 0; c0 < nrb && !bad; c0 += 64) {
-        const uint32_t j = c0 + lane;
-        const bool inb = j < nrb;
-        const uint32_t byte = inb ? read_byte(runs_lds, j) : 0u;
-        const bool end = inb && !(byte & 0x80u);
-        const uint64_t em = __ballot(end);
-        const uint64_t below = em & lanemask_lt(lane);
-        const int start = below ? (int)(c0 + 63 - __clzll(below)) + 1 : prev_end + 1;
-        uint32_t v = 0;
-        bool over = false;
-        if (end) {
-            const int L = (int)j - start + 1;
-            if (L > 5) over = true;
-            else
-                for (int t = 0; t < L; ++t) v |= (read_byte(runs_lds, (uint32_t)(start + t)) & 0x7Fu) << (7 * t);
-        }
-        const uint32_t kk = nruns + (uint32_t)__popcll(below);
-        if (end && kk >= (uint32_t)QMAX_RUNS) over = true;
-        if (__ballot(over)) {
-            bad = true;
-            break;
-        }
-        const uint32_t x = wave_incl_scan(end ? v + 1 : 0u, lane);
-        if (end) bsum[kk] = carry + x;
-        carry += __shfl(x, 63);
-        nruns += (uint32_t)__popcll(em);
-        if (em) prev_end = (int)(c0 + 63 - __clzll(em));
-    }
-    if (nrb > 0 && prev_end != (int)nrb - 1) bad = true;   // an unterminated last run
-    __syncthreads();
+    const uint32_t nruns = sh_nruns;
+    bad = sh_bad != 0;
     uint32_t rk = 0, spos = 0, tpos = 0;
     const uint64_t me = 1ull << lane, lt = me - 1;
     for (int p = QPLANES - 1; p >= P && k != QKZERO && !bad; --p) {
         const int upto = p == P ? cb : m;
-        // word `lane`: significant and leading positions below upto, their
-        // prefix counts over the words before it
+        // every wavefront: word `lane`'s significant and leading positions
+        // below upto and their prefix counts over the words before it
+        const uint64_t sw_l = lane < nw ? sigw[lane] : 0ull;
         uint64_t sw = 0, lw = 0;
         if (lane < nw) {
             const int c = min(64, max(0, upto - 64 * lane));
@@ -935,64 +953,76 @@ __global__ void __launch_bounds__(64) k_dq_decode(const DJobs B, int len) {
         const uint32_t isig = wave_incl_scan(cs, lane), ilead = wave_incl_scan(cl, lane);
         const uint32_t nsig = __shfl(isig, 63), nlead = __shfl(ilead, 63);
         const uint32_t sigpre_l = isig - cs, leadpre_l = ilead - cl;
-        if (lane < nw) onew[lane] = 0;
         if (tpos + nsig > ntb) {
+            bad = true;   // the same in every wavefront
+            break;
+        }
+        if (tid < nw) onew[tid] = 0;
+        {
+            const uint32_t tw = ((tpos & 31u) + nsig + 31u) >> 5;   // at most QMAX_BLOCK / 32 + 1
+            for (uint32_t i = tid; i < tw; i += 64 * DQ_WAVES) tplane[i] = trail[(tpos >> 5) + i];
+        }
+        __syncthreads();
+        // this plane's runs (wavefront 0): one-bits at the leading ranks below
+        // nlead, then the final run
+        if (wave == 0) {
+            uint32_t nones = 0;
+            bool wbad = false;
+            if (nlead > 0) {
+                const uint32_t base = rk > 0 ? bsum[rk - 1] : 0u;
+                bool found = false;
+                for (uint32_t c0 = rk; !found; c0 += 64) {
+                    if (c0 >= nruns) {
+                        wbad = true;
+                        break;
+                    }
+                    const uint32_t kk = c0 + lane;
+                    const bool inr = kk < nruns;
+                    const uint32_t val = inr ? bsum[kk] - base - 1u : 0u;
+                    const uint64_t endm = __ballot(inr && val == nlead);
+                    const uint64_t overm = __ballot(inr && val > nlead);
+                    const int le = endm ? __ffsll((long long)endm) - 1 : 64;
+                    const int lov = overm ? __ffsll((long long)overm) - 1 : 64;
+                    if (lov < le) {
+                        wbad = true;
+                        break;
+                    }
+                    const bool one = inr && lane < le && val < nlead;
+                    if (one) atomicOr((unsigned long long*)&onew[val >> 6], 1ull << (val & 63));
+                    nones += (uint32_t)__popcll(__ballot(one));
+                    if (endm) {
+                        found = true;
+                        rk = c0 + (uint32_t)le + 1;
+                    }
+                }
+                if (!wbad && spos + nones > nsb) wbad = true;
+            }
+            if (lane == 0) {
+                sh_nones = nones;
+                sh_rk = rk;
+                sh_bad = wbad ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        const uint32_t nones = sh_nones;
+        rk = sh_rk;
+        if (sh_bad) {
             bad = true;
             break;
         }
-        {
-            const uint32_t tw = ((tpos & 31u) + nsig + 31u) >> 5;   // at most QMAX_BLOCK / 32 + 1
-            for (uint32_t i = lane; i < tw; i += 64) tplane[i] = trail[(tpos >> 5) + i];
-        }
-        __syncthreads();
-        // this plane's runs: one-bits at the leading ranks below nlead, then the final run
-        uint32_t nones = 0;
-        if (nlead > 0) {
-            const uint32_t base = rk > 0 ? bsum[rk - 1] : 0u;
-            bool found = false;
-            for (uint32_t c0 = rk; !found; c0 += 64) {
-                if (c0 >= nruns) {
-                    bad = true;
-                    break;
-                }
-                const uint32_t kk = c0 + lane;
-                const bool inr = kk < nruns;
-                const uint32_t val = inr ? bsum[kk] - base - 1u : 0u;
-                const uint64_t endm = __ballot(inr && val == nlead);
-                const uint64_t overm = __ballot(inr && val > nlead);
-                const int le = endm ? __ffsll((long long)endm) - 1 : 64;
-                const int lov = overm ? __ffsll((long long)overm) - 1 : 64;
-                if (lov < le) {
-                    bad = true;
-                    break;
-                }
-                const bool one = inr && lane < le && val < nlead;
-                if (one) atomicOr((unsigned long long*)&onew[val >> 6], 1ull << (val & 63));
-                nones += (uint32_t)__popcll(__ballot(one));
-                if (endm) {
-                    found = true;
-                    rk = c0 + (uint32_t)le + 1;
-                }
-            }
-            if (bad) break;
-            if (spos + nones > nsb) {
-                bad = true;
-                break;
-            }
-        }
-        __syncthreads();
         // one-bits of the words before each word of onew (lane w: word w)
         const uint64_t onew_l = lane < nw ? onew[lane] : 0ull;
         const uint32_t co = (uint32_t)__popcll(onew_l);
         const uint32_t onepre_l = wave_incl_scan(co, lane) - co;
         const uint32_t tb0 = tpos & 31u;
-        // lane l, word w: coefficient 64 w + l.  A significant one reads its
-        // trailing bit at (bits so far) + (its rank among the significant); a
-        // leading one looks its rank a up in onew, and a one-bit there takes
-        // the next sign bit in rank order.  Every word's loads are independent
-        // of the others' (the word state sits in registers), so they overlap.
+        // this wavefront's words; lane l, word w: coefficient 64 w + l.  A
+        // significant one reads its trailing bit at (bits so far) + (its rank
+        // among the significant); a leading one looks its rank a up in onew,
+        // and a one-bit there takes the next sign bit in rank order.
+        uint64_t sw_own = sw_l;   // lane w of word w's wavefront: its updated mask
 #pragma unroll
-        for (int w = 0; w < MAXW; ++w) {
+        for (int j = 0; j < MW; ++j) {
+            const int w = DQ_WAVES * j + wave;
             if (w < nw) {
                 const int c = min(64, max(0, upto - 64 * w));
                 const uint64_t vm = c >= 64 ? ~0ull : ((1ull << c) - 1);
@@ -1018,22 +1048,25 @@ __global__ void __launch_bounds__(64) k_dq_decode(const DJobs B, int len) {
                         negative = read_bit(signs_lds, si) != 0;
                     }
                 }
-                if (setbit) mag[w] |= 1ull << p;
+                if (setbit) mag[j] |= 1ull << p;
                 const uint64_t nbm = __ballot(becomes), ngm = __ballot(negative);
                 if (lane == w) {
-                    sw_l |= nbm;
+                    sw_own |= nbm;
                     ng_l |= ngm;
                 }
             }
         }
+        // the new significance masks of this wavefront's words, for the next plane
+        if (lane < nw && (lane % DQ_WAVES) == wave) sigw[lane] = sw_own;
         tpos += nsig;
         spos += nones;
         __syncthreads();
     }
     if (!bad && k != QKZERO && P < QPLANES && (rk != nruns || spos != nsb || tpos != ntb)) bad = true;
-    if (bad && lane == 0 && status) atomicOr(status, 1);
+    if (bad && tid == 0 && status) atomicOr(status, 1);
 #pragma unroll
-    for (int w = 0; w < MAXW; ++w) {
+    for (int j = 0; j < MW; ++j) {
+        const int w = DQ_WAVES * j + wave;
         const int i = 64 * w + lane;
         const uint64_t ngw = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(ng_l >> 32), w) << 32) |
                              (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)ng_l, w);
@@ -1041,7 +1074,7 @@ __global__ void __launch_bounds__(64) k_dq_decode(const DJobs B, int len) {
             double v = 0.0;
             if (k != QKZERO) {
                 const int lowp = i < cb ? P : P + 1;
-                const uint64_t d = dec_mag(mag[w], lowp);
+                const uint64_t d = dec_mag(mag[j], lowp);
                 if (d) {
                     v = ldexp((double)d, -k);
                     if ((ngw >> lane) & 1ull) v = -v;
@@ -1104,11 +1137,11 @@ hipError_t launch_dequantize_jobs(const DJobs& B, int count, int f64, int len, h
     hipLaunchKernelGGL(k_dq_offsets, dim3(1, 1, Z), dim3(256), 0, st, B, len);
     const dim3 grid((unsigned)maxnb, 1, Z);
     if (len <= 1024) {
-        if (f64) hipLaunchKernelGGL((k_dq_decode<double, 16>), grid, dim3(64), 0, st, B, len);
-        else hipLaunchKernelGGL((k_dq_decode<float, 16>), grid, dim3(64), 0, st, B, len);
+        if (f64) hipLaunchKernelGGL((k_dq_decode<double, 16>), grid, dim3(64 * DQ_WAVES), 0, st, B, len);
+        else hipLaunchKernelGGL((k_dq_decode<float, 16>), grid, dim3(64 * DQ_WAVES), 0, st, B, len);
     } else {
-        if (f64) hipLaunchKernelGGL((k_dq_decode<double, QMAX_WORDS>), grid, dim3(64), 0, st, B, len);
-        else hipLaunchKernelGGL((k_dq_decode<float, QMAX_WORDS>), grid, dim3(64), 0, st, B, len);
+        if (f64) hipLaunchKernelGGL((k_dq_decode<double, QMAX_WORDS>), grid, dim3(64 * DQ_WAVES), 0, st, B, len);
+        else hipLaunchKernelGGL((k_dq_decode<float, QMAX_WORDS>), grid, dim3(64 * DQ_WAVES), 0, st, B, len);
     }
     return hipGetLastError();
 }
