@@ -14,6 +14,7 @@
 //   k_q_max        max |b| (bit pattern of the double, atomicMax) + non-finite
 //   k_q_planes     per block: q_i (kept in the workspace), and for every plane
 //                  p in 0..64 the block's error with all its planes >= p known
+//                  (15 partial sums per plane, 1024 threads)
 //   k_q_plane_sums one workgroup per plane: the core's error at its end
 //   k_q_plane_pick the breakpoint plane P (the first whose end reaches T)
 //   k_q_run_start  one workgroup: the error at the start of every block on
@@ -230,10 +231,27 @@ __global__ void k_q_max(const QJobs B) {
         const unsigned long long t = __shfl_xor(m, o);
         m = max(m, t);
     }
+    // one atomic per workgroup (per-wavefront atomics on the one word
+    // serialised at L2: ~80 us for a 2M-coefficient core)
+    __shared__ unsigned long long wm[4];
+    __shared__ int wb[4];
+    const int wave = threadIdx.x >> 6;
+    const bool anybad = __ballot(bad) != 0;
     if ((threadIdx.x & 63) == 0) {
-        if (m) atomicMax(&st->maxbits, m);
+        wm[wave] = m;
+        wb[wave] = anybad ? 1 : 0;
     }
-    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(&st->nonfinite, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long bm = 0;
+        int bb = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            bm = max(bm, wm[w]);
+            bb |= wb[w];
+        }
+        if (bm) atomicMax(&st->maxbits, bm);
+        if (bb) atomicOr(&st->nonfinite, 1);
+    }
 }
 
 // k with 2^63 <= 2^k m < 2^64 for the maximum m > 0 (Section 3.3)
@@ -244,7 +262,8 @@ __device__ __forceinline__ int32_t scale_of(unsigned long long maxbits) {
     return 64 - e;
 }
 
-constexpr int PLANES_THREADS = 320;   // 65 planes x 4 partial sums, 5 wavefronts
+constexpr int PLANES_J = 15;          // partial sums per plane
+constexpr int PLANES_THREADS = 1024;  // 65 planes x 15 partial sums (975 threads), 16 wavefronts
 
 template <typename T>
 __global__ void __launch_bounds__(PLANES_THREADS) k_q_planes(const QJobs B, int len) {
@@ -271,20 +290,19 @@ __global__ void __launch_bounds__(PLANES_THREADS) k_q_planes(const QJobs B, int 
         w.neg[lo + i] = v < 0.0 ? 1 : 0;
     }
     __syncthreads();
-    // thread (p, j): plane p = tid / 4, every fourth coefficient from j
+    // thread (p, j): plane p = tid / PLANES_J, every PLANES_J-th coefficient
+    // from j (exact integer sums: the order does not matter)
     const int tid = threadIdx.x;
     U192 acc = u192_zero();
-    if (tid < 65 * 4) {
-        const int p = tid >> 2, j = tid & 3;
-        for (int i = j; i < m; i += 4) u192_add(acc, err128(sq[i], p));
+    if (tid < 65 * PLANES_J) {
+        const int p = tid / PLANES_J, j = tid - p * PLANES_J;
+        for (int i = j; i < m; i += PLANES_J) u192_add(acc, err128(sq[i], p));
     }
     red[tid] = acc;
     __syncthreads();
     if (tid < 65) {
-        U192 s = red[4 * tid];
-        u192_add(s, red[4 * tid + 1]);
-        u192_add(s, red[4 * tid + 2]);
-        u192_add(s, red[4 * tid + 3]);
+        U192 s = red[PLANES_J * tid];
+        for (int j = 1; j < PLANES_J; ++j) u192_add(s, red[PLANES_J * tid + j]);
         w.part[(size_t)b * 65 + tid] = s;
     }
 }
@@ -1108,7 +1126,7 @@ hipError_t launch_quantize_jobs(const QJobs& B, int count, int f64, int len, hip
     }
     const unsigned Z = (unsigned)count, nb = (unsigned)maxnb;
     hipLaunchKernelGGL(k_q_init, dim3(1, 1, Z), dim3(64), 0, st, B);
-    const unsigned gmax = (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, ceil_div(maxn, 256)));
+    const unsigned gmax = (unsigned)std::min<int64_t>(256, std::max<int64_t>(1, ceil_div(maxn, 256)));
     if (f64) hipLaunchKernelGGL(k_q_max<double>, dim3(gmax, 1, Z), dim3(256), 0, st, B);
     else hipLaunchKernelGGL(k_q_max<float>, dim3(gmax, 1, Z), dim3(256), 0, st, B);
     if (f64) hipLaunchKernelGGL(k_q_planes<double>, dim3(nb, 1, Z), dim3(PLANES_THREADS), 0, st, B, len);
