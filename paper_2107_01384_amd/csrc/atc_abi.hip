@@ -866,7 +866,16 @@ atc_status reconstruct_impl(const atc_shape* shape, const int64_t* ranks, const 
     int64_t cur[ATC_MAX_DIMS];
     for (int k = 0; k < d; ++k) cur[k] = ranks[k];
     const void* src = core;
-    for (int i = 0; i < d; ++i) {
+    // the last two products in one pass when they are the two trailing modes
+    // (in either order) and their sizes fit the fused kernel (float32)
+    const int64_t lead = d >= 2 ? prod(shape->dims, 0, d - 2) : 0;
+    const bool fuse = !f64 && d >= 2 &&
+                      ((order[d - 2] == d - 2 && order[d - 1] == d - 1) ||
+                       (order[d - 2] == d - 1 && order[d - 1] == d - 2)) &&
+                      ttm_fused_last2_fits(lead, (int)ranks[d - 2], (int)ranks[d - 1], (int)shape->dims[d - 2],
+                                           (int)shape->dims[d - 1], xhat);
+    const int steps = fuse ? d - 2 : d;
+    for (int i = 0; i < steps; ++i) {
         const int k = order[i];
         const int64_t L = prod(cur, 0, k), R = prod(cur, k + 1, d);
         const int rk = (int)ranks[k], nk = (int)shape->dims[k];
@@ -877,6 +886,10 @@ atc_status reconstruct_impl(const atc_shape* shape, const int64_t* ranks, const 
         cur[k] = nk;
         src = dst;
     }
+    if (fuse)
+        HIP_TRY(launch_ttm_fused_last2((const float*)src, lead, (int)ranks[d - 2], (int)ranks[d - 1],
+                                       (int)shape->dims[d - 2], (int)shape->dims[d - 1],
+                                       (const float*)factors[d - 2], (const float*)factors[d - 1], (float*)xhat, st));
     return ATC_OK;
 }
 

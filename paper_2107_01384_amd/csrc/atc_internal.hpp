@@ -190,6 +190,14 @@ TtmPlan ttm_plan(int prec, int64_t L, int n, int64_t R, int m_out);
 // device (a rank chosen by a kernel earlier on the stream); none when < 1.
 hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, const void* Mh,
                       const void* Ml, void* Z, hipStream_t st, const int32_t* m_dev = nullptr);
+// The last two mode products of a reconstruction in one pass (float32): Y is
+// (L, r_a, r_b) row-major, U_a n_a x r_a and U_b n_b x r_b (the factors as
+// given), X (L, n_a, n_b) = Y x_a U_a x_b U_b.  For r_a <= 32, r_b <= 16,
+// n_a <= 128, n_b <= 64 (and X 16-byte aligned when n_b % 4 == 0): the fits
+// test, then the launch (hipErrorInvalidValue when it does not fit).
+bool ttm_fused_last2_fits(int64_t L, int ra, int rb, int na, int nb, const void* X);
+hipError_t launch_ttm_fused_last2(const float* Y, int64_t L, int ra, int rb, int na, int nb, const float* Ua,
+                                  const float* Ub, float* X, hipStream_t st);
 
 // Symmetric eigensolvers (FP64).  Outputs lam (descending; not clamped, so a
 // tail sum over rounding-level eigenvalues of an FP32-accurate Gram matrix

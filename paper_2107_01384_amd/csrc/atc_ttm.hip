@@ -576,6 +576,109 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_expand_last(const float* __res
     }
 }
 
+// The last two mode products of a reconstruction in one pass (float32):
+// for every l of the leading modes, X[l] = U_a Y[l] U_b^T with Y[l] the
+// r_a x r_b slab of the input (r_a <= 32, r_b <= 16), U_a n_a x r_a (n_a <=
+// 128) and U_b n_b x r_b (n_b <= 64), so the n_a x r_b intermediate never
+// goes to memory.  Per slab: T = U_a Y[l] (wavefront w: rows 32 w .. 32 w +
+// 31 of T, K = r_a in steps of 4, Y read from global, U_a held in registers),
+// T through LDS, X = T U_b^T (the same rows, U_b in registers), X staged in
+// LDS and stored as one contiguous n_a x n_b block with 16-byte stores.
+// FP32 products and sums on v_mfma_f32_16x16x4f32.
+constexpr int F2_RA = 32, F2_RB = 16, F2_NA = 128, F2_NB = 64;
+constexpr int F2_TS = F2_RB + 1;   // T row stride (floats)
+
+__global__ __launch_bounds__(NTHREADS) void k_ttm_fused_last2(const float* __restrict__ Y, int64_t L, int ra, int rb,
+                                                              int na, int nb, const float* __restrict__ Ua,
+                                                              const float* __restrict__ Ub, float* __restrict__ X) {
+    __shared__ float ts[F2_NA * F2_TS];
+    __shared__ float xs[F2_NA * (F2_NB + 4)];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int c = lane & 15, q = lane >> 4;
+    const int xstride = nb + 4;   // staged X row stride (floats): rows 4 apart in distinct banks
+    // A operands of T = U_a Y: rows 32 w + 16 h + c of U_a, K = 4 s + q
+    float ua[2][F2_RA / 4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int st = 0; st < F2_RA / 4; ++st) {
+            const int row = 32 * wave + 16 * h + c, k = 4 * st + q;
+            ua[h][st] = (row < na && k < ra) ? Ua[(int64_t)row * ra + k] : 0.f;
+        }
+    // B operands of X = T U_b^T: B[k][col] = U_b[16 t + col][k], K = 4 s + q
+    float ub[F2_NB / 16][F2_RB / 4];
+#pragma unroll
+    for (int t = 0; t < F2_NB / 16; ++t)
+#pragma unroll
+        for (int st = 0; st < F2_RB / 4; ++st) {
+            const int d = 16 * t + c, k = 4 * st + q;
+            ub[t][st] = (d < nb && k < rb) ? Ub[(int64_t)d * rb + k] : 0.f;
+        }
+    const int xsz = na * nb;   // <= 8192
+    const bool vec = (nb & 3) == 0;
+    // B operands of T = U_a Y[l]: Y[l][4 s + q][c], loaded one slab ahead
+    float yv[F2_RA / 4];
+    auto load_y = [&](int64_t l) {
+        const float* yl = Y + min(l, L - 1) * (int64_t)ra * rb;
+#pragma unroll
+        for (int st = 0; st < F2_RA / 4; ++st) {
+            const int k = 4 * st + q;
+            yv[st] = (k < ra && c < rb) ? yl[k * rb + c] : 0.f;
+        }
+    };
+    load_y(blockIdx.x);
+    for (int64_t l = blockIdx.x; l < L; l += gridDim.x) {
+        // T rows 32 w + 16 h + (4 q + e), column c
+        f32x4 tacc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int st = 0; st < F2_RA / 4; ++st)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) tacc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[h][st], yv[st], tacc[h], 0, 0, 0);
+        load_y(l + gridDim.x);   // the next slab's loads in flight over the rest
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ts[(32 * wave + 16 * h + 4 * q + e) * F2_TS + c] = tacc[h][e];
+        __syncthreads();
+        // X rows 32 w + 16 h + (4 q + e), columns 16 t + c
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            f32x4 xacc[F2_NB / 16];
+#pragma unroll
+            for (int t = 0; t < F2_NB / 16; ++t) xacc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < F2_RB / 4; ++st) {
+                const float tv = ts[(32 * wave + 16 * h + c) * F2_TS + 4 * st + q];
+#pragma unroll
+                for (int t = 0; t < F2_NB / 16; ++t)
+                    xacc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tv, ub[t][st], xacc[t], 0, 0, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < F2_NB / 16; ++t)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = 32 * wave + 16 * h + 4 * q + e, col = 16 * t + c;
+                    if (row < na && col < nb) xs[row * xstride + col] = xacc[t][e];
+                }
+        }
+        __syncthreads();
+        // the slab's n_a x n_b block, contiguous in X
+        float* xl = X + l * (int64_t)xsz;
+        if (vec) {
+            for (int e4 = 4 * tid; e4 < xsz; e4 += 4 * NTHREADS) {
+                const int row = e4 / nb, col = e4 - row * nb;
+                const float4 v = *reinterpret_cast<const float4*>(&xs[row * xstride + col]);
+                *reinterpret_cast<float4*>(xl + e4) = v;
+            }
+        } else {
+            for (int e = tid; e < xsz; e += NTHREADS) {
+                const int row = e / nb, col = e - row * nb;
+                xl[e] = xs[row * xstride + col];
+            }
+        }
+    }
+}
+
 template <int KC>
 void launch_expand_last_k(int jt, unsigned grid, hipStream_t st, const float* Y, int64_t L, int n, int m_out,
                           const float* M, float* Z) {
@@ -721,6 +824,21 @@ TtmPlan ttm_plan(int prec, int64_t L, int n, int64_t R, int m_out) {
     }
     t.jtiles = (int)ceil_div(m_out, TILE);
     return t;
+}
+
+bool ttm_fused_last2_fits(int64_t L, int ra, int rb, int na, int nb, const void* X) {
+    // float4 stores (n_b % 4 == 0) need 16-byte aligned slabs
+    const bool aligned = (nb & 3) != 0 || reinterpret_cast<uintptr_t>(X) % 16 == 0;
+    return L >= 1 && ra >= 1 && ra <= F2_RA && rb >= 1 && rb <= F2_RB && na >= 1 && na <= F2_NA && nb >= 1 &&
+           nb <= F2_NB && aligned;
+}
+
+hipError_t launch_ttm_fused_last2(const float* Y, int64_t L, int ra, int rb, int na, int nb, const float* Ua,
+                                  const float* Ub, float* X, hipStream_t st) {
+    if (!ttm_fused_last2_fits(L, ra, rb, na, nb, X)) return hipErrorInvalidValue;
+    const unsigned grid = (unsigned)std::min<int64_t>(L, 2048);
+    hipLaunchKernelGGL(k_ttm_fused_last2, dim3(grid), dim3(NTHREADS), 0, st, Y, L, ra, rb, na, nb, Ua, Ub, X);
+    return hipGetLastError();
 }
 
 hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, const void* Mh, const void* Ml,
