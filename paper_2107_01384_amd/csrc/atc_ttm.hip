@@ -580,29 +580,35 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_expand_last(const float* __res
 // for every l of the leading modes, X[l] = U_a Y[l] U_b^T with Y[l] the
 // r_a x r_b slab of the input (r_a <= 32, r_b <= 16), U_a n_a x r_a (n_a <=
 // 128) and U_b n_b x r_b (n_b <= 64), so the n_a x r_b intermediate never
-// goes to memory.  Per slab: T = U_a Y[l] (wavefront w: rows 32 w .. 32 w +
-// 31 of T, K = r_a in steps of 4, Y read from global, U_a held in registers),
-// T through LDS, X = T U_b^T (the same rows, U_b in registers), X staged in
-// LDS and stored as one contiguous n_a x n_b block with 16-byte stores.
-// FP32 products and sums on v_mfma_f32_16x16x4f32.
+// goes to memory.  Wavefront w owns rows 32 w .. 32 w + 31 of T and X for
+// every slab, so the wavefronts never wait for each other: T = U_a Y[l]
+// (K = r_a in steps of 4, U_a rows in registers, Y[l] loaded one slab
+// ahead), T through the wavefront's LDS rows (read back whole), X = T U_b^T
+// (U_b in registers), X staged in the same LDS rows and written as one
+// contiguous block of 32 rows with 16-byte stores.  FP32 products and sums
+// on v_mfma_f32_16x16x4f32.
 constexpr int F2_RA = 32, F2_RB = 16, F2_NA = 128, F2_NB = 64;
 constexpr int F2_TS = F2_RB + 1;   // T row stride (floats)
+constexpr int F2_XS = F2_NB + 4;   // staged X row stride (floats): rows 4 apart in distinct banks
 
 __global__ __launch_bounds__(NTHREADS) void k_ttm_fused_last2(const float* __restrict__ Y, int64_t L, int ra, int rb,
                                                               int na, int nb, const float* __restrict__ Ua,
                                                               const float* __restrict__ Ub, float* __restrict__ X) {
-    __shared__ float ts[F2_NA * F2_TS];
-    __shared__ float xs[F2_NA * (F2_NB + 4)];
+    static_assert(32 * F2_TS <= 32 * F2_XS, "T fits in the staging rows");
+    __shared__ float xs_all[F2_NA * F2_XS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int c = lane & 15, q = lane >> 4;
-    const int xstride = nb + 4;   // staged X row stride (floats): rows 4 apart in distinct banks
+    float* xs = xs_all + 32 * wave * F2_XS;   // this wavefront's 32 rows
+    float* ts = xs;                           // T goes through the same rows first
+    const int row0 = 32 * wave;
+    const int rows = max(0, min(32, na - row0));
     // A operands of T = U_a Y: rows 32 w + 16 h + c of U_a, K = 4 s + q
     float ua[2][F2_RA / 4];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int st = 0; st < F2_RA / 4; ++st) {
-            const int row = 32 * wave + 16 * h + c, k = 4 * st + q;
+            const int row = row0 + 16 * h + c, k = 4 * st + q;
             ua[h][st] = (row < na && k < ra) ? Ua[(int64_t)row * ra + k] : 0.f;
         }
     // B operands of X = T U_b^T: B[k][col] = U_b[16 t + col][k], K = 4 s + q
@@ -635,11 +641,19 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_fused_last2(const float* __res
 #pragma unroll
             for (int h = 0; h < 2; ++h) tacc[h] = __builtin_amdgcn_mfma_f32_16x16x4f32(ua[h][st], yv[st], tacc[h], 0, 0, 0);
         load_y(l + gridDim.x);   // the next slab's loads in flight over the rest
+        // (LDS accesses of one wavefront take effect in issue order)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) ts[(32 * wave + 16 * h + 4 * q + e) * F2_TS + c] = tacc[h][e];
-        __syncthreads();
+            for (int e = 0; e < 4; ++e) ts[(16 * h + 4 * q + e) * F2_TS + c] = tacc[h][e];
+        __builtin_amdgcn_wave_barrier();
+        // T back as A operands (all of it before X overwrites the rows)
+        float tv[2][F2_RB / 4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int st = 0; st < F2_RB / 4; ++st) tv[h][st] = ts[(16 * h + c) * F2_TS + 4 * st + q];
+        __builtin_amdgcn_wave_barrier();
         // X rows 32 w + 16 h + (4 q + e), columns 16 t + c
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -647,35 +661,35 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_fused_last2(const float* __res
 #pragma unroll
             for (int t = 0; t < F2_NB / 16; ++t) xacc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int st = 0; st < F2_RB / 4; ++st) {
-                const float tv = ts[(32 * wave + 16 * h + c) * F2_TS + 4 * st + q];
+            for (int st = 0; st < F2_RB / 4; ++st)
 #pragma unroll
                 for (int t = 0; t < F2_NB / 16; ++t)
-                    xacc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tv, ub[t][st], xacc[t], 0, 0, 0);
-            }
+                    xacc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(tv[h][st], ub[t][st], xacc[t], 0, 0, 0);
 #pragma unroll
             for (int t = 0; t < F2_NB / 16; ++t)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int row = 32 * wave + 16 * h + 4 * q + e, col = 16 * t + c;
-                    if (row < na && col < nb) xs[row * xstride + col] = xacc[t][e];
+                    const int r = 16 * h + 4 * q + e, col = 16 * t + c;
+                    if (r < rows && col < nb) xs[r * F2_XS + col] = xacc[t][e];
                 }
         }
-        __syncthreads();
-        // the slab's n_a x n_b block, contiguous in X
-        float* xl = X + l * (int64_t)xsz;
+        __builtin_amdgcn_wave_barrier();
+        // this wavefront's rows of X[l]: rows * n_b consecutive floats
+        float* xl = X + l * (int64_t)xsz + (int64_t)row0 * nb;
+        const int wsz = rows * nb;
         if (vec) {
-            for (int e4 = 4 * tid; e4 < xsz; e4 += 4 * NTHREADS) {
-                const int row = e4 / nb, col = e4 - row * nb;
-                const float4 v = *reinterpret_cast<const float4*>(&xs[row * xstride + col]);
+            for (int e4 = 4 * lane; e4 < wsz; e4 += 256) {
+                const int r = e4 / nb, col = e4 - r * nb;
+                const float4 v = *reinterpret_cast<const float4*>(&xs[r * F2_XS + col]);
                 *reinterpret_cast<float4*>(xl + e4) = v;
             }
         } else {
-            for (int e = tid; e < xsz; e += NTHREADS) {
-                const int row = e / nb, col = e - row * nb;
-                xl[e] = xs[row * xstride + col];
+            for (int e = lane; e < wsz; e += 64) {
+                const int r = e / nb, col = e - r * nb;
+                xl[e] = xs[r * F2_XS + col];
             }
         }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
