@@ -592,7 +592,8 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
                 // mode on, the rank slot holds 0 and the product writes nothing
                 const TtmPlan tp = ttm_plan(prec, L, n, R, S32_RANKS - SUBSPACE_GUARD);
                 HIP_TRY(mark(i, 3));
-                HIP_TRY(launch_ttm(prec, tp, src, M, w.Mth, w.Mtl, dst, st, &w.book->rank[k]));
+                HIP_TRY(launch_ttm(prec, tp, src, M, w.Mth, w.Mtl, dst, st, &w.book->rank[k], (float*)w.part,
+                                   w.part_cap));
                 HIP_TRY(mark(i, 4));
                 queued = true;
             } else if (attempt == 1 && subspace32_available(n)) {
@@ -674,7 +675,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
             if (split_yq) {
                 const TtmPlan tw = ttm_plan(prec, L, S32_RANKS, R, S32_RANKS - SUBSPACE_GUARD);
                 HIP_TRY(launch_ttm(prec, tw, split_yq, f64 ? (const void*)w.wt.Wt64 : (const void*)w.wt.Wt32,
-                                   split_sr.Wth, split_sr.Wtl, dst, st, &w.book->rank[k]));
+                                   split_sr.Wth, split_sr.Wtl, dst, st, &w.book->rank[k], (float*)w.part, w.part_cap));
                 HIP_TRY(mark(i, 4));
                 queued = true;
             }
@@ -695,7 +696,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         }
         const TtmPlan tp = ttm_plan(prec, L, n, R, r);
         HIP_TRY(mark(i, 3));
-        HIP_TRY(launch_ttm(prec, tp, src, M, w.Mth, w.Mtl, dst, st));
+        HIP_TRY(launch_ttm(prec, tp, src, M, w.Mth, w.Mtl, dst, st, nullptr, (float*)w.part, w.part_cap));
         HIP_TRY(mark(i, 4));
         src = dst;
     }

@@ -188,8 +188,12 @@ struct TtmPlan {
 TtmPlan ttm_plan(int prec, int64_t L, int n, int64_t R, int m_out);
 // m_dev (optional): the output rows are min(t.m_out, *m_dev), read on the
 // device (a rank chosen by a kernel earlier on the stream); none when < 1.
+// kpart (optional, kpart_bytes of device scratch): lets a product over few
+// output tiles and a long mode split its K range across workgroups into
+// partial outputs that a second kernel sums in a fixed order.
 hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, const void* Mh,
-                      const void* Ml, void* Z, hipStream_t st, const int32_t* m_dev = nullptr);
+                      const void* Ml, void* Z, hipStream_t st, const int32_t* m_dev = nullptr,
+                      float* kpart = nullptr, size_t kpart_bytes = 0);
 // The last two mode products of a reconstruction in one pass (float32): Y is
 // (L, r_a, r_b) row-major, U_a n_a x r_a and U_b n_b x r_b (the factors as
 // given), X (L, n_a, n_b) = Y x_a U_a x_b U_b.  For r_a <= 32, r_b <= 16,

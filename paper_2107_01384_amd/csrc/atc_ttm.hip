@@ -217,10 +217,15 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm(const typename ElemOf<P>::T* _
 template <int P, int MT>
 __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__ Y, int64_t L, int n, int64_t R,
                                                        int m_out, int64_t tpl, int pl, const float* __restrict__ M32,
-                                                       float* __restrict__ Z, const int32_t* __restrict__ m_dev) {
+                                                       float* __restrict__ Z, const int32_t* __restrict__ m_dev,
+                                                       int kchunk) {
     constexpr int W = 256, BK = 32, MR = 16 * MT;
     if (m_dev) m_out = min(m_out, *m_dev);  // the rank chosen on the device
     if (m_out < 1) return;
+    // split K (gridDim.y > 1): slice blockIdx.y of K (kchunk terms, a multiple
+    // of BK) into its own partial output, Z + blockIdx.y * L m_out R
+    const int k_lo = (int)blockIdx.y * kchunk, k_hi = min(n, k_lo + kchunk);
+    Z += (int64_t)blockIdx.y * L * m_out * R;
     constexpr int YP = (P == PREC_BF16X3) ? BK : BK + 4;  // row of a staged column
     // bf16 columns staged without padding (37 KB of LDS: four workgroups per
     // CU): the 16-byte chunk c of row r sits at c ^ ((r >> 1) ^ (r >> 3)) & 3,
@@ -254,8 +259,8 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int i = i0 + 8 * rg + e;
-            yv[e] = (colok && i < n) ? *reinterpret_cast<const float4*>(ybase + (int64_t)i * R)
-                                     : float4{0.f, 0.f, 0.f, 0.f};
+            yv[e] = (colok && i < k_hi) ? *reinterpret_cast<const float4*>(ybase + (int64_t)i * R)
+                                        : float4{0.f, 0.f, 0.f, 0.f};
         }
         // M: MR rows x 32 k, eight consecutive k per (thread, row block)
 #pragma unroll
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int i = i0 + kq + e;
-                mv[q][e] = (idx < MR * 4 && mr < m_out && i < n) ? M32[(int64_t)mr * n + i] : 0.f;
+                mv[q][e] = (idx < MR * 4 && mr < m_out && i < k_hi) ? M32[(int64_t)mr * n + i] : 0.f;
             }
         }
     };
@@ -349,12 +354,12 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_wide(const float* __restrict__
     for (int a = 0; a < MT; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    load(0);
-    for (int i0 = 0; i0 < n; i0 += BK) {
+    load(k_lo);
+    for (int i0 = k_lo; i0 < k_hi; i0 += BK) {
         __syncthreads();
         stage();
         __syncthreads();
-        if (i0 + BK < n) load(i0 + BK);
+        if (i0 + BK < k_hi) load(i0 + BK);
         if constexpr (P == PREC_BF16X3) {
             const int kq = 8 * (lane >> 4);
             bf16x8 bh[4], bl[4];
@@ -573,6 +578,21 @@ __global__ __launch_bounds__(NTHREADS) void k_ttm_expand_last(const float* __res
             }
         }
         __syncthreads();
+    }
+}
+
+// Z = sum over the ks partial outputs of a split-K mode product, in split
+// order (rows min(m_out, *m_dev) of the device-side rank, as the product).
+__global__ __launch_bounds__(NTHREADS) void k_ttm_ksum(const float* __restrict__ part, int ks, int64_t L, int m_out,
+                                                       int64_t R, const int32_t* __restrict__ m_dev,
+                                                       float* __restrict__ Z) {
+    if (m_dev) m_out = min(m_out, *m_dev);
+    if (m_out < 1) return;
+    const int64_t total = L * m_out * R;
+    for (int64_t i = (int64_t)blockIdx.x * NTHREADS + threadIdx.x; i < total; i += (int64_t)gridDim.x * NTHREADS) {
+        float s = part[i];
+        for (int k = 1; k < ks; ++k) s += part[(int64_t)k * total + i];
+        Z[i] = s;
     }
 }
 
@@ -856,25 +876,41 @@ hipError_t launch_ttm_fused_last2(const float* Y, int64_t L, int ra, int rb, int
 }
 
 hipError_t launch_ttm(int prec, const TtmPlan& t, const void* Y, const void* M, const void* Mh, const void* Ml,
-                      void* Z, hipStream_t st, const int32_t* m_dev) {
+                      void* Z, hipStream_t st, const int32_t* m_dev, float* kpart, size_t kpart_bytes) {
     if (prec != PREC_F64 && t.layout == LAYOUT_KC && t.R >= 32 && t.R % 4 == 0 && t.m_out <= 64 &&
         reinterpret_cast<uintptr_t>(Y) % 16 == 0) {
         // R >= 256: 256-column chunks of one slice; R < 256: 256 / R whole slices per workgroup
         const int pl = t.R >= 256 ? 1 : (int)(256 / t.R);
         const int64_t tpl = t.R >= 256 ? ceil_div(t.R, (int64_t)256) : 1;
-        const dim3 grid((unsigned)(pl > 1 ? ceil_div(t.L, (int64_t)pl) : t.L * tpl));
+        const int64_t tiles = pl > 1 ? ceil_div(t.L, (int64_t)pl) : t.L * tpl;
+        // few tiles over a long K: K split over grid.y into partial outputs,
+        // summed in split order by k_ttm_ksum (each workgroup otherwise walks
+        // all of K, one memory latency per 32 terms)
+        int ks = 1;
+        if (kpart && tiles < 128 && t.n >= 256) {
+            ks = (int)std::min<int64_t>(8, std::max<int64_t>(1, 256 / tiles));
+            while (ks > 1 && (size_t)ks * t.L * t.m_out * t.R * sizeof(float) > kpart_bytes) --ks;
+        }
+        const int kchunk = (int)(ceil_div(ceil_div((int64_t)t.n, (int64_t)ks), (int64_t)32) * 32);
+        ks = (int)ceil_div((int64_t)t.n, (int64_t)kchunk);
+        const dim3 grid((unsigned)tiles, (unsigned)ks);
         const float* y = (const float*)Y;
         const float* m = (const float*)M;
-        float* z = (float*)Z;
+        float* z = ks > 1 ? kpart : (float*)Z;
         if (prec == PREC_BF16X3) {
-            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 2>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
-            else hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 4>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
+            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 2>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev, kchunk);
+            else hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X3, 4>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev, kchunk);
         } else if (prec == PREC_BF16X6) {
-            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X6, 2>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
-            else hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X6, 4>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
+            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X6, 2>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev, kchunk);
+            else hipLaunchKernelGGL((k_ttm_wide<PREC_BF16X6, 4>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev, kchunk);
         } else {
-            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 2>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
-            else hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 4>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev);
+            if (t.m_out <= 32) hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 2>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev, kchunk);
+            else hipLaunchKernelGGL((k_ttm_wide<PREC_F32, 4>), grid, dim3(NTHREADS), 0, st, y, t.L, t.n, t.R, t.m_out, tpl, pl, m, z, m_dev, kchunk);
+        }
+        if (ks > 1) {
+            const unsigned g = (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, ceil_div(t.L * t.m_out * t.R, (int64_t)1024)));
+            hipLaunchKernelGGL(k_ttm_ksum, dim3(g), dim3(NTHREADS), 0, st, (const float*)kpart, ks, t.L, t.m_out, t.R, m_dev,
+                               (float*)Z);
         }
         return hipGetLastError();
     }
