@@ -114,7 +114,21 @@ typedef struct {
      * Nonzero turns the guard off.  atc_result.gram_prec reports what each
      * mode used. */
     int32_t no_precision_guard;
-    int32_t reserved[4];
+    /* Nonzero (needs has_fixed_ranks, profile = 0): every step is enqueued on
+     * `stream` with no host wait and no host-side decision from device
+     * results, so the call can be captured in a HIP graph.  The eigensolver of
+     * each mode is picked from its fixed rank (n <= 64, FP64 data or
+     * eig_path 1: dense; r <= 24: the m = 32 subspace path; r <= 56: m = 64;
+     * else the dense solver in global memory), all as ordinary launches (no
+     * cooperative grid).  atc_result gets the ranks, order, paths and Gram
+     * precisions only; atc_sthosvd_finish reads the rest and the status once
+     * the stream has run.  A subspace mode whose data has fewer than r_k
+     * positive Ritz values is reported by atc_sthosvd_finish, not handed on
+     * to the dense solver.  The host-side state of the library (the report
+     * block, the per-device flags) is set up by the first call of a process:
+     * make one ordinary call before capturing. */
+    int32_t no_host_wait;
+    int32_t reserved[3];
 } atc_sthosvd_opts;
 
 /* Host-side record of one ST-HOSVD call. */
@@ -168,6 +182,18 @@ size_t atc_sthosvd_workspace_size(const atc_shape* shape, const atc_sthosvd_opts
 atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_opts* opts,
                        void* core, void* const* factors, atc_result* result,
                        void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * After an opts.no_host_wait call (or the replay of a graph that captured
+ * one): waits for `stream`, reads the call's device record from `workspace`
+ * (the same buffer, shape and opts) and fills result's norm2, sse_pred, tail,
+ * budget and eig_sweeps.  Returns the call's status: ATC_ERR_NONFINITE_INPUT,
+ * ATC_ERR_NOT_CONVERGED (an eigensolver hit max_sweeps), ATC_ERR_INTERNAL (a
+ * fixed rank left the subspace fewer than 8 unused Ritz pairs, or a Ritz value
+ * at the rank was not positive), else ATC_OK.
+ */
+atc_status atc_sthosvd_finish(const atc_shape* shape, const atc_sthosvd_opts* opts, const void* workspace,
+                              size_t workspace_bytes, atc_result* result, void* stream);
 
 /* ---------------------------------------------------------------- batched */
 

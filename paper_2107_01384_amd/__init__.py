@@ -53,7 +53,8 @@ class Opts(ctypes.Structure):
         ("rank_rule", ctypes.c_int32), ("has_order", ctypes.c_int32), ("mode_order", ctypes.c_int32 * MAX_DIMS),
         ("has_fixed_ranks", ctypes.c_int32), ("fixed_ranks", ctypes.c_int32 * MAX_DIMS),
         ("max_sweeps", ctypes.c_int32), ("eig_path", ctypes.c_int32), ("profile", ctypes.c_int32),
-        ("no_precision_guard", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4),
+        ("no_precision_guard", ctypes.c_int32), ("no_host_wait", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -102,6 +103,7 @@ SIGNATURES = [
     ("atc_default_opts", None, [_P(Opts)]),
     ("atc_sthosvd_workspace_size", _SZ, [_P(Shape), _P(Opts)]),
     ("atc_sthosvd", _I32, [_VP, _P(Shape), _P(Opts), _VP, _P(_VP), _P(Result), _VP, _SZ, _VP]),
+    ("atc_sthosvd_finish", _I32, [_P(Shape), _P(Opts), _VP, _SZ, _P(Result), _VP]),
     ("atc_batch_plan_create", _I32, [_P(_I32), _P(_I64), _I64, _P(Opts), _P(_VP)]),
     ("atc_batch_plan_destroy", None, [_VP]),
     ("atc_batch_plan_info", _I32, [_VP, _P(_I64), _P(_I64), _P(_I64), _P(_SZ)]),
@@ -200,7 +202,7 @@ def _shape(dims: Sequence[int], dtype: torch.dtype) -> Shape:
 
 def make_opts(rel_error: float = 1e-3, precision: str = "native", order=None, rtmss: float = 1.0,
               rule: str = "adaptive", fixed_ranks=None, max_sweeps: int = 0, eig_path: int = 0,
-              profile: bool = False, precision_guard: bool = True) -> Opts:
+              profile: bool = False, precision_guard: bool = True, no_host_wait: bool = False) -> Opts:
     o = Opts()
     load().atc_default_opts(ctypes.byref(o))
     o.rel_error = float(rel_error)
@@ -219,6 +221,7 @@ def make_opts(rel_error: float = 1e-3, precision: str = "native", order=None, rt
     o.eig_path = int(eig_path)
     o.profile = 1 if profile else 0
     o.no_precision_guard = 0 if precision_guard else 1
+    o.no_host_wait = 1 if no_host_wait else 0
     return o
 
 
@@ -251,16 +254,19 @@ def sthosvd_workspace_size(dims, dtype=torch.float32, **opt_kw) -> int:
 def sthosvd(x: torch.Tensor, rel_error: float = 1e-3, precision: str = "native", order=None, rtmss: float = 1.0,
             rule: str = "adaptive", fixed_ranks=None, max_sweeps: int = 0, eig_path: int = 0,
             workspace: Optional[torch.Tensor] = None, stream=None, profile: bool = False,
-            out: Optional[tuple] = None, precision_guard: bool = True) -> Tucker:
+            out: Optional[tuple] = None, precision_guard: bool = True, no_host_wait: bool = False) -> Tucker:
     """ST-HOSVD of x (GPU tensor) to relative error rel_error; see atc_sthosvd in include/atc.h.
     The ranks and figures of the result are final on return; core and factors
-    are written in the order of `stream` (torch's current stream by default)."""
+    are written in the order of `stream` (torch's current stream by default).
+    With no_host_wait (fixed_ranks required) nothing waits for the device, so
+    the call can be captured in a graph: norm2, sse_pred, tails, budgets and
+    eig_sweeps are then zero until sthosvd_finish reads them."""
     lib = load()
     _require_gpu(x, "x")
     dims = list(x.shape)
     s = _shape(dims, x.dtype)
     o = make_opts(rel_error, precision, order, rtmss, rule, fixed_ranks, max_sweeps, eig_path, profile,
-                  precision_guard)
+                  precision_guard, no_host_wait)
     need = lib.atc_sthosvd_workspace_size(ctypes.byref(s), ctypes.byref(o))
     if need == 0:
         _check(-1)
@@ -292,6 +298,26 @@ def sthosvd(x: torch.Tensor, rel_error: float = 1e-3, precision: str = "native",
         phase_ms={name: [float(getattr(res, name + "_ms")[k]) for k in range(d)]
                   for name in ("gram", "reduce", "eig", "ttm")},
         gram_prec=[_PREC_NAMES[int(res.gram_prec[k])] for k in range(d)])
+
+
+def sthosvd_finish(dims, dtype, workspace: torch.Tensor, stream=None, **opt_kw) -> dict:
+    """Waits for `stream` after a no_host_wait call (or a graph replay of one)
+    made with `workspace` and the same options, and returns the figures that
+    call left on the device; raises on the status it recorded.  See
+    atc_sthosvd_finish."""
+    lib = load()
+    if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda:
+        raise ValueError("workspace must be a GPU tensor")
+    d = len(dims)
+    s = _shape(dims, dtype)
+    o = make_opts(**opt_kw, no_host_wait=True)
+    res = Result()
+    _check(lib.atc_sthosvd_finish(ctypes.byref(s), ctypes.byref(o), ctypes.c_void_p(workspace.data_ptr()),
+                                  workspace.numel() * workspace.element_size(), ctypes.byref(res),
+                                  ctypes.c_void_p(_stream(stream))))
+    return dict(norm2=float(res.norm2), sse_pred=float(res.sse_pred), tails=[float(res.tail[k]) for k in range(d)],
+                budgets=[float(res.budget[k]) for k in range(d)],
+                eig_sweeps=[int(res.eig_sweeps[k]) for k in range(d)])
 
 
 # ----------------------------------------------------------------- reconstruction

@@ -105,6 +105,8 @@ atc_status check_opts(const atc_shape* s, const atc_sthosvd_opts* o) {
     }
     for (int k = 0; k < s->ndim; ++k)
         if (s->dims[k] > MAX_MODE) return fail(ATC_ERR_UNSUPPORTED, "mode %d longer than %d", k, MAX_MODE);
+    if (o->no_host_wait && (!o->has_fixed_ranks || o->profile))
+        return fail(ATC_ERR_INVALID_ARGUMENT, "no_host_wait needs fixed ranks and no profiling");
     return ATC_OK;
 }
 
@@ -379,6 +381,15 @@ hipError_t wait_selection(const volatile HostFlags* f, int32_t expect, hipStream
     }
 }
 
+// No-host-wait calls: the outcome of one mode's eigensolver and rank choice
+// folded into the book's status (the first failure stays).
+__global__ void k_book_check(DevBook* bk) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (bk->status != 0) return;
+    if (bk->need_dense) bk->status = ATC_ERR_INTERNAL;
+    else if (!bk->eig_ok) bk->status = ATC_ERR_NOT_CONVERGED;
+}
+
 double event_ms(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.0;
@@ -435,7 +446,9 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
     auto mark = [&](int i, int j) -> hipError_t { return prof ? hipEventRecord(g_phase.ev[i][j], st) : hipSuccess; };
 
     if (prof) g_timer.start(st);
-    HIP_TRY(hipMemsetAsync(w.book, 0, sizeof(DevBook), st));
+    const bool nowait = opts->no_host_wait != 0;
+    // cleared by a kernel (a memset node misbehaves in captured graphs)
+    HIP_TRY(launch_zero(w.book, sizeof(DevBook), st));
     int64_t cur[ATC_MAX_DIMS];
     for (int k = 0; k < d; ++k) cur[k] = shape->dims[k];
     const void* src = x;
@@ -522,6 +535,49 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         // FP32-grade Gram matrix carries, not to FP64) unless eig_path forces it.
         const int32_t zero = 0;
         const bool dense_first = n <= 64 || opts->eig_path == 1 || (f64 && opts->eig_path != 2);
+        if (nowait) {
+            // the eigensolver from the fixed rank, ordinary launches only; the
+            // outcome goes to the book's status (atc_sthosvd_finish reads it)
+            const int r = opts->fixed_ranks[k];
+            sa.seq = ++g_flags.seq;
+            void* const dst_nw = (i == d - 1) ? core : (src == w.buf[0] ? w.buf[1] : w.buf[0]);
+            if (!dense_first && r <= S32_RANKS - SUBSPACE_GUARD && subspace32_available(n)) {
+                sa.ldv = 32;
+                sa.ncand = 32;
+                sa.subspace = 1;
+                paths[k] = 2;
+                HIP_TRY(run_subspace32_select(w.G, n, SUBSPACE_ITERS, max_sweeps, w.sub, sa, st, false));
+            } else if (!dense_first && r <= SUBSPACE_M - SUBSPACE_GUARD && subspace32_available(n)) {
+                sa.ldv = 64;
+                sa.ncand = 64;
+                sa.subspace = 1;
+                sa.lam = w.lam;
+                sa.V = w.V;
+                paths[k] = 2;
+                HIP_TRY(run_subspace64_select(w.G, n, max_sweeps, w.sub, w.lam, w.V, sweeps_dev, ok_dev, sa, st,
+                                              false));
+            } else {
+                if (n <= 64) HIP_TRY(launch_eig_jacobi_lds(w.G, n, n, max_sweeps, w.lam, w.V, n, sweeps_dev, ok_dev, st));
+                else HIP_TRY(launch_eig_jacobi_global(w.G, n, max_sweeps, w.jac, w.lam, w.V, sweeps_dev, ok_dev, st));
+                sa.ldv = n;
+                sa.ncand = n;
+                sa.subspace = 0;
+                paths[k] = 1;
+                HIP_TRY(launch_select_factor(sa, st));
+            }
+            hipLaunchKernelGGL(k_book_check, dim3(1), dim3(64), 0, st, w.book);
+            HIP_TRY(hipGetLastError());
+            cur[k] = r;
+            if (r == n && i + 1 < d) {
+                lazy[nlazy++] = k;   // rotated on the final core, as below
+                continue;
+            }
+            const TtmPlan tp = ttm_plan(prec, L, n, R, r);
+            HIP_TRY(launch_ttm(prec, tp, src, f64 ? (const void*)w.Mt64 : (const void*)w.Mt32, w.Mth, w.Mtl, dst_nw,
+                               st, nullptr, (float*)w.part, w.part_cap));
+            src = dst_nw;
+            continue;
+        }
         // a mode after one whose rank needed the m = 64 subspace starts there
         // (ranks of neighbouring modes tend to be alike; m = 64 is never less
         // accurate, only slower when m = 32 would have done)
@@ -750,6 +806,40 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         result->elapsed_ms = ms;
     }
     return ATC_OK;
+}
+
+atc_status atc_sthosvd_finish(const atc_shape* shape, const atc_sthosvd_opts* opts, const void* workspace,
+                              size_t workspace_bytes, atc_result* result, void* stream) {
+    atc_status s;
+    if ((s = check_shape(shape)) != ATC_OK) return s;
+    if ((s = check_opts(shape, opts)) != ATC_OK) return s;
+    if (!opts->no_host_wait) return fail(ATC_ERR_INVALID_ARGUMENT, "atc_sthosvd_finish follows a no_host_wait call");
+    const size_t need = carve_sthosvd(shape, nullptr, nullptr);
+    if (!workspace || workspace_bytes < need)
+        return fail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
+    SthosvdWs w;
+    carve_sthosvd(shape, (char*)workspace, &w);
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    DevBook bk;
+    HIP_TRY(hipMemcpy(&bk, w.book, sizeof(bk), hipMemcpyDeviceToHost));
+    if (result) {
+        const int d = shape->ndim;
+        for (int k = 0; k < d; ++k) {
+            result->tail[k] = bk.tail[k];
+            result->budget[k] = bk.budget[k];
+            result->eig_sweeps[k] = bk.sweeps[k];
+        }
+        result->norm2 = bk.norm2;
+        result->sse_pred = bk.used;
+    }
+    switch (bk.status) {
+        case 0: return ATC_OK;
+        case ATC_ERR_NONFINITE_INPUT: return fail(ATC_ERR_NONFINITE_INPUT, "input |A|^2 is not finite");
+        case ATC_ERR_NOT_CONVERGED: return fail(ATC_ERR_NOT_CONVERGED, "an eigensolver hit its sweep cap");
+        default:
+            return fail((atc_status)bk.status,
+                        "a fixed rank the chosen eigensolver could not serve (or a grid wait gave up)");
+    }
 }
 
 // ------------------------------------------------------------ reconstruction

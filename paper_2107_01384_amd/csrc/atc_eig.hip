@@ -2405,7 +2405,7 @@ Sub32Grid sub32_grid_args(double* ws, int n, const SelectArgs& sa) {
 }  // namespace
 
 hipError_t run_subspace32_select(const double* G, int n, int iters, int max_sweeps, double* ws, const SelectArgs& sa,
-                                 hipStream_t st) {
+                                 hipStream_t st, bool allow_coop) {
     if (!subspace32_available(n)) return hipErrorInvalidValue;
     if (sa.ncand != S32 || sa.ldv != S32 || !sa.subspace) return hipErrorInvalidValue;
     double* P1 = ws;                   // n x 32
@@ -2413,7 +2413,7 @@ hipError_t run_subspace32_select(const double* G, int n, int iters, int max_swee
     int32_t* ok = reinterpret_cast<int32_t*>(P2 + (size_t)n * S32);
     const int steps = iters < 1 ? 1 : iters;
     hipError_t e;
-    if (sub32_grid_ready()) {
+    if (allow_coop && sub32_grid_ready()) {
         Sub32Grid g = sub32_grid_args(ws, n, sa);
         const int nb = (int)ceil_div(n, GRID_ROWS);
         int n_ = n, steps_ = steps, sweeps_ = max_sweeps;
@@ -2486,7 +2486,7 @@ size_t subspace64b_ws_doubles(int n) {
 }
 
 hipError_t run_subspace64_select(const double* G, int n, int max_sweeps, double* ws, double* lam, double* V,
-                                 int32_t* sweeps_dev, int32_t* ok_dev, const SelectArgs& sa, hipStream_t st) {
+                                 int32_t* sweeps_dev, int32_t* ok_dev, const SelectArgs& sa, hipStream_t st, bool allow_coop) {
     if (!subspace32_available(n) || !sub64_ready()) return hipErrorInvalidValue;
     if (sa.ncand != 64 || sa.ldv != 64 || !sa.subspace) return hipErrorInvalidValue;
     double* Pa = ws;
@@ -2500,7 +2500,7 @@ hipError_t run_subspace64_select(const double* G, int n, int max_sweeps, double*
     const dim3 gb(64 * GX_SPLIT);
     hipError_t e;
     bool prepared = false;
-    if (sub64_grid_ready()) {
+    if (allow_coop && sub64_grid_ready()) {
         Sub32Grid g;
         g.P1 = nullptr;
         g.P2 = nullptr;

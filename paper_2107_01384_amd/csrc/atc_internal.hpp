@@ -299,7 +299,7 @@ hipError_t run_subspace32_basis(const double* G, int n, int iters, double* ws, c
 hipError_t run_rr32_select(int n, int iters, int max_sweeps, double* ws, const SelectArgs& sa, hipStream_t st);
 const int32_t* split_rows_dev(const double* ws, int n);
 hipError_t run_subspace32_select(const double* G, int n, int iters, int max_sweeps, double* ws, const SelectArgs& sa,
-                                 hipStream_t st);
+                                 hipStream_t st, bool allow_coop = true);
 // m = 64 for 64 <= n <= 512 from the m = 32 kernels: the block as two
 // orthonormalised 32-column halves, the 64 x 64 Rayleigh-Ritz problem on the
 // LDS Jacobi, then launch_select_factor (sa: ncand = ldv = 64, subspace = 1,
@@ -307,7 +307,8 @@ hipError_t run_subspace32_select(const double* G, int n, int iters, int max_swee
 // subspace64b_ws_doubles(n) doubles.
 size_t subspace64b_ws_doubles(int n);
 hipError_t run_subspace64_select(const double* G, int n, int max_sweeps, double* ws, double* lam, double* V,
-                                 int32_t* sweeps_dev, int32_t* ok_dev, const SelectArgs& sa, hipStream_t st);
+                                 int32_t* sweeps_dev, int32_t* ok_dev, const SelectArgs& sa, hipStream_t st,
+                                 bool allow_coop = true);
 
 // Prepares the mode-product matrix for reconstruction: M = U (n x r, dtype)
 // converted to FP64 / FP32 / bf16 hi-lo.  transpose != 0 gives U^T (r x n).

@@ -74,7 +74,8 @@ def test_argument_validation_without_device():
         assert lib.atc_sthosvd(ctypes.c_void_p(1), ctypes.byref(bad), ctypes.byref(o), ctypes.c_void_p(1), facs,
                                None, ctypes.c_void_p(1), ws, null) == -1
     for kw in ({"rel_error": -1.0}, {"rtmss": 1.5}, {"order": [0, 0, 1]}, {"fixed_ranks": [5, 1, 1]},
-               {"max_sweeps": -3}, {"eig_path": 3}):
+               {"max_sweeps": -3}, {"eig_path": 3}, {"no_host_wait": True},
+               {"no_host_wait": True, "fixed_ranks": [2, 2, 2], "profile": True}):
         args = {"rel_error": 1e-3}
         args.update(kw)
         ob = atc.make_opts(**args)
@@ -85,6 +86,14 @@ def test_argument_validation_without_device():
     assert lib.atc_sthosvd(ctypes.c_void_p(1), ctypes.byref(_shape([4, 5], 1)), ctypes.byref(o3), ctypes.c_void_p(1),
                            facs, None, ctypes.c_void_p(1), ws, null) == -2
     assert lib.atc_sthosvd_workspace_size(ctypes.byref(_shape([5000, 2])), ctypes.byref(o)) == 0
+    # atc_sthosvd_finish: only after a no-host-wait call, with the same workspace size
+    res = atc.Result()
+    assert lib.atc_sthosvd_finish(ctypes.byref(s), ctypes.byref(o), ctypes.c_void_p(1), ws, ctypes.byref(res),
+                                  null) == -1
+    onw = atc.make_opts(1e-3, fixed_ranks=[2, 2, 2], no_host_wait=True)
+    assert lib.atc_sthosvd_workspace_size(ctypes.byref(s), ctypes.byref(onw)) == ws
+    assert lib.atc_sthosvd_finish(ctypes.byref(s), ctypes.byref(onw), ctypes.c_void_p(1), ws - 1,
+                                  ctypes.byref(res), null) == -3
     # reconstruction: ranks outside [1, n]
     ra = (ctypes.c_int64 * 8)(3, 6, 2)
     assert lib.atc_reconstruct_workspace_size(ctypes.byref(s), ra) == 0
