@@ -119,8 +119,9 @@ typedef struct {
      * results, so the call can be captured in a HIP graph.  The eigensolver of
      * each mode is picked from its fixed rank (n <= 64, FP64 data or
      * eig_path 1: dense; r <= 24: the m = 32 subspace path; r <= 56: m = 64;
-     * else the dense solver in global memory), all as ordinary launches (no
-     * cooperative grid).  atc_result gets the ranks, order, paths and Gram
+     * else the dense solver in global memory); on a capturing stream the
+     * subspace solvers run as kernel chains (a cooperative launch is not
+     * recorded into a graph), otherwise in their one-launch form.  atc_result gets the ranks, order, paths and Gram
      * precisions only; atc_sthosvd_finish reads the rest and the status once
      * the stream has run.  A subspace mode whose data has fewer than r_k
      * positive Ritz values is reported by atc_sthosvd_finish, not handed on

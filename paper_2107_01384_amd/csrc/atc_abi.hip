@@ -447,6 +447,14 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
 
     if (prof) g_timer.start(st);
     const bool nowait = opts->no_host_wait != 0;
+    // a cooperative launch is not recorded into a graph: under capture the
+    // eigensolvers run as kernel chains, otherwise in their one-launch form
+    bool coop_ok = true;
+    if (nowait) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIP_TRY(hipStreamIsCapturing(st, &cs));
+        coop_ok = cs == hipStreamCaptureStatusNone;
+    }
     // cleared by a kernel (a memset node misbehaves in captured graphs)
     HIP_TRY(launch_zero(w.book, sizeof(DevBook), st));
     int64_t cur[ATC_MAX_DIMS];
@@ -541,12 +549,56 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
             const int r = opts->fixed_ranks[k];
             sa.seq = ++g_flags.seq;
             void* const dst_nw = (i == d - 1) ? core : (src == w.buf[0] ? w.buf[1] : w.buf[0]);
+            // the split form of the m = 32 solver, as below, with the rotation
+            // queued at once (its rows come from the device-side rank, 0 when
+            // the selection failed, which the record's status reports)
+            const size_t esz_nw = f64 ? 8 : 4;
+            const size_t qoff_nw = ((size_t)L * (S32_RANKS - SUBSPACE_GUARD) * R * esz_nw + 255) & ~(size_t)255;
+            const bool split_nw = coop_ok && !dense_first && r <= S32_RANKS - SUBSPACE_GUARD && i + 1 < d &&
+                                  (size_t)L * n * R * esz_nw >= split_min_bytes() && (w.qt.t64 || w.qt.t32) &&
+                                  overlap_enabled() && dst_nw != core &&
+                                  qoff_nw + (size_t)L * S32_RANKS * R * esz_nw <=
+                                      (size_t)prod(shape->dims, 0, d) * esz_nw &&
+                                  subspace32_split_available(n);
+            SideQueue::Dev* sq_nw = split_nw ? g_side.get() : nullptr;
+            if (sq_nw) {
+                sa.ldv = 32;
+                sa.ncand = 32;
+                sa.subspace = 1;
+                paths[k] = 2;
+                HIP_TRY(run_subspace32_basis(w.G, n, SUBSPACE_ITERS, w.sub, sa, w.qt, st));
+                void* yq = (char*)dst_nw + qoff_nw;
+                const TtmPlan tq = ttm_plan(prec, L, n, R, S32_RANKS);
+                HIP_TRY(hipEventRecord(sq_nw->basis, st));
+                HIP_TRY(hipStreamWaitEvent(sq_nw->ttm, sq_nw->basis, 0));
+                HIP_TRY(launch_ttm(prec, tq, src, f64 ? (const void*)w.qt.t64 : (const void*)w.qt.t32, w.qt.th,
+                                   w.qt.tl, yq, sq_nw->ttm, split_rows_dev(w.sub, n)));
+                HIP_TRY(hipEventRecord(sq_nw->proj, sq_nw->ttm));
+                SelectArgs sr = sa;
+                sr.Wt64 = w.wt.Wt64;
+                sr.Wt32 = w.wt.Wt32;
+                sr.Wth = prec == PREC_BF16X3 ? w.wt.Wth : nullptr;
+                sr.Wtl = prec == PREC_BF16X3 ? w.wt.Wtl : nullptr;
+                sr.Mt64 = nullptr;
+                sr.Mt32 = nullptr;
+                sr.Mth = sr.Mtl = nullptr;
+                HIP_TRY(run_rr32_select(n, SUBSPACE_ITERS, max_sweeps, w.sub, sr, st));
+                hipLaunchKernelGGL(k_book_check, dim3(1), dim3(64), 0, st, w.book);
+                HIP_TRY(hipGetLastError());
+                HIP_TRY(hipStreamWaitEvent(st, sq_nw->proj, 0));
+                const TtmPlan tw = ttm_plan(prec, L, S32_RANKS, R, S32_RANKS - SUBSPACE_GUARD);
+                HIP_TRY(launch_ttm(prec, tw, yq, f64 ? (const void*)w.wt.Wt64 : (const void*)w.wt.Wt32, sr.Wth,
+                                   sr.Wtl, dst_nw, st, &w.book->rank[k], (float*)w.part, w.part_cap));
+                cur[k] = r;
+                src = dst_nw;
+                continue;
+            }
             if (!dense_first && r <= S32_RANKS - SUBSPACE_GUARD && subspace32_available(n)) {
                 sa.ldv = 32;
                 sa.ncand = 32;
                 sa.subspace = 1;
                 paths[k] = 2;
-                HIP_TRY(run_subspace32_select(w.G, n, SUBSPACE_ITERS, max_sweeps, w.sub, sa, st, false));
+                HIP_TRY(run_subspace32_select(w.G, n, SUBSPACE_ITERS, max_sweeps, w.sub, sa, st, coop_ok));
             } else if (!dense_first && r <= SUBSPACE_M - SUBSPACE_GUARD && subspace32_available(n)) {
                 sa.ldv = 64;
                 sa.ncand = 64;
@@ -555,7 +607,7 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
                 sa.V = w.V;
                 paths[k] = 2;
                 HIP_TRY(run_subspace64_select(w.G, n, max_sweeps, w.sub, w.lam, w.V, sweeps_dev, ok_dev, sa, st,
-                                              false));
+                                              coop_ok));
             } else {
                 if (n <= 64) HIP_TRY(launch_eig_jacobi_lds(w.G, n, n, max_sweeps, w.lam, w.V, n, sweeps_dev, ok_dev, st));
                 else HIP_TRY(launch_eig_jacobi_global(w.G, n, max_sweeps, w.jac, w.lam, w.V, sweeps_dev, ok_dev, st));

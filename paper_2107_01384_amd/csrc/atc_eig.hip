@@ -2080,9 +2080,10 @@ __global__ __launch_bounds__(RT) void k_sub32_grid(const double* __restrict__ G,
     grid_exit(g.sync);
 }
 
-// The cooperative path needs cooperative launches and its LDS; ATC_SUB32_KERNELS=1
-// in the environment (read at every call) selects the kernel-per-step path.
-bool sub32_grid_ready() {
+// The cooperative path needs cooperative launches and its LDS (checked once);
+// ATC_SUB32_KERNELS=1 in the environment (read at every call) selects the
+// kernel-per-step path.
+bool sub32_grid_supported() {
     static int state = 0;
     if (state == 0) {
         int dev = 0, coop = 0;
@@ -2092,9 +2093,15 @@ bool sub32_grid_ready() {
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)RR_LDS) == hipSuccess;
         state = (a && b) ? 1 : -1;
     }
-    const char* env = getenv("ATC_SUB32_KERNELS");
-    return state == 1 && !(env && env[0] == '1');
+    return state == 1;
 }
+
+bool kernel_chain_forced() {
+    const char* env = getenv("ATC_SUB32_KERNELS");
+    return env && env[0] == '1';
+}
+
+bool sub32_grid_ready() { return sub32_grid_supported() && !kernel_chain_forced(); }
 
 bool sub32_ready() {
     static int state = 0;
@@ -2365,13 +2372,12 @@ bool sub64_ready() {
 bool sub64_grid_ready() {
     static int state = 0;
     if (state == 0)
-        state = sub32_grid_ready() && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sub64_grid),
-                                                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                          (int)RR_LDS) == hipSuccess
+        state = sub32_grid_supported() && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sub64_grid),
+                                                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                              (int)RR_LDS) == hipSuccess
                     ? 1
                     : -1;
-    const char* env = getenv("ATC_SUB32_KERNELS");
-    return state == 1 && !(env && env[0] == '1');
+    return state == 1 && !kernel_chain_forced();
 }
 
 }  // namespace

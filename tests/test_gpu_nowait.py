@@ -2,16 +2,17 @@
 and its capture in a graph, through the C ABI.
 
 Bars:
-  * eager no-host-wait call vs the ordinary call with the same fixed ranks
-    (both with the eigensolvers as kernel chains and no split solver, so the
-    first mode's factor comes from the same launches): same ranks, tails and
-    |A|^2 to 1e-6 relative, kept subspaces within 1e-6, reconstructions
-    within 1e-5 of |X|;
+  * eager no-host-wait call (subspace solvers in their one-launch form) vs
+    the ordinary call with the same fixed ranks (kernel chains, no split
+    solver): same ranks, tails and |A|^2 to 1e-6 relative, kept subspaces
+    within 1e-6, reconstructions within 1e-5 of |X| (the two forms agree to
+    1e-7 in the kept subspaces on their own);
   * against the FP64 oracle at the same fixed ranks: predicted SSE within
     1e-5 |A|^2 + 1% of the oracle's, reconstruction within 1e-4 of |X|;
   * graph replays on changing inputs (eager library calls and synchronisations
     between them): core, factors and the figures read by atc_sthosvd_finish
-    equal bit for bit to the eager no-host-wait call on the same input.
+    equal bit for bit to the eager no-host-wait call on the same input (its
+    subspace solvers as kernel chains, the form a capture records).
 Inputs: known multilinear rank plus 1% noise, so every kept Ritz value is a
 signal eigenvalue well above rounding.  The ranks cover each eigensolver the
 fixed rank picks: r <= 24 (m = 32 subspace), 24 < r <= 56 (m = 64), r > 56
@@ -53,6 +54,20 @@ def _snapshot(t):
 
 @pytest.mark.parametrize("shape,ranks,precision,dtype", CASES)
 def test_no_host_wait_matches_ordinary_call_and_oracle(shape, ranks, precision, dtype, monkeypatch):
+    _check_against_ordinary_and_oracle(shape, ranks, precision, dtype, monkeypatch)
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "native"])
+def test_no_host_wait_split_solver(precision, monkeypatch):
+    """Mode 0 (n = 96, r = 12) is the second of three in increasing-length
+    order: with the size threshold at zero it takes the split m = 32 solver
+    (basis, the product by it on the second stream, the rotation queued with
+    the device-side rank) with no host wait in between."""
+    monkeypatch.setenv("ATC_SPLIT_MIN_BYTES", "0")
+    _check_against_ordinary_and_oracle((96, 80, 120), (12, 40, 100), precision, torch.float32, monkeypatch)
+
+
+def _check_against_ordinary_and_oracle(shape, ranks, precision, dtype, monkeypatch):
     x = _input(shape, ranks, 31)
     xd = to_dev(x, dtype)
     kw = dict(precision=precision, fixed_ranks=list(ranks))
@@ -87,7 +102,10 @@ def test_no_host_wait_matches_ordinary_call_and_oracle(shape, ranks, precision, 
 
 
 @pytest.mark.parametrize("shape,ranks,precision,dtype", CASES[:2])
-def test_no_host_wait_graph_replays(shape, ranks, precision, dtype):
+def test_no_host_wait_graph_replays(shape, ranks, precision, dtype, monkeypatch):
+    # under capture the subspace solvers run as kernel chains: the eager
+    # references take the same form
+    monkeypatch.setenv("ATC_SUB32_KERNELS", "1")
     kw = dict(precision=precision, fixed_ranks=list(ranks))
     need = atc.sthosvd_workspace_size(shape, dtype, no_host_wait=True, **kw)
     xs = [to_dev(_input(shape, ranks, s), dtype) for s in (41, 42)]
