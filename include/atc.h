@@ -120,8 +120,10 @@ typedef struct {
      * each mode is picked from its fixed rank (n <= 64, FP64 data or
      * eig_path 1: dense; r <= 24: the m = 32 subspace path; r <= 56: m = 64;
      * else the dense solver in global memory); on a capturing stream the
-     * subspace solvers run as kernel chains (a cooperative launch is not
-     * recorded into a graph), otherwise in their one-launch form.  atc_result gets the ranks, order, paths and Gram
+     * subspace solvers run as kernel chains (the library records no
+     * cooperative launch into a graph: the one-launch form's grid barriers
+     * need all of its workgroups resident at once), otherwise in their
+     * one-launch form.  atc_result gets the ranks, order, paths and Gram
      * precisions only; atc_sthosvd_finish reads the rest and the status once
      * the stream has run.  A subspace mode whose data has fewer than r_k
      * positive Ritz values is reported by atc_sthosvd_finish, not handed on

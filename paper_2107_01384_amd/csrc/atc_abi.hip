@@ -447,8 +447,9 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
 
     if (prof) g_timer.start(st);
     const bool nowait = opts->no_host_wait != 0;
-    // a cooperative launch is not recorded into a graph: under capture the
-    // eigensolvers run as kernel chains, otherwise in their one-launch form
+    // no cooperative launch goes into a graph (its grid barriers need every
+    // workgroup resident at once): under capture the eigensolvers run as
+    // kernel chains, otherwise in their one-launch form
     bool coop_ok = true;
     if (nowait) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
