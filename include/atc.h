@@ -28,7 +28,9 @@
  *  * Calls are re-entrant across host threads (each on its own stream with its
  *    own workspace).  atc_sthosvd returns only once the calling thread has
  *    learnt every rank, so one host thread runs its single-tensor calls one
- *    after another; the batched and reconstruction calls never wait.
+ *    after another, except those with opts.no_host_wait, which never wait
+ *    and write nothing to host memory; the batched and reconstruction calls
+ *    never wait.
  */
 #ifndef ATC_H_
 #define ATC_H_

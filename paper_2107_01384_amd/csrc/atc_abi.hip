@@ -532,7 +532,9 @@ atc_status atc_sthosvd(const void* x, const atc_shape* shape, const atc_sthosvd_
         sa.Mth = prec == PREC_BF16X3 ? w.Mth : nullptr;
         sa.Mtl = prec == PREC_BF16X3 ? w.Mtl : nullptr;
         sa.guard = SUBSPACE_GUARD;
-        sa.hflags = g_flags.d;
+        // a no-host-wait call reports nothing to the host: its kernels may
+        // still run while a later call of this thread waits on the report block
+        sa.hflags = nowait ? nullptr : g_flags.d;
         sa.publish_late = i == d - 1 ? 1 : 0;
         int32_t* sweeps_dev = &w.book->sweeps[k];
         int32_t* ok_dev = &w.book->eig_ok;

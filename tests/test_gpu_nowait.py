@@ -144,3 +144,49 @@ def test_no_host_wait_graph_replays(shape, ranks, precision, dtype, monkeypatch)
         # and torch kernels on the same stream
         atc.sthosvd(other, 1e-2, precision=precision)
         torch.cuda.synchronize()
+
+
+def test_no_host_wait_calls_overlap_on_streams(monkeypatch):
+    """One host thread queues two no-host-wait calls on two streams (both taking
+    the split m = 32 solver, which shares the thread's second stream) and then
+    an ordinary call on a third, with no synchronisation in between: every
+    result equals, bit for bit, the same call made alone."""
+    monkeypatch.setenv("ATC_SPLIT_MIN_BYTES", "0")
+    shape, ranks = (96, 80, 120), (12, 40, 100)
+    kw = dict(precision="bf16x3", fixed_ranks=list(ranks))
+    need = atc.sthosvd_workspace_size(shape, torch.float32, no_host_wait=True, **kw)
+    xs = [to_dev(_input(shape, ranks, s), torch.float32) for s in (51, 52, 53)]
+    bufs = [_buffers(shape, torch.float32, need) for _ in range(2)]
+
+    def nowait(j, stream=None):
+        ws, core, facs = bufs[j]
+        return atc.sthosvd(xs[j], workspace=ws, out=(core, facs), no_host_wait=True, stream=stream, **kw)
+
+    ref = []
+    for j in range(2):
+        t = nowait(j)
+        ref.append((_snapshot(t), atc.sthosvd_finish(shape, torch.float32, bufs[j][0], **kw)))
+    t3 = atc.sthosvd(xs[2], 1e-3, precision="bf16x3")
+    torch.cuda.synchronize()
+    ref3 = _snapshot(t3)
+    for j in range(2):
+        bufs[j][1].zero_()
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    for s in streams:
+        s.wait_stream(torch.cuda.current_stream())
+    log("overlapping calls", shape, ranks)
+    ts = [nowait(j, streams[j]) for j in range(2)]
+    o3 = atc.sthosvd(xs[2], 1e-3, precision="bf16x3")
+    figs = [atc.sthosvd_finish(shape, torch.float32, bufs[j][0], stream=streams[j], **kw) for j in range(2)]
+    torch.cuda.synchronize()
+    for j in range(2):
+        (c_ref, f_ref), fig_ref = ref[j]
+        assert torch.equal(ts[j].core, c_ref), j
+        for k in range(3):
+            assert torch.equal(ts[j].factors[k], f_ref[k]), (j, k)
+        assert figs[j] == fig_ref, j
+    assert o3.ranks == t3.ranks
+    assert torch.equal(o3.core, ref3[0])
+    for k in range(3):
+        assert torch.equal(o3.factors[k], ref3[1][k]), k
