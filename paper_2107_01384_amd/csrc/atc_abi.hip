@@ -107,6 +107,11 @@ atc_status check_opts(const atc_shape* s, const atc_sthosvd_opts* o) {
         if (s->dims[k] > MAX_MODE) return fail(ATC_ERR_UNSUPPORTED, "mode %d longer than %d", k, MAX_MODE);
     if (o->no_host_wait && (!o->has_fixed_ranks || o->profile))
         return fail(ATC_ERR_INVALID_ARGUMENT, "no_host_wait needs fixed ranks and no profiling");
+    if (o->no_host_wait && o->eig_path == 2)
+        for (int k = 0; k < s->ndim; ++k)
+            if (s->dims[k] > 64 && o->fixed_ranks[k] > SUBSPACE_M - SUBSPACE_GUARD)
+                return fail(ATC_ERR_UNSUPPORTED, "mode %d: rank needs more than %d Ritz pairs", k,
+                            SUBSPACE_M - SUBSPACE_GUARD);
     return ATC_OK;
 }
 

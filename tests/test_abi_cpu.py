@@ -90,6 +90,12 @@ def test_argument_validation_without_device():
     res = atc.Result()
     assert lib.atc_sthosvd_finish(ctypes.byref(s), ctypes.byref(o), ctypes.c_void_p(1), ws, ctypes.byref(res),
                                   null) == -1
+    # forced subspace path with a rank beyond its Ritz pairs: refused up front
+    big = _shape([100, 90, 80])
+    assert lib.atc_sthosvd_workspace_size(ctypes.byref(big), ctypes.byref(
+        atc.make_opts(1e-3, fixed_ranks=[57, 5, 5], eig_path=2, no_host_wait=True))) == 0
+    assert lib.atc_sthosvd_workspace_size(ctypes.byref(big), ctypes.byref(
+        atc.make_opts(1e-3, fixed_ranks=[56, 5, 5], eig_path=2, no_host_wait=True))) > 0
     onw = atc.make_opts(1e-3, fixed_ranks=[2, 2, 2], no_host_wait=True)
     assert lib.atc_sthosvd_workspace_size(ctypes.byref(s), ctypes.byref(onw)) == ws
     assert lib.atc_sthosvd_finish(ctypes.byref(s), ctypes.byref(onw), ctypes.c_void_p(1), ws - 1,
