@@ -25,6 +25,15 @@
  *    hold unspecified values).  atc_last_error() returns a thread-local
  *    message describing the last failure of the calling thread.  No C++
  *    exception and no abort crosses this boundary.
+ *  * Environment switches, read at every call (for tests and measurement; the
+ *    results stay within each path's bounds): ATC_SUB32_KERNELS=1 runs the
+ *    subspace eigensolvers as kernel chains instead of one cooperative
+ *    launch; ATC_NO_OVERLAP=1 keeps a long mode's m = 32 solver in one launch
+ *    (no second stream); ATC_SPLIT_MIN_BYTES=<bytes> sets the smallest
+ *    tensor that takes the split solver (default 64 MiB);
+ *    ATC_GRID_SPIN_LIMIT=<polls> bounds each grid-barrier wait of the
+ *    one-launch eigensolvers (default 2^20; a wait that gives up makes the
+ *    call return ATC_ERR_INTERNAL).
  *  * Calls are re-entrant across host threads (each on its own stream with its
  *    own workspace).  atc_sthosvd returns only once the calling thread has
  *    learnt every rank, so one host thread runs its single-tensor calls one
