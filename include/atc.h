@@ -29,7 +29,8 @@
  *    results stay within each path's bounds): ATC_SUB32_KERNELS=1 runs the
  *    subspace eigensolvers as kernel chains instead of one cooperative
  *    launch; ATC_NO_OVERLAP=1 keeps a long mode's m = 32 solver in one launch
- *    (no second stream); ATC_SPLIT_MIN_BYTES=<bytes> sets the smallest
+ *    and the reconstruction adjoint's first-mode chain on the caller's
+ *    stream (no second stream); ATC_SPLIT_MIN_BYTES=<bytes> sets the smallest
  *    tensor that takes the split solver (default 64 MiB);
  *    ATC_GRID_SPIN_LIMIT=<polls> bounds each grid-barrier wait of the
  *    one-launch eigensolvers (default 2^20; a wait that gives up makes the
@@ -331,7 +332,11 @@ size_t atc_reconstruct_backward_workspace_size(const atc_shape* shape, const int
  *   dfactors[n] = R_(n) W_(n)^T, W = G x_{m != n} U_m              (n_n x r_n)
  * (the mode-product rules of Section 3.1).  Partial products are recomputed
  * from G and the U_k, not read from the forward pass.  dfactors: host array of
- * d device pointers; any of dcore / dfactors[n] may be NULL to skip it.
+ * d device pointers; any of dcore / dfactors[n] may be NULL to skip it.  The
+ * chain of one mode (its own pass over R) may run on a second stream of the
+ * library, ordered after the call's earlier work on `stream` and joined back
+ * into `stream` before the call returns: the outputs are complete in the
+ * order of `stream` like those of any kernel launch.
  */
 atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks, const void* core,
                                     const void* const* factors, const void* dxhat, void* dcore,

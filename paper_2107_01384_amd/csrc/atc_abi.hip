@@ -1194,6 +1194,9 @@ BwdPlan bwd_plan(const atc_shape* s, const int64_t* ranks) {
     return p;
 }
 
+// bufs: P, the main chains' two scratch buffers, then the two of the mode-a
+// chain (which may run on a second stream); part / cg: the main chains' Gram
+// partials and FP64 product, then the mode-a chain's.
 size_t carve_bwd(const atc_shape* s, const int64_t* ranks, char* base, void** bufs, double** part, size_t* part_cap,
                  double** cg, MatBufs* mb) {
     const int d = s->ndim;
@@ -1210,19 +1213,31 @@ size_t carve_bwd(const atc_shape* s, const int64_t* ranks, char* base, void** bu
     void* P = c.take((size_t)p.big * esz);     // R shrunk in one mode
     void* b0 = c.take((size_t)p.big * esz);    // chain scratch
     void* b1 = c.take((size_t)p.big * esz);
+    void* b2 = c.take((size_t)p.big * esz);
+    void* b3 = c.take((size_t)p.big * esz);
     const size_t pc = part_capacity(nmax);
     double* pt = (double*)c.take(pc);
+    double* pt2 = (double*)c.take(pc);
     double* cgb = (double*)c.take(nr * 8);
+    double* cgb2 = (double*)c.take(nr * 8);
     double* m64 = (double*)c.take((size_t)d * nr * 8);
     float* m32 = (float*)c.take(s->dtype == ATC_F32 ? (size_t)d * nr * 4 : 0);
     if (bufs) {
         bufs[0] = P;
         bufs[1] = b0;
         bufs[2] = b1;
+        bufs[3] = b2;
+        bufs[4] = b3;
     }
-    if (part) *part = pt;
+    if (part) {
+        part[0] = pt;
+        part[1] = pt2;
+    }
     if (part_cap) *part_cap = pc;
-    if (cg) *cg = cgb;
+    if (cg) {
+        cg[0] = cgb;
+        cg[1] = cgb2;
+    }
     if (mb) {
         mb->m64 = m64;
         mb->m32 = m32;
@@ -1257,12 +1272,12 @@ atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks
     const size_t need = carve_bwd(shape, ranks, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     if (!workspace || workspace_bytes < need)
         return fail(ATC_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
-    void* bufs[3];
-    double* part;
+    void* bufs[5];
+    double* part[2];
     size_t part_cap;
-    double* cg;
+    double* cg[2];
     MatBufs mb;
-    carve_bwd(shape, ranks, (char*)workspace, bufs, &part, &part_cap, &cg, &mb);
+    carve_bwd(shape, ranks, (char*)workspace, bufs, part, &part_cap, cg, &mb);
     hipStream_t st = (hipStream_t)stream;
     const bool f64 = shape->dtype == ATC_F64;
     const int prec = f64 ? PREC_F64 : PREC_F32;
@@ -1284,17 +1299,25 @@ atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks
 
     // Shrinks `src` (current sizes cur) in every mode of `modes` (in order) and
     // leaves the result in *out (one of the scratch buffers or `final_dst`).
-    auto shrink_chain = [&](const void* src, int64_t* cur, const std::vector<int>& modes, void* final_dst,
-                            const void** out) -> atc_status {
+    // a chain's stream and buffers: the main chains, or the mode-a chain
+    struct Lane {
+        hipStream_t st;
+        void* b[2];
+        double* part;
+        double* cg;
+    };
+    const Lane main_lane{st, {bufs[1], bufs[2]}, part[0], cg[0]};
+    auto shrink_chain = [&](const Lane& ln, const void* src, int64_t* cur, const std::vector<int>& modes,
+                            void* final_dst, const void** out) -> atc_status {
         const void* s_ = src;
         int flip = 0;
         for (size_t i = 0; i < modes.size(); ++i) {
             const int k = modes[i];
             const int64_t L = prod(cur, 0, k), R = prod(cur, k + 1, d);
-            void* dst = (i + 1 == modes.size() && final_dst) ? final_dst : bufs[1 + flip];
+            void* dst = (i + 1 == modes.size() && final_dst) ? final_dst : ln.b[flip];
             flip ^= 1;
             const TtmPlan tp = ttm_plan(tprec, L, (int)cur[k], R, (int)ranks[k]);
-            HIP_TRY(launch_ttm(tprec, tp, s_, Mt[k], nullptr, nullptr, dst, st));
+            HIP_TRY(launch_ttm(tprec, tp, s_, Mt[k], nullptr, nullptr, dst, ln.st));
             cur[k] = ranks[k];
             s_ = dst;
         }
@@ -1302,23 +1325,48 @@ atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks
         return ATC_OK;
     };
     // dU_n = T_n(n) G_(n)^T: cross Gram over the (L, ., R) view of mode n
-    auto factor_grad = [&](const void* Tn, int n) -> atc_status {
+    auto factor_grad = [&](const Lane& ln, const void* Tn, int n) -> atc_status {
         if (!dfactors || !dfactors[n]) return ATC_OK;
         int64_t rr[ATC_MAX_DIMS];
         for (int k = 0; k < d; ++k) rr[k] = ranks[k];
         const int64_t L = prod(rr, 0, n), R = prod(rr, n + 1, d);
         const GramPlan gp = gram_plan(prec, L, (int)shape->dims[n], (int)ranks[n], R, false, part_cap);
-        HIP_TRY(launch_gram(prec, gp, Tn, core, part, st));
-        HIP_TRY(launch_gram_reduce(gp, part, cg, st));
+        HIP_TRY(launch_gram(prec, gp, Tn, core, ln.part, ln.st));
+        HIP_TRY(launch_gram_reduce(gp, ln.part, ln.cg, ln.st));
         const int64_t cnt = shape->dims[n] * ranks[n];
-        hipLaunchKernelGGL(k_cast_out, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, cg, dfactors[n], cnt,
-                           f64 ? 1 : 0);
+        hipLaunchKernelGGL(k_cast_out, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, ln.st, ln.cg, dfactors[n],
+                           cnt, f64 ? 1 : 0);
         HIP_TRY(hipGetLastError());
         return ATC_OK;
     };
 
-    // P = R x_a U_a^T
     const int a = bp.a;
+    // T_a (every mode but a shrunk): a second pass over R, independent of the
+    // others; on the second stream with its own buffers, beside the pass that
+    // makes P and the chains from P, and joined before the call returns
+    SideQueue::Dev* sq = nullptr;
+    if (dfactors && dfactors[a] && !bp.chain[a].empty() && overlap_enabled()) sq = g_side.get();
+    const Lane a_lane{sq ? sq->ttm : st, {bufs[3], bufs[4]}, part[1], cg[1]};
+    auto chain_a = [&]() -> atc_status {
+        if (!dfactors || !dfactors[a]) return ATC_OK;
+        const std::vector<int>& modes = bp.chain[a];
+        int64_t cur[ATC_MAX_DIMS];
+        for (int k = 0; k < d; ++k) cur[k] = shape->dims[k];
+        const void* Ta = dxhat;
+        if (!modes.empty()) {
+            atc_status e = shrink_chain(a_lane, dxhat, cur, modes, nullptr, &Ta);
+            if (e != ATC_OK) return e;
+        }
+        return factor_grad(a_lane, Ta, a);
+    };
+    if (sq) {
+        HIP_TRY(hipEventRecord(sq->basis, st));  // the mode-product operands are ready
+        HIP_TRY(hipStreamWaitEvent(sq->ttm, sq->basis, 0));
+        atc_status e = chain_a();
+        if (e != ATC_OK) return e;
+        HIP_TRY(hipEventRecord(sq->proj, sq->ttm));
+    }
+    // P = R x_a U_a^T
     int64_t curP[ATC_MAX_DIMS];
     for (int k = 0; k < d; ++k) curP[k] = shape->dims[k];
     {
@@ -1335,31 +1383,25 @@ atc_status atc_reconstruct_backward(const atc_shape* shape, const int64_t* ranks
         for (int k = 0; k < d; ++k) cur[k] = curP[k];
         const void* Tn = bufs[0];
         if (!modes.empty()) {
-            atc_status e = shrink_chain(bufs[0], cur, modes, nullptr, &Tn);
+            atc_status e = shrink_chain(main_lane, bufs[0], cur, modes, nullptr, &Tn);
             if (e != ATC_OK) return e;
         }
-        atc_status e = factor_grad(Tn, n);
+        atc_status e = factor_grad(main_lane, Tn, n);
         if (e != ATC_OK) return e;
         // dG = T_n x_n U_n^T, once
         if (dcore && n == (a == 0 ? 1 : 0)) {
             std::vector<int> last{n};
             const void* outp;
             // shrink T_n in mode n straight into dcore
-            e = shrink_chain(Tn, cur, last, dcore, &outp);
+            e = shrink_chain(main_lane, Tn, cur, last, dcore, &outp);
             if (e != ATC_OK) return e;
         }
     }
-    // T_a: one more pass over R, shrinking every other mode
-    if (dfactors && dfactors[a]) {
-        const std::vector<int>& modes = bp.chain[a];
-        int64_t cur[ATC_MAX_DIMS];
-        for (int k = 0; k < d; ++k) cur[k] = shape->dims[k];
-        const void* Ta = dxhat;
-        if (!modes.empty()) {
-            atc_status e = shrink_chain(dxhat, cur, modes, nullptr, &Ta);
-            if (e != ATC_OK) return e;
-        }
-        atc_status e = factor_grad(Ta, a);
+    // T_a: joined from the second stream, or made here
+    if (sq) {
+        HIP_TRY(hipStreamWaitEvent(st, sq->proj, 0));
+    } else {
+        atc_status e = chain_a();
         if (e != ATC_OK) return e;
     }
     if (dcore && d == 1) {
