@@ -45,9 +45,14 @@ def test_backward_parity(dims, ranks, dtype, tol):
     dcore, dfs = atc.reconstruct_backward(to_dev(core, dtype), [to_dev(f, dtype) for f in facs],
                                           to_dev(xh - y, dtype))
     torch.cuda.synchronize()
+    # norm-wise, and entry by entry against the largest entry of each output
+    ratios = [np.abs(np64(dcore) - dg).max() / np.abs(dg).max()]
     assert np.linalg.norm(np64(dcore) - dg) <= tol * np.linalg.norm(dg)
     for n in range(len(dims)):
         assert np.linalg.norm(np64(dfs[n]) - dus[n]) <= tol * np.linalg.norm(dus[n])
+        ratios.append(np.abs(np64(dfs[n]) - dus[n]).max() / np.abs(dus[n]).max())
+    log("  entry-wise max error / max entry: dG %.2e, dU %s" % (ratios[0], ["%.2e" % r for r in ratios[1:]]))
+    assert max(ratios) <= tol, ratios
 
 
 def test_autograd_function_matches_oracle_and_saves_only_inputs():
