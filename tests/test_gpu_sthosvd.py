@@ -146,6 +146,19 @@ def test_f32_parity_fields(shape, eps, precision):
     diff = recon_rel_diff(x, t_g, t_f)
     log("  |X~_gpu - X~_oracle| / |X| = %.3e" % diff)
     assert diff <= 0.2 * eps
+    # the sign rule on both sides: each kept column whose eigenvalue is well
+    # separated (gaps above 1e-3 of the largest) points the oracle's way (a
+    # flipped sign gives -1, a swapped column about 0)
+    for k in range(len(shape)):
+        lam = np.asarray(t_f.eigvals[k], dtype=np.float64)
+        ug, uf = np64(t_g.factors[k]), t_f.factors[k]
+        dots = []
+        for j in range(t_g.ranks[k]):
+            gap = min(lam[j - 1] - lam[j] if j > 0 else np.inf, lam[j] - lam[j + 1] if j + 1 < len(lam) else np.inf)
+            if gap > 1e-3 * lam[0]:
+                dots.append(float(ug[:, j] @ uf[:, j]))
+        log("  mode", k, "separated columns", len(dots), "min dot %.6f" % (min(dots) if dots else 1.0))
+        assert all(v >= 0.9 for v in dots), (k, dots)
 
 
 def test_f64_known_rank_padded_jacobi():
